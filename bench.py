@@ -1,0 +1,312 @@
+#!/usr/bin/env python3
+"""Benchmark of the fused Dirac sweep on one MI355X.
+
+Headline (`value`): spinor site-updates per second of the FP32-storage sweep
+on the 2-D 2048 x 2048 tanh-step workload (complex64 state, FP64 potential
+and phases), inputs resident in HBM.  A "step" is one full time step of the
+hot path: x transport, y transport and the local phase step, fused in one
+launch.  The same line carries the FP64 path, the FP32-vs-FP64 error after
+the timed steps, the roofline of the sweep kernel, the CPU oracle baseline
+and the secondary workloads (1-D resident, 3-D, observables, batched,
+adjoint).
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1]
+  python bench.py --only sweep --steps 20     # kernel loop only (profiling)
+  python bench.py --calibrate-copy            # a plain copy of known size
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+BYTES_F32 = 72                 # read psi 32 B + write psi 32 B + read V 8 B per site-update
+BYTES_F64 = 136                # read psi 64 B + write psi 64 B + read V 8 B
+METRIC = "spinor site-updates/s + % HBM roofline, FP32 vs FP64 at rel-L2 <=1e-4"
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("dirac_device.h", "dirac_sweep.hip", "dirac_launch.h"):
+        with open(os.path.join(ROOT, "paper_1107_4650_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def timed_sweep(plan, psi, V, steps, warmup):
+    """Alternate psi <-> tmp with dl_step_out; HIP events around every launch on
+    the launch stream.  Returns (wall seconds, mean per-launch ms, final tensor)."""
+    import torch
+    a, b = psi, torch.empty_like(psi)
+    for _ in range(warmup):
+        plan.step_out(a, b, V)
+        a, b = b, a
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for i in range(steps):
+        starts[i].record()
+        plan.step_out(a, b, V)
+        ends[i].record()
+        a, b = b, a
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = float(np.mean([s.elapsed_time(e) for s, e in zip(starts, ends)]))
+    return wall, per, a
+
+
+def to_dev(x, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+    return t if dtype is None else t.to(dtype)
+
+
+def rel_l2(a, b):
+    import torch
+    a = a.to(torch.complex128)
+    b = b.to(torch.complex128)
+    return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+
+
+def load_traffic(kernel_name):
+    """HBM bytes per launch from committed rocprofv3 PMC summaries, if they were
+    taken on the current kernel source; None otherwise."""
+    path = os.path.join(PROFILES, "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    ent = t.get(kernel_name)
+    if not ent or ent.get("source_hash") != kernel_source_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def bench_main(args):
+    import torch
+    from paper_1107_4650_amd import libdirac as L
+    from paper_1107_4650_amd.inputs import config_2d_tanh
+
+    L.load()
+    w = config_2d_tanh(n=2048, nsteps=args.steps)
+    sites = w.sites
+    log(f"workload {w.name}: {sites} sites, {args.steps} steps, warmup {args.warmup}")
+    V = to_dev(w.V)
+    res = {}
+
+    # ---- FP32 storage (headline) -------------------------------------------
+    with L.Plan(w.shape, w.dx, w.dt, w.c, w.m, dtype="c64", xmin=w.xmin) as p32:
+        psi32 = to_dev(w.psi0, torch.complex64)
+        wall32, per32, out32 = timed_sweep(p32, psi32, V, args.steps, args.warmup)
+        info = p32.info()
+        obs32 = p32.observables(out32, 0.0)
+    res["fp32"] = dict(wall=wall32, per_launch_ms=per32)
+    log(f"fp32: {wall32 * 1e3 / args.steps:.4f} ms/step wall, {per32:.4f} ms/launch")
+    if args.only == "sweep":
+        return None
+
+    # ---- FP64 path on the same steps (also the reference for the FP32 error) -
+    with L.Plan(w.shape, w.dx, w.dt, w.c, w.m, dtype="c128", xmin=w.xmin) as p64:
+        psi64 = to_dev(w.psi0)
+        wall64, per64, out64 = timed_sweep(p64, psi64, V, args.steps, args.warmup)
+        obs64 = p64.observables(out64, 0.0)
+    # both runs advanced warmup + steps steps from the same initial state
+    err = rel_l2(out32, out64)
+    log(f"fp64: {wall64 * 1e3 / args.steps:.4f} ms/step wall; fp32 vs fp64 rel-L2 {err:.3e}")
+    del psi32, psi64, out32, out64
+    torch.cuda.empty_cache()
+
+    achieved = BYTES_F32 * sites / (per32 * 1e-3) / 1e9
+    traffic = load_traffic("sweep2d_f32_2048")
+    line = {
+        "metric": METRIC,
+        "value": sites * args.steps / wall32,
+        "unit": "site-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall32 * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "2-D Dirac, 2048x2048 cells, tanh step V0*tanh(x/0.1), "
+                               "Gaussian packet sigma 1.5 p0=(40,0), complex64 state, FP64 V "
+                               "and phases, dx=0.01, c*dt=dx, zero walls",
+                   "grid": [2048, 2048], "steps_per_call": 1,
+                   "tiling": info},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic,
+                     "kernel": "k_sweep2d<float,0,1>",
+                     "bytes_per_site": BYTES_F32},
+        "fp64": {"value": sites * args.steps / wall64, "unit": "site-updates/s",
+                 "ms_per_step": wall64 * 1e3 / args.steps, "per_launch_ms": per64,
+                 "roofline_frac": BYTES_F64 * sites / (per64 * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "fp32_vs_fp64_rel_l2": err,
+        "fp32_vs_fp64_steps": args.steps + args.warmup,
+        "norm_fp32": obs32[0], "norm_fp64": obs64[0],
+    }
+    return line
+
+
+def bench_extras(args, line):
+    """Secondary workloads of the same library (not the headline)."""
+    import torch
+    from paper_1107_4650_amd import libdirac as L
+    from paper_1107_4650_amd.inputs import config_1d_step
+    ex = {}
+    # 1-D N = 4096, 2000 steps, complex128 (one resident workgroup)
+    w = config_1d_step()
+    with L.Plan(w.shape, w.dx, w.dt, w.c, w.m, dtype="c128", xmin=w.xmin) as p:
+        psi = to_dev(w.psi0)
+        V = to_dev(w.V)
+        p.step(psi, V, 10)
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        p.step(psi, V, w.nsteps)
+        e.record()
+        torch.cuda.synchronize()
+        ms = s.elapsed_time(e)
+    ex["1d_4096_c128"] = {"steps": w.nsteps, "ms": ms,
+                          "site_updates_per_s": w.sites * w.nsteps / (ms * 1e-3)}
+    log(f"1-D 4096 x {w.nsteps}: {ms:.3f} ms")
+    # 3-D 512^3 FP32 and FP64, a prefix of the 2000-step run
+    ex["3d_512"] = bench_3d(args)
+    # observables pass on the 2048^2 FP32 state
+    ex["observables_2048_f32"] = bench_observables()
+    line["extras"] = ex
+
+
+def bench_3d(args):
+    import torch
+    from paper_1107_4650_amd import libdirac as L
+    n, dx = 512, 0.02
+    c, m = 137.036, 1.0
+    steps = args.steps3d
+    # separable packet and spherical barrier built on the device (input generation only)
+    x = (torch.arange(n, dtype=torch.float64, device="cuda") + 0.5) * dx - n * dx / 2
+    delta = 2.0
+    gx = torch.exp(1j * 30.0 * x) * torch.exp(-((x + 2.5) ** 2) / (4 * delta * delta))
+    gy = torch.exp(1j * 10.0 * x) * torch.exp(-(x ** 2) / (4 * delta * delta))
+    gz = torch.exp(-(x ** 2) / (4 * delta * delta)).to(torch.complex128)
+    p0 = np.array([30.0, 10.0, 0.0])
+    E = np.sqrt(c * c * (p0 ** 2).sum() + m * m * c ** 4)
+    u = torch.tensor([1.0, 0.0, c * p0[2] / (E + m * c * c), c * (p0[0] + 1j * p0[1]) / (E + m * c * c)],
+                     dtype=torch.complex128, device="cuda")
+    out = {}
+    r2 = (x[:, None, None] ** 2 + x[None, :, None] ** 2 + x[None, None, :] ** 2)
+    V = (1.5 * m * c * c) * torch.exp(-r2 / 4.0)
+    del r2
+    for dt_name, tdt, bps in (("f32", torch.complex64, BYTES_F32), ("f64", torch.complex128, BYTES_F64)):
+        f = (gz[:, None, None] * gy[None, :, None] * gx[None, None, :])
+        psi = (f[..., None] * u).to(tdt).contiguous()
+        del f
+        with L.Plan((n, n, n), dx, dx / c, c, m, dtype=str(tdt).split(".")[1]) as p:
+            wall, per, _ = timed_sweep(p, psi, V, steps, 2)
+        sites = n ** 3
+        out[dt_name] = {"steps": steps, "ms_per_step": wall * 1e3 / steps, "per_launch_ms": per,
+                        "site_updates_per_s": sites * steps / wall,
+                        "roofline_frac": bps * sites / (per * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        log(f"3-D 512^3 {dt_name}: {per:.3f} ms/launch")
+        del psi
+        torch.cuda.empty_cache()
+    return out
+
+
+def bench_observables():
+    import torch
+    from paper_1107_4650_amd import libdirac as L
+    from paper_1107_4650_amd.inputs import config_2d_tanh
+    w = config_2d_tanh(n=2048, nsteps=1)
+    with L.Plan(w.shape, w.dx, w.dt, w.c, w.m, dtype="c64", xmin=w.xmin) as p:
+        psi = to_dev(w.psi0, torch.complex64)
+        p.observables(psi, 0.0)
+        reps = 20
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            p.observables(psi, 0.0)
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+    return {"ms_per_call_incl_sync": ms, "bytes_per_site": 32,
+            "GBps": 32 * w.sites / (ms * 1e-3) / 1e9}
+
+
+def cpu_baseline(min_seconds=10.0, max_seconds=30.0):
+    """The FP64 oracle, as it stands, on the host's cores: bounded sample of the
+    same 2048^2 workload (whole steps until ~min_seconds of CPU time)."""
+    from oracle import oracle as O
+    from paper_1107_4650_amd.inputs import config_2d_tanh
+    w = config_2d_tanh(n=2048, nsteps=1)
+    threads = O.max_threads()
+    psi = w.psi0
+    done, t_used, chunk = 0, 0.0, 4
+    while t_used < min_seconds and t_used < max_seconds:
+        t0 = time.perf_counter()
+        psi = O.step(psi, w.V, dt=w.dt, c=w.c, m=w.m, nsteps=chunk, axes=w.axes, threads=threads)
+        t_used += time.perf_counter() - t0
+        done += chunk
+    return {"value": w.sites * done / t_used, "unit": "site-updates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{done} FP64 steps of the 2048x2048 tanh-step workload "
+                      f"({w.sites * done:.3e} site-updates, {t_used:.1f} s, {threads} OpenMP threads)"}
+
+
+def calibrate_copy(nbytes=1 << 30, reps=5):
+    """A plain device copy of known size, for scaling the PMC byte counters."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibrate_copy_bytes_read": nbytes, "bytes_written": nbytes, "reps": reps}))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps3d", type=int, default=50)
+    ap.add_argument("--only", choices=["all", "sweep", "main"], default="all")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build runs the sweep on a single MI355X; "
+              f"--gpus {args.gpus} is not supported (multi-GPU slab decomposition is design only).",
+              file=sys.stderr)
+        sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
+    line = bench_main(args)
+    if line is None:
+        return
+    if args.only == "all":
+        bench_extras(args, line)
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,167 @@
+/*
+ * libdirac.h -- C ABI of the MI355X split-operator Dirac sweep.
+ *
+ * The library advances a four-component complex spinor field on a regular
+ * grid with the lowest-order operator splitting of the time-dependent Dirac
+ * equation in coordinate space (Fillion-Gourdeau, Lorin, Bandrauk, Sec. 2):
+ * per time step, for every active grid axis d in the order x, y, z, the exact
+ * characteristic transport
+ *
+ *     psi'(i) = 1/2 (I + alpha_d) psi(i - e_d) + 1/2 (I - alpha_d) psi(i + e_d)
+ *
+ * (eq:sol_dis_1-3, valid because c dt equals the cell size a), then the local
+ * step D (eq:sol_dis_4 without vector potential, static V so Vtilde = V dt):
+ *
+ *     psi_c(i) <- exp(-i (beta_cc m c^2 + V(i)) dt) psi_c(i).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All calls return a dl_status; none throws or aborts.  On a non-OK
+ *    status, dl_last_error() returns a message for the calling thread.
+ *  - Pointers named psi, lam, V, Q, G are DEVICE pointers owned by the caller;
+ *    the library never frees them.  Arrays are C-contiguous with grid
+ *    dimension 0 (x) fastest and the spinor component last:
+ *    psi[((k * n1 + j) * n0 + i) * 4 + comp], each component an interleaved
+ *    (re, im) pair of float (DL_C64) or double (DL_C128).  V, Q and G hold
+ *    one double per cell in the same cell order.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued
+ *    on it and the call returns without waiting, except where noted.
+ *    Kernel faults surface at the next synchronising call as DL_ERR_HIP.
+ *  - A plan owns its scratch (a second state buffer, reduction partials),
+ *    allocated in dl_plan_create.  One plan must not be used from two
+ *    streams or threads at once.
+ *  - psi and lam must be 16-byte aligned, V, Q and G 8-byte aligned.
+ */
+#ifndef LIBDIRAC_H
+#define LIBDIRAC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LIBDIRAC_VERSION 1
+
+typedef struct dl_plan_s *dl_plan;
+
+typedef enum {
+    DL_OK = 0,
+    DL_ERR_ARG = -1,    /* null pointer, bad size, bad enum, nsteps < 0 ... */
+    DL_ERR_CFL = -2,    /* c dt differs from the cell size (relative 1e-12) */
+    DL_ERR_DTYPE = -3,  /* unknown dtype, or call not valid for the plan's dtype */
+    DL_ERR_ALIGN = -4,  /* a pointer is not aligned as required */
+    DL_ERR_NOMEM = -5,  /* device allocation failed */
+    DL_ERR_HIP = -6,    /* a HIP runtime call or kernel failed */
+    DL_ERR_STATE = -7   /* call not allowed on this plan (e.g. a dry plan) */
+} dl_status;
+
+typedef enum { DL_C64 = 0, DL_C128 = 1 } dl_dtype;
+
+/* Cells outside the box: DL_BC_ZERO = zero (the Dirichlet wall of Sec. 5);
+ * DL_BC_PERIODIC = the box wraps around (exactly unitary steps). */
+typedef enum { DL_BC_ZERO = 0, DL_BC_PERIODIC = 1 } dl_bc;
+
+/* Plan flags */
+#define DL_DRY 1u    /* validate only: no HIP call, no allocation; every other
+                        entry point then returns DL_ERR_STATE */
+#define DL_GRAPH 2u  /* replay long step sequences from captured hipGraphs */
+
+/* Grid of P0 cells (Sec. 2.3).  n[d] cells along grid dimension d, n[0]
+ * fastest.  axis[d] is the Dirac matrix carried by dimension d (0 = alpha_x,
+ * 1 = alpha_y, 2 = alpha_z); it must increase with d, so the transports run
+ * in the paper's order A, B, C.  Cell centres are
+ * xmin[d] + (i + 1/2) dx; xmin only enters the observables. */
+typedef struct {
+    int ndim;        /* 1, 2 or 3 */
+    int64_t n[3];    /* each >= 2 for d < ndim */
+    int axis[3];
+    double xmin[3];
+} dl_grid;
+
+/* Create a plan for grid g with cell size dx, time step dt, speed of light c
+ * and mass m (atomic units in the paper).  Requires c dt = dx to relative
+ * 1e-12 (the characteristic condition with K = 1, Sec. 2.3), dx, dt, c > 0 and
+ * m >= 0.  On success *out holds the plan; on failure *out is NULL. */
+int dl_plan_create(dl_plan *out, const dl_grid *g, double dx, double dt, double c,
+                   double m, dl_dtype dtype, dl_bc bc, unsigned flags);
+
+/* Release the plan and its scratch.  Waits for the plan's own work. */
+int dl_plan_destroy(dl_plan p);
+
+/* Advance psi in place by nsteps full steps (transports in the order x, y, z,
+ * then D).  V: potential energy per cell (FP64) or NULL for V = 0.  With m = 0
+ * and V = NULL the step is pure streaming and D is skipped.
+ * In the complex64 plan the state is stored in FP32 while the phase
+ * exp(-i theta) is formed from the FP64 V and applied in FP64, then rounded
+ * once to FP32.  nsteps = 0 is a no-op. */
+int dl_step(dl_plan p, void *psi, const double *V, int64_t nsteps, void *stream);
+
+/* One step out of place: dst = S src (same step as dl_step with nsteps = 1).
+ * src and dst must not overlap; src is left unchanged.  Lets a caller keep
+ * both time levels, or alternate two buffers without the copy dl_step makes
+ * for an odd number of steps. */
+int dl_step_out(dl_plan p, const void *src, void *dst, const double *V, void *stream);
+
+/* Observables of psi (Sec. 5.2.1 R/T integrals on the cell grid), as FP64
+ * compensated sums, written to the HOST array out[5]:
+ *   out[0] = N    = dV sum |psi|^2            (dV = dx^ndim)
+ *   out[1..3]     = sum x_d |psi|^2 / sum |psi|^2 along grid dims 0..2 (0 if absent)
+ *   out[4] = P_T  = dV sum_{x_0 > x_b} |psi|^2 (cell centres, strict >)
+ * Synchronises `stream`. */
+int dl_observables(dl_plan p, const void *psi, double x_b, double out[5], void *stream);
+
+/* Seed the adjoint of L = P_T(psi_N): lam = M psi with M the indicator of
+ * x_0 > x_b, and Q = 0.  lam has psi's layout, Q one double per cell. */
+int dl_seed_adjoint(dl_plan p, const void *psi, double x_b, void *lam, double *Q,
+                    void *stream);
+
+/* nsteps reverse steps of the discrete adjoint (derived from eq:sol_dis_1-4).
+ * Each step first accumulates, per cell,
+ *     Q += 2 dt dV Im(lam^H psi),
+ * then replaces psi by S^{-1} psi and lam by S^H lam, where S is one forward
+ * step.  S^H lam is exact for both boundary conditions; S^{-1} = S^H holds
+ * exactly with DL_BC_PERIODIC (with zero walls it holds only while nothing has
+ * left the box).  After N steps from (psi_N, lam_N = M psi_N, Q = 0), Q is
+ * dL/dV and psi is the reconstructed psi_0. */
+int dl_grad_step(dl_plan p, void *psi, void *lam, const double *V, double *Q,
+                 int64_t nsteps, void *stream);
+
+/* out[j] = sum_cells G[j][cell] * Q[cell] for j < nb (deterministic FP64
+ * reduction).  G: nb rows of one double per cell (device); out: nb doubles
+ * (device).  Gives dL/dtheta_j from dL/dV when G holds dV/dtheta_j. */
+int dl_project(dl_plan p, const double *Q, const double *G, int nb, double *out,
+               void *stream);
+
+/* V[cell] = sum_j theta[j] G[j][cell] (FP64; the transpose of dl_project).
+ * G: nb rows of one double per cell, theta: nb doubles, V: one double per
+ * cell, all device pointers.  Builds a parametrised potential on the device. */
+int dl_expand(dl_plan p, const double *G, const double *theta, int nb, double *V,
+              void *stream);
+
+/* ---- batches: many independent plans advanced by shared launches ------- */
+
+/* Build a batch of `count` instances; grids[k], dx[k], dt[k], c[k], m[k] as in
+ * dl_plan_create, one dtype and bc for all.  Instances must be 1-D or 2-D. */
+int dl_batch_create(dl_plan *out, const dl_grid *grids, const double *dx,
+                    const double *dt, const double *c, const double *m, int count,
+                    dl_dtype dtype, dl_bc bc, unsigned flags);
+
+/* Advance instance k in place by nsteps[k] steps: psi[k] (device), V[k]
+ * (device or NULL).  The arrays psi, V and nsteps are HOST arrays of length
+ * count.  Each instance's result is bit-identical to dl_step on a plan with
+ * the same parameters. */
+int dl_batch_step(dl_plan b, void *const *psi, const double *const *V,
+                  const int64_t *nsteps, void *stream);
+
+/* Thread-local message for the last non-OK status ("" if none). */
+const char *dl_last_error(void);
+
+/* LIBDIRAC_VERSION of the built library. */
+int dl_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LIBDIRAC_H */

@@ -1,0 +1,290 @@
+// dirac_device.h -- device building blocks of the MI355X Dirac sweep (gfx950).
+//
+// Site layout: one cell = 4 complex components (a, b, c, d) = 8 reals of type
+// T, stored (a.re, a.im, b.re, b.im, c.re, c.im, d.re, d.im).
+//
+// Transport along one axis (eq:sol_dis_1-3, App. A):
+//     psi'(i) = 1/2 (I + alpha) psi(i - e) + 1/2 (I - alpha) psi(i + e).
+// Each site is split into two "right movers" r (the two independent entries
+// of (I + alpha) psi, taken from the left neighbour) and two "left movers" l
+// (entries of (I - alpha) psi, taken from the right neighbour); the output is
+// recombined from r of the left neighbour and l of the right neighbour.
+// This is the eigenbasis rotation of App. A without its 1/sqrt(2) factors:
+// only additions and exact multiplications by +-i occur, and the factor 1/2
+// of every transport is deferred and applied once per step, as an exact
+// power of two folded into the phase factor.  The rounding of each output
+// component is therefore that of fl(x_L + x_R) with x_L, x_R the rounded
+// two-term movers, i.e. the same as the plain projector formula evaluated
+// neighbour by neighbour (barring subnormal intermediates).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dirac {
+
+template <typename T> struct Site { T v[8]; };
+template <typename T> struct Mov { T v[4]; };  // two complex numbers
+
+template <typename T> __device__ __forceinline__ void zero(Site<T>& s) {
+#pragma unroll
+  for (int k = 0; k < 8; ++k) s.v[k] = T(0);
+}
+template <typename T> __device__ __forceinline__ void zero(Mov<T>& s) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) s.v[k] = T(0);
+}
+
+// ---------------------------------------------------------------------------
+// global memory: 16-byte vector loads/stores of one site
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void load_site(const float* __restrict__ p, Site<float>& s) {
+  const float4 lo = reinterpret_cast<const float4*>(p)[0];
+  const float4 hi = reinterpret_cast<const float4*>(p)[1];
+  s.v[0] = lo.x; s.v[1] = lo.y; s.v[2] = lo.z; s.v[3] = lo.w;
+  s.v[4] = hi.x; s.v[5] = hi.y; s.v[6] = hi.z; s.v[7] = hi.w;
+}
+__device__ __forceinline__ void load_site(const double* __restrict__ p, Site<double>& s) {
+  const double2* q = reinterpret_cast<const double2*>(p);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double2 t = q[k];
+    s.v[2 * k] = t.x;
+    s.v[2 * k + 1] = t.y;
+  }
+}
+__device__ __forceinline__ void store_site(float* __restrict__ p, const Site<float>& s) {
+  reinterpret_cast<float4*>(p)[0] = make_float4(s.v[0], s.v[1], s.v[2], s.v[3]);
+  reinterpret_cast<float4*>(p)[1] = make_float4(s.v[4], s.v[5], s.v[6], s.v[7]);
+}
+__device__ __forceinline__ void store_site(double* __restrict__ p, const Site<double>& s) {
+  double2* q = reinterpret_cast<double2*>(p);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) q[k] = make_double2(s.v[2 * k], s.v[2 * k + 1]);
+}
+
+// ---------------------------------------------------------------------------
+// wave64 neighbour exchange with DPP (wave_shr:1 / wave_shl:1).  Lanes whose
+// source lies outside the wave (lane 0 for shr, lane 63 for shl) keep `old`.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float dpp_from_left(float old, float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+      __builtin_bit_cast(int, old), __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float dpp_from_right(float old, float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+      __builtin_bit_cast(int, old), __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double dpp_from_left(double old, double v) {
+  const int2 o = __builtin_bit_cast(int2, old), s = __builtin_bit_cast(int2, v);
+  int2 r;
+  r.x = __builtin_amdgcn_update_dpp(o.x, s.x, 0x138, 0xf, 0xf, false);
+  r.y = __builtin_amdgcn_update_dpp(o.y, s.y, 0x138, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, r);
+}
+__device__ __forceinline__ double dpp_from_right(double old, double v) {
+  const int2 o = __builtin_bit_cast(int2, old), s = __builtin_bit_cast(int2, v);
+  int2 r;
+  r.x = __builtin_amdgcn_update_dpp(o.x, s.x, 0x130, 0xf, 0xf, false);
+  r.y = __builtin_amdgcn_update_dpp(o.y, s.y, 0x130, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, r);
+}
+
+// ---------------------------------------------------------------------------
+// Per-axis movers and recombination (outputs are 2x the transported value).
+// ---------------------------------------------------------------------------
+template <int AX, typename T> struct Axis;
+
+// alpha_x: (I+alpha)psi ~ (a+d, b+c, b+c, a+d); (I-alpha)psi ~ (a-d, b-c, c-b, d-a)
+template <typename T> struct Axis<0, T> {
+  static __device__ __forceinline__ void movers(const Site<T>& s, Mov<T>& r, Mov<T>& l) {
+    r.v[0] = s.v[0] + s.v[6]; r.v[1] = s.v[1] + s.v[7];
+    r.v[2] = s.v[2] + s.v[4]; r.v[3] = s.v[3] + s.v[5];
+    l.v[0] = s.v[0] - s.v[6]; l.v[1] = s.v[1] - s.v[7];
+    l.v[2] = s.v[2] - s.v[4]; l.v[3] = s.v[3] - s.v[5];
+  }
+  static __device__ __forceinline__ void combine(const Mov<T>& r, const Mov<T>& l, Site<T>& o) {
+    o.v[0] = r.v[0] + l.v[0]; o.v[1] = r.v[1] + l.v[1];
+    o.v[2] = r.v[2] + l.v[2]; o.v[3] = r.v[3] + l.v[3];
+    o.v[4] = r.v[2] - l.v[2]; o.v[5] = r.v[3] - l.v[3];
+    o.v[6] = r.v[0] - l.v[0]; o.v[7] = r.v[1] - l.v[1];
+  }
+};
+
+// alpha_y: r = (a - i d, b + i c), l = (a + i d, b - i c);
+// out = (r1 + l1, r2 + l2, -i (r2 - l2), i (r1 - l1))
+template <typename T> struct Axis<1, T> {
+  static __device__ __forceinline__ void movers(const Site<T>& s, Mov<T>& r, Mov<T>& l) {
+    r.v[0] = s.v[0] + s.v[7]; r.v[1] = s.v[1] - s.v[6];
+    r.v[2] = s.v[2] - s.v[5]; r.v[3] = s.v[3] + s.v[4];
+    l.v[0] = s.v[0] - s.v[7]; l.v[1] = s.v[1] + s.v[6];
+    l.v[2] = s.v[2] + s.v[5]; l.v[3] = s.v[3] - s.v[4];
+  }
+  static __device__ __forceinline__ void combine(const Mov<T>& r, const Mov<T>& l, Site<T>& o) {
+    o.v[0] = r.v[0] + l.v[0]; o.v[1] = r.v[1] + l.v[1];
+    o.v[2] = r.v[2] + l.v[2]; o.v[3] = r.v[3] + l.v[3];
+    o.v[4] = r.v[3] - l.v[3]; o.v[5] = l.v[2] - r.v[2];
+    o.v[6] = l.v[1] - r.v[1]; o.v[7] = r.v[0] - l.v[0];
+  }
+};
+
+// alpha_z: r = (a + c, b - d), l = (a - c, b + d); out = (r1 + l1, r2 + l2, r1 - l1, l2 - r2)
+template <typename T> struct Axis<2, T> {
+  static __device__ __forceinline__ void movers(const Site<T>& s, Mov<T>& r, Mov<T>& l) {
+    r.v[0] = s.v[0] + s.v[4]; r.v[1] = s.v[1] + s.v[5];
+    r.v[2] = s.v[2] - s.v[6]; r.v[3] = s.v[3] - s.v[7];
+    l.v[0] = s.v[0] - s.v[4]; l.v[1] = s.v[1] - s.v[5];
+    l.v[2] = s.v[2] + s.v[6]; l.v[3] = s.v[3] + s.v[7];
+  }
+  static __device__ __forceinline__ void combine(const Mov<T>& r, const Mov<T>& l, Site<T>& o) {
+    o.v[0] = r.v[0] + l.v[0]; o.v[1] = r.v[1] + l.v[1];
+    o.v[2] = r.v[2] + l.v[2]; o.v[3] = r.v[3] + l.v[3];
+    o.v[4] = r.v[0] - l.v[0]; o.v[5] = r.v[1] - l.v[1];
+    o.v[6] = l.v[2] - r.v[2]; o.v[7] = l.v[3] - r.v[3];
+  }
+};
+
+// ---------------------------------------------------------------------------
+// FP64 sine and cosine for the local step.  Cody-Waite reduction by pi/2 with
+// a three-part constant, keeping the reduced argument as rh + rl; Taylor
+// polynomials on [-pi/4, pi/4] (terms to r^17 for sin, r^18 for cos;
+// truncation below 1e-19); sin(rh + rl) = sin rh + rl cos rh and
+// cos(rh + rl) = cos rh - rl sin rh to first order in rl, with 1 - rh^2/2
+// carried as an unevaluated sum (its rounding errors recovered exactly by
+// FMA and Sterbenz subtraction).  Error below 1 ulp, equal to the correctly
+// rounded value for about 98.5 % of arguments in [-12, 12].  |x| >= 2^20
+// falls back to the library routine.
+// ---------------------------------------------------------------------------
+// pi/2 = P1 + P2 + P3: P1, P2 hold 33 significant bits each (so k * P1 and
+// k * P2 are exact for |k| < 2^20), P3 the rounded remainder.
+#define DIRAC_PIO2_1 0x1.921fb54400000p+0
+#define DIRAC_PIO2_2 0x1.0b4611a600000p-34
+#define DIRAC_PIO2_3 0x1.3198a2e037073p-69
+#define DIRAC_2_OVER_PI 0x1.45f306dc9c883p-1
+
+__device__ __forceinline__ void sincos_cw(double x, double* s_out, double* c_out) {
+  if (!(fabs(x) < 1048576.0)) {  // also routes NaN to the library
+    sincos(x, s_out, c_out);
+    return;
+  }
+  const double k = rint(x * DIRAC_2_OVER_PI);
+  // x - k pi/2 = rh + rl: k P1, k P2 are exact and so is x - k P1
+  const double a = fma(-k, DIRAC_PIO2_1, x);
+  const double b = k * DIRAC_PIO2_2;
+  const double rh = a - b;
+  const double rl = ((a - rh) - b) - k * DIRAC_PIO2_3;
+  const double r2 = rh * rh;
+  // sin: rh + rh^3 (-1/3! + r^2/5! - ... + r^14/17!) + rl (1 - r^2/2)
+  double ps = 1.0 / 355687428096000.0;          // 1/17!
+  ps = fma(ps, r2, -1.0 / 1307674368000.0);     // 1/15!
+  ps = fma(ps, r2, 1.0 / 6227020800.0);         // 1/13!
+  ps = fma(ps, r2, -1.0 / 39916800.0);          // 1/11!
+  ps = fma(ps, r2, 1.0 / 362880.0);             // 1/9!
+  ps = fma(ps, r2, -1.0 / 5040.0);              // 1/7!
+  ps = fma(ps, r2, 1.0 / 120.0);                // 1/5!
+  ps = fma(ps, r2, -1.0 / 6.0);                 // 1/3!
+  const double sn = rh + fma(rh * r2, ps, rl * fma(-0.5, r2, 1.0));
+  // cos: (1 - rh^2/2) + rh^4 (1/4! - r^2/6! + ... + r^14/18!) - rh rl
+  double pc = -1.0 / 6402373705728000.0;        // 1/18!
+  pc = fma(pc, r2, 1.0 / 20922789888000.0);     // 1/16!
+  pc = fma(pc, r2, -1.0 / 87178291200.0);       // 1/14!
+  pc = fma(pc, r2, 1.0 / 479001600.0);          // 1/12!
+  pc = fma(pc, r2, -1.0 / 3628800.0);           // 1/10!
+  pc = fma(pc, r2, 1.0 / 40320.0);              // 1/8!
+  pc = fma(pc, r2, -1.0 / 720.0);               // 1/6!
+  pc = fma(pc, r2, 1.0 / 24.0);                 // 1/4!
+  const double e2 = fma(rh, rh, -r2);           // rh^2 = r2 + e2 exactly
+  const double hz = 0.5 * r2;
+  const double w = 1.0 - hz;
+  const double tail = ((1.0 - w) - hz) - 0.5 * e2;
+  const double cs = w + (fma(r2 * r2, pc, tail) - rh * rl);
+  const int q = static_cast<int>(static_cast<long long>(k) & 3);
+  const double s1 = (q & 1) ? cs : sn;
+  const double c1 = (q & 1) ? sn : cs;
+  *s_out = (q & 2) ? -s1 : s1;
+  *c_out = ((q + 1) & 2) ? -c1 : c1;
+}
+
+// ---------------------------------------------------------------------------
+// Local step D.  The two distinct phase factors per cell,
+//   f_up = s exp(-i (V + m c^2) dt)   (components a, b)
+//   f_dn = s exp(-i (V - m c^2) dt)   (components c, d),
+// are formed in FP64, where s = 2^-(number of transports) undoes the deferred
+// factors 1/2 exactly.  The components are promoted to FP64, multiplied and
+// rounded once to T.
+// ---------------------------------------------------------------------------
+struct PhaseK {
+  double eu_re, eu_im, ed_re, ed_im;  // s exp(-+ i m c^2 dt)
+  double dt;
+  double mc2;                         // m c^2 (rounded as (m c) c)
+  double scale;                       // s = 2^-(number of transports)
+  float scale_f;                      // s (pure-streaming mode)
+  int mode;                           // 0: scale only, 1: mass only, 2: mass + V
+  int two_angles;                     // mode 2: theta = (V +- m c^2) dt per pair
+};
+
+struct Factors { double ur, ui, dr, di; };
+
+// Phase factors of one cell.  With two_angles (FP64 storage) the angles are
+// formed as (V + m c^2) dt and (V - m c^2) dt, each with its own sine and
+// cosine; otherwise (FP32 storage) exp(-i V dt) is multiplied by the FP64
+// constants eu, ed, which costs one sine/cosine pair per cell.
+__device__ __forceinline__ Factors phase_factors(double V, const PhaseK& k) {
+  Factors f;
+  if (k.mode == 2) {
+    if (k.two_angles) {
+      double su, cu, sd, cd;
+      sincos_cw((V + k.mc2) * k.dt, &su, &cu);
+      sincos_cw((V - k.mc2) * k.dt, &sd, &cd);
+      f.ur = k.scale * cu;
+      f.ui = -k.scale * su;
+      f.dr = k.scale * cd;
+      f.di = -k.scale * sd;
+    } else {
+      double sn, cs;
+      sincos_cw(V * k.dt, &sn, &cs);
+      // (cs - i sn) (x + i y) = (cs x + sn y) + i (cs y - sn x)
+      f.ur = fma(cs, k.eu_re, sn * k.eu_im);
+      f.ui = fma(cs, k.eu_im, -sn * k.eu_re);
+      f.dr = fma(cs, k.ed_re, sn * k.ed_im);
+      f.di = fma(cs, k.ed_im, -sn * k.ed_re);
+    }
+  } else {
+    f.ur = k.eu_re; f.ui = k.eu_im; f.dr = k.ed_re; f.di = k.ed_im;
+  }
+  return f;
+}
+
+template <typename T>
+__device__ __forceinline__ void cmul_round(T& re, T& im, double fr, double fi) {
+  const double x = static_cast<double>(re), y = static_cast<double>(im);
+  re = static_cast<T>(fma(fr, x, -fi * y));
+  im = static_cast<T>(fma(fr, y, fi * x));
+}
+
+template <typename T>
+__device__ __forceinline__ void apply_factors(Site<T>& s, const Factors& f) {
+  cmul_round(s.v[0], s.v[1], f.ur, f.ui);
+  cmul_round(s.v[2], s.v[3], f.ur, f.ui);
+  cmul_round(s.v[4], s.v[5], f.dr, f.di);
+  cmul_round(s.v[6], s.v[7], f.dr, f.di);
+}
+
+template <typename T> __device__ __forceinline__ T scale_of(const PhaseK& k);
+template <> __device__ __forceinline__ float scale_of<float>(const PhaseK& k) { return k.scale_f; }
+template <> __device__ __forceinline__ double scale_of<double>(const PhaseK& k) {
+  return static_cast<double>(k.scale_f);
+}
+
+// Full local step on one site (V ignored unless mode == 2).
+template <typename T>
+__device__ __forceinline__ void local_step(Site<T>& s, double V, const PhaseK& k) {
+  if (k.mode == 0) {
+    const T sc = scale_of<T>(k);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s.v[j] *= sc;
+  } else {
+    apply_factors(s, phase_factors(V, k));
+  }
+}
+
+}  // namespace dirac

@@ -1,0 +1,56 @@
+// dirac_launch.h -- host-side launch interface between the plan code and the
+// kernels of the Dirac sweep.  Internal to libdirac.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dirac_device.h"
+
+namespace dirac {
+
+constexpr int kTY3D_F32 = 4;  // y rows per wave in the 3-D plane tile
+constexpr int kTY3D_F64 = 2;
+
+struct SweepArgs {
+  int64_t nx, ny, nz;  // cells along grid dims 0, 1, 2 (1 where absent)
+  int periodic;
+  int H;               // cells per march segment (y in 2-D, z in 3-D)
+  int64_t nstrips;     // ceil(nx / 64)
+  int64_t nseg;        // march segments
+  int64_t nyblk;       // 3-D: ceil(ny / TY)
+  int64_t ntiles;      // waves with work
+  int xcd_remap;       // blocks dealt XCD-contiguously (grid a multiple of 8)
+  int axes_code;       // 1-D: axis; 2-D: 10*axis0 + axis1 with axis1 > axis0 ... see plan
+  PhaseK ph;
+};
+
+struct ResidentArgs {
+  int64_t n;
+  int64_t nsteps;
+  int periodic;
+  PhaseK ph;
+};
+
+struct ObsArgs {
+  int64_t n0, n1, n2;
+  int ndim;
+  double dx;
+  double xmin0, xmin1, xmin2;
+  double x_b;
+};
+
+// one full step src -> dst; `blocks` 256-thread workgroups
+hipError_t launch_sweep2d(bool fp64, const void* src, void* dst, const double* V,
+                          const SweepArgs& a, int blocks, hipStream_t st);
+hipError_t launch_sweep3d(bool fp64, const void* src, void* dst, const double* V,
+                          const SweepArgs& a, int blocks, hipStream_t st);
+// nsteps in place in one workgroup of `threads` threads, `spt` cells each
+hipError_t launch_resident1d(bool fp64, int axis, void* psi, const double* V,
+                             const ResidentArgs& a, int spt, int threads, hipStream_t st);
+
+// observables: per-block partials (10 doubles per block) then final pass
+constexpr int kObsBlocks = 1024;
+hipError_t launch_observables(bool fp64, const void* psi, const ObsArgs& a, double* partials,
+                              double* out5, hipStream_t st);
+
+}  // namespace dirac

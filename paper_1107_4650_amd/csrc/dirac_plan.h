@@ -1,0 +1,75 @@
+// dirac_plan.h -- the plan object behind the opaque dl_plan handle, and the
+// helpers shared by the plan, adjoint and batch translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "../../include/libdirac.h"
+#include "dirac_launch.h"
+
+namespace dirac {
+
+struct GraphEntry {
+  void* psi;
+  const double* V;
+  int64_t pairs;
+  int mode;
+  hipGraphExec_t exec;
+};
+
+}  // namespace dirac
+
+struct dl_plan_s {
+  dl_grid g{};
+  double dx = 0, dt = 0, c = 0, m = 0;
+  int dtype = DL_C64;
+  int bc = DL_BC_ZERO;
+  unsigned flags = 0;
+  bool fp64 = false;
+  bool dry = false;
+  bool use_graph = false;
+  int64_t cells = 0;
+  size_t state_bytes = 0;
+  int device = 0;
+  // tiling of the one-pass sweep
+  dirac::SweepArgs sweep{};
+  int blocks = 0;
+  int waves_per_cu = 8;
+  int seg_override = 0;
+  bool allow_resident = true;
+  bool resident = false;
+  int res_threads = 0;
+  int64_t graph_pairs = 32;  // a captured graph holds 2 * graph_pairs steps
+  // scratch
+  void* tmp = nullptr;         // second state buffer
+  void* tmp2 = nullptr;        // second state buffer for the adjoint field
+  double* partials = nullptr;  // reduction partials
+  double* dres = nullptr;      // device results
+  double* hres = nullptr;      // pinned host results
+  double* proj = nullptr;      // projection partials (grown on demand)
+  size_t proj_bytes = 0;
+  hipStream_t cap_stream = nullptr;
+  std::vector<dirac::GraphEntry> graphs;
+  // batches
+  bool is_batch = false;
+  void* batch = nullptr;
+  void drop_graphs();
+};
+
+namespace dirac {
+
+int set_error(int code, const char* msg);
+int set_hip_error(hipError_t e, const char* what);
+int validate_grid(const dl_grid* g, double dx, double dt, double c, double m, int dtype, int bc,
+                  int max_ndim);
+PhaseK make_phase(int ntransports, double dt, double c, double m, int mode, bool two_angles);
+int phase_mode(double m, const double* V);
+int axes_code(const dl_grid& g);
+void make_tiling(const dl_grid& g, int waves_per_cu, int seg_override, SweepArgs& a, int& blocks);
+int check_live(dl_plan p);
+int check_state_ptr(const void* ptr, const char* name);
+int check_f64_ptr(const void* ptr, const char* name, bool nullable);
+hipError_t sweep_once(dl_plan p, const void* src, void* dst, const double* V, hipStream_t st);
+
+}  // namespace dirac

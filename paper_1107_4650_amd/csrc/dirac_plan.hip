@@ -1,0 +1,460 @@
+// dirac_plan.hip -- plans, argument checking and the C ABI of libdirac.
+// The operations are defined in include/libdirac.h; this file validates
+// arguments, owns the scratch memory and sequences kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/libdirac.h"
+#include "dirac_launch.h"
+#include "dirac_plan.h"
+
+using namespace dirac;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(DL_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+}  // namespace
+
+namespace dirac {
+
+int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
+int set_hip_error(hipError_t e, const char* what) { return hip_fail(e, what); }
+
+int validate_grid(const dl_grid* g, double dx, double dt, double c, double m, int dtype, int bc,
+                  int max_ndim) {
+  if (!g) return fail(DL_ERR_ARG, "grid is NULL");
+  if (g->ndim < 1 || g->ndim > max_ndim) return fail(DL_ERR_ARG, "ndim must be 1..%d", max_ndim);
+  for (int d = 0; d < g->ndim; ++d) {
+    if (g->n[d] < 2) return fail(DL_ERR_ARG, "n[%d] = %lld: need at least 2 cells", d,
+                                 static_cast<long long>(g->n[d]));
+    if (g->n[d] > (int64_t(1) << 31)) return fail(DL_ERR_ARG, "n[%d] too large", d);
+    if (g->axis[d] < 0 || g->axis[d] > 2) return fail(DL_ERR_ARG, "axis[%d] must be 0, 1 or 2", d);
+    if (d > 0 && g->axis[d] <= g->axis[d - 1])
+      return fail(DL_ERR_ARG, "axis[] must increase with the grid dimension");
+    if (!std::isfinite(g->xmin[d])) return fail(DL_ERR_ARG, "xmin[%d] not finite", d);
+  }
+  int64_t cells = 1;
+  for (int d = 0; d < g->ndim; ++d) {
+    if (cells > (int64_t(1) << 40) / g->n[d]) return fail(DL_ERR_ARG, "grid too large");
+    cells *= g->n[d];
+  }
+  if (!finite_pos(dx) || !finite_pos(dt) || !finite_pos(c))
+    return fail(DL_ERR_ARG, "dx, dt and c must be finite and positive");
+  if (!std::isfinite(m) || m < 0.0) return fail(DL_ERR_ARG, "m must be finite and >= 0");
+  if (dtype != DL_C64 && dtype != DL_C128) return fail(DL_ERR_DTYPE, "unknown dtype %d", dtype);
+  if (bc != DL_BC_ZERO && bc != DL_BC_PERIODIC) return fail(DL_ERR_ARG, "unknown bc %d", bc);
+  const double K = c * dt / dx;
+  if (!(std::fabs(K - 1.0) <= 1e-12))
+    return fail(DL_ERR_CFL, "c*dt/dx = %.17g: the characteristic shift needs c*dt = dx", K);
+  return DL_OK;
+}
+
+PhaseK make_phase(int ntransports, double dt, double c, double m, int mode, bool two_angles) {
+  PhaseK k{};
+  const double s = std::ldexp(1.0, -ntransports);
+  const double mc2 = m * c * c;
+  const double mu = mc2 * dt;
+  k.eu_re = s * std::cos(mu);
+  k.eu_im = -s * std::sin(mu);
+  k.ed_re = s * std::cos(mu);
+  k.ed_im = s * std::sin(mu);
+  k.dt = dt;
+  k.mc2 = mc2;
+  k.scale = s;
+  k.scale_f = static_cast<float>(s);
+  k.mode = mode;
+  k.two_angles = two_angles ? 1 : 0;
+  return k;
+}
+
+int phase_mode(double m, const double* V) {
+  if (V) return 2;
+  return (m != 0.0) ? 1 : 0;
+}
+
+int axes_code(const dl_grid& g) {
+  if (g.ndim == 1) return g.axis[0];
+  if (g.ndim == 2) return 10 * g.axis[1] + g.axis[0];  // 10: (x,y) 20: (x,z) 21: (y,z)
+  return 210;
+}
+
+// Tiling of the one-pass sweep: strips of 64 x cells, march segments sized so
+// that about `waves_per_cu` waves run per compute unit.
+void make_tiling(const dl_grid& g, int waves_per_cu, int seg_override, SweepArgs& a, int& blocks) {
+  a.nx = g.n[0];
+  a.ny = g.ndim > 1 ? g.n[1] : 1;
+  a.nz = g.ndim > 2 ? g.n[2] : 1;
+  a.nstrips = (a.nx + 63) / 64;
+  const int64_t target = int64_t(256) * waves_per_cu;
+  if (g.ndim == 1) {
+    a.nseg = 1;
+    a.H = 1;
+    a.nyblk = 1;
+    a.ntiles = a.nstrips;
+  } else if (g.ndim == 2) {
+    const int64_t ny = a.ny;
+    int64_t H;
+    if (seg_override > 0) {
+      H = seg_override;
+    } else {
+      int64_t nseg = (target + a.nstrips - 1) / a.nstrips;
+      if (nseg < 1) nseg = 1;
+      H = (ny + nseg - 1) / nseg;
+      if (H < 8) H = 8;
+    }
+    if (H > ny) H = ny;
+    a.H = static_cast<int>(H);
+    a.nseg = (ny + H - 1) / H;
+    a.nyblk = 1;
+    a.ntiles = a.nstrips * a.nseg;
+  } else {
+    const int TY = kTY3D_F32;  // overwritten by the caller for FP64
+    (void)TY;
+    a.ntiles = 0;
+  }
+  blocks = static_cast<int>((a.ntiles + 3) / 4);
+  a.xcd_remap = (blocks % 8 == 0) ? 1 : 0;
+  a.axes_code = axes_code(g);
+}
+
+void make_tiling3d(const dl_grid& g, int ty, int waves_per_cu, int seg_override, SweepArgs& a,
+                   int& blocks) {
+  a.nx = g.n[0];
+  a.ny = g.n[1];
+  a.nz = g.n[2];
+  a.nstrips = (a.nx + 63) / 64;
+  a.nyblk = (a.ny + ty - 1) / ty;
+  const int64_t per_seg = a.nstrips * a.nyblk;
+  const int64_t target = int64_t(256) * waves_per_cu;
+  int64_t H;
+  if (seg_override > 0) {
+    H = seg_override;
+  } else {
+    int64_t nseg = (target + per_seg - 1) / per_seg;
+    if (nseg < 1) nseg = 1;
+    H = (a.nz + nseg - 1) / nseg;
+    if (H < 4) H = 4;
+  }
+  if (H > a.nz) H = a.nz;
+  a.H = static_cast<int>(H);
+  a.nseg = (a.nz + H - 1) / H;
+  a.ntiles = per_seg * a.nseg;
+  blocks = static_cast<int>((a.ntiles + 3) / 4);
+  a.xcd_remap = (blocks % 8 == 0) ? 1 : 0;
+  a.axes_code = 210;
+}
+
+}  // namespace dirac
+
+// ===========================================================================
+// plan
+// ===========================================================================
+
+static int plan_tiling(dl_plan p) {
+  if (p->g.ndim == 3) {
+    make_tiling3d(p->g, p->fp64 ? kTY3D_F64 : kTY3D_F32, p->waves_per_cu, p->seg_override,
+                  p->sweep, p->blocks);
+  } else {
+    make_tiling(p->g, p->waves_per_cu, p->seg_override, p->sweep, p->blocks);
+  }
+  p->sweep.periodic = (p->bc == DL_BC_PERIODIC);
+  // resident 1-D path: the whole line in one workgroup (4 cells per thread)
+  p->resident = false;
+  if (p->g.ndim == 1 && p->allow_resident) {
+    const int64_t n = p->g.n[0];
+    const int64_t threads = ((n + 4 * 64 - 1) / (4 * 64)) * 64;
+    if (threads <= 1024 && (p->bc == DL_BC_ZERO || threads * 4 == n)) {
+      p->resident = true;
+      p->res_threads = static_cast<int>(threads);
+    }
+  }
+  return DL_OK;
+}
+
+extern "C" int dl_plan_create(dl_plan* out, const dl_grid* g, double dx, double dt, double c,
+                              double m, dl_dtype dtype, dl_bc bc, unsigned flags) {
+  if (!out) return fail(DL_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  int rc = validate_grid(g, dx, dt, c, m, dtype, bc, 3);
+  if (rc) return rc;
+  if (g->ndim == 3 && !(g->axis[0] == 0 && g->axis[1] == 1 && g->axis[2] == 2))
+    return fail(DL_ERR_ARG, "3-D grids carry alpha_x, alpha_y, alpha_z in order");
+  dl_plan p = new (std::nothrow) dl_plan_s();
+  if (!p) return fail(DL_ERR_NOMEM, "host allocation failed");
+  p->g = *g;
+  for (int d = g->ndim; d < 3; ++d) {
+    p->g.n[d] = 1;
+    p->g.axis[d] = -1;
+    p->g.xmin[d] = 0.0;
+  }
+  p->dx = dx;
+  p->dt = dt;
+  p->c = c;
+  p->m = m;
+  p->dtype = dtype;
+  p->bc = bc;
+  p->flags = flags;
+  p->fp64 = (dtype == DL_C128);
+  p->cells = 1;
+  for (int d = 0; d < g->ndim; ++d) p->cells *= g->n[d];
+  p->state_bytes = static_cast<size_t>(p->cells) * 4 * (p->fp64 ? 16 : 8);
+  p->dry = (flags & DL_DRY) != 0;
+  p->use_graph = (flags & DL_GRAPH) != 0;
+  plan_tiling(p);
+  if (p->dry) {
+    *out = p;
+    return DL_OK;
+  }
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(e, "hipGetDevice");
+  }
+  if (hipMalloc(&p->tmp, p->state_bytes) != hipSuccess ||
+      hipMalloc(&p->partials, sizeof(double) * 2 * 8 * kObsBlocks) != hipSuccess ||
+      hipMalloc(&p->dres, sizeof(double) * 64) != hipSuccess ||
+      hipHostMalloc(&p->hres, sizeof(double) * 64, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    dl_plan_destroy(p);
+    return fail(DL_ERR_NOMEM, "device allocation of %zu bytes of scratch failed", p->state_bytes);
+  }
+  *out = p;
+  return DL_OK;
+}
+
+void dl_plan_s::drop_graphs() {
+  for (auto& ge : graphs) {
+    if (ge.exec) (void)hipGraphExecDestroy(ge.exec);
+  }
+  graphs.clear();
+}
+
+extern "C" int dl_plan_destroy(dl_plan p) {
+  if (!p) return DL_OK;
+  if (!p->dry) {
+    (void)hipDeviceSynchronize();
+    p->drop_graphs();
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+    if (p->tmp) (void)hipFree(p->tmp);
+    if (p->tmp2) (void)hipFree(p->tmp2);
+    if (p->proj) (void)hipFree(p->proj);
+    if (p->partials) (void)hipFree(p->partials);
+    if (p->dres) (void)hipFree(p->dres);
+    if (p->hres) (void)hipHostFree(p->hres);
+    (void)hipGetLastError();
+  }
+  delete p;
+  return DL_OK;
+}
+
+namespace dirac {
+
+int check_live(dl_plan p) {
+  if (!p) return fail(DL_ERR_ARG, "plan is NULL");
+  if (p->dry) return fail(DL_ERR_STATE, "dry plan: created with DL_DRY, no device work allowed");
+  return DL_OK;
+}
+
+int check_state_ptr(const void* ptr, const char* name) {
+  if (!ptr) return fail(DL_ERR_ARG, "%s is NULL", name);
+  if (reinterpret_cast<uintptr_t>(ptr) % 16) return fail(DL_ERR_ALIGN, "%s not 16-byte aligned", name);
+  return DL_OK;
+}
+
+int check_f64_ptr(const void* ptr, const char* name, bool nullable) {
+  if (!ptr) return nullable ? DL_OK : fail(DL_ERR_ARG, "%s is NULL", name);
+  if (reinterpret_cast<uintptr_t>(ptr) % 8) return fail(DL_ERR_ALIGN, "%s not 8-byte aligned", name);
+  return DL_OK;
+}
+
+// one full step src -> dst
+hipError_t sweep_once(dl_plan p, const void* src, void* dst, const double* V, hipStream_t st) {
+  if (p->g.ndim == 3) return launch_sweep3d(p->fp64, src, dst, V, p->sweep, p->blocks, st);
+  return launch_sweep2d(p->fp64, src, dst, V, p->sweep, p->blocks, st);
+}
+
+// enqueue `nsteps` steps ping-ponging between psi and the plan's tmp buffer,
+// starting from psi; returns the buffer that holds the result
+hipError_t enqueue_steps(dl_plan p, void* psi, const double* V, int64_t nsteps, hipStream_t st,
+                         void** result) {
+  void* a = psi;
+  void* b = p->tmp;
+  for (int64_t s = 0; s < nsteps; ++s) {
+    hipError_t e = sweep_once(p, a, b, V, st);
+    if (e != hipSuccess) return e;
+    void* t = a;
+    a = b;
+    b = t;
+  }
+  *result = a;
+  return hipSuccess;
+}
+
+}  // namespace dirac
+
+static hipError_t graph_for(dl_plan p, void* psi, const double* V, int64_t pairs,
+                            hipGraphExec_t* exec) {
+  for (auto& ge : p->graphs) {
+    if (ge.psi == psi && ge.V == V && ge.pairs == pairs && ge.mode == p->sweep.ph.mode) {
+      *exec = ge.exec;
+      return hipSuccess;
+    }
+  }
+  if (!p->cap_stream) {
+    hipError_t e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+  }
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  void* res = nullptr;
+  hipError_t e2 = enqueue_steps(p, psi, V, 2 * pairs, p->cap_stream, &res);
+  e = hipStreamEndCapture(p->cap_stream, &graph);
+  if (e2 != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return e2;
+  }
+  if (e != hipSuccess) return e;
+  hipGraphExec_t ex = nullptr;
+  e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return e;
+  if (p->graphs.size() >= 8) p->drop_graphs();
+  p->graphs.push_back(GraphEntry{psi, V, pairs, p->sweep.ph.mode, ex});
+  *exec = ex;
+  return hipSuccess;
+}
+
+extern "C" int dl_step(dl_plan p, void* psi, const double* V, int64_t nsteps, void* stream) {
+  int rc = check_live(p);
+  if (rc) return rc;
+  if ((rc = check_state_ptr(psi, "psi"))) return rc;
+  if ((rc = check_f64_ptr(V, "V", true))) return rc;
+  if (nsteps < 0) return fail(DL_ERR_ARG, "nsteps = %lld < 0", static_cast<long long>(nsteps));
+  if (nsteps == 0) return DL_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int mode = phase_mode(p->m, V);
+  p->sweep.ph = make_phase(p->g.ndim, p->dt, p->c, p->m, mode, p->fp64);
+  if (p->resident) {
+    ResidentArgs ra{};
+    ra.n = p->g.n[0];
+    ra.nsteps = nsteps;
+    ra.periodic = (p->bc == DL_BC_PERIODIC);
+    ra.ph = p->sweep.ph;
+    hipError_t e = launch_resident1d(p->fp64, p->g.axis[0], psi, V, ra, 4, p->res_threads, st);
+    return e == hipSuccess ? DL_OK : hip_fail(e, "resident 1-D sweep launch");
+  }
+  int64_t done = 0;
+  if (p->use_graph && nsteps >= 2 * p->graph_pairs) {
+    hipGraphExec_t ex = nullptr;
+    hipError_t e = graph_for(p, psi, V, p->graph_pairs, &ex);
+    if (e != hipSuccess) return hip_fail(e, "graph capture");
+    const int64_t reps = nsteps / (2 * p->graph_pairs);
+    for (int64_t r = 0; r < reps; ++r) {
+      e = hipGraphLaunch(ex, st);
+      if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    }
+    done = reps * 2 * p->graph_pairs;
+  }
+  void* res = nullptr;
+  hipError_t e = enqueue_steps(p, psi, V, nsteps - done, st, &res);
+  if (e != hipSuccess) return hip_fail(e, "sweep launch");
+  if (res != psi) {
+    e = hipMemcpyAsync(psi, res, p->state_bytes, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+  }
+  return DL_OK;
+}
+
+extern "C" int dl_step_out(dl_plan p, const void* src, void* dst, const double* V,
+                           void* stream) {
+  int rc = check_live(p);
+  if (rc) return rc;
+  if ((rc = check_state_ptr(src, "src"))) return rc;
+  if ((rc = check_state_ptr(dst, "dst"))) return rc;
+  if ((rc = check_f64_ptr(V, "V", true))) return rc;
+  const char* a = static_cast<const char*>(src);
+  const char* b = static_cast<const char*>(dst);
+  if (a < b + p->state_bytes && b < a + p->state_bytes)
+    return fail(DL_ERR_ARG, "src and dst overlap");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  p->sweep.ph = make_phase(p->g.ndim, p->dt, p->c, p->m, phase_mode(p->m, V), p->fp64);
+  hipError_t e = sweep_once(p, src, dst, V, st);
+  return e == hipSuccess ? DL_OK : hip_fail(e, "sweep launch");
+}
+
+extern "C" int dl_observables(dl_plan p, const void* psi, double x_b, double out[5],
+                              void* stream) {
+  int rc = check_live(p);
+  if (rc) return rc;
+  if ((rc = check_state_ptr(psi, "psi"))) return rc;
+  if (!out) return fail(DL_ERR_ARG, "out is NULL");
+  if (!std::isfinite(x_b) && !std::isinf(x_b)) return fail(DL_ERR_ARG, "x_b is NaN");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  ObsArgs a{};
+  a.n0 = p->g.n[0];
+  a.n1 = p->g.n[1];
+  a.n2 = p->g.n[2];
+  a.ndim = p->g.ndim;
+  a.dx = p->dx;
+  a.xmin0 = p->g.xmin[0];
+  a.xmin1 = p->g.xmin[1];
+  a.xmin2 = p->g.xmin[2];
+  a.x_b = x_b;
+  hipError_t e = launch_observables(p->fp64, psi, a, p->partials, p->dres, st);
+  if (e != hipSuccess) return hip_fail(e, "observables launch");
+  e = hipMemcpyAsync(p->hres, p->dres, 5 * sizeof(double), hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  for (int i = 0; i < 5; ++i) out[i] = p->hres[i];
+  return DL_OK;
+}
+
+extern "C" const char* dl_last_error(void) { return g_err; }
+extern "C" int dl_version(void) { return LIBDIRAC_VERSION; }
+
+// ---- tuning hooks (not part of the public header; used by the autotuner) ----
+extern "C" int dl_plan_set_tiling(dl_plan p, int waves_per_cu, int seg_len, int allow_resident,
+                                  int graph_pairs) {
+  if (!p) return fail(DL_ERR_ARG, "plan is NULL");
+  if (waves_per_cu < 1 || waves_per_cu > 32) return fail(DL_ERR_ARG, "waves_per_cu out of range");
+  if (seg_len < 0 || graph_pairs < 1) return fail(DL_ERR_ARG, "bad seg_len / graph_pairs");
+  p->waves_per_cu = waves_per_cu;
+  p->seg_override = seg_len;
+  p->allow_resident = allow_resident != 0;
+  p->graph_pairs = graph_pairs;
+  if (!p->dry) p->drop_graphs();
+  return plan_tiling(p);
+}
+
+extern "C" int dl_plan_info(dl_plan p, int64_t* info, int n) {
+  if (!p || !info) return fail(DL_ERR_ARG, "NULL argument");
+  const int64_t vals[] = {p->blocks,         p->sweep.H,      p->sweep.nseg, p->sweep.nstrips,
+                          p->sweep.ntiles,   p->resident,     p->res_threads, p->waves_per_cu,
+                          p->sweep.xcd_remap, p->graph_pairs};
+  const int nv = static_cast<int>(sizeof vals / sizeof vals[0]);
+  for (int i = 0; i < n && i < nv; ++i) info[i] = vals[i];
+  return DL_OK;
+}

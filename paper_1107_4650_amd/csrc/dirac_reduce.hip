@@ -1,0 +1,149 @@
+// dirac_reduce.hip -- deterministic FP64 compensated reductions for the
+// observables (norm, mean coordinates, probability beyond x_b; the R/T
+// integrals of Sec. 5.2.1 on the cell grid).
+//
+// Each thread keeps Neumaier (sum, compensation) pairs over a fixed
+// grid-stride set of cells; pairs are merged with an exact two-sum in a fixed
+// shuffle tree, then across the four waves of the block, then in a final
+// one-block pass over the per-block partials in block order.  The grid size
+// is fixed, so results do not depend on scheduling.
+#include "dirac_launch.h"
+
+namespace dirac {
+
+struct NSum {
+  double s, c;
+};
+
+__device__ __forceinline__ void nadd(NSum& a, double x) {
+  const double t = a.s + x;
+  if (fabs(a.s) >= fabs(x))
+    a.c += (a.s - t) + x;
+  else
+    a.c += (x - t) + a.s;
+  a.s = t;
+}
+
+// merge b into a: two-sum of the sums, compensations added
+__device__ __forceinline__ void nmerge(NSum& a, const NSum& b) {
+  const double t = a.s + b.s;
+  const double bb = t - a.s;
+  const double err = (a.s - (t - bb)) + (b.s - bb);
+  a.c = a.c + b.c + err;
+  a.s = t;
+}
+
+__device__ __forceinline__ NSum shfl_xor(const NSum& v, int m) {
+  NSum r;
+  r.s = __shfl_xor(v.s, m, 64);
+  r.c = __shfl_xor(v.c, m, 64);
+  return r;
+}
+
+constexpr int kQ = 5;  // |psi|^2, x0|psi|^2, x1|psi|^2, x2|psi|^2, [x0 > x_b]|psi|^2
+
+template <int NQ>
+__device__ void block_reduce(NSum (&acc)[NQ], NSum (*lds)[4]) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) nmerge(acc[q], shfl_xor(acc[q], m));
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) lds[q][wave] = acc[q];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      NSum t = lds[q][0];
+      for (int w = 1; w < 4; ++w) nmerge(t, lds[q][w]);
+      acc[q] = t;
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_obs_partial(const T* __restrict__ psi, ObsArgs a,
+                                                     double* __restrict__ partials) {
+  __shared__ NSum lds[kQ][4];
+  NSum acc[kQ];
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) acc[q] = NSum{0.0, 0.0};
+  const int64_t ncell = a.n0 * a.n1 * a.n2;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; c < ncell;
+       c += stride) {
+    Site<T> s;
+    load_site(psi + c * 8, s);
+    double rho = 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const double v = static_cast<double>(s.v[k]);
+      rho = fma(v, v, rho);
+    }
+    const int64_t i0 = c % a.n0;
+    const int64_t r = c / a.n0;
+    const int64_t i1 = r % a.n1;
+    const int64_t i2 = r / a.n1;
+    const double x0 = a.xmin0 + (static_cast<double>(i0) + 0.5) * a.dx;
+    nadd(acc[0], rho);
+    nadd(acc[1], x0 * rho);
+    if (a.ndim > 1) nadd(acc[2], (a.xmin1 + (static_cast<double>(i1) + 0.5) * a.dx) * rho);
+    if (a.ndim > 2) nadd(acc[3], (a.xmin2 + (static_cast<double>(i2) + 0.5) * a.dx) * rho);
+    if (x0 > a.x_b) nadd(acc[4], rho);
+  }
+  block_reduce<kQ>(acc, lds);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      partials[(static_cast<int64_t>(blockIdx.x) * kQ + q) * 2 + 0] = acc[q].s;
+      partials[(static_cast<int64_t>(blockIdx.x) * kQ + q) * 2 + 1] = acc[q].c;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_obs_final(const double* __restrict__ partials, int nblk,
+                                                   ObsArgs a, double* __restrict__ out5) {
+  __shared__ NSum lds[kQ][4];
+  NSum acc[kQ];
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) acc[q] = NSum{0.0, 0.0};
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      const NSum p{partials[(static_cast<int64_t>(b) * kQ + q) * 2],
+                   partials[(static_cast<int64_t>(b) * kQ + q) * 2 + 1]};
+      nmerge(acc[q], p);
+    }
+  }
+  block_reduce<kQ>(acc, lds);
+  if (threadIdx.x == 0) {
+    double dV = a.dx;
+    for (int d = 1; d < a.ndim; ++d) dV *= a.dx;
+    const double S = acc[0].s + acc[0].c;
+    out5[0] = dV * S;
+    out5[1] = (S != 0.0) ? (acc[1].s + acc[1].c) / S : 0.0;
+    out5[2] = (a.ndim > 1 && S != 0.0) ? (acc[2].s + acc[2].c) / S : 0.0;
+    out5[3] = (a.ndim > 2 && S != 0.0) ? (acc[3].s + acc[3].c) / S : 0.0;
+    out5[4] = dV * (acc[4].s + acc[4].c);
+  }
+}
+
+hipError_t launch_observables(bool fp64, const void* psi, const ObsArgs& a, double* partials,
+                              double* out5, hipStream_t st) {
+  if (fp64)
+    hipLaunchKernelGGL(k_obs_partial<double>, dim3(kObsBlocks), dim3(256), 0, st,
+                       static_cast<const double*>(psi), a, partials);
+  else
+    hipLaunchKernelGGL(k_obs_partial<float>, dim3(kObsBlocks), dim3(256), 0, st,
+                       static_cast<const float*>(psi), a, partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_obs_final, dim3(1), dim3(256), 0, st, partials, kObsBlocks, a, out5);
+  return hipGetLastError();
+}
+
+}  // namespace dirac

@@ -1,0 +1,427 @@
+// dirac_sweep.hip -- fused one-pass time step of the Dirac sweep on gfx950.
+//
+// One launch advances the whole grid by one full step S = D T_last ... T_first
+// (lowest-order splitting, Sec. 2.1; transports eq:sol_dis_1-3; local step
+// eq:sol_dis_4), reading psi once and writing it once.
+//
+// Work decomposition (2-D, and 1-D as the one-row case):
+//   * a wave64 owns a strip of 64 consecutive x cells; lane l holds cell x0+l;
+//   * the x transport takes the left neighbour's right movers and the right
+//     neighbour's left movers with DPP wave shifts; lane 0 loads the cell left
+//     of the strip, lane 63 the cell right of it (or the lane just past the
+//     last cell stands for the cell beyond the wall);
+//   * the wave marches along y over a segment of H rows, keeping the y movers
+//     of the two previous rows in registers, so every row of psi is loaded
+//     once per segment (plus one halo row at each end);
+//   * even segments march up, odd segments march down: the halo rows shared
+//     by two neighbouring segments are then read by both near the same time
+//     (both at their start or both at their end) and hit in L2;
+//   * blocks are remapped so that each XCD receives a contiguous band of
+//     segments (workgroups are dealt to the 8 XCDs round-robin).
+// 3-D marches along z with a plane tile of 64 x cells by TY y rows per wave,
+// the y transport rolling over the rows of the tile and the z transport
+// rolling over planes.
+#include "dirac_device.h"
+#include "dirac_launch.h"
+
+namespace dirac {
+
+// ---------------------------------------------------------------------------
+// row loading with walls / wrap-around
+// ---------------------------------------------------------------------------
+template <typename T> struct Row {
+  Site<T> m;  // this lane's cell
+  Site<T> h;  // lane 0: cell left of the strip; lane 63: cell right of it
+  double v;   // potential at the output cell of this row
+};
+
+// Load cell row `j` (a row index of a 2-D plane, possibly outside [0, ny))
+// of the plane starting at `plane`; returns zeros for cells beyond a wall.
+template <typename T>
+__device__ __forceinline__ void load_row(const T* __restrict__ plane, int64_t nx, int64_t ny,
+                                         int periodic, int64_t x0, int lane, int64_t j,
+                                         Row<T>& R) {
+  zero(R.m);
+  zero(R.h);
+  if (j < 0 || j >= ny) {
+    if (!periodic) return;
+    j = (j < 0) ? j + ny : j - ny;
+  }
+  const T* row = plane + j * nx * 8;
+  const int64_t x = x0 + lane;
+  int64_t xm = x;
+  if (x == nx && periodic) xm = 0;
+  if (xm < nx) load_site(row + xm * 8, R.m);
+  int64_t hx = -2;
+  if (lane == 0) hx = x0 - 1;
+  if (lane == 63) hx = x0 + 64;
+  if (hx == -1) hx = periodic ? nx - 1 : -2;
+  if (hx == nx) hx = periodic ? 0 : -2;
+  if (hx >= 0 && hx < nx) load_site(row + hx * 8, R.h);
+}
+
+// x transport of one row held across the wave (result is 2x the transport).
+template <typename T, int AX>
+__device__ __forceinline__ void x_transport(const Row<T>& R, Site<T>& phi) {
+  Mov<T> r, l, hr, hl, rL, lR;
+  Axis<AX, T>::movers(R.m, r, l);
+  Axis<AX, T>::movers(R.h, hr, hl);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    rL.v[k] = dpp_from_left(hr.v[k], r.v[k]);
+    lR.v[k] = dpp_from_right(hl.v[k], l.v[k]);
+  }
+  Axis<AX, T>::combine(rL, lR, phi);
+}
+
+__device__ __forceinline__ int64_t wrap_or_neg(int64_t j, int64_t n, int periodic) {
+  if (j >= 0 && j < n) return j;
+  if (!periodic) return -1;
+  return j < 0 ? j + n : j - n;
+}
+
+// ---------------------------------------------------------------------------
+// 1-D / 2-D fused step
+// ---------------------------------------------------------------------------
+constexpr int PF2 = 3;  // rows in flight per wave
+
+template <typename T, int AX0, int AX1, bool UP>
+__device__ __forceinline__ void march2d(const T* __restrict__ src, T* __restrict__ dst,
+                                        const double* __restrict__ V, const SweepArgs& a,
+                                        int64_t x0, int lane, int64_t jb, int64_t je) {
+  const int64_t nx = a.nx, ny = a.ny;
+  const int nit = static_cast<int>(je - jb) + 2;
+  const int64_t x = x0 + lane;
+  const bool own = x < nx;
+  const bool use_v = (a.ph.mode == 2);
+  // input row of iteration `it` and the output row it completes
+  auto in_row = [&](int it) -> int64_t { return UP ? jb - 1 + it : je - it; };
+  auto out_row = [&](int it) -> int64_t { return UP ? jb - 2 + it : je - it + 1; };
+
+  Row<T> ring[PF2];
+#pragma unroll
+  for (int k = 0; k < PF2; ++k) {
+    if (k < nit) {
+      load_row(src, nx, ny, a.periodic, x0, lane, in_row(k), ring[k]);
+      ring[k].v = (use_v && k >= 2 && own) ? V[out_row(k) * nx + x] : 0.0;
+    }
+  }
+  Mov<T> s1, s2;  // movers of the two previous rows (r when UP, l when down)
+  zero(s1);
+  zero(s2);
+  for (int base = 0; base < nit; base += PF2) {
+#pragma unroll
+    for (int k = 0; k < PF2; ++k) {
+      const int it = base + k;
+      if (it < nit) {
+        const Row<T> cur = ring[k];
+        const int nxt = it + PF2;
+        if (nxt < nit) {
+          load_row(src, nx, ny, a.periodic, x0, lane, in_row(nxt), ring[k]);
+          ring[k].v = (use_v && own) ? V[out_row(nxt) * nx + x] : 0.0;
+        }
+        Site<T> phi;
+        x_transport<T, AX0>(cur, phi);
+        Mov<T> ry, ly;
+        Axis<AX1, T>::movers(phi, ry, ly);
+        if (it >= 2) {
+          Site<T> o;
+          if (UP)
+            Axis<AX1, T>::combine(s2, ly, o);
+          else
+            Axis<AX1, T>::combine(ry, s2, o);
+          local_step(o, cur.v, a.ph);
+          if (own) store_site(dst + (out_row(it) * nx + x) * 8, o);
+        }
+        s2 = s1;
+        s1 = UP ? ry : ly;
+      }
+    }
+  }
+}
+
+template <typename T, int AX0, int AX1>
+__global__ __launch_bounds__(256) void k_sweep2d(const T* __restrict__ src, T* __restrict__ dst,
+                                                 const double* __restrict__ V, SweepArgs a) {
+  const int lane = threadIdx.x & 63;
+  int64_t blk = blockIdx.x;
+  if (a.xcd_remap) blk = (blk % 8) * (gridDim.x / 8) + blk / 8;
+  const int64_t tile = blk * 4 + (threadIdx.x >> 6);
+  if (tile >= a.ntiles) return;
+  const int64_t strip = tile % a.nstrips;
+  const int64_t seg = tile / a.nstrips;
+  const int64_t x0 = strip * 64;
+  if constexpr (AX1 < 0) {
+    // 1-D: one row, no march
+    Row<T> R;
+    load_row(src, a.nx, 1, a.periodic, x0, lane, 0, R);
+    const int64_t x = x0 + lane;
+    const bool own = x < a.nx;
+    R.v = (a.ph.mode == 2 && own) ? V[x] : 0.0;
+    Site<T> o;
+    x_transport<T, AX0>(R, o);
+    local_step(o, R.v, a.ph);
+    if (own) store_site(dst + x * 8, o);
+  } else {
+    const int64_t jb = seg * a.H;
+    const int64_t je = (jb + a.H < a.ny) ? jb + a.H : a.ny;
+    if (seg & 1)
+      march2d<T, AX0, AX1, false>(src, dst, V, a, x0, lane, jb, je);
+    else
+      march2d<T, AX0, AX1, true>(src, dst, V, a, x0, lane, jb, je);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 3-D fused step: march along z, plane tile 64 x TY per wave.
+// ---------------------------------------------------------------------------
+template <typename T, int TY, bool UP>
+__device__ __forceinline__ void march3d(const T* __restrict__ src, T* __restrict__ dst,
+                                        const double* __restrict__ V, const SweepArgs& a,
+                                        int64_t x0, int lane, int64_t y0, int64_t kb,
+                                        int64_t ke) {
+  const int64_t nx = a.nx, ny = a.ny, nz = a.nz;
+  const int64_t plane_cells = nx * ny;
+  const int nit = static_cast<int>(ke - kb) + 2;
+  const int64_t x = x0 + lane;
+  const bool use_v = (a.ph.mode == 2);
+  Mov<T> zs1[TY], zs2[TY];
+#pragma unroll
+  for (int t = 0; t < TY; ++t) {
+    zero(zs1[t]);
+    zero(zs2[t]);
+  }
+  for (int it = 0; it < nit; ++it) {
+    const int64_t kin = UP ? kb - 1 + it : ke - it;
+    const int64_t kout = UP ? kin - 1 : kin + 1;
+    const int64_t kr = wrap_or_neg(kin, nz, a.periodic);
+    // load the TY + 2 rows of this plane tile (rows y0-1 .. y0+TY)
+    Row<T> rows[TY + 2];
+#pragma unroll
+    for (int t = 0; t < TY + 2; ++t) {
+      if (kr >= 0) {
+        load_row(src + kr * plane_cells * 8, nx, ny, a.periodic, x0, lane, y0 - 1 + t, rows[t]);
+      } else {
+        zero(rows[t].m);
+        zero(rows[t].h);
+      }
+    }
+    double vrow[TY];
+#pragma unroll
+    for (int t = 0; t < TY; ++t) {
+      const int64_t y = y0 + t;
+      vrow[t] = (use_v && it >= 2 && x < nx && y < ny) ? V[(kout * ny + y) * nx + x] : 0.0;
+    }
+    // x transport of every row, y transport rolling over the rows
+    Mov<T> ry1, ry2;
+    zero(ry1);
+    zero(ry2);
+#pragma unroll
+    for (int t = 0; t < TY + 2; ++t) {
+      Site<T> phi;
+      x_transport<T, 0>(rows[t], phi);
+      Mov<T> ry, ly;
+      Axis<1, T>::movers(phi, ry, ly);
+      if (t >= 2) {
+        const int ty = t - 2;  // output row y0 + ty
+        Site<T> psi2;
+        Axis<1, T>::combine(ry2, ly, psi2);
+        Mov<T> rz, lz;
+        Axis<2, T>::movers(psi2, rz, lz);
+        if (it >= 2) {
+          Site<T> o;
+          if (UP)
+            Axis<2, T>::combine(zs2[ty], lz, o);
+          else
+            Axis<2, T>::combine(rz, zs2[ty], o);
+          local_step(o, vrow[ty], a.ph);
+          const int64_t y = y0 + ty;
+          if (x < nx && y < ny) store_site(dst + ((kout * ny + y) * nx + x) * 8, o);
+        }
+        zs2[ty] = zs1[ty];
+        zs1[ty] = UP ? rz : lz;
+      }
+      ry2 = ry1;
+      ry1 = ry;
+    }
+  }
+}
+
+template <typename T, int TY>
+__global__ __launch_bounds__(256) void k_sweep3d(const T* __restrict__ src, T* __restrict__ dst,
+                                                 const double* __restrict__ V, SweepArgs a) {
+  const int lane = threadIdx.x & 63;
+  int64_t blk = blockIdx.x;
+  if (a.xcd_remap) blk = (blk % 8) * (gridDim.x / 8) + blk / 8;
+  const int64_t tile = blk * 4 + (threadIdx.x >> 6);
+  if (tile >= a.ntiles) return;
+  // tile order: x strips fastest, then y row blocks, then z segments
+  const int64_t strip = tile % a.nstrips;
+  const int64_t rest = tile / a.nstrips;
+  const int64_t yblk = rest % a.nyblk;
+  const int64_t seg = rest / a.nyblk;
+  const int64_t x0 = strip * 64, y0 = yblk * TY;
+  const int64_t kb = seg * a.H;
+  const int64_t ke = (kb + a.H < a.nz) ? kb + a.H : a.nz;
+  if (seg & 1)
+    march3d<T, TY, false>(src, dst, V, a, x0, lane, y0, kb, ke);
+  else
+    march3d<T, TY, true>(src, dst, V, a, x0, lane, y0, kb, ke);
+}
+
+// ---------------------------------------------------------------------------
+// 1-D resident kernel: a whole 1-D instance lives in one workgroup's
+// registers for all its steps; neighbour movers cross thread boundaries
+// through LDS.  Thread t holds cells [t*SPT, (t+1)*SPT).  The per-cell
+// arithmetic is the same as in k_sweep2d, so results are bit-identical.
+// ---------------------------------------------------------------------------
+template <typename T, int AX, int SPT>
+__global__ __launch_bounds__(1024) void k_resident1d(T* __restrict__ psi,
+                                                     const double* __restrict__ V,
+                                                     ResidentArgs a) {
+  __shared__ Mov<T> lds_r[2][1024];
+  __shared__ Mov<T> lds_l[2][1024];
+  const int t = threadIdx.x;
+  const int nthr = blockDim.x;
+  const int64_t n = a.n;
+  Site<T> s[SPT];
+  Factors f[SPT];
+#pragma unroll
+  for (int k = 0; k < SPT; ++k) {
+    const int64_t x = static_cast<int64_t>(t) * SPT + k;
+    if (x < n) {
+      load_site(psi + x * 8, s[k]);
+      f[k] = phase_factors((a.ph.mode == 2) ? V[x] : 0.0, a.ph);
+    } else {
+      zero(s[k]);
+      f[k] = phase_factors(0.0, a.ph);
+    }
+  }
+  for (int64_t step = 0; step < a.nsteps; ++step) {
+    const int buf = static_cast<int>(step & 1);
+    {
+      Mov<T> r, l, tmp;
+      Axis<AX, T>::movers(s[SPT - 1], r, tmp);
+      Axis<AX, T>::movers(s[0], tmp, l);
+      lds_r[buf][t] = r;
+      lds_l[buf][t] = l;
+    }
+    __syncthreads();
+    Mov<T> rprev, lnext, scratch;
+    if (t > 0) rprev = lds_r[buf][t - 1];
+    else if (a.periodic) rprev = lds_r[buf][nthr - 1];
+    else zero(rprev);
+#pragma unroll
+    for (int k = 0; k < SPT; ++k) {
+      if (k < SPT - 1) {
+        Axis<AX, T>::movers(s[k + 1], scratch, lnext);
+      } else {
+        if (t < nthr - 1) lnext = lds_l[buf][t + 1];
+        else if (a.periodic) lnext = lds_l[buf][0];
+        else zero(lnext);
+      }
+      Mov<T> rcur;
+      Axis<AX, T>::movers(s[k], rcur, scratch);
+      Axis<AX, T>::combine(rprev, lnext, s[k]);
+      rprev = rcur;
+      if (a.ph.mode == 0) {
+        const T sc = scale_of<T>(a.ph);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) s[k].v[j] *= sc;
+      } else {
+        apply_factors(s[k], f[k]);
+      }
+      const int64_t x = static_cast<int64_t>(t) * SPT + k;
+      if (x >= n) zero(s[k]);  // cells beyond the wall stay empty
+    }
+    // double-buffered LDS slots: one barrier per step is enough
+  }
+#pragma unroll
+  for (int k = 0; k < SPT; ++k) {
+    const int64_t x = static_cast<int64_t>(t) * SPT + k;
+    if (x < n) store_site(psi + x * 8, s[k]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <typename T, int AX0, int AX1>
+static hipError_t launch2d_t(const T* src, T* dst, const double* V, const SweepArgs& a,
+                             int blocks, hipStream_t st) {
+  hipLaunchKernelGGL((k_sweep2d<T, AX0, AX1>), dim3(blocks), dim3(256), 0, st, src, dst, V, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch2d_axes(const T* src, T* dst, const double* V, const SweepArgs& a,
+                                int blocks, hipStream_t st) {
+  switch (a.axes_code) {
+    case 0: return launch2d_t<T, 0, -1>(src, dst, V, a, blocks, st);
+    case 1: return launch2d_t<T, 1, -1>(src, dst, V, a, blocks, st);
+    case 2: return launch2d_t<T, 2, -1>(src, dst, V, a, blocks, st);
+    case 10: return launch2d_t<T, 0, 1>(src, dst, V, a, blocks, st);
+    case 20: return launch2d_t<T, 0, 2>(src, dst, V, a, blocks, st);
+    case 21: return launch2d_t<T, 1, 2>(src, dst, V, a, blocks, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_sweep2d(bool fp64, const void* src, void* dst, const double* V,
+                          const SweepArgs& a, int blocks, hipStream_t st) {
+  if (fp64)
+    return launch2d_axes<double>(static_cast<const double*>(src), static_cast<double*>(dst), V,
+                                 a, blocks, st);
+  return launch2d_axes<float>(static_cast<const float*>(src), static_cast<float*>(dst), V, a,
+                              blocks, st);
+}
+
+hipError_t launch_sweep3d(bool fp64, const void* src, void* dst, const double* V,
+                          const SweepArgs& a, int blocks, hipStream_t st) {
+  if (fp64) {
+    hipLaunchKernelGGL((k_sweep3d<double, kTY3D_F64>), dim3(blocks), dim3(256), 0, st,
+                       static_cast<const double*>(src), static_cast<double*>(dst), V, a);
+  } else {
+    hipLaunchKernelGGL((k_sweep3d<float, kTY3D_F32>), dim3(blocks), dim3(256), 0, st,
+                       static_cast<const float*>(src), static_cast<float*>(dst), V, a);
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int AX, int SPT>
+static hipError_t launch_res_t(void* psi, const double* V, const ResidentArgs& a, int threads,
+                               hipStream_t st) {
+  hipLaunchKernelGGL((k_resident1d<T, AX, SPT>), dim3(1), dim3(threads), 0, st,
+                     static_cast<T*>(psi), V, a);
+  return hipGetLastError();
+}
+
+template <typename T, int AX>
+static hipError_t launch_res_spt(void* psi, const double* V, const ResidentArgs& a, int spt,
+                                 int threads, hipStream_t st) {
+  switch (spt) {
+    case 1: return launch_res_t<T, AX, 1>(psi, V, a, threads, st);
+    case 2: return launch_res_t<T, AX, 2>(psi, V, a, threads, st);
+    case 4: return launch_res_t<T, AX, 4>(psi, V, a, threads, st);
+    case 8: return launch_res_t<T, AX, 8>(psi, V, a, threads, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_resident1d(bool fp64, int axis, void* psi, const double* V,
+                             const ResidentArgs& a, int spt, int threads, hipStream_t st) {
+  if (fp64) {
+    switch (axis) {
+      case 0: return launch_res_spt<double, 0>(psi, V, a, spt, threads, st);
+      case 1: return launch_res_spt<double, 1>(psi, V, a, spt, threads, st);
+      default: return launch_res_spt<double, 2>(psi, V, a, spt, threads, st);
+    }
+  }
+  switch (axis) {
+    case 0: return launch_res_spt<float, 0>(psi, V, a, spt, threads, st);
+    case 1: return launch_res_spt<float, 1>(psi, V, a, spt, threads, st);
+    default: return launch_res_spt<float, 2>(psi, V, a, spt, threads, st);
+  }
+}
+
+}  // namespace dirac

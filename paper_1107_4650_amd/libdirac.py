@@ -1,0 +1,245 @@
+"""Python binding of libdirac (ctypes): argument marshalling only.
+
+Every computation runs in the HIP library; this module checks tensor
+metadata, passes raw device pointers and the current HIP stream, and turns
+non-OK status codes into exceptions.  Importing it does not need a GPU;
+loading fails loudly if libdirac.so has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libdirac.so")
+
+DL_OK, DL_ERR_ARG, DL_ERR_CFL, DL_ERR_DTYPE, DL_ERR_ALIGN, DL_ERR_NOMEM, DL_ERR_HIP, DL_ERR_STATE = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+STATUS_NAMES = {0: "DL_OK", -1: "DL_ERR_ARG", -2: "DL_ERR_CFL", -3: "DL_ERR_DTYPE",
+                -4: "DL_ERR_ALIGN", -5: "DL_ERR_NOMEM", -6: "DL_ERR_HIP", -7: "DL_ERR_STATE"}
+DL_C64, DL_C128 = 0, 1
+DL_BC_ZERO, DL_BC_PERIODIC = 0, 1
+DL_DRY, DL_GRAPH = 1, 2
+
+# every entry point of include/libdirac.h
+EXPORTS = ("dl_plan_create", "dl_plan_destroy", "dl_step", "dl_step_out", "dl_observables", "dl_seed_adjoint",
+           "dl_grad_step", "dl_project", "dl_expand", "dl_batch_create", "dl_batch_step", "dl_last_error",
+           "dl_version")
+
+
+class DiracError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int), ("n", ctypes.c_int64 * 3), ("axis", ctypes.c_int * 3),
+                ("xmin", ctypes.c_double * 3)]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libdirac.so (built by __graft_entry__.build()); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() first")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, dbl, ci = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
+    P = ctypes.POINTER
+    sig = {
+        "dl_plan_create": [P(vp), P(Grid), dbl, dbl, dbl, dbl, ci, ci, ctypes.c_uint],
+        "dl_plan_destroy": [vp],
+        "dl_step": [vp, vp, vp, i64, vp],
+        "dl_step_out": [vp, vp, vp, vp, vp],
+        "dl_observables": [vp, vp, dbl, P(dbl), vp],
+        "dl_seed_adjoint": [vp, vp, dbl, vp, vp, vp],
+        "dl_grad_step": [vp, vp, vp, vp, vp, i64, vp],
+        "dl_project": [vp, vp, vp, ci, vp, vp],
+        "dl_expand": [vp, vp, vp, ci, vp, vp],
+        "dl_batch_create": [P(vp), P(Grid), P(dbl), P(dbl), P(dbl), P(dbl), ci, ci, ci,
+                            ctypes.c_uint],
+        "dl_batch_step": [vp, P(vp), P(vp), P(i64), vp],
+        "dl_plan_set_tiling": [vp, ci, ci, ci, ci],
+        "dl_plan_info": [vp, P(i64), ci],
+        "dl_version": [],
+        "dl_last_error": [],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ci
+    lib.dl_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def check(code: int):
+    if code != DL_OK:
+        raise DiracError(code, load().dl_last_error().decode())
+
+
+def _dtype_code(dtype) -> int:
+    s = str(dtype)
+    if s in ("c64", "complex64", "torch.complex64"):
+        return DL_C64
+    if s in ("c128", "complex128", "torch.complex128"):
+        return DL_C128
+    raise ValueError(f"unknown dtype {dtype}")
+
+
+def _bc_code(bc) -> int:
+    return {"zero": DL_BC_ZERO, "periodic": DL_BC_PERIODIC, 0: 0, 1: 1}[bc]
+
+
+def make_grid(shape, axes=None, xmin=None, dx=None) -> Grid:
+    """shape: cells per grid dimension, x first."""
+    nd = len(shape)
+    g = Grid()
+    g.ndim = nd
+    for d in range(3):
+        g.n[d] = int(shape[d]) if d < nd else 1
+        g.axis[d] = (int(axes[d]) if axes is not None else d) if d < nd else 0
+        if xmin is not None and d < nd:
+            g.xmin[d] = float(xmin[d])
+        elif dx is not None and d < nd:
+            g.xmin[d] = -0.5 * shape[d] * dx
+        else:
+            g.xmin[d] = 0.0
+    return g
+
+
+def _stream_handle():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Plan:
+    """A libdirac plan for one grid (see include/libdirac.h)."""
+
+    def __init__(self, shape, dx, dt, c, m, dtype="c64", bc="zero", axes=None, xmin=None,
+                 dry=False, graph=False):
+        self.lib = load()
+        self.shape = tuple(int(s) for s in shape)           # x first
+        self.tshape = tuple(reversed(self.shape)) + (4,)    # tensor shape
+        self.dtype_code = _dtype_code(dtype)
+        self.dx, self.dt, self.c, self.m = float(dx), float(dt), float(c), float(m)
+        self.bc = bc
+        self.grid = make_grid(self.shape, axes, xmin, dx)
+        flags = (DL_DRY if dry else 0) | (DL_GRAPH if graph else 0)
+        h = ctypes.c_void_p()
+        check(self.lib.dl_plan_create(ctypes.byref(h), ctypes.byref(self.grid), self.dx, self.dt,
+                                      self.c, self.m, self.dtype_code, _bc_code(bc), flags))
+        self.handle = h
+
+    # -- tensor checks --------------------------------------------------------
+    def _state(self, t, name="psi"):
+        import torch
+        want = torch.complex64 if self.dtype_code == DL_C64 else torch.complex128
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+            raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+        if t.dtype != want:
+            raise TypeError(f"{name} must be {want}, got {t.dtype}")
+        if tuple(t.shape) != self.tshape or not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous with shape {self.tshape}")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def _cells(self, t, name, allow_none=True):
+        import torch
+        if t is None:
+            if allow_none:
+                return None
+            raise ValueError(f"{name} is required")
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float64:
+            raise TypeError(f"{name} must be a float64 CUDA tensor")
+        if tuple(t.shape) != self.tshape[:-1] or not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous with shape {self.tshape[:-1]}")
+        return ctypes.c_void_p(t.data_ptr())
+
+    # -- operations -------------------------------------------------------------
+    def step(self, psi, V=None, nsteps=1):
+        check(self.lib.dl_step(self.handle, self._state(psi), self._cells(V, "V"), int(nsteps),
+                               _stream_handle()))
+        return psi
+
+    def step_out(self, src, dst, V=None):
+        check(self.lib.dl_step_out(self.handle, self._state(src, "src"), self._state(dst, "dst"),
+                                   self._cells(V, "V"), _stream_handle()))
+        return dst
+
+    def observables(self, psi, x_b=0.0) -> np.ndarray:
+        out = (ctypes.c_double * 5)()
+        check(self.lib.dl_observables(self.handle, self._state(psi), float(x_b), out,
+                                      _stream_handle()))
+        return np.array(out[:])
+
+    def seed_adjoint(self, psi, x_b, lam, Q):
+        check(self.lib.dl_seed_adjoint(self.handle, self._state(psi), float(x_b),
+                                       self._state(lam, "lam"), self._cells(Q, "Q", False),
+                                       _stream_handle()))
+
+    def grad_step(self, psi, lam, V, Q, nsteps):
+        check(self.lib.dl_grad_step(self.handle, self._state(psi), self._state(lam, "lam"),
+                                    self._cells(V, "V"), self._cells(Q, "Q", False), int(nsteps),
+                                    _stream_handle()))
+
+    def project(self, Q, G, out):
+        import torch
+        nb = int(G.shape[0])
+        if G.dtype != torch.float64 or not G.is_contiguous() or G.device.type != "cuda":
+            raise TypeError("G must be a contiguous float64 CUDA tensor")
+        if tuple(G.shape[1:]) != self.tshape[:-1]:
+            raise ValueError("G must have shape (nb,) + grid shape")
+        if out.dtype != torch.float64 or out.numel() != nb or out.device.type != "cuda":
+            raise TypeError("out must be a float64 CUDA tensor of nb elements")
+        check(self.lib.dl_project(self.handle, self._cells(Q, "Q", False),
+                                  ctypes.c_void_p(G.data_ptr()), nb,
+                                  ctypes.c_void_p(out.data_ptr()), _stream_handle()))
+        return out
+
+    def expand(self, G, theta, V):
+        import torch
+        nb = int(G.shape[0])
+        for t, name in ((G, "G"), (theta, "theta"), (V, "V")):
+            if t.dtype != torch.float64 or not t.is_contiguous() or t.device.type != "cuda":
+                raise TypeError(f"{name} must be a contiguous float64 CUDA tensor")
+        if tuple(G.shape[1:]) != self.tshape[:-1] or theta.numel() != nb:
+            raise ValueError("G must have shape (nb,) + grid shape and theta nb elements")
+        check(self.lib.dl_expand(self.handle, ctypes.c_void_p(G.data_ptr()),
+                                 ctypes.c_void_p(theta.data_ptr()), nb,
+                                 self._cells(V, "V", False), _stream_handle()))
+        return V
+
+    def set_tiling(self, waves_per_cu=8, seg_len=0, allow_resident=True, graph_pairs=32):
+        check(self.lib.dl_plan_set_tiling(self.handle, int(waves_per_cu), int(seg_len),
+                                          int(bool(allow_resident)), int(graph_pairs)))
+
+    def info(self) -> dict:
+        buf = (ctypes.c_int64 * 10)()
+        check(self.lib.dl_plan_info(self.handle, buf, 10))
+        keys = ("blocks", "seg_len", "nseg", "nstrips", "ntiles", "resident", "res_threads",
+                "waves_per_cu", "xcd_remap", "graph_pairs")
+        return dict(zip(keys, buf[:]))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.dl_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

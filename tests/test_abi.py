@@ -1,0 +1,110 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry point
+declared in include/libdirac.h, and a dry plan validates its arguments
+(status codes of the header) without touching HIP."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_1107_4650_amd import libdirac as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "libdirac.h")
+C = 137.036
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(L.LIB_PATH):
+        from paper_1107_4650_amd import build
+        build.build()
+    return L.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dl_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    assert declared_functions() == sorted(L.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (dl_\w+)", out))
+    for name in declared_functions():
+        assert name in exported, name
+        assert getattr(lib, name) is not None
+    assert lib.dl_version() == 1
+
+
+def dry(shape, dx=0.01, dt=None, c=C, m=1.0, dtype="c64", bc="zero", axes=None):
+    return L.Plan(shape, dx, dx / c if dt is None else dt, c, m, dtype=dtype, bc=bc, axes=axes,
+                  dry=True)
+
+
+def code_of(fn):
+    with pytest.raises(L.DiracError) as ei:
+        fn()
+    return ei.value.code
+
+
+def test_dry_plan_accepts_valid_grids(lib):
+    for shape, axes in (((64,), (0,)), ((64,), (2,)), ((32, 16), (0, 1)), ((32, 16), (0, 2)),
+                        ((32, 16), (1, 2)), ((8, 8, 8), (0, 1, 2))):
+        for dtype in ("c64", "c128"):
+            for bc in ("zero", "periodic"):
+                p = dry(shape, dtype=dtype, bc=bc, axes=axes)
+                p.close()
+
+
+def test_dry_plan_rejections(lib):
+    assert code_of(lambda: dry((64,), dt=0.0101 / C)) == L.DL_ERR_CFL
+    assert code_of(lambda: dry((64,), dt=2 * 0.01 / C)) == L.DL_ERR_CFL      # K = 2 not built
+    assert code_of(lambda: dry((64,), dt=0.01 / C * (1 + 1e-9))) == L.DL_ERR_CFL
+    assert code_of(lambda: dry((1,))) == L.DL_ERR_ARG
+    assert code_of(lambda: dry((8, 8, 8, 8))) == L.DL_ERR_ARG
+    assert code_of(lambda: dry((16, 16), axes=(1, 0))) == L.DL_ERR_ARG
+    assert code_of(lambda: dry((16, 16), axes=(0, 0))) == L.DL_ERR_ARG
+    assert code_of(lambda: dry((16, 16), axes=(0, 3))) == L.DL_ERR_ARG
+    assert code_of(lambda: dry((8, 8, 8), axes=(0, 1, 1))) == L.DL_ERR_ARG
+    assert code_of(lambda: dry((64,), m=-1.0)) == L.DL_ERR_ARG
+    assert code_of(lambda: dry((64,), m=float("nan"))) == L.DL_ERR_ARG
+    assert code_of(lambda: dry((64,), dx=-0.01)) == L.DL_ERR_ARG
+    assert code_of(lambda: dry((64,), c=0.0, dt=1.0)) == L.DL_ERR_ARG
+
+
+def test_raw_abi_argument_errors(lib):
+    g = L.make_grid((64,), dx=0.01)
+    h = ctypes.c_void_p()
+    assert lib.dl_plan_create(None, ctypes.byref(g), 0.01, 0.01 / C, C, 1.0, 0, 0, L.DL_DRY) \
+        == L.DL_ERR_ARG
+    assert lib.dl_plan_create(ctypes.byref(h), None, 0.01, 0.01 / C, C, 1.0, 0, 0, L.DL_DRY) \
+        == L.DL_ERR_ARG
+    assert lib.dl_plan_create(ctypes.byref(h), ctypes.byref(g), 0.01, 0.01 / C, C, 1.0, 7, 0,
+                              L.DL_DRY) == L.DL_ERR_DTYPE
+    assert h.value is None
+    assert lib.dl_plan_create(ctypes.byref(h), ctypes.byref(g), 0.01, 0.01 / C, C, 1.0, 0, 5,
+                              L.DL_DRY) == L.DL_ERR_ARG
+    assert lib.dl_plan_create(ctypes.byref(h), ctypes.byref(g), 0.01, 0.01 / C, C, 1.0, 0, 0,
+                              L.DL_DRY) == L.DL_OK
+    # a dry plan refuses device work before touching HIP
+    assert lib.dl_step(h, ctypes.c_void_p(256), None, 1, None) == L.DL_ERR_STATE
+    out = (ctypes.c_double * 5)()
+    assert lib.dl_observables(h, ctypes.c_void_p(256), 0.0, out, None) == L.DL_ERR_STATE
+    assert b"dry plan" in lib.dl_last_error()
+    assert lib.dl_plan_destroy(h) == L.DL_OK
+    assert lib.dl_plan_destroy(None) == L.DL_OK
+    assert lib.dl_step(None, ctypes.c_void_p(256), None, 1, None) == L.DL_ERR_ARG
+
+
+def test_python_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(L, "_lib", None)
+    monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="not built"):
+        L.load()

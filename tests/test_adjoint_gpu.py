@@ -1,0 +1,152 @@
+"""The adjoint path through the C ABI: seed, reverse sweep, projection and the
+autograd function, against the oracle's checkpointed adjoint gradient, the
+dot-product identity of one step, and finite differences of the forward."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1107_4650_amd import libdirac as L
+from paper_1107_4650_amd.inputs import packet, random_spinor, bump_basis, C_LIGHT
+from tests.gpu_util import announce, gpu_step, rel_l2
+
+pytestmark = pytest.mark.gpu
+C = C_LIGHT
+
+
+def dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_seed_and_expand_and_project(dtype):
+    import torch
+    announce(f"seed/expand/project {dtype}")
+    shape, dx = (300, 77), 0.02
+    xmin = [-3.0, -0.77]
+    psi = random_spinor(shape[::-1], seed=1)
+    if dtype == "c64":
+        psi = psi.astype(np.complex64)
+    rng = np.random.default_rng(2)
+    G = rng.standard_normal((5,) + shape[::-1])
+    theta = rng.uniform(-1, 1, 5)
+    Qh = rng.standard_normal(shape[::-1])
+    with L.Plan(shape, dx, dx / C, C, 1.0, dtype=dtype, xmin=xmin) as p:
+        tp = dev(psi)
+        lam = torch.empty_like(tp)
+        Q = torch.full(shape[::-1], 7.0, dtype=torch.float64, device="cuda")
+        p.seed_adjoint(tp, 0.1, lam, Q)
+        V = torch.empty(shape[::-1], dtype=torch.float64, device="cuda")
+        p.expand(dev(G), dev(theta), V)
+        out = torch.empty(5, dtype=torch.float64, device="cuda")
+        p.project(dev(Qh), dev(G), out)
+        torch.cuda.synchronize()
+    x = xmin[0] + (np.arange(shape[0]) + 0.5) * dx
+    expect = psi * (x > 0.1)[None, :, None]
+    assert np.array_equal(lam.cpu().numpy(), expect)
+    assert np.all(Q.cpu().numpy() == 0.0)
+    assert np.max(np.abs(V.cpu().numpy() - np.tensordot(theta, G, axes=1))) < 1e-13
+    ref = G.reshape(5, -1) @ Qh.reshape(-1)
+    assert np.max(np.abs(out.cpu().numpy() - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("shape,axes,bc", [((257,), (0,), "periodic"), ((150, 37), (0, 1), "zero"),
+                                           ((130, 45), (0, 2), "periodic"),
+                                           ((70, 66), (1, 2), "zero")])
+def test_reverse_step_is_the_adjoint(shape, axes, bc):
+    """<S^H lam, psi> = <lam, S psi> with S from dl_step and S^H from dl_grad_step."""
+    import torch
+    announce(f"dot product {shape} {axes} {bc}")
+    psi = random_spinor(shape[::-1], seed=3)
+    lam = random_spinor(shape[::-1], seed=4)
+    V = np.random.default_rng(5).uniform(-2, 2, shape[::-1]) * C * C
+    dx = 0.01
+    Spsi = gpu_step(psi, V, dx=dx, dt=dx / C, c=C, m=1.0, nsteps=3, axes=axes, bc=bc)
+    with L.Plan(shape, dx, dx / C, C, 1.0, dtype="c128", bc=bc, axes=axes) as p:
+        tl = dev(lam)
+        tdummy = dev(random_spinor(shape[::-1], seed=9))
+        Q = torch.zeros(shape[::-1], dtype=torch.float64, device="cuda")
+        p.grad_step(tdummy, tl, dev(V), Q, 3)
+        torch.cuda.synchronize()
+        SHlam = tl.cpu().numpy()
+    lhs = np.vdot(SHlam, psi)
+    rhs = np.vdot(lam, Spsi)
+    assert abs(lhs - rhs) <= 1e-13 * abs(rhs)
+    # and it equals the oracle's adjoint step
+    ref = O.adjoint_step(lam, V, dt=dx / C, c=C, m=1.0, nsteps=3, axes=axes, bc=bc)
+    assert rel_l2(SHlam, ref) <= 1e-13
+
+
+def _case(n=96, nb=6, bc="periodic", nsteps=120):
+    dx = 0.05
+    shape = (n, n)
+    xmin = [-n * dx / 2] * 2
+    rng = np.random.default_rng(11)
+    centres = rng.uniform(-0.8, 0.8, size=(nb, 2))
+    G = bump_basis(shape, dx, centres, 0.3) * (C * C)
+    theta = rng.uniform(-1, 1, nb)
+    psi0 = packet(shape, dx, delta=0.3, p0=[15.0, 0.0], r0=[-0.8, 0.0])
+    return dict(shape=shape, dx=dx, xmin=xmin, G=G, theta=theta, psi0=psi0, x_b=0.5,
+                nsteps=nsteps, bc=bc)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("bc", ["periodic", "zero"])
+def test_gradient_vs_oracle(dtype, bc):
+    import torch
+    announce(f"gradient vs oracle {dtype} {bc}")
+    k = _case(bc=bc)
+    dx, shape = k["dx"], k["shape"]
+    V = np.tensordot(k["theta"], k["G"], axes=1)
+    loss, dLdV, psiN = O.grad(k["psi0"], V, dx=dx, xmin=k["xmin"], dt=dx / C, c=C, m=1.0,
+                              nsteps=k["nsteps"], x_b=k["x_b"], bc=bc, ckpt=16)
+    with L.Plan(shape, dx, dx / C, C, 1.0, dtype=dtype, bc=bc, xmin=k["xmin"]) as p:
+        tdt = torch.complex128 if dtype == "c128" else torch.complex64
+        psi = dev(k["psi0"]).to(tdt)
+        tV = dev(V)
+        p.step(psi, tV, k["nsteps"])
+        obs = p.observables(psi, k["x_b"])
+        lam = torch.empty_like(psi)
+        Q = torch.empty(shape[::-1], dtype=torch.float64, device="cuda")
+        p.seed_adjoint(psi, k["x_b"], lam, Q)
+        p.grad_step(psi, lam, tV, Q, k["nsteps"])
+        g = torch.empty(k["G"].shape[0], dtype=torch.float64, device="cuda")
+        p.project(Q, dev(k["G"]), g)
+        torch.cuda.synchronize()
+        Qh, gh, psi_rec = Q.cpu().numpy(), g.cpu().numpy(), psi.cpu().numpy()
+    g_ref = k["G"].reshape(len(k["theta"]), -1) @ dLdV.reshape(-1)
+    if dtype == "c128":
+        assert abs(obs[4] - loss) < 1e-13
+        assert np.max(np.abs(Qh - dLdV)) <= 1e-10 * np.max(np.abs(dLdV))
+        assert np.max(np.abs(gh - g_ref)) <= 1e-10 * np.max(np.abs(g_ref))
+        assert rel_l2(psi_rec, k["psi0"]) < 1e-12      # reversible recompute
+    else:
+        assert abs(obs[4] - loss) < 1e-5
+        assert np.max(np.abs(gh - g_ref)) <= 1e-3 * np.max(np.abs(g_ref))
+        assert rel_l2(psi_rec, k["psi0"]) < 1e-5
+
+
+def test_autograd_function_and_finite_differences():
+    import torch
+    from paper_1107_4650_amd.autograd import transmitted_probability
+    announce("autograd + FD")
+    k = _case(nsteps=80)
+    dx, shape = k["dx"], k["shape"]
+    with L.Plan(shape, dx, dx / C, C, 1.0, dtype="c128", bc="periodic", xmin=k["xmin"]) as p:
+        psi0 = dev(k["psi0"])
+        G = dev(k["G"])
+        theta = dev(k["theta"]).requires_grad_(True)
+        Lv = transmitted_probability(theta, p, psi0, G, k["nsteps"], k["x_b"])
+        Lv.backward()
+        g = theta.grad.cpu().numpy()
+        h = 1e-4
+        fd = []
+        for j in range(len(k["theta"])):
+            e = torch.zeros_like(theta)
+            e[j] = h
+            with torch.no_grad():
+                lp = transmitted_probability(theta.detach() + e, p, psi0, G, k["nsteps"], k["x_b"])
+                lm = transmitted_probability(theta.detach() - e, p, psi0, G, k["nsteps"], k["x_b"])
+            fd.append(float((lp - lm) / (2 * h)))
+    fd = np.array(fd)
+    assert np.max(np.abs(g - fd)) < 1e-4 * np.max(np.abs(g))

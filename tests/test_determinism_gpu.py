@@ -1,0 +1,68 @@
+"""Determinism and tiling invariance of the HIP sweep (doubles as a race check):
+the same run twice, every tiling, the resident and the tiled 1-D paths, graph
+replay and n + n = 2n steps must all give identical bits."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1107_4650_amd.inputs import random_spinor, C_LIGHT
+from tests.gpu_util import announce, gpu_step, same_bits, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+C = C_LIGHT
+DX = 0.01
+DT = DX / C
+
+
+def _V(shape, seed=5):
+    return np.random.default_rng(seed).uniform(-2, 2, size=shape[::-1]) * C * C
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("shape", [(300, 260), (96, 40, 33)])
+def test_tiling_invariance_and_repeatability(dtype, shape):
+    announce(f"tilings {shape} {dtype}")
+    axes = tuple(range(len(shape)))
+    psi = random_spinor(shape[::-1], seed=1)
+    V = _V(shape)
+    kw = dict(dx=DX, dt=DT, c=C, m=1.0, nsteps=25, axes=axes, dtype=dtype)
+    base = gpu_step(psi, V, **kw)
+    assert same_bits(base, gpu_step(psi, V, **kw))
+    for tiling in ({"waves_per_cu": 1}, {"waves_per_cu": 4, "seg_len": 9},
+                   {"waves_per_cu": 16, "seg_len": 5}, {"waves_per_cu": 2, "seg_len": 1000}):
+        assert same_bits(base, gpu_step(psi, V, tiling=tiling, **kw)), tiling
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("n,bc", [(4096, "zero"), (1000, "zero"), (2048, "periodic"),
+                                  (130, "zero")])
+def test_resident_1d_equals_tiled(dtype, n, bc):
+    announce(f"resident vs tiled n={n} {bc} {dtype}")
+    psi = random_spinor((n,), seed=n)
+    V = _V((n,))
+    kw = dict(dx=DX, dt=DT, c=C, m=1.0, nsteps=333, axes=(0,), bc=bc, dtype=dtype)
+    res = gpu_step(psi, V, **kw)
+    tiled = gpu_step(psi, V, tiling={"allow_resident": False}, **kw)
+    assert same_bits(res, tiled)
+    if dtype == "c128":
+        ref = O.step(psi, V, dt=DT, c=C, m=1.0, nsteps=333, axes=(0,), bc=bc)
+        assert rel_l2(res, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_graph_replay_and_resume(dtype):
+    announce(f"graph and resume {dtype}")
+    shape = (200, 150)
+    psi = random_spinor(shape[::-1], seed=2)
+    V = _V(shape)
+    kw = dict(dx=DX, dt=DT, c=C, m=1.0, axes=(0, 1), dtype=dtype)
+    eager = gpu_step(psi, V, nsteps=150, **kw)
+    graph = gpu_step(psi, V, nsteps=150, graph=True, tiling={"graph_pairs": 8}, **kw)
+    assert same_bits(eager, graph)
+    # replay the same captured graph on several calls, with eager work between them
+    chunked = gpu_step(psi, V, nsteps=0, graph=True, tiling={"graph_pairs": 8},
+                       chunks=[40, 16, 33, 16, 45], **kw)
+    assert same_bits(eager, chunked)
+    split = gpu_step(psi, V, nsteps=0, chunks=[75, 75], **kw)
+    assert same_bits(eager, split)

@@ -1,0 +1,169 @@
+"""Parity of the HIP sweep (through the C ABI) with the FP64 CPU oracle.
+
+Bars: pure streaming (m = 0, V = NULL) bit-exact in FP64 and, against the
+oracle's float instance, in FP32; full steps (mass + potential) to relative
+L2 1e-12 in FP64; FP32 within the rounding budget of its step count; FP32
+after 10^4 steps within 1e-4.  Sizes span several 64-cell strips, several
+march segments and ragged tails; both wall conditions; every axis layout.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1107_4650_amd.inputs import (random_spinor, config_1d_step, config_2d_tanh,
+                                        packet, C_LIGHT)
+from tests.gpu_util import announce, gpu_step, rel_l2, same_bits
+
+pytestmark = pytest.mark.gpu
+
+C = C_LIGHT
+DX = 0.01
+DT = DX / C
+
+LAYOUTS = [
+    ((300,), (0,)), ((300,), (1,)), ((257,), (2,)), ((10000,), (0,)),
+    ((150, 37), (0, 1)), ((130, 45), (0, 2)), ((70, 33), (1, 2)), ((64, 64), (0, 1)),
+    ((70, 13, 11), (0, 1, 2)), ((64, 9, 10), (0, 1, 2)),
+]
+
+
+def _ids(v):
+    if isinstance(v, tuple):
+        return "x".join(str(int(s)) for s in v)
+    return str(v)
+
+
+@pytest.mark.parametrize("shape,axes", LAYOUTS, ids=[f"{_ids(s)}-ax{_ids(a)}" for s, a in LAYOUTS])
+@pytest.mark.parametrize("bc", ["zero", "periodic"])
+def test_pure_streaming_bit_exact(shape, axes, bc):
+    announce(f"streaming {shape} axes={axes} bc={bc}")
+    psi = random_spinor(shape[::-1], seed=sum(shape))
+    nsteps = 100
+    ref64 = O.step(psi, None, dt=DT, c=C, m=0.0, nsteps=nsteps, axes=axes, bc=bc)
+    got64 = gpu_step(psi, None, dx=DX, dt=DT, c=C, m=0.0, nsteps=nsteps, axes=axes, bc=bc,
+                     dtype="c128")
+    assert same_bits(got64, ref64)
+    psi32 = psi.astype(np.complex64)
+    ref32 = O.stream_f32(psi32, nsteps=nsteps, axes=axes, bc=bc)
+    got32 = gpu_step(psi32, None, dx=DX, dt=DT, c=C, m=0.0, nsteps=nsteps, axes=axes, bc=bc,
+                     dtype="c64")
+    assert same_bits(got32, ref32)
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_eigen_aligned_shift_fp32(axis):
+    """Massless data in the +1 eigenspace of alpha move one cell per step, exactly."""
+    announce(f"exact shift axis={axis}")
+    n, steps = 5000, 37
+    rng = np.random.default_rng(axis)
+    u = (rng.uniform(-1, 1, (n, 2)) + 1j * rng.uniform(-1, 1, (n, 2))).astype(np.complex64)
+    u[:64] = 0
+    u[-64:] = 0
+    pauli = [np.array([[0, 1], [1, 0]]), np.array([[0, -1j], [1j, 0]]),
+             np.array([[1, 0], [0, -1]])][axis]
+    psi = np.zeros((n, 4), np.complex64)
+    psi[:, :2] = u
+    psi[:, 2:] = (u.astype(np.complex128) @ pauli.T).astype(np.complex64)
+    got = gpu_step(psi, None, dx=DX, dt=DT, c=C, m=0.0, nsteps=steps, axes=(axis,), dtype="c64")
+    assert same_bits(got, np.roll(psi, steps, axis=0))
+
+
+@pytest.mark.parametrize("shape,axes", LAYOUTS, ids=[f"{_ids(s)}-ax{_ids(a)}" for s, a in LAYOUTS])
+@pytest.mark.parametrize("bc", ["zero", "periodic"])
+def test_full_step_fp64_and_fp32(shape, axes, bc):
+    announce(f"full step {shape} axes={axes} bc={bc}")
+    psi = random_spinor(shape[::-1], seed=7 + sum(shape))
+    rng = np.random.default_rng(3)
+    V = rng.uniform(-3, 3, size=shape[::-1]) * C * C
+    nsteps = 60
+    ref = O.step(psi, V, dt=DT, c=C, m=1.0, nsteps=nsteps, axes=axes, bc=bc)
+    got64 = gpu_step(psi, V, dx=DX, dt=DT, c=C, m=1.0, nsteps=nsteps, axes=axes, bc=bc,
+                     dtype="c128")
+    assert rel_l2(got64, ref) <= 1e-12
+    got32 = gpu_step(psi.astype(np.complex64), V, dx=DX, dt=DT, c=C, m=1.0, nsteps=nsteps,
+                     axes=axes, bc=bc, dtype="c64")
+    # FP32 storage: about sqrt(3 * steps) roundings of 6e-8 per value
+    assert rel_l2(got32, ref) <= 5e-6
+    # mass without potential (constant phase factors)
+    ref_m = O.step(psi, None, dt=DT, c=C, m=1.0, nsteps=7, axes=axes, bc=bc)
+    got_m = gpu_step(psi, None, dx=DX, dt=DT, c=C, m=1.0, nsteps=7, axes=axes, bc=bc,
+                     dtype="c128")
+    assert rel_l2(got_m, ref_m) <= 1e-13
+
+
+def test_config_1d_full_run():
+    """1-D N = 4096, 2000 steps, complex128 (resident one-workgroup path)."""
+    w = config_1d_step()
+    announce("1-D 4096 x 2000 steps")
+    ref = O.step(w.psi0, w.V, dt=w.dt, c=w.c, m=w.m, nsteps=w.nsteps, axes=w.axes)
+    got = gpu_step(w.psi0, w.V, dx=w.dx, dt=w.dt, c=w.c, m=w.m, nsteps=w.nsteps, axes=w.axes)
+    assert rel_l2(got, ref) <= 1e-12
+    got32 = gpu_step(w.psi0.astype(np.complex64), w.V, dx=w.dx, dt=w.dt, c=w.c, m=w.m,
+                     nsteps=w.nsteps, axes=w.axes, dtype="c64")
+    assert rel_l2(got32, ref) <= 2e-5
+
+
+def test_config_2d_full_size_few_steps():
+    """2048 x 2048 at the benchmark's launch configuration, every cell compared."""
+    w = config_2d_tanh(n=2048, nsteps=6)
+    announce("2-D 2048^2 x 6 steps")
+    ref = O.step(w.psi0, w.V, dt=w.dt, c=w.c, m=w.m, nsteps=w.nsteps, axes=w.axes)
+    got = gpu_step(w.psi0, w.V, dx=w.dx, dt=w.dt, c=w.c, m=w.m, nsteps=w.nsteps, axes=w.axes)
+    assert rel_l2(got, ref) <= 1e-12
+    got32 = gpu_step(w.psi0.astype(np.complex64), w.V, dx=w.dx, dt=w.dt, c=w.c, m=w.m,
+                     nsteps=w.nsteps, axes=w.axes, dtype="c64")
+    assert rel_l2(got32, ref) <= 1e-6
+
+
+def test_fp32_after_1e4_steps_vs_oracle():
+    """The FP32 target: relative L2 <= 1e-4 against the FP64 oracle after 10^4
+    steps, at the 2-D workload's cell size and phase per step (dx = 0.01,
+    V0 tanh(x/0.1)), on a 192^2 periodic box with a narrower packet so that the
+    oracle finishes in seconds."""
+    c, m, dx = C, 1.0, 0.01
+    n = 192
+    shape = (n, n)
+    V0 = 2.5 * m * c * c
+    from paper_1107_4650_amd.inputs import potential_tanh
+    psi0 = packet(shape, dx, delta=0.25, p0=[40.0, 0.0], r0=[-0.4, 0.1])
+    V = potential_tanh(shape, dx, V0, 0.1)
+    announce("2-D 192^2 periodic x 1e4 steps FP32")
+    nsteps = 10000
+    ref = O.step(psi0, V, dt=dx / c, c=c, m=m, nsteps=nsteps, axes=(0, 1), bc="periodic")
+    got32 = gpu_step(psi0.astype(np.complex64), V, dx=dx, dt=dx / c, c=c, m=m, nsteps=nsteps,
+                     axes=(0, 1), bc="periodic", dtype="c64")
+    err = rel_l2(got32, ref)
+    announce(f"rel-L2 = {err:.3e}")
+    assert err <= 1e-4
+    got64 = gpu_step(psi0, V, dx=dx, dt=dx / c, c=c, m=m, nsteps=nsteps, axes=(0, 1),
+                     bc="periodic", dtype="c128")
+    assert rel_l2(got64, ref) <= 1e-12
+
+
+def test_config_2d_fp32_vs_fp64_1e4_steps():
+    """Full 2048^2 run of 10^4 steps: FP32 bulk vs the FP64 path (which is pinned
+    to the oracle above)."""
+    w = config_2d_tanh(n=2048, nsteps=10000)
+    announce("2-D 2048^2 x 1e4 steps FP32 vs FP64")
+    g64 = gpu_step(w.psi0, w.V, dx=w.dx, dt=w.dt, c=w.c, m=w.m, nsteps=w.nsteps, axes=w.axes)
+    g32 = gpu_step(w.psi0.astype(np.complex64), w.V, dx=w.dx, dt=w.dt, c=w.c, m=w.m,
+                   nsteps=w.nsteps, axes=w.axes, dtype="c64")
+    err = rel_l2(g32, g64)
+    announce(f"rel-L2 = {err:.3e}")
+    print(f"config-2 FP32 vs FP64 after 1e4 steps: rel-L2 = {err:.3e}")
+    assert err <= 1e-4
+
+
+def test_3d_fp64_vs_oracle():
+    announce("3-D 96x80x72")
+    shape = (96, 80, 72)
+    psi = packet(shape, 0.02, delta=0.4, p0=[30.0, 10.0, 0.0], r0=[-0.2, 0.1, 0.0])
+    from paper_1107_4650_amd.inputs import potential_sphere
+    V = potential_sphere(shape, 0.02, 1.5 * C * C, width2=0.25)
+    dt = 0.02 / C
+    ref = O.step(psi, V, dt=dt, c=C, m=1.0, nsteps=20, axes=(0, 1, 2))
+    got = gpu_step(psi, V, dx=0.02, dt=dt, c=C, m=1.0, nsteps=20, axes=(0, 1, 2))
+    assert rel_l2(got, ref) <= 1e-12
+    got32 = gpu_step(psi.astype(np.complex64), V, dx=0.02, dt=dt, c=C, m=1.0, nsteps=20,
+                     axes=(0, 1, 2), dtype="c64")
+    assert rel_l2(got32, ref) <= 3e-6
