@@ -192,6 +192,10 @@ def bench_extras(args, line):
     ex["3d_512"] = bench_3d(args)
     # observables pass on the 2048^2 FP32 state
     ex["observables_2048_f32"] = bench_observables()
+    # adjoint: 1024^2 periodic, forward + reversible backward
+    ex["adjoint_1024"] = bench_adjoint(args)
+    # batch of 256 uneven instances vs the same instances one at a time
+    ex["batch_256"] = bench_batch(args)
     line["extras"] = ex
 
 
@@ -248,6 +252,95 @@ def bench_observables():
             "GBps": 32 * w.sites / (ms * 1e-3) / 1e9}
 
 
+def bench_adjoint(args):
+    """Adjoint workload: 1024^2 complex64 periodic box, V from 64 Gaussian bumps,
+    forward nsteps (dl_expand + dl_step + observables) and the fused reverse sweep
+    (dl_seed_adjoint + dl_grad_step + dl_project)."""
+    import torch
+    from paper_1107_4650_amd import libdirac as L
+    from paper_1107_4650_amd.inputs import config_adjoint
+    w = config_adjoint(nsteps=args.adjoint_steps)
+    nb = len(w.extra["theta"])
+    G = to_dev(w.extra["dVdtheta"])
+    theta = to_dev(w.extra["theta"])
+    x_b = w.extra["x_b"]
+    with L.Plan(w.shape, w.dx, w.dt, w.c, w.m, dtype="c64", bc="periodic", xmin=w.xmin) as p:
+        psi0 = to_dev(w.psi0, torch.complex64)
+        V = torch.empty(w.psi0.shape[:-1], dtype=torch.float64, device="cuda")
+        psi = psi0.clone()
+        lam = torch.empty_like(psi)
+        Q = torch.empty_like(V)
+        g = torch.empty(nb, dtype=torch.float64, device="cuda")
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        torch.cuda.synchronize()
+        ev[0].record()
+        p.expand(G, theta, V)
+        p.step(psi, V, w.nsteps)
+        ev[1].record()
+        L_T = p.observables(psi, x_b)[4]
+        ev[2].record()
+        p.seed_adjoint(psi, x_b, lam, Q)
+        p.grad_step(psi, lam, V, Q, w.nsteps)
+        p.project(Q, G, g)
+        ev[3].record()
+        torch.cuda.synchronize()
+        fwd_ms = ev[0].elapsed_time(ev[1])
+        bwd_ms = ev[2].elapsed_time(ev[3])
+        rec = rel_l2(psi, psi0)
+        gn = float(torch.linalg.vector_norm(g))
+    sites = w.sites * w.nsteps
+    log(f"adjoint: fwd {fwd_ms:.2f} ms, bwd {bwd_ms:.2f} ms, reconstruction {rec:.2e}")
+    return {"steps": w.nsteps, "forward_ms": fwd_ms, "backward_ms": bwd_ms,
+            "forward_site_updates_per_s": sites / (fwd_ms * 1e-3),
+            "backward_site_updates_per_s": sites / (bwd_ms * 1e-3),
+            "backward_bytes_per_site": 152,
+            "backward_roofline_frac": 152 * sites / (bwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "loss_P_T": L_T, "grad_norm": gn, "psi0_reconstruction_rel_l2": rec}
+
+
+def bench_batch(args):
+    """256 uneven 1-D/2-D instances: one batched launch per step (graph replay)
+    vs the same instances advanced one at a time with their own plans."""
+    import torch
+    from paper_1107_4650_amd import libdirac as L
+    from paper_1107_4650_amd.inputs import config_batch
+    steps = args.batch_steps
+    ws = config_batch(count=256, nsteps=steps, seed=0)
+    sites = sum(w.sites for w in ws)
+    psis = [to_dev(w.psi0, torch.complex64) for w in ws]
+    Vs = [to_dev(w.V) for w in ws]
+    out = {"instances": len(ws), "sites": sites, "steps": steps,
+           "n_1d": sum(1 for w in ws if w.ndim == 1), "n_2d": sum(1 for w in ws if w.ndim == 2)}
+    with L.Batch([w.shape for w in ws], [w.dx for w in ws], [w.dt for w in ws],
+                 [w.c for w in ws], [w.m for w in ws], dtype="c64", graph=True) as b:
+        out["autotuned_seg_len"] = b.autotune(psis, Vs, trials=3)
+        b.step(psis, Vs, [2] * len(ws))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.step(psis, Vs, [steps] * len(ws))
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+    out["batched_s"] = tb
+    out["batched_site_updates_per_s"] = sites * steps / tb
+    out["batched_roofline_frac"] = BYTES_F32 * sites * steps / tb / 1e9 / HBM_PEAK_GBS
+    plans = [L.Plan(w.shape, w.dx, w.dt, w.c, w.m, dtype="c64") for w in ws]
+    for p, t, v in zip(plans, psis, Vs):
+        p.step(t, v, 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p, t, v in zip(plans, psis, Vs):
+        p.step(t, v, steps)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    for p in plans:
+        p.close()
+    out["one_at_a_time_s"] = ts
+    out["one_at_a_time_site_updates_per_s"] = sites * steps / ts
+    out["speedup"] = ts / tb
+    log(f"batch: {tb:.3f} s batched vs {ts:.3f} s one at a time")
+    return out
+
+
 def cpu_baseline(min_seconds=10.0, max_seconds=30.0):
     """The FP64 oracle, as it stands, on the host's cores: bounded sample of the
     same 2048^2 workload (whole steps until ~min_seconds of CPU time)."""
@@ -285,6 +378,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--steps3d", type=int, default=50)
+    ap.add_argument("--adjoint-steps", type=int, default=4000)
+    ap.add_argument("--batch-steps", type=int, default=500)
     ap.add_argument("--only", choices=["all", "sweep", "main"], default="all")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")

@@ -161,9 +161,19 @@ template <typename T> struct Axis<2, T> {
 #define DIRAC_PIO2_3 0x1.3198a2e037073p-69
 #define DIRAC_2_OVER_PI 0x1.45f306dc9c883p-1
 
+// Arguments beyond the reduction range go to the library routine, kept out of
+// line so that its large-argument reduction does not occupy the hot loop.
+__device__ __attribute__((noinline)) double2 sincos_far(double x) {
+  double2 r;
+  sincos(x, &r.x, &r.y);
+  return r;
+}
+
 __device__ __forceinline__ void sincos_cw(double x, double* s_out, double* c_out) {
   if (!(fabs(x) < 1048576.0)) {  // also routes NaN to the library
-    sincos(x, s_out, c_out);
+    const double2 r = sincos_far(x);
+    *s_out = r.x;
+    *c_out = r.y;
     return;
   }
   const double k = rint(x * DIRAC_2_OVER_PI);

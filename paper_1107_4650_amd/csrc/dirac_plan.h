@@ -71,5 +71,6 @@ int check_live(dl_plan p);
 int check_state_ptr(const void* ptr, const char* name);
 int check_f64_ptr(const void* ptr, const char* name, bool nullable);
 hipError_t sweep_once(dl_plan p, const void* src, void* dst, const double* V, hipStream_t st);
+void destroy_batch(dl_plan p);
 
 }  // namespace dirac

@@ -252,6 +252,12 @@ void dl_plan_s::drop_graphs() {
 
 extern "C" int dl_plan_destroy(dl_plan p) {
   if (!p) return DL_OK;
+  if (p->is_batch) {
+    if (!p->dry) (void)hipDeviceSynchronize();
+    destroy_batch(p);
+    delete p;
+    return DL_OK;
+  }
   if (!p->dry) {
     (void)hipDeviceSynchronize();
     p->drop_graphs();
@@ -272,6 +278,7 @@ namespace dirac {
 
 int check_live(dl_plan p) {
   if (!p) return fail(DL_ERR_ARG, "plan is NULL");
+  if (p->is_batch) return fail(DL_ERR_STATE, "a batch handle: use dl_batch_step");
   if (p->dry) return fail(DL_ERR_STATE, "dry plan: created with DL_DRY, no device work allowed");
   return DL_OK;
 }

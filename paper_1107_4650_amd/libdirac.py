@@ -67,6 +67,8 @@ def load() -> ctypes.CDLL:
                             ctypes.c_uint],
         "dl_batch_step": [vp, P(vp), P(vp), P(i64), vp],
         "dl_plan_set_tiling": [vp, ci, ci, ci, ci],
+        "dl_batch_autotune": [vp, P(vp), P(vp), ci, P(ci), vp],
+        "dl_batch_set": [vp, ci, ci],
         "dl_plan_info": [vp, P(i64), ci],
         "dl_version": [],
         "dl_last_error": [],
@@ -243,3 +245,87 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class Batch:
+    """Independent 1-D / 2-D instances advanced by shared launches."""
+
+    def __init__(self, shapes, dx, dt, c, m, dtype="c64", bc="zero", axes=None, xmins=None,
+                 dry=False, graph=True):
+        self.lib = load()
+        self.count = len(shapes)
+        self.shapes = [tuple(int(v) for v in s) for s in shapes]
+        self.tshapes = [tuple(reversed(s)) + (4,) for s in self.shapes]
+        self.dtype_code = _dtype_code(dtype)
+        grids = (Grid * self.count)()
+        for k, s in enumerate(self.shapes):
+            g = make_grid(s, None if axes is None else axes[k],
+                          None if xmins is None else xmins[k], _at(dx, k))
+            grids[k] = g
+        arr = lambda v: (ctypes.c_double * self.count)(*[_at(v, k) for k in range(self.count)])
+        flags = (DL_DRY if dry else 0) | (DL_GRAPH if graph else 0)
+        h = ctypes.c_void_p()
+        check(self.lib.dl_batch_create(ctypes.byref(h), grids, arr(dx), arr(dt), arr(c), arr(m),
+                                       self.count, self.dtype_code, _bc_code(bc), flags))
+        self.handle = h
+
+    def _ptrs(self, psis, Vs):
+        import torch
+        want = torch.complex64 if self.dtype_code == DL_C64 else torch.complex128
+        if len(psis) != self.count:
+            raise ValueError("one state per instance")
+        P = (ctypes.c_void_p * self.count)()
+        for k, t in enumerate(psis):
+            if t.device.type != "cuda" or t.dtype != want or not t.is_contiguous() \
+                    or tuple(t.shape) != self.tshapes[k]:
+                raise ValueError(f"psi[{k}] must be a contiguous {want} CUDA tensor of shape "
+                                 f"{self.tshapes[k]}")
+            P[k] = t.data_ptr()
+        Vp = None
+        if Vs is not None:
+            Vp = (ctypes.c_void_p * self.count)()
+            for k, v in enumerate(Vs):
+                if v is None:
+                    Vp[k] = None
+                    continue
+                if v.device.type != "cuda" or v.dtype != torch.float64 or not v.is_contiguous() \
+                        or tuple(v.shape) != self.tshapes[k][:-1]:
+                    raise ValueError(f"V[{k}] must be a contiguous float64 CUDA tensor")
+                Vp[k] = v.data_ptr()
+        return P, Vp
+
+    def step(self, psis, Vs, nsteps):
+        P, Vp = self._ptrs(psis, Vs)
+        ns = (ctypes.c_int64 * self.count)(*[int(_at(nsteps, k)) for k in range(self.count)])
+        check(self.lib.dl_batch_step(self.handle, P, Vp, ns, _stream_handle()))
+
+    def autotune(self, psis, Vs, trials=4) -> int:
+        P, Vp = self._ptrs(psis, Vs)
+        out = ctypes.c_int(0)
+        check(self.lib.dl_batch_autotune(self.handle, P, Vp, int(trials), ctypes.byref(out),
+                                         _stream_handle()))
+        return out.value
+
+    def set(self, seg_len=32, graph_pairs=16):
+        check(self.lib.dl_batch_set(self.handle, int(seg_len), int(graph_pairs)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.dl_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def _at(v, k):
+    return v[k] if isinstance(v, (list, tuple)) or hasattr(v, "__len__") else v

@@ -108,3 +108,15 @@ def test_python_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="not built"):
         L.load()
+
+
+def test_dry_batch_validation(lib):
+    shapes = [(128,), (64, 32)]
+    b = L.Batch(shapes, 0.01, 0.01 / C, C, 1.0, dry=True)
+    b.close()
+    with pytest.raises(L.DiracError) as ei:
+        L.Batch([(128,), (8, 8, 8)], 0.01, 0.01 / C, C, 1.0, dry=True)
+    assert ei.value.code == L.DL_ERR_ARG
+    with pytest.raises(L.DiracError) as ei:
+        L.Batch([(128,), (64, 32)], [0.01, 0.01], [0.01 / C, 0.02 / C], C, 1.0, dry=True)
+    assert ei.value.code == L.DL_ERR_CFL

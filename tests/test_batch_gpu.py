@@ -1,0 +1,72 @@
+"""Batched launches: every instance of a mixed 1-D / 2-D batch ends bit-identical
+to the same instance advanced alone with dl_step, for uneven step counts (odd,
+even, zero), both dtypes, with and without graph replay, and after autotuning
+(which must leave the caller's states untouched)."""
+import numpy as np
+import pytest
+
+from paper_1107_4650_amd import libdirac as L
+from paper_1107_4650_amd.inputs import config_batch, C_LIGHT
+from tests.gpu_util import announce, same_bits
+
+pytestmark = pytest.mark.gpu
+
+
+def _instances(count, seed, max_side=256):
+    ws = config_batch(count=count, nsteps=1, seed=seed, sides=(64, 96, 160), n1d=(200, 5000),
+                      max_side=max_side)
+    return ws
+
+
+def _alone(w, nsteps, dtype):
+    import torch
+    tdt = torch.complex64 if dtype == "c64" else torch.complex128
+    psi = torch.from_numpy(w.psi0).to("cuda").to(tdt)
+    V = torch.from_numpy(w.V).to("cuda")
+    with L.Plan(w.shape, w.dx, w.dt, w.c, w.m, dtype=dtype, axes=w.axes) as p:
+        p.step(psi, V, nsteps)
+        torch.cuda.synchronize()
+    return psi.cpu().numpy()
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_matches_single_runs(dtype, graph):
+    import torch
+    announce(f"batch dtype={dtype} graph={graph}")
+    ws = _instances(12, seed=3)
+    rng = np.random.default_rng(4)
+    nsteps = [int(v) for v in rng.integers(0, 90, size=len(ws))]
+    nsteps[0] = 0
+    nsteps[1] = 77
+    nsteps[2] = 64
+    tdt = torch.complex64 if dtype == "c64" else torch.complex128
+    psis = [torch.from_numpy(w.psi0).to("cuda").to(tdt) for w in ws]
+    Vs = [torch.from_numpy(w.V).to("cuda") for w in ws]
+    with L.Batch([w.shape for w in ws], [w.dx for w in ws], [w.dt for w in ws],
+                 [w.c for w in ws], [w.m for w in ws], dtype=dtype, graph=graph) as b:
+        b.set(seg_len=24, graph_pairs=8)
+        b.step(psis, Vs, nsteps)
+        torch.cuda.synchronize()
+    for w, n, t in zip(ws, nsteps, psis):
+        assert same_bits(t.cpu().numpy(), _alone(w, n, dtype)), (w.name, w.shape, n)
+
+
+def test_autotune_leaves_inputs_and_keeps_bits():
+    import torch
+    announce("batch autotune")
+    ws = _instances(6, seed=8)
+    psis = [torch.from_numpy(w.psi0).to("cuda").to(torch.complex64) for w in ws]
+    Vs = [torch.from_numpy(w.V).to("cuda") for w in ws]
+    before = [t.cpu().numpy() for t in psis]
+    with L.Batch([w.shape for w in ws], [w.dx for w in ws], [w.dt for w in ws],
+                 [w.c for w in ws], [w.m for w in ws], dtype="c64") as b:
+        H = b.autotune(psis, Vs, trials=2)
+        torch.cuda.synchronize()
+        assert H in (8, 16, 32, 64, 128)
+        for t, ref in zip(psis, before):
+            assert same_bits(t.cpu().numpy(), ref)
+        b.step(psis, Vs, [40] * len(ws))
+        torch.cuda.synchronize()
+    for w, t in zip(ws, psis):
+        assert same_bits(t.cpu().numpy(), _alone(w, 40, "c64"))
