@@ -78,6 +78,10 @@ def test_reverse_step_is_the_adjoint(shape, axes, bc):
 
 
 def _case(n=96, nb=6, bc="periodic", nsteps=120):
+    """Periodic: a packet that wraps around freely.  Zero walls: S^{-1} = S^H
+    only while nothing has reached a wall, so the packet is narrow (Delta =
+    0.1 a.u. = 2 cells), centred, and its light cone after `nsteps` (20) stays
+    2.4 a.u. = 14 Delta inside the box (initial amplitude there ~ e^-49)."""
     dx = 0.05
     shape = (n, n)
     xmin = [-n * dx / 2] * 2
@@ -85,8 +89,13 @@ def _case(n=96, nb=6, bc="periodic", nsteps=120):
     centres = rng.uniform(-0.8, 0.8, size=(nb, 2))
     G = bump_basis(shape, dx, centres, 0.3) * (C * C)
     theta = rng.uniform(-1, 1, nb)
-    psi0 = packet(shape, dx, delta=0.3, p0=[15.0, 0.0], r0=[-0.8, 0.0])
-    return dict(shape=shape, dx=dx, xmin=xmin, G=G, theta=theta, psi0=psi0, x_b=0.5,
+    if bc == "periodic":
+        psi0 = packet(shape, dx, delta=0.3, p0=[15.0, 0.0], r0=[-0.8, 0.0])
+        x_b = 0.5
+    else:
+        psi0 = packet(shape, dx, delta=0.1, p0=[15.0, 0.0], r0=[0.0, 0.0])
+        x_b, nsteps = 0.1, 20
+    return dict(shape=shape, dx=dx, xmin=xmin, G=G, theta=theta, psi0=psi0, x_b=x_b,
                 nsteps=nsteps, bc=bc)
 
 
