@@ -47,21 +47,26 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def timed_sweep(plan, psi, V, steps, warmup):
-    """Alternate psi <-> tmp with dl_step_out; HIP events around every launch on
-    the launch stream.  Returns (wall seconds, mean per-launch ms, final tensor)."""
+def timed_sweep(plan, psi, V, steps, warmup, pair=False):
+    """Alternate psi <-> tmp with dl_step_out (one step per launch) or
+    dl_step_pair_out (two fused steps per launch); HIP events around every
+    launch on the launch stream.  `steps` counts time steps.  Returns (wall
+    seconds, mean per-launch ms, final tensor)."""
     import torch
+    per_launch = 2 if pair else 1
+    launch = plan.step_pair_out if pair else plan.step_out
+    nl, nw = max(1, steps // per_launch), max(0, warmup // per_launch)
     a, b = psi, torch.empty_like(psi)
-    for _ in range(warmup):
-        plan.step_out(a, b, V)
+    for _ in range(nw):
+        launch(a, b, V)
         a, b = b, a
     torch.cuda.synchronize()
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(nl)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(nl)]
     t0 = time.perf_counter()
-    for i in range(steps):
+    for i in range(nl):
         starts[i].record()
-        plan.step_out(a, b, V)
+        launch(a, b, V)
         ends[i].record()
         a, b = b, a
     torch.cuda.synchronize()
@@ -112,18 +117,18 @@ def bench_main(args):
     # ---- FP32 storage (headline) -------------------------------------------
     with L.Plan(w.shape, w.dx, w.dt, w.c, w.m, dtype="c64", xmin=w.xmin) as p32:
         psi32 = to_dev(w.psi0, torch.complex64)
-        wall32, per32, out32 = timed_sweep(p32, psi32, V, args.steps, args.warmup)
+        wall32, per32, out32 = timed_sweep(p32, psi32, V, args.steps, args.warmup, pair=True)
         info = p32.info()
         obs32 = p32.observables(out32, 0.0)
     res["fp32"] = dict(wall=wall32, per_launch_ms=per32)
-    log(f"fp32: {wall32 * 1e3 / args.steps:.4f} ms/step wall, {per32:.4f} ms/launch")
+    log(f"fp32: {wall32 * 1e3 / args.steps:.4f} ms/step wall, {per32:.4f} ms per two-step launch")
     if args.only == "sweep":
         return None
 
     # ---- FP64 path on the same steps (also the reference for the FP32 error) -
     with L.Plan(w.shape, w.dx, w.dt, w.c, w.m, dtype="c128", xmin=w.xmin) as p64:
         psi64 = to_dev(w.psi0)
-        wall64, per64, out64 = timed_sweep(p64, psi64, V, args.steps, args.warmup)
+        wall64, per64, out64 = timed_sweep(p64, psi64, V, args.steps, args.warmup, pair=True)
         obs64 = p64.observables(out64, 0.0)
     # both runs advanced warmup + steps steps from the same initial state
     err = rel_l2(out32, out64)
@@ -131,8 +136,10 @@ def bench_main(args):
     del psi32, psi64, out32, out64
     torch.cuda.empty_cache()
 
+    # one launch advances every cell two steps, reading psi and V once and
+    # writing psi once: 72 B per cell per launch, 36 B per site-update
     achieved = BYTES_F32 * sites / (per32 * 1e-3) / 1e9
-    traffic = load_traffic("sweep2d_f32_2048")
+    traffic = load_traffic("sweep2d_x2_f32_2048")
     line = {
         "metric": METRIC,
         "value": sites * args.steps / wall32,
@@ -149,15 +156,18 @@ def bench_main(args):
         "config": {"workload": "2-D Dirac, 2048x2048 cells, tanh step V0*tanh(x/0.1), "
                                "Gaussian packet sigma 1.5 p0=(40,0), complex64 state, FP64 V "
                                "and phases, dx=0.01, c*dt=dx, zero walls",
-                   "grid": [2048, 2048], "steps_per_call": 1,
+                   "grid": [2048, 2048], "steps_per_launch": 2,
                    "tiling": info},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
-                     "kernel": "k_sweep2d<float,0,1>",
-                     "bytes_per_site": BYTES_F32},
+                     "kernel": "k_sweep2d_x2<float,0,1,2>",
+                     "bytes_per_launch_per_cell": BYTES_F32,
+                     "bytes_per_site_update": BYTES_F32 / 2,
+                     "per_launch_ms": per32, "site_updates_per_launch": 2 * sites},
         "fp64": {"value": sites * args.steps / wall64, "unit": "site-updates/s",
                  "ms_per_step": wall64 * 1e3 / args.steps, "per_launch_ms": per64,
+                 "per_launch_ms_two_steps": per64,
                  "roofline_frac": BYTES_F64 * sites / (per64 * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "fp32_vs_fp64_rel_l2": err,
         "fp32_vs_fp64_steps": args.steps + args.warmup,

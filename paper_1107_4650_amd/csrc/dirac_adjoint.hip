@@ -47,13 +47,6 @@ __device__ __forceinline__ Factors adjoint_factors(double V, const PhaseK& k) {
   return f;
 }
 
-template <typename T>
-__device__ __forceinline__ void scale_site(Site<T>& s, const PhaseK& k) {
-  const T sc = scale_of<T>(k);
-#pragma unroll
-  for (int j = 0; j < 8; ++j) s.v[j] *= sc;
-}
-
 // load the cell at column x of row j (walls / wrap-around), zeros outside
 template <typename T>
 __device__ __forceinline__ void load_cell(const T* __restrict__ f, int64_t nx, int64_t ny,
@@ -365,6 +358,26 @@ static hipError_t launch_rev(void* po, void* lo, const void* pi, const void* li,
   }
 }
 
+template <typename T>
+static int rev_occ(int axes_code) {
+  const void* k;
+  switch (axes_code) {
+    case 0: k = reinterpret_cast<const void*>(&k_reverse<T, 0, -1>); break;
+    case 1: k = reinterpret_cast<const void*>(&k_reverse<T, 1, -1>); break;
+    case 2: k = reinterpret_cast<const void*>(&k_reverse<T, 2, -1>); break;
+    case 10: k = reinterpret_cast<const void*>(&k_reverse<T, 0, 1>); break;
+    case 20: k = reinterpret_cast<const void*>(&k_reverse<T, 0, 2>); break;
+    case 21: k = reinterpret_cast<const void*>(&k_reverse<T, 1, 2>); break;
+    default: return 0;
+  }
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, 256, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return n;
+}
+
 }  // namespace dirac
 
 using namespace dirac;
@@ -374,14 +387,21 @@ static void rev_tiling(dl_plan p, RevArgs& a, int& blocks) {
   a.ny = p->g.ndim > 1 ? p->g.n[1] : 1;
   a.periodic = (p->bc == DL_BC_PERIODIC);
   a.nstrips = (a.nx + 61) / 62;
-  const int64_t target = int64_t(256) * p->waves_per_cu;
+  int64_t target;
+  if (p->waves_per_cu > 0) {
+    target = int64_t(p->cu_count) * p->waves_per_cu;
+  } else {
+    int occ = p->fp64 ? rev_occ<double>(axes_code(p->g)) : rev_occ<float>(axes_code(p->g));
+    if (occ <= 0) occ = 2;
+    target = int64_t(occ) * 4 * p->cu_count;
+  }
   if (p->g.ndim == 1) {
     a.nseg = 1;
     a.H = 1;
   } else {
     int64_t H = p->seg_override;
     if (H <= 0) {
-      int64_t nseg = (target + a.nstrips - 1) / a.nstrips;
+      int64_t nseg = target / a.nstrips;
       if (nseg < 1) nseg = 1;
       H = (a.ny + nseg - 1) / nseg;
       if (H < 8) H = 8;

@@ -66,12 +66,12 @@ __global__ __launch_bounds__(256) void k_batch(const BatchInst* __restrict__ ins
   const int64_t x0 = static_cast<int64_t>(t.strip) * 64;
   const bool up = t.up != 0;
   switch (I.axes_code) {
-    case 0: one_row<T, 0>(src, dst, I.V, a, x0, lane); break;
-    case 1: one_row<T, 1>(src, dst, I.V, a, x0, lane); break;
-    case 2: one_row<T, 2>(src, dst, I.V, a, x0, lane); break;
-    case 10: march_dir<T, 0, 1>(src, dst, I.V, a, x0, lane, t.jb, t.je, up); break;
-    case 20: march_dir<T, 0, 2>(src, dst, I.V, a, x0, lane, t.jb, t.je, up); break;
-    case 21: march_dir<T, 1, 2>(src, dst, I.V, a, x0, lane, t.jb, t.je, up); break;
+    case 0: one_row<T, 0, -1>(src, dst, I.V, a, x0, lane); break;
+    case 1: one_row<T, 1, -1>(src, dst, I.V, a, x0, lane); break;
+    case 2: one_row<T, 2, -1>(src, dst, I.V, a, x0, lane); break;
+    case 10: march_dir<T, 0, 1, -1>(src, dst, I.V, a, x0, lane, t.jb, t.je, up); break;
+    case 20: march_dir<T, 0, 2, -1>(src, dst, I.V, a, x0, lane, t.jb, t.je, up); break;
+    case 21: march_dir<T, 1, 2, -1>(src, dst, I.V, a, x0, lane, t.jb, t.je, up); break;
     default: break;
   }
 }

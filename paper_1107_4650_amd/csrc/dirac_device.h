@@ -145,14 +145,18 @@ template <typename T> struct Axis<2, T> {
 
 // ---------------------------------------------------------------------------
 // FP64 sine and cosine for the local step.  Cody-Waite reduction by pi/2 with
-// a three-part constant, keeping the reduced argument as rh + rl; Taylor
-// polynomials on [-pi/4, pi/4] (terms to r^17 for sin, r^18 for cos;
-// truncation below 1e-19); sin(rh + rl) = sin rh + rl cos rh and
-// cos(rh + rl) = cos rh - rl sin rh to first order in rl, with 1 - rh^2/2
-// carried as an unevaluated sum (its rounding errors recovered exactly by
-// FMA and Sterbenz subtraction).  Error below 1 ulp, equal to the correctly
-// rounded value for about 98.5 % of arguments in [-12, 12].  |x| >= 2^20
-// falls back to the library routine.
+// a three-part constant; Taylor polynomials on [-pi/4, pi/4].
+//   ACC = 2 (FP64 storage): terms to r^17 (sin) and r^18 (cos), truncation
+//     below 1e-19; the reduced argument is kept as rh + rl and
+//     sin(rh + rl) = sin rh + rl cos rh, cos(rh + rl) = cos rh - rl sin rh to
+//     first order in rl, with 1 - rh^2/2 carried as an unevaluated sum (its
+//     rounding errors recovered exactly by FMA and Sterbenz subtraction).
+//     Error below 1 ulp, equal to the correctly rounded value for about
+//     98.5 % of arguments in [-12, 12].
+//   ACC = 1 (FP32 storage): terms to r^13 and r^14 (truncation below 3e-14),
+//     no tail terms; a few ulp, far below the FP32 rounding of the state.
+// Valid for |x| < 2^20; far_arg() flags the rest (and NaN), which callers
+// route to the library routine outside their hot loops.
 // ---------------------------------------------------------------------------
 // pi/2 = P1 + P2 + P3: P1, P2 hold 33 significant bits each (so k * P1 and
 // k * P2 are exact for |k| < 2^20), P3 the rounded remainder.
@@ -160,6 +164,70 @@ template <typename T> struct Axis<2, T> {
 #define DIRAC_PIO2_2 0x1.0b4611a600000p-34
 #define DIRAC_PIO2_3 0x1.3198a2e037073p-69
 #define DIRAC_2_OVER_PI 0x1.45f306dc9c883p-1
+
+__device__ __forceinline__ bool far_arg(double x) { return !(fabs(x) < 1048576.0); }
+
+template <int ACC>
+__device__ __forceinline__ void sincos_fast(double x, double* s_out, double* c_out) {
+  const double k = rint(x * DIRAC_2_OVER_PI);
+  // x - k pi/2 = rh + rl: k P1, k P2 are exact and so is x - k P1
+  const double a = fma(-k, DIRAC_PIO2_1, x);
+  const double b = k * DIRAC_PIO2_2;
+  const double rh = a - b;
+  const double r2 = rh * rh;
+  double sn, cs;
+  if constexpr (ACC >= 2) {
+    const double rl = ((a - rh) - b) - k * DIRAC_PIO2_3;
+    // sin: rh + rh^3 (-1/3! + r^2/5! - ... + r^14/17!) + rl (1 - r^2/2)
+    double ps = 1.0 / 355687428096000.0;          // 1/17!
+    ps = fma(ps, r2, -1.0 / 1307674368000.0);     // 1/15!
+    ps = fma(ps, r2, 1.0 / 6227020800.0);         // 1/13!
+    ps = fma(ps, r2, -1.0 / 39916800.0);          // 1/11!
+    ps = fma(ps, r2, 1.0 / 362880.0);             // 1/9!
+    ps = fma(ps, r2, -1.0 / 5040.0);              // 1/7!
+    ps = fma(ps, r2, 1.0 / 120.0);                // 1/5!
+    ps = fma(ps, r2, -1.0 / 6.0);                 // 1/3!
+    sn = rh + fma(rh * r2, ps, rl * fma(-0.5, r2, 1.0));
+    // cos: (1 - rh^2/2) + rh^4 (1/4! - r^2/6! + ... + r^14/18!) - rh rl
+    double pc = -1.0 / 6402373705728000.0;        // 1/18!
+    pc = fma(pc, r2, 1.0 / 20922789888000.0);     // 1/16!
+    pc = fma(pc, r2, -1.0 / 87178291200.0);       // 1/14!
+    pc = fma(pc, r2, 1.0 / 479001600.0);          // 1/12!
+    pc = fma(pc, r2, -1.0 / 3628800.0);           // 1/10!
+    pc = fma(pc, r2, 1.0 / 40320.0);              // 1/8!
+    pc = fma(pc, r2, -1.0 / 720.0);               // 1/6!
+    pc = fma(pc, r2, 1.0 / 24.0);                 // 1/4!
+    const double e2 = fma(rh, rh, -r2);           // rh^2 = r2 + e2 exactly
+    const double hz = 0.5 * r2;
+    const double w = 1.0 - hz;
+    const double tail = ((1.0 - w) - hz) - 0.5 * e2;
+    cs = w + (fma(r2 * r2, pc, tail) - rh * rl);
+  } else {
+    const double r = fma(-k, DIRAC_PIO2_3, rh);
+    const double q2 = r * r;
+    double ps = 1.0 / 6227020800.0;               // 1/13!
+    ps = fma(ps, q2, -1.0 / 39916800.0);          // 1/11!
+    ps = fma(ps, q2, 1.0 / 362880.0);             // 1/9!
+    ps = fma(ps, q2, -1.0 / 5040.0);              // 1/7!
+    ps = fma(ps, q2, 1.0 / 120.0);                // 1/5!
+    ps = fma(ps, q2, -1.0 / 6.0);                 // 1/3!
+    sn = fma(r * q2, ps, r);
+    double pc = 1.0 / 87178291200.0;              // 1/14!
+    pc = fma(pc, q2, -1.0 / 479001600.0);         // 1/12!
+    pc = fma(pc, q2, 1.0 / 3628800.0);            // 1/10!
+    pc = fma(pc, q2, -1.0 / 40320.0);             // 1/8!
+    pc = fma(pc, q2, 1.0 / 720.0);                // 1/6!
+    pc = fma(pc, q2, -1.0 / 24.0);                // 1/4!
+    pc = fma(pc, q2, 0.5);                        // 1/2!
+    cs = fma(-pc, q2, 1.0);
+    (void)r2;
+  }
+  const int q = static_cast<int>(static_cast<long long>(k) & 3);
+  const double s1 = (q & 1) ? cs : sn;
+  const double c1 = (q & 1) ? sn : cs;
+  *s_out = (q & 2) ? -s1 : s1;
+  *c_out = ((q + 1) & 2) ? -c1 : c1;
+}
 
 // Arguments beyond the reduction range go to the library routine, kept out of
 // line so that its large-argument reduction does not occupy the hot loop.
@@ -169,49 +237,15 @@ __device__ __attribute__((noinline)) double2 sincos_far(double x) {
   return r;
 }
 
-__device__ __forceinline__ void sincos_cw(double x, double* s_out, double* c_out) {
-  if (!(fabs(x) < 1048576.0)) {  // also routes NaN to the library
+template <int ACC>
+__device__ __forceinline__ void sincos_any(double x, double* s_out, double* c_out) {
+  if (far_arg(x)) {
     const double2 r = sincos_far(x);
     *s_out = r.x;
     *c_out = r.y;
-    return;
+  } else {
+    sincos_fast<ACC>(x, s_out, c_out);
   }
-  const double k = rint(x * DIRAC_2_OVER_PI);
-  // x - k pi/2 = rh + rl: k P1, k P2 are exact and so is x - k P1
-  const double a = fma(-k, DIRAC_PIO2_1, x);
-  const double b = k * DIRAC_PIO2_2;
-  const double rh = a - b;
-  const double rl = ((a - rh) - b) - k * DIRAC_PIO2_3;
-  const double r2 = rh * rh;
-  // sin: rh + rh^3 (-1/3! + r^2/5! - ... + r^14/17!) + rl (1 - r^2/2)
-  double ps = 1.0 / 355687428096000.0;          // 1/17!
-  ps = fma(ps, r2, -1.0 / 1307674368000.0);     // 1/15!
-  ps = fma(ps, r2, 1.0 / 6227020800.0);         // 1/13!
-  ps = fma(ps, r2, -1.0 / 39916800.0);          // 1/11!
-  ps = fma(ps, r2, 1.0 / 362880.0);             // 1/9!
-  ps = fma(ps, r2, -1.0 / 5040.0);              // 1/7!
-  ps = fma(ps, r2, 1.0 / 120.0);                // 1/5!
-  ps = fma(ps, r2, -1.0 / 6.0);                 // 1/3!
-  const double sn = rh + fma(rh * r2, ps, rl * fma(-0.5, r2, 1.0));
-  // cos: (1 - rh^2/2) + rh^4 (1/4! - r^2/6! + ... + r^14/18!) - rh rl
-  double pc = -1.0 / 6402373705728000.0;        // 1/18!
-  pc = fma(pc, r2, 1.0 / 20922789888000.0);     // 1/16!
-  pc = fma(pc, r2, -1.0 / 87178291200.0);       // 1/14!
-  pc = fma(pc, r2, 1.0 / 479001600.0);          // 1/12!
-  pc = fma(pc, r2, -1.0 / 3628800.0);           // 1/10!
-  pc = fma(pc, r2, 1.0 / 40320.0);              // 1/8!
-  pc = fma(pc, r2, -1.0 / 720.0);               // 1/6!
-  pc = fma(pc, r2, 1.0 / 24.0);                 // 1/4!
-  const double e2 = fma(rh, rh, -r2);           // rh^2 = r2 + e2 exactly
-  const double hz = 0.5 * r2;
-  const double w = 1.0 - hz;
-  const double tail = ((1.0 - w) - hz) - 0.5 * e2;
-  const double cs = w + (fma(r2 * r2, pc, tail) - rh * rl);
-  const int q = static_cast<int>(static_cast<long long>(k) & 3);
-  const double s1 = (q & 1) ? cs : sn;
-  const double c1 = (q & 1) ? sn : cs;
-  *s_out = (q & 2) ? -s1 : s1;
-  *c_out = ((q + 1) & 2) ? -c1 : c1;
 }
 
 // ---------------------------------------------------------------------------
@@ -234,34 +268,64 @@ struct PhaseK {
 
 struct Factors { double ur, ui, dr, di; };
 
-// Phase factors of one cell.  With two_angles (FP64 storage) the angles are
+// Phase factors of one cell in mode 2.  TWO (FP64 storage): the angles are
 // formed as (V + m c^2) dt and (V - m c^2) dt, each with its own sine and
-// cosine; otherwise (FP32 storage) exp(-i V dt) is multiplied by the FP64
-// constants eu, ed, which costs one sine/cosine pair per cell.
-__device__ __forceinline__ Factors phase_factors(double V, const PhaseK& k) {
+// cosine (ACC 2).  Otherwise (FP32 storage) exp(-i V dt) (ACC 1) is multiplied
+// by the FP64 constants eu, ed: one sine/cosine pair per cell.
+template <bool TWO, bool ANY>
+__device__ __forceinline__ Factors factors_v(double V, const PhaseK& k) {
   Factors f;
-  if (k.mode == 2) {
-    if (k.two_angles) {
-      double su, cu, sd, cd;
-      sincos_cw((V + k.mc2) * k.dt, &su, &cu);
-      sincos_cw((V - k.mc2) * k.dt, &sd, &cd);
-      f.ur = k.scale * cu;
-      f.ui = -k.scale * su;
-      f.dr = k.scale * cd;
-      f.di = -k.scale * sd;
+  if constexpr (TWO) {
+    double su, cu, sd, cd;
+    const double tu = (V + k.mc2) * k.dt, td = (V - k.mc2) * k.dt;
+    if constexpr (ANY) {
+      sincos_any<2>(tu, &su, &cu);
+      sincos_any<2>(td, &sd, &cd);
     } else {
-      double sn, cs;
-      sincos_cw(V * k.dt, &sn, &cs);
-      // (cs - i sn) (x + i y) = (cs x + sn y) + i (cs y - sn x)
-      f.ur = fma(cs, k.eu_re, sn * k.eu_im);
-      f.ui = fma(cs, k.eu_im, -sn * k.eu_re);
-      f.dr = fma(cs, k.ed_re, sn * k.ed_im);
-      f.di = fma(cs, k.ed_im, -sn * k.ed_re);
+      sincos_fast<2>(tu, &su, &cu);
+      sincos_fast<2>(td, &sd, &cd);
     }
+    f.ur = k.scale * cu;
+    f.ui = -k.scale * su;
+    f.dr = k.scale * cd;
+    f.di = -k.scale * sd;
   } else {
-    f.ur = k.eu_re; f.ui = k.eu_im; f.dr = k.ed_re; f.di = k.ed_im;
+    double sn, cs;
+    if constexpr (ANY)
+      sincos_any<1>(V * k.dt, &sn, &cs);
+    else
+      sincos_fast<1>(V * k.dt, &sn, &cs);
+    // (cs - i sn) (x + i y) = (cs x + sn y) + i (cs y - sn x)
+    f.ur = fma(cs, k.eu_re, sn * k.eu_im);
+    f.ui = fma(cs, k.eu_im, -sn * k.eu_re);
+    f.dr = fma(cs, k.ed_re, sn * k.ed_im);
+    f.di = fma(cs, k.ed_im, -sn * k.ed_re);
   }
   return f;
+}
+
+// true if a phase angle of this cell lies outside the fast reduction range
+template <bool TWO>
+__device__ __forceinline__ bool factors_far(double V, const PhaseK& k) {
+  if constexpr (TWO)
+    return far_arg((V + k.mc2) * k.dt) || far_arg((V - k.mc2) * k.dt);
+  else
+    return far_arg(V * k.dt);
+}
+
+__device__ __forceinline__ Factors const_factors(const PhaseK& k) {
+  Factors f;
+  f.ur = k.eu_re; f.ui = k.eu_im; f.dr = k.ed_re; f.di = k.ed_im;
+  return f;
+}
+
+// Generic factors for any mode and argument (same values as the fast path).
+__device__ __forceinline__ Factors phase_factors(double V, const PhaseK& k) {
+  if (k.mode == 2) {
+    if (k.two_angles) return factors_v<true, true>(V, k);
+    return factors_v<false, true>(V, k);
+  }
+  return const_factors(k);
 }
 
 template <typename T>
@@ -283,6 +347,49 @@ template <typename T> __device__ __forceinline__ T scale_of(const PhaseK& k);
 template <> __device__ __forceinline__ float scale_of<float>(const PhaseK& k) { return k.scale_f; }
 template <> __device__ __forceinline__ double scale_of<double>(const PhaseK& k) {
   return static_cast<double>(k.scale_f);
+}
+
+template <typename T>
+__device__ __forceinline__ void scale_site(Site<T>& s, const PhaseK& k) {
+  const T sc = scale_of<T>(k);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) s.v[j] *= sc;
+}
+
+// Local step with the phase mode fixed at compile time (MODE < 0: read it
+// from k at run time); f holds the cell's factors for modes 1 and 2.
+template <int MODE, typename T>
+__device__ __forceinline__ void apply_local(Site<T>& s, const Factors& f, const PhaseK& k) {
+  if constexpr (MODE == 0) {
+    scale_site(s, k);
+  } else if constexpr (MODE > 0) {
+    apply_factors(s, f);
+  } else {
+    if (k.mode == 0)
+      scale_site(s, k);
+    else
+      apply_factors(s, f);
+  }
+}
+
+// Factors of a cell for the given mode, fast path only for mode 2 (callers
+// repair far arguments with factors_fix).
+template <int MODE, bool TWO>
+__device__ __forceinline__ Factors factors_of(double V, const PhaseK& k) {
+  if constexpr (MODE == 2) return factors_v<TWO, false>(V, k);
+  else if constexpr (MODE == 1 || MODE == 0) return const_factors(k);
+  else return (k.mode == 2) ? factors_v<TWO, false>(V, k) : const_factors(k);
+}
+
+// After factors_of: if any lane of the wave had an angle outside the fast
+// range, recompute that wave's factors with the library fallback (the values
+// of in-range lanes are unchanged).  A wave-uniform, rarely taken branch.
+template <int MODE, bool TWO>
+__device__ __forceinline__ void factors_fix(Factors& f, double V, const PhaseK& k) {
+  if constexpr (MODE == 2 || MODE < 0) {
+    const bool need = (MODE == 2 || k.mode == 2) && factors_far<TWO>(V, k);
+    if (__any(need)) f = factors_v<TWO, true>(V, k);
+  }
 }
 
 // Full local step on one site (V ignored unless mode == 2).

@@ -42,8 +42,14 @@ struct ObsArgs {
 // one full step src -> dst; `blocks` 256-thread workgroups
 hipError_t launch_sweep2d(bool fp64, const void* src, void* dst, const double* V,
                           const SweepArgs& a, int blocks, hipStream_t st);
+// two steps src -> dst in one pass (1-D / 2-D), waves of 62 output columns
+hipError_t launch_sweep2d_x2(bool fp64, const void* src, void* dst, const double* V,
+                             const SweepArgs& a, int blocks, hipStream_t st);
 hipError_t launch_sweep3d(bool fp64, const void* src, void* dst, const double* V,
                           const SweepArgs& a, int blocks, hipStream_t st);
+// resident 256-thread blocks per CU of the sweep kernel for this layout and
+// phase mode (0 if the runtime cannot tell)
+int sweep_occupancy(bool fp64, int ndim, int axes_code, int mode, bool x2);
 // nsteps in place in one workgroup of `threads` threads, `spt` cells each
 hipError_t launch_resident1d(bool fp64, int axis, void* psi, const double* V,
                              const ResidentArgs& a, int spt, int threads, hipStream_t st);

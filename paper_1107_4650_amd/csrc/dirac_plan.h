@@ -10,6 +10,11 @@
 
 namespace dirac {
 
+struct PlanTiling {
+  SweepArgs a1{}, a2{};  // one step per launch / two steps per launch
+  int b1 = 0, b2 = 0;    // blocks
+};
+
 struct GraphEntry {
   void* psi;
   const double* V;
@@ -35,7 +40,13 @@ struct dl_plan_s {
   // tiling of the one-pass sweep
   dirac::SweepArgs sweep{};
   int blocks = 0;
-  int waves_per_cu = 8;
+  dirac::SweepArgs sweep2{};   // tiling of the two-steps-per-pass kernel
+  int blocks2 = 0;
+  bool allow_x2 = true;
+  bool x2 = false;
+  int waves_per_cu = 0;        // 0: size the grid from the kernels' occupancy
+  int cu_count = 256;
+  dirac::PlanTiling tiling[3];  // per phase mode
   int seg_override = 0;
   bool allow_resident = true;
   bool resident = false;
@@ -66,7 +77,8 @@ int validate_grid(const dl_grid* g, double dx, double dt, double c, double m, in
 PhaseK make_phase(int ntransports, double dt, double c, double m, int mode, bool two_angles);
 int phase_mode(double m, const double* V);
 int axes_code(const dl_grid& g);
-void make_tiling(const dl_grid& g, int waves_per_cu, int seg_override, SweepArgs& a, int& blocks);
+void make_tiling(const dl_grid& g, int64_t target, int seg_override, SweepArgs& a, int& blocks,
+                 int strip_width);
 int check_live(dl_plan p);
 int check_state_ptr(const void* ptr, const char* name);
 int check_f64_ptr(const void* ptr, const char* name, bool nullable);

@@ -99,14 +99,15 @@ int axes_code(const dl_grid& g) {
   return 210;
 }
 
-// Tiling of the one-pass sweep: strips of 64 x cells, march segments sized so
-// that about `waves_per_cu` waves run per compute unit.
-void make_tiling(const dl_grid& g, int waves_per_cu, int seg_override, SweepArgs& a, int& blocks) {
+// Tiling of the one-pass sweep: strips of `strip_width` x cells, march
+// segments sized so that at most `target` waves (one full round of resident
+// waves) are created, avoiding a partial second round.
+void make_tiling(const dl_grid& g, int64_t target, int seg_override, SweepArgs& a, int& blocks,
+                 int strip_width) {
   a.nx = g.n[0];
   a.ny = g.ndim > 1 ? g.n[1] : 1;
   a.nz = g.ndim > 2 ? g.n[2] : 1;
-  a.nstrips = (a.nx + 63) / 64;
-  const int64_t target = int64_t(256) * waves_per_cu;
+  a.nstrips = (a.nx + strip_width - 1) / strip_width;
   if (g.ndim == 1) {
     a.nseg = 1;
     a.H = 1;
@@ -118,7 +119,7 @@ void make_tiling(const dl_grid& g, int waves_per_cu, int seg_override, SweepArgs
     if (seg_override > 0) {
       H = seg_override;
     } else {
-      int64_t nseg = (target + a.nstrips - 1) / a.nstrips;
+      int64_t nseg = target / a.nstrips;
       if (nseg < 1) nseg = 1;
       H = (ny + nseg - 1) / nseg;
       if (H < 8) H = 8;
@@ -138,7 +139,7 @@ void make_tiling(const dl_grid& g, int waves_per_cu, int seg_override, SweepArgs
   a.axes_code = axes_code(g);
 }
 
-void make_tiling3d(const dl_grid& g, int ty, int waves_per_cu, int seg_override, SweepArgs& a,
+void make_tiling3d(const dl_grid& g, int ty, int64_t target, int seg_override, SweepArgs& a,
                    int& blocks) {
   a.nx = g.n[0];
   a.ny = g.n[1];
@@ -146,12 +147,11 @@ void make_tiling3d(const dl_grid& g, int ty, int waves_per_cu, int seg_override,
   a.nstrips = (a.nx + 63) / 64;
   a.nyblk = (a.ny + ty - 1) / ty;
   const int64_t per_seg = a.nstrips * a.nyblk;
-  const int64_t target = int64_t(256) * waves_per_cu;
   int64_t H;
   if (seg_override > 0) {
     H = seg_override;
   } else {
-    int64_t nseg = (target + per_seg - 1) / per_seg;
+    int64_t nseg = target / per_seg;
     if (nseg < 1) nseg = 1;
     H = (a.nz + nseg - 1) / nseg;
     if (H < 4) H = 4;
@@ -171,14 +171,41 @@ void make_tiling3d(const dl_grid& g, int ty, int waves_per_cu, int seg_override,
 // plan
 // ===========================================================================
 
+// make the tiling of phase mode `mode` current (keeps the phase constants)
+static void select_tiling(dl_plan p, int mode) {
+  const PhaseK ph = p->sweep.ph;
+  const PlanTiling& t = p->tiling[mode < 0 || mode > 2 ? 2 : mode];
+  p->sweep = t.a1;
+  p->blocks = t.b1;
+  p->sweep2 = t.a2;
+  p->blocks2 = t.b2;
+  p->sweep.ph = ph;
+  p->sweep2.ph = ph;
+}
+
+// waves that can be resident at once for the sweep kernel of this plan
+static int64_t resident_waves(dl_plan p, int mode, bool x2) {
+  if (p->waves_per_cu > 0) return int64_t(p->cu_count) * p->waves_per_cu;
+  int occ = p->dry ? 0 : sweep_occupancy(p->fp64, p->g.ndim, axes_code(p->g), mode, x2);
+  if (occ <= 0) occ = 2;
+  return int64_t(occ) * 4 * p->cu_count;
+}
+
 static int plan_tiling(dl_plan p) {
-  if (p->g.ndim == 3) {
-    make_tiling3d(p->g, p->fp64 ? kTY3D_F64 : kTY3D_F32, p->waves_per_cu, p->seg_override,
-                  p->sweep, p->blocks);
-  } else {
-    make_tiling(p->g, p->waves_per_cu, p->seg_override, p->sweep, p->blocks);
+  for (int mode = 0; mode < 3; ++mode) {
+    PlanTiling& t = p->tiling[mode];
+    if (p->g.ndim == 3) {
+      make_tiling3d(p->g, p->fp64 ? kTY3D_F64 : kTY3D_F32, resident_waves(p, mode, false),
+                    p->seg_override, t.a1, t.b1);
+    } else {
+      make_tiling(p->g, resident_waves(p, mode, false), p->seg_override, t.a1, t.b1, 64);
+      make_tiling(p->g, resident_waves(p, mode, true), p->seg_override, t.a2, t.b2, 62);
+    }
+    t.a1.periodic = t.a2.periodic = (p->bc == DL_BC_PERIODIC);
   }
-  p->sweep.periodic = (p->bc == DL_BC_PERIODIC);
+  select_tiling(p, 2);
+  // two steps per pass for 1-D and 2-D grids
+  p->x2 = p->allow_x2 && p->g.ndim <= 2;
   // resident 1-D path: the whole line in one workgroup (4 cells per thread)
   p->resident = false;
   if (p->g.ndim == 1 && p->allow_resident) {
@@ -231,6 +258,11 @@ extern "C" int dl_plan_create(dl_plan* out, const dl_grid* g, double dx, double 
     delete p;
     return hip_fail(e, "hipGetDevice");
   }
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess &&
+      ncu > 0)
+    p->cu_count = ncu;
+  plan_tiling(p);
   if (hipMalloc(&p->tmp, p->state_bytes) != hipSuccess ||
       hipMalloc(&p->partials, sizeof(double) * 2 * 8 * kObsBlocks) != hipSuccess ||
       hipMalloc(&p->dres, sizeof(double) * 64) != hipSuccess ||
@@ -302,12 +334,24 @@ hipError_t sweep_once(dl_plan p, const void* src, void* dst, const double* V, hi
 }
 
 // enqueue `nsteps` steps ping-ponging between psi and the plan's tmp buffer,
-// starting from psi; returns the buffer that holds the result
+// starting from psi (two steps per launch where the plan allows it); returns
+// the buffer that holds the result
 hipError_t enqueue_steps(dl_plan p, void* psi, const double* V, int64_t nsteps, hipStream_t st,
                          void** result) {
   void* a = psi;
   void* b = p->tmp;
-  for (int64_t s = 0; s < nsteps; ++s) {
+  int64_t s = 0;
+  if (p->x2) {
+    p->sweep2.ph = p->sweep.ph;
+    for (; s + 2 <= nsteps; s += 2) {
+      hipError_t e = launch_sweep2d_x2(p->fp64, a, b, V, p->sweep2, p->blocks2, st);
+      if (e != hipSuccess) return e;
+      void* t = a;
+      a = b;
+      b = t;
+    }
+  }
+  for (; s < nsteps; ++s) {
     hipError_t e = sweep_once(p, a, b, V, st);
     if (e != hipSuccess) return e;
     void* t = a;
@@ -363,6 +407,7 @@ extern "C" int dl_step(dl_plan p, void* psi, const double* V, int64_t nsteps, vo
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int mode = phase_mode(p->m, V);
   p->sweep.ph = make_phase(p->g.ndim, p->dt, p->c, p->m, mode, p->fp64);
+  select_tiling(p, mode);
   if (p->resident) {
     ResidentArgs ra{};
     ra.n = p->g.n[0];
@@ -407,7 +452,33 @@ extern "C" int dl_step_out(dl_plan p, const void* src, void* dst, const double* 
     return fail(DL_ERR_ARG, "src and dst overlap");
   hipStream_t st = static_cast<hipStream_t>(stream);
   p->sweep.ph = make_phase(p->g.ndim, p->dt, p->c, p->m, phase_mode(p->m, V), p->fp64);
+  select_tiling(p, p->sweep.ph.mode);
   hipError_t e = sweep_once(p, src, dst, V, st);
+  return e == hipSuccess ? DL_OK : hip_fail(e, "sweep launch");
+}
+
+extern "C" int dl_step_pair_out(dl_plan p, const void* src, void* dst, const double* V,
+                                void* stream) {
+  int rc = check_live(p);
+  if (rc) return rc;
+  if ((rc = check_state_ptr(src, "src"))) return rc;
+  if ((rc = check_state_ptr(dst, "dst"))) return rc;
+  if ((rc = check_f64_ptr(V, "V", true))) return rc;
+  const char* a = static_cast<const char*>(src);
+  const char* b = static_cast<const char*>(dst);
+  if (a < b + p->state_bytes && b < a + p->state_bytes)
+    return fail(DL_ERR_ARG, "src and dst overlap");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  p->sweep.ph = make_phase(p->g.ndim, p->dt, p->c, p->m, phase_mode(p->m, V), p->fp64);
+  select_tiling(p, p->sweep.ph.mode);
+  hipError_t e;
+  if (p->x2) {
+    p->sweep2.ph = p->sweep.ph;
+    e = launch_sweep2d_x2(p->fp64, src, dst, V, p->sweep2, p->blocks2, st);
+  } else {
+    e = sweep_once(p, src, p->tmp, V, st);
+    if (e == hipSuccess) e = sweep_once(p, p->tmp, dst, V, st);
+  }
   return e == hipSuccess ? DL_OK : hip_fail(e, "sweep launch");
 }
 
@@ -446,7 +517,7 @@ extern "C" int dl_version(void) { return LIBDIRAC_VERSION; }
 extern "C" int dl_plan_set_tiling(dl_plan p, int waves_per_cu, int seg_len, int allow_resident,
                                   int graph_pairs) {
   if (!p) return fail(DL_ERR_ARG, "plan is NULL");
-  if (waves_per_cu < 1 || waves_per_cu > 32) return fail(DL_ERR_ARG, "waves_per_cu out of range");
+  if (waves_per_cu < 0 || waves_per_cu > 32) return fail(DL_ERR_ARG, "waves_per_cu out of range");
   if (seg_len < 0 || graph_pairs < 1) return fail(DL_ERR_ARG, "bad seg_len / graph_pairs");
   p->waves_per_cu = waves_per_cu;
   p->seg_override = seg_len;
@@ -456,11 +527,18 @@ extern "C" int dl_plan_set_tiling(dl_plan p, int waves_per_cu, int seg_len, int 
   return plan_tiling(p);
 }
 
+extern "C" int dl_plan_set_x2(dl_plan p, int enable) {
+  if (!p) return fail(DL_ERR_ARG, "plan is NULL");
+  p->allow_x2 = enable != 0;
+  if (!p->dry) p->drop_graphs();
+  return plan_tiling(p);
+}
+
 extern "C" int dl_plan_info(dl_plan p, int64_t* info, int n) {
   if (!p || !info) return fail(DL_ERR_ARG, "NULL argument");
   const int64_t vals[] = {p->blocks,         p->sweep.H,      p->sweep.nseg, p->sweep.nstrips,
                           p->sweep.ntiles,   p->resident,     p->res_threads, p->waves_per_cu,
-                          p->sweep.xcd_remap, p->graph_pairs};
+                          p->sweep.xcd_remap, p->graph_pairs, p->x2,        p->blocks2};
   const int nv = static_cast<int>(sizeof vals / sizeof vals[0]);
   for (int i = 0; i < n && i < nv; ++i) info[i] = vals[i];
   return DL_OK;

@@ -27,7 +27,7 @@
 
 namespace dirac {
 
-template <typename T, int AX0, int AX1>
+template <typename T, int AX0, int AX1, int MODE>
 __global__ __launch_bounds__(256) void k_sweep2d(const T* __restrict__ src, T* __restrict__ dst,
                                                  const double* __restrict__ V, SweepArgs a) {
   const int lane = threadIdx.x & 63;
@@ -39,39 +39,78 @@ __global__ __launch_bounds__(256) void k_sweep2d(const T* __restrict__ src, T* _
   const int64_t seg = tile / a.nstrips;
   const int64_t x0 = strip * 64;
   if constexpr (AX1 < 0) {
-    one_row<T, AX0>(src, dst, V, a, x0, lane);  // 1-D: one row, no march
+    one_row<T, AX0, MODE>(src, dst, V, a, x0, lane);  // 1-D: one row, no march
   } else {
     const int64_t jb = seg * a.H;
     const int64_t je = (jb + a.H < a.ny) ? jb + a.H : a.ny;
     // even segments march up, odd ones down
-    march_dir<T, AX0, AX1>(src, dst, V, a, x0, lane, jb, je, (seg & 1) == 0);
+    march_dir<T, AX0, AX1, MODE>(src, dst, V, a, x0, lane, jb, je, (seg & 1) == 0);
+  }
+}
+
+// two steps per launch (1-D / 2-D): waves of 62 output columns
+template <typename T, int AX0, int AX1, int MODE>
+__global__ __launch_bounds__(256) void k_sweep2d_x2(const T* __restrict__ src,
+                                                    T* __restrict__ dst,
+                                                    const double* __restrict__ V, SweepArgs a) {
+  const int lane = threadIdx.x & 63;
+  int64_t blk = blockIdx.x;
+  if (a.xcd_remap) blk = (blk % 8) * (gridDim.x / 8) + blk / 8;
+  const int64_t tile = blk * 4 + (threadIdx.x >> 6);
+  if (tile >= a.ntiles) return;
+  const int64_t strip = tile % a.nstrips;
+  const int64_t seg = tile / a.nstrips;
+  const int64_t xs = strip * 62 - 1;
+  if constexpr (AX1 < 0) {
+    one_row_x2<T, AX0, MODE>(src, dst, V, a, xs, lane);
+  } else {
+    const int64_t jb = seg * a.H;
+    const int64_t je = (jb + a.H < a.ny) ? jb + a.H : a.ny;
+    march_dir_x2<T, AX0, AX1, MODE>(src, dst, V, a, xs, lane, jb, je, (seg & 1) == 0);
   }
 }
 
 // ---------------------------------------------------------------------------
-// 3-D fused step: march along z, plane tile 64 x TY per wave.
+// 3-D fused step: march along z, plane tile 64 x TY per wave.  The potential
+// of the TY output rows is loaded one plane ahead, so each plane starts with
+// the TY independent phase-factor chains, which run while the plane's rows
+// are still in flight.
 // ---------------------------------------------------------------------------
-template <typename T, int TY, bool UP>
+template <typename T, int TY, bool UP, int MODE>
 __device__ __forceinline__ void march3d(const T* __restrict__ src, T* __restrict__ dst,
                                         const double* __restrict__ V, const SweepArgs& a,
                                         int64_t x0, int lane, int64_t y0, int64_t kb,
                                         int64_t ke) {
+  constexpr bool TWO = sizeof(T) == 8;
   const int64_t nx = a.nx, ny = a.ny, nz = a.nz;
   const int64_t plane_cells = nx * ny;
   const int nit = static_cast<int>(ke - kb) + 2;
   const int64_t x = x0 + lane;
-  const bool use_v = (a.ph.mode == 2);
+  const int64_t xv = x < nx ? x : nx - 1;
+  const bool read_v = (MODE == 2);
+  auto kout_of = [&](int it) -> int64_t { return UP ? kb - 2 + it : ke - it + 1; };
+  auto load_v = [&](int it, double* v) {
+    int64_t k = kout_of(it);
+    k = k < 0 ? 0 : (k >= nz ? nz - 1 : k);
+#pragma unroll
+    for (int t = 0; t < TY; ++t) {
+      const int64_t y = (y0 + t < ny) ? y0 + t : ny - 1;
+      v[t] = read_v ? V[(k * ny + y) * nx + xv] : 0.0;
+    }
+  };
   Mov<T> zs1[TY], zs2[TY];
 #pragma unroll
   for (int t = 0; t < TY; ++t) {
     zero(zs1[t]);
     zero(zs2[t]);
   }
+  double vcur[TY];
+  load_v(0, vcur);
   for (int it = 0; it < nit; ++it) {
     const int64_t kin = UP ? kb - 1 + it : ke - it;
-    const int64_t kout = UP ? kin - 1 : kin + 1;
+    const int64_t kout = kout_of(it);
     const int64_t kr = wrap_or_neg(kin, nz, a.periodic);
-    // load the TY + 2 rows of this plane tile (rows y0-1 .. y0+TY)
+    // loads of this plane tile (rows y0-1 .. y0+TY) and of the next plane's potential
     Row<T> rows[TY + 2];
 #pragma unroll
     for (int t = 0; t < TY + 2; ++t) {
@@ -82,12 +121,13 @@ __device__ __forceinline__ void march3d(const T* __restrict__ src, T* __restrict
         zero(rows[t].h);
       }
     }
-    double vrow[TY];
+    double vnext[TY];
+    load_v(it + 1, vnext);
+    Factors fac[TY];
 #pragma unroll
-    for (int t = 0; t < TY; ++t) {
-      const int64_t y = y0 + t;
-      vrow[t] = (use_v && it >= 2 && x < nx && y < ny) ? V[(kout * ny + y) * nx + x] : 0.0;
-    }
+    for (int t = 0; t < TY; ++t) fac[t] = factors_of<MODE, TWO>(vcur[t], a.ph);
+#pragma unroll
+    for (int t = 0; t < TY; ++t) factors_fix<MODE, TWO>(fac[t], vcur[t], a.ph);
     // x transport of every row, y transport rolling over the rows
     Mov<T> ry1, ry2;
     zero(ry1);
@@ -110,7 +150,7 @@ __device__ __forceinline__ void march3d(const T* __restrict__ src, T* __restrict
             Axis<2, T>::combine(zs2[ty], lz, o);
           else
             Axis<2, T>::combine(rz, zs2[ty], o);
-          local_step(o, vrow[ty], a.ph);
+          apply_local<MODE>(o, fac[ty], a.ph);
           const int64_t y = y0 + ty;
           if (x < nx && y < ny) store_site(dst + ((kout * ny + y) * nx + x) * 8, o);
         }
@@ -120,10 +160,12 @@ __device__ __forceinline__ void march3d(const T* __restrict__ src, T* __restrict
       ry2 = ry1;
       ry1 = ry;
     }
+#pragma unroll
+    for (int t = 0; t < TY; ++t) vcur[t] = vnext[t];
   }
 }
 
-template <typename T, int TY>
+template <typename T, int TY, int MODE>
 __global__ __launch_bounds__(256) void k_sweep3d(const T* __restrict__ src, T* __restrict__ dst,
                                                  const double* __restrict__ V, SweepArgs a) {
   const int lane = threadIdx.x & 63;
@@ -140,9 +182,9 @@ __global__ __launch_bounds__(256) void k_sweep3d(const T* __restrict__ src, T* _
   const int64_t kb = seg * a.H;
   const int64_t ke = (kb + a.H < a.nz) ? kb + a.H : a.nz;
   if (seg & 1)
-    march3d<T, TY, false>(src, dst, V, a, x0, lane, y0, kb, ke);
+    march3d<T, TY, false, MODE>(src, dst, V, a, x0, lane, y0, kb, ke);
   else
-    march3d<T, TY, true>(src, dst, V, a, x0, lane, y0, kb, ke);
+    march3d<T, TY, true, MODE>(src, dst, V, a, x0, lane, y0, kb, ke);
 }
 
 // ---------------------------------------------------------------------------
@@ -222,25 +264,134 @@ __global__ __launch_bounds__(1024) void k_resident1d(T* __restrict__ psi,
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-template <typename T, int AX0, int AX1>
+template <typename T, int AX0, int AX1, int MODE>
 static hipError_t launch2d_t(const T* src, T* dst, const double* V, const SweepArgs& a,
                              int blocks, hipStream_t st) {
-  hipLaunchKernelGGL((k_sweep2d<T, AX0, AX1>), dim3(blocks), dim3(256), 0, st, src, dst, V, a);
+  hipLaunchKernelGGL((k_sweep2d<T, AX0, AX1, MODE>), dim3(blocks), dim3(256), 0, st, src, dst, V,
+                     a);
   return hipGetLastError();
+}
+
+template <typename T, int AX0, int AX1>
+static hipError_t launch2d_mode(const T* src, T* dst, const double* V, const SweepArgs& a,
+                                int blocks, hipStream_t st) {
+  switch (a.ph.mode) {
+    case 0: return launch2d_t<T, AX0, AX1, 0>(src, dst, V, a, blocks, st);
+    case 1: return launch2d_t<T, AX0, AX1, 1>(src, dst, V, a, blocks, st);
+    default: return launch2d_t<T, AX0, AX1, 2>(src, dst, V, a, blocks, st);
+  }
 }
 
 template <typename T>
 static hipError_t launch2d_axes(const T* src, T* dst, const double* V, const SweepArgs& a,
                                 int blocks, hipStream_t st) {
   switch (a.axes_code) {
-    case 0: return launch2d_t<T, 0, -1>(src, dst, V, a, blocks, st);
-    case 1: return launch2d_t<T, 1, -1>(src, dst, V, a, blocks, st);
-    case 2: return launch2d_t<T, 2, -1>(src, dst, V, a, blocks, st);
-    case 10: return launch2d_t<T, 0, 1>(src, dst, V, a, blocks, st);
-    case 20: return launch2d_t<T, 0, 2>(src, dst, V, a, blocks, st);
-    case 21: return launch2d_t<T, 1, 2>(src, dst, V, a, blocks, st);
+    case 0: return launch2d_mode<T, 0, -1>(src, dst, V, a, blocks, st);
+    case 1: return launch2d_mode<T, 1, -1>(src, dst, V, a, blocks, st);
+    case 2: return launch2d_mode<T, 2, -1>(src, dst, V, a, blocks, st);
+    case 10: return launch2d_mode<T, 0, 1>(src, dst, V, a, blocks, st);
+    case 20: return launch2d_mode<T, 0, 2>(src, dst, V, a, blocks, st);
+    case 21: return launch2d_mode<T, 1, 2>(src, dst, V, a, blocks, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+template <typename T, int AX0, int AX1, int MODE>
+static hipError_t launch2x_t(const T* src, T* dst, const double* V, const SweepArgs& a,
+                             int blocks, hipStream_t st) {
+  hipLaunchKernelGGL((k_sweep2d_x2<T, AX0, AX1, MODE>), dim3(blocks), dim3(256), 0, st, src, dst,
+                     V, a);
+  return hipGetLastError();
+}
+
+template <typename T, int AX0, int AX1>
+static hipError_t launch2x_mode(const T* src, T* dst, const double* V, const SweepArgs& a,
+                                int blocks, hipStream_t st) {
+  switch (a.ph.mode) {
+    case 0: return launch2x_t<T, AX0, AX1, 0>(src, dst, V, a, blocks, st);
+    case 1: return launch2x_t<T, AX0, AX1, 1>(src, dst, V, a, blocks, st);
+    default: return launch2x_t<T, AX0, AX1, 2>(src, dst, V, a, blocks, st);
+  }
+}
+
+template <typename T>
+static hipError_t launch2x_axes(const T* src, T* dst, const double* V, const SweepArgs& a,
+                                int blocks, hipStream_t st) {
+  switch (a.axes_code) {
+    case 0: return launch2x_mode<T, 0, -1>(src, dst, V, a, blocks, st);
+    case 1: return launch2x_mode<T, 1, -1>(src, dst, V, a, blocks, st);
+    case 2: return launch2x_mode<T, 2, -1>(src, dst, V, a, blocks, st);
+    case 10: return launch2x_mode<T, 0, 1>(src, dst, V, a, blocks, st);
+    case 20: return launch2x_mode<T, 0, 2>(src, dst, V, a, blocks, st);
+    case 21: return launch2x_mode<T, 1, 2>(src, dst, V, a, blocks, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// ---- occupancy queries (resident 256-thread blocks per CU) -------------------
+template <typename K>
+static int occ_of(K kernel) {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(kernel), 256,
+                                                   0) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return n;
+}
+
+template <typename T, int AX0, int AX1, int MODE>
+static int occ2d_t(bool x2) {
+  return x2 ? occ_of(&k_sweep2d_x2<T, AX0, AX1, MODE>) : occ_of(&k_sweep2d<T, AX0, AX1, MODE>);
+}
+
+template <typename T, int AX0, int AX1>
+static int occ2d_mode(int mode, bool x2) {
+  switch (mode) {
+    case 0: return occ2d_t<T, AX0, AX1, 0>(x2);
+    case 1: return occ2d_t<T, AX0, AX1, 1>(x2);
+    default: return occ2d_t<T, AX0, AX1, 2>(x2);
+  }
+}
+
+template <typename T>
+static int occ2d_axes(int axes_code, int mode, bool x2) {
+  switch (axes_code) {
+    case 0: return occ2d_mode<T, 0, -1>(mode, x2);
+    case 1: return occ2d_mode<T, 1, -1>(mode, x2);
+    case 2: return occ2d_mode<T, 2, -1>(mode, x2);
+    case 10: return occ2d_mode<T, 0, 1>(mode, x2);
+    case 20: return occ2d_mode<T, 0, 2>(mode, x2);
+    case 21: return occ2d_mode<T, 1, 2>(mode, x2);
+    default: return 0;
+  }
+}
+
+int sweep_occupancy(bool fp64, int ndim, int axes_code, int mode, bool x2) {
+  if (ndim == 3) {
+    if (fp64) {
+      switch (mode) {
+        case 0: return occ_of(&k_sweep3d<double, kTY3D_F64, 0>);
+        case 1: return occ_of(&k_sweep3d<double, kTY3D_F64, 1>);
+        default: return occ_of(&k_sweep3d<double, kTY3D_F64, 2>);
+      }
+    }
+    switch (mode) {
+      case 0: return occ_of(&k_sweep3d<float, kTY3D_F32, 0>);
+      case 1: return occ_of(&k_sweep3d<float, kTY3D_F32, 1>);
+      default: return occ_of(&k_sweep3d<float, kTY3D_F32, 2>);
+    }
+  }
+  return fp64 ? occ2d_axes<double>(axes_code, mode, x2) : occ2d_axes<float>(axes_code, mode, x2);
+}
+
+hipError_t launch_sweep2d_x2(bool fp64, const void* src, void* dst, const double* V,
+                             const SweepArgs& a, int blocks, hipStream_t st) {
+  if (fp64)
+    return launch2x_axes<double>(static_cast<const double*>(src), static_cast<double*>(dst), V,
+                                 a, blocks, st);
+  return launch2x_axes<float>(static_cast<const float*>(src), static_cast<float*>(dst), V, a,
+                              blocks, st);
 }
 
 hipError_t launch_sweep2d(bool fp64, const void* src, void* dst, const double* V,
@@ -252,16 +403,29 @@ hipError_t launch_sweep2d(bool fp64, const void* src, void* dst, const double* V
                               blocks, st);
 }
 
-hipError_t launch_sweep3d(bool fp64, const void* src, void* dst, const double* V,
-                          const SweepArgs& a, int blocks, hipStream_t st) {
-  if (fp64) {
-    hipLaunchKernelGGL((k_sweep3d<double, kTY3D_F64>), dim3(blocks), dim3(256), 0, st,
-                       static_cast<const double*>(src), static_cast<double*>(dst), V, a);
-  } else {
-    hipLaunchKernelGGL((k_sweep3d<float, kTY3D_F32>), dim3(blocks), dim3(256), 0, st,
-                       static_cast<const float*>(src), static_cast<float*>(dst), V, a);
+template <typename T, int TY>
+static hipError_t launch3d_t(const void* src, void* dst, const double* V, const SweepArgs& a,
+                             int blocks, hipStream_t st) {
+  const T* s = static_cast<const T*>(src);
+  T* d = static_cast<T*>(dst);
+  switch (a.ph.mode) {
+    case 0:
+      hipLaunchKernelGGL((k_sweep3d<T, TY, 0>), dim3(blocks), dim3(256), 0, st, s, d, V, a);
+      break;
+    case 1:
+      hipLaunchKernelGGL((k_sweep3d<T, TY, 1>), dim3(blocks), dim3(256), 0, st, s, d, V, a);
+      break;
+    default:
+      hipLaunchKernelGGL((k_sweep3d<T, TY, 2>), dim3(blocks), dim3(256), 0, st, s, d, V, a);
+      break;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_sweep3d(bool fp64, const void* src, void* dst, const double* V,
+                          const SweepArgs& a, int blocks, hipStream_t st) {
+  if (fp64) return launch3d_t<double, kTY3D_F64>(src, dst, V, a, blocks, st);
+  return launch3d_t<float, kTY3D_F32>(src, dst, V, a, blocks, st);
 }
 
 template <typename T, int AX, int SPT>

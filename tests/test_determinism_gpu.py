@@ -66,3 +66,40 @@ def test_graph_replay_and_resume(dtype):
     assert same_bits(eager, chunked)
     split = gpu_step(psi, V, nsteps=0, chunks=[75, 75], **kw)
     assert same_bits(eager, split)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("shape,axes,bc", [((300, 260), (0, 1), "zero"), ((130, 45), (0, 2), "periodic"),
+                                           ((5000,), (1,), "zero"), ((4099,), (0,), "periodic"),
+                                           ((63, 70), (1, 2), "periodic"), ((62, 9), (0, 1), "zero")])
+def test_two_steps_per_pass_same_bits(dtype, shape, axes, bc):
+    """The fused two-step pass gives the bits of two single steps (odd and even
+    counts, tilings, walls and wrap-around)."""
+    announce(f"two steps per pass {shape} {axes} {bc} {dtype}")
+    psi = random_spinor(shape[::-1], seed=21)
+    V = _V(shape, seed=22)
+    kw = dict(dx=DX, dt=DT, c=C, m=1.0, axes=axes, bc=bc, dtype=dtype,
+              tiling={"allow_resident": False})
+    for n in (1, 2, 7, 20):
+        single = gpu_step(psi, V, nsteps=n, x2=False, **kw)
+        fused = gpu_step(psi, V, nsteps=n, x2=True, **kw)
+        assert same_bits(single, fused), n
+    massless = gpu_step(psi, None, nsteps=9, x2=True, **{**kw, "m": 0.0})
+    assert same_bits(massless, gpu_step(psi, None, nsteps=9, x2=False, **{**kw, "m": 0.0}))
+
+
+def test_step_pair_out_matches_two_single_steps():
+    import torch
+    from paper_1107_4650_amd import libdirac as L
+    announce("step_pair_out")
+    shape = (257, 130)
+    psi = random_spinor(shape[::-1], seed=5).astype(np.complex64)
+    V = torch.from_numpy(_V(shape)).to("cuda")
+    with L.Plan(shape, DX, DT, C, 1.0, dtype="c64") as p:
+        a = torch.from_numpy(psi).to("cuda")
+        b, c2, d = torch.empty_like(a), torch.empty_like(a), torch.empty_like(a)
+        p.step_out(a, b, V)
+        p.step_out(b, c2, V)
+        p.step_pair_out(a, d, V)
+        torch.cuda.synchronize()
+    assert same_bits(c2.cpu().numpy(), d.cpu().numpy())
