@@ -41,24 +41,29 @@ def log(msg):
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("dirac_device.h", "dirac_sweep.hip", "dirac_launch.h"):
+    for f in ("dirac_device.h", "dirac_sweep_impl.h", "dirac_sweep.hip", "dirac_launch.h"):
         with open(os.path.join(ROOT, "paper_1107_4650_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def timed_sweep(plan, psi, V, steps, warmup, pair=False):
-    """Alternate psi <-> tmp with dl_step_out (one step per launch) or
-    dl_step_pair_out (two fused steps per launch); HIP events around every
-    launch on the launch stream.  `steps` counts time steps.  Returns (wall
-    seconds, mean per-launch ms, final tensor)."""
+def timed_sweep(plan, psi, V, steps, warmup, fused=1):
+    """Alternate psi <-> tmp with passes of `fused` steps each (dl_step_out for
+    one step, dl_step_fused_out otherwise: one launch per pass within the
+    plan's depth); HIP events around every launch on the launch stream.
+    `steps` counts time steps and is rounded down to whole passes.  Returns
+    (wall seconds, mean per-launch ms, final tensor, steps timed)."""
     import torch
-    per_launch = 2 if pair else 1
-    launch = plan.step_pair_out if pair else plan.step_out
-    nl, nw = max(1, steps // per_launch), max(0, warmup // per_launch)
+    if fused == 1:
+        def launch(a, b):
+            plan.step_out(a, b, V)
+    else:
+        def launch(a, b):
+            plan.step_fused_out(a, b, V, fused)
+    nl, nw = max(1, steps // fused), max(0, warmup // fused)
     a, b = psi, torch.empty_like(psi)
     for _ in range(nw):
-        launch(a, b, V)
+        launch(a, b)
         a, b = b, a
     torch.cuda.synchronize()
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(nl)]
@@ -66,13 +71,13 @@ def timed_sweep(plan, psi, V, steps, warmup, pair=False):
     t0 = time.perf_counter()
     for i in range(nl):
         starts[i].record()
-        launch(a, b, V)
+        launch(a, b)
         ends[i].record()
         a, b = b, a
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     per = float(np.mean([s.elapsed_time(e) for s, e in zip(starts, ends)]))
-    return wall, per, a
+    return wall, per, a, nl * fused
 
 
 def to_dev(x, dtype=None):
@@ -116,38 +121,43 @@ def bench_main(args):
 
     # ---- FP32 storage (headline) -------------------------------------------
     with L.Plan(w.shape, w.dx, w.dt, w.c, w.m, dtype="c64", xmin=w.xmin) as p32:
+        d32 = p32.info()["depth"]
         psi32 = to_dev(w.psi0, torch.complex64)
-        wall32, per32, out32 = timed_sweep(p32, psi32, V, args.steps, args.warmup, pair=True)
+        wall32, per32, out32, n32 = timed_sweep(p32, psi32, V, args.steps, args.warmup, d32)
         info = p32.info()
         obs32 = p32.observables(out32, 0.0)
     res["fp32"] = dict(wall=wall32, per_launch_ms=per32)
-    log(f"fp32: {wall32 * 1e3 / args.steps:.4f} ms/step wall, {per32:.4f} ms per two-step launch")
+    log(f"fp32: {wall32 * 1e3 / n32:.4f} ms/step wall, {per32:.4f} ms per {d32}-step launch")
     if args.only == "sweep":
         return None
 
     # ---- FP64 path on the same steps (also the reference for the FP32 error) -
     with L.Plan(w.shape, w.dx, w.dt, w.c, w.m, dtype="c128", xmin=w.xmin) as p64:
+        d64 = p64.info()["depth"]
         psi64 = to_dev(w.psi0)
-        wall64, per64, out64 = timed_sweep(p64, psi64, V, args.steps, args.warmup, pair=True)
+        wall64, per64, out64, n64 = timed_sweep(p64, psi64, V, n32, args.warmup - args.warmup % d32,
+                                                d64)
         obs64 = p64.observables(out64, 0.0)
-    # both runs advanced warmup + steps steps from the same initial state
+    # both runs advanced the same number of steps from the same initial state
+    assert n64 == n32, (n64, n32)
     err = rel_l2(out32, out64)
-    log(f"fp64: {wall64 * 1e3 / args.steps:.4f} ms/step wall; fp32 vs fp64 rel-L2 {err:.3e}")
+    log(f"fp64: {wall64 * 1e3 / n64:.4f} ms/step wall; fp32 vs fp64 rel-L2 {err:.3e}")
     del psi32, psi64, out32, out64
     torch.cuda.empty_cache()
 
-    # one launch advances every cell two steps, reading psi and V once and
-    # writing psi once: 72 B per cell per launch, 36 B per site-update
+    # one launch advances every cell d32 steps, reading psi and V once and
+    # writing psi once: 72 B per cell per launch, 72 / d32 B per site-update
     achieved = BYTES_F32 * sites / (per32 * 1e-3) / 1e9
-    traffic = load_traffic("sweep2d_x2_f32_2048")
+    kname = f"sweep2d_d{d32}_f32_2048"
+    traffic = load_traffic(kname)
     line = {
         "metric": METRIC,
-        "value": sites * args.steps / wall32,
+        "value": sites * n32 / wall32,
         "unit": "site-updates/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": wall32 * 1e3 / args.steps,
+        "steps": n32,
+        "warmup": args.warmup - args.warmup % d32,
+        "ms_per_step": wall32 * 1e3 / n32,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -156,21 +166,21 @@ def bench_main(args):
         "config": {"workload": "2-D Dirac, 2048x2048 cells, tanh step V0*tanh(x/0.1), "
                                "Gaussian packet sigma 1.5 p0=(40,0), complex64 state, FP64 V "
                                "and phases, dx=0.01, c*dt=dx, zero walls",
-                   "grid": [2048, 2048], "steps_per_launch": 2,
+                   "grid": [2048, 2048], "steps_per_launch": d32,
                    "tiling": info},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
-                     "kernel": "k_sweep2d_x2<float,0,1,2>",
+                     "kernel": f"k_sweep2d<float,{d32},0,1,2>",
                      "bytes_per_launch_per_cell": BYTES_F32,
-                     "bytes_per_site_update": BYTES_F32 / 2,
-                     "per_launch_ms": per32, "site_updates_per_launch": 2 * sites},
-        "fp64": {"value": sites * args.steps / wall64, "unit": "site-updates/s",
-                 "ms_per_step": wall64 * 1e3 / args.steps, "per_launch_ms": per64,
-                 "per_launch_ms_two_steps": per64,
+                     "bytes_per_site_update": BYTES_F32 / d32,
+                     "per_launch_ms": per32, "site_updates_per_launch": d32 * sites},
+        "fp64": {"value": sites * n64 / wall64, "unit": "site-updates/s",
+                 "ms_per_step": wall64 * 1e3 / n64, "per_launch_ms": per64,
+                 "steps_per_launch": d64,
                  "roofline_frac": BYTES_F64 * sites / (per64 * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "fp32_vs_fp64_rel_l2": err,
-        "fp32_vs_fp64_steps": args.steps + args.warmup,
+        "fp32_vs_fp64_steps": n32 + args.warmup - args.warmup % d32,
         "norm_fp32": obs32[0], "norm_fp64": obs64[0],
     }
     return line
@@ -234,7 +244,7 @@ def bench_3d(args):
         psi = (f[..., None] * u).to(tdt).contiguous()
         del f
         with L.Plan((n, n, n), dx, dx / c, c, m, dtype=str(tdt).split(".")[1]) as p:
-            wall, per, _ = timed_sweep(p, psi, V, steps, 2)
+            wall, per, _, steps = timed_sweep(p, psi, V, steps, 2)
         sites = n ** 3
         out[dt_name] = {"steps": steps, "ms_per_step": wall * 1e3 / steps, "per_launch_ms": per,
                         "site_updates_per_s": sites * steps / wall,

@@ -96,20 +96,23 @@ int dl_plan_destroy(dl_plan p);
  * exp(-i theta) is formed from the FP64 V and applied in FP64, then rounded
  * once to FP32.  nsteps = 0 is a no-op. */
 int dl_step(dl_plan p, void *psi, const double *V, int64_t nsteps, void *stream);
-/* (1-D and 2-D grids advance two steps per pass over memory; an odd count ends
- * with one single step.  The bits do not depend on this grouping.) */
+/* (1-D and 2-D grids fuse several steps into one pass over memory: up to 5
+ * with complex64 state, 2 with complex128, fewer on periodic 2-D boxes of
+ * fewer than twice that many rows; the remainder of nsteps runs in
+ * shallower passes.  The bits do not depend on this grouping.) */
 
 /* One step out of place: dst = S src (same step as dl_step with nsteps = 1).
  * src and dst must not overlap; src is left unchanged.  Lets a caller keep
  * both time levels, or alternate two buffers without the copy dl_step makes
- * for an odd number of steps. */
+ * when its passes end in the plan's buffer. */
 int dl_step_out(dl_plan p, const void *src, void *dst, const double *V, void *stream);
 
-/* Two steps out of place, dst = S S src, in one pass over memory where the
- * grid allows it (1-D and 2-D: the two steps are fused, with the same bits as
- * two single steps); 3-D grids use two launches through the plan's buffer.
- * src and dst must not overlap. */
-int dl_step_pair_out(dl_plan p, const void *src, void *dst, const double *V, void *stream);
+/* nsteps >= 1 steps out of place, dst = S^nsteps src, with the same bits as
+ * nsteps single steps.  Up to the plan's fusion depth (see dl_step) this is
+ * one pass over memory; larger counts run several passes through the plan's
+ * buffer, the last one writing dst.  src and dst must not overlap. */
+int dl_step_fused_out(dl_plan p, const void *src, void *dst, const double *V, int64_t nsteps,
+                      void *stream);
 
 /* Observables of psi (Sec. 5.2.1 R/T integrals on the cell grid), as FP64
  * compensated sums, written to the HOST array out[5]:

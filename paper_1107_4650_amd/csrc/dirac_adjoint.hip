@@ -202,7 +202,7 @@ __global__ __launch_bounds__(256) void k_reverse(T* __restrict__ psi_out, T* __r
   const int lane = threadIdx.x & 63;
   int64_t blk = blockIdx.x;
   if (a.xcd_remap) blk = (blk % 8) * (gridDim.x / 8) + blk / 8;
-  const int64_t tile = blk * 4 + (threadIdx.x >> 6);
+  const int64_t tile = blk * 4 + wave_in_block();
   if (tile >= a.ntiles) return;
   const int64_t strip = tile % a.nstrips;
   const int64_t seg = tile / a.nstrips;

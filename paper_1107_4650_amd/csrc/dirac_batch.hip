@@ -1,11 +1,11 @@
 // dirac_batch.hip -- many independent 1-D / 2-D instances advanced together.
 //
 // One launch performs one time step of every active instance: the grid is a
-// flat table of tiles (instance, 64-cell strip, march segment), ordered
+// flat table of tiles (instance, 62-cell strip, march segment), ordered
 // longest first (2-D segments of H rows before single 1-D rows) so that the
 // workgroup dispatcher's in-order assignment is a longest-processing-time
 // list schedule.  Each tile runs exactly the per-cell code of the single-plan
-// sweep (load_row / x transport / y march / local step), so every instance
+// sweep (x transport / y march / local step), so every instance
 // ends bit-identical to dl_step on its own plan.  Consecutive steps are
 // ordered by the launch boundary (no cross-workgroup waits inside a kernel);
 // long runs are replayed from a captured hipGraph.  The segment length is
@@ -63,15 +63,15 @@ __global__ __launch_bounds__(256) void k_batch(const BatchInst* __restrict__ ins
   a.nz = 1;
   a.periodic = I.periodic;
   a.ph = I.ph;
-  const int64_t x0 = static_cast<int64_t>(t.strip) * 64;
+  const int64_t x0 = static_cast<int64_t>(t.strip) * strip_width(1) - 1;  // lanes 1 .. 62 written
   const bool up = t.up != 0;
   switch (I.axes_code) {
-    case 0: one_row<T, 0, -1>(src, dst, I.V, a, x0, lane); break;
-    case 1: one_row<T, 1, -1>(src, dst, I.V, a, x0, lane); break;
-    case 2: one_row<T, 2, -1>(src, dst, I.V, a, x0, lane); break;
-    case 10: march_dir<T, 0, 1, -1>(src, dst, I.V, a, x0, lane, t.jb, t.je, up); break;
-    case 20: march_dir<T, 0, 2, -1>(src, dst, I.V, a, x0, lane, t.jb, t.je, up); break;
-    case 21: march_dir<T, 1, 2, -1>(src, dst, I.V, a, x0, lane, t.jb, t.je, up); break;
+    case 0: one_row<T, 1, 0, -1>(src, dst, I.V, a, x0, lane); break;
+    case 1: one_row<T, 1, 1, -1>(src, dst, I.V, a, x0, lane); break;
+    case 2: one_row<T, 1, 2, -1>(src, dst, I.V, a, x0, lane); break;
+    case 10: march_dir<T, 1, 0, 1, -1>(src, dst, I.V, a, x0, lane, t.jb, t.je, up); break;
+    case 20: march_dir<T, 1, 0, 2, -1>(src, dst, I.V, a, x0, lane, t.jb, t.je, up); break;
+    case 21: march_dir<T, 1, 1, 2, -1>(src, dst, I.V, a, x0, lane, t.jb, t.je, up); break;
     default: break;
   }
 }
@@ -118,7 +118,7 @@ std::vector<BatchTile> make_tiles(const Batch& B) {
   std::vector<BatchTile> two, one;
   for (int k = 0; k < B.count; ++k) {
     const dl_grid& g = B.grids[k];
-    const int64_t nstrips = (g.n[0] + 63) / 64;
+    const int64_t nstrips = (g.n[0] + strip_width(1) - 1) / strip_width(1);
     if (g.ndim == 1) {
       for (int64_t s = 0; s < nstrips; ++s)
         one.push_back(BatchTile{k, static_cast<int>(s), 0, 1, 1});

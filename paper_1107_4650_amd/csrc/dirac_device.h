@@ -22,6 +22,12 @@
 
 namespace dirac {
 
+// index of this wave in its workgroup, as a wave-uniform (scalar) value, so
+// that everything derived from it (tile, rows, addresses) stays in SGPRs
+__device__ __forceinline__ int wave_in_block() {
+  return __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+}
+
 template <typename T> struct Site { T v[8]; };
 template <typename T> struct Mov { T v[4]; };  // two complex numbers
 
@@ -86,6 +92,31 @@ __device__ __forceinline__ double dpp_from_right(double old, double v) {
   int2 r;
   r.x = __builtin_amdgcn_update_dpp(o.x, s.x, 0x130, 0xf, 0xf, false);
   r.y = __builtin_amdgcn_update_dpp(o.y, s.y, 0x130, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, r);
+}
+
+// Same shifts with zero fill: the lane without a source receives 0, and no
+// old value is needed, so the shift can fold into the instruction using it.
+__device__ __forceinline__ float dpp_from_left_zero(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+      0, __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float dpp_from_right_zero(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+      0, __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, true));
+}
+__device__ __forceinline__ double dpp_from_left_zero(double v) {
+  const int2 s = __builtin_bit_cast(int2, v);
+  int2 r;
+  r.x = __builtin_amdgcn_update_dpp(0, s.x, 0x138, 0xf, 0xf, true);
+  r.y = __builtin_amdgcn_update_dpp(0, s.y, 0x138, 0xf, 0xf, true);
+  return __builtin_bit_cast(double, r);
+}
+__device__ __forceinline__ double dpp_from_right_zero(double v) {
+  const int2 s = __builtin_bit_cast(int2, v);
+  int2 r;
+  r.x = __builtin_amdgcn_update_dpp(0, s.x, 0x130, 0xf, 0xf, true);
+  r.y = __builtin_amdgcn_update_dpp(0, s.y, 0x130, 0xf, 0xf, true);
   return __builtin_bit_cast(double, r);
 }
 

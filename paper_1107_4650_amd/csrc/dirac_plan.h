@@ -11,8 +11,8 @@
 namespace dirac {
 
 struct PlanTiling {
-  SweepArgs a1{}, a2{};  // one step per launch / two steps per launch
-  int b1 = 0, b2 = 0;    // blocks
+  SweepArgs a[kMaxDepth]{};  // index depth - 1 (3-D grids: depth 1 only)
+  int b[kMaxDepth] = {};     // blocks
 };
 
 struct GraphEntry {
@@ -37,13 +37,13 @@ struct dl_plan_s {
   int64_t cells = 0;
   size_t state_bytes = 0;
   int device = 0;
-  // tiling of the one-pass sweep
-  dirac::SweepArgs sweep{};
-  int blocks = 0;
-  dirac::SweepArgs sweep2{};   // tiling of the two-steps-per-pass kernel
-  int blocks2 = 0;
-  bool allow_x2 = true;
-  bool x2 = false;
+  dirac::PhaseK ph{};          // phase constants of the current call
+  // tilings of the passes of 1 .. kMaxDepth fused steps (index depth - 1),
+  // for the phase mode of the current call
+  dirac::SweepArgs sw[dirac::kMaxDepth]{};
+  int bl[dirac::kMaxDepth] = {};
+  int depth_limit = dirac::kMaxDepth;  // caller's cap on fused steps per pass
+  int depth = 1;                        // fused steps per pass in use
   int waves_per_cu = 0;        // 0: size the grid from the kernels' occupancy
   int cu_count = 256;
   dirac::PlanTiling tiling[3];  // per phase mode

@@ -3,6 +3,7 @@
 // arguments, owns the scratch memory and sequences kernel launches.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -171,41 +172,47 @@ void make_tiling3d(const dl_grid& g, int ty, int64_t target, int seg_override, S
 // plan
 // ===========================================================================
 
-// make the tiling of phase mode `mode` current (keeps the phase constants)
+// make the tilings of phase mode `mode` current
 static void select_tiling(dl_plan p, int mode) {
-  const PhaseK ph = p->sweep.ph;
   const PlanTiling& t = p->tiling[mode < 0 || mode > 2 ? 2 : mode];
-  p->sweep = t.a1;
-  p->blocks = t.b1;
-  p->sweep2 = t.a2;
-  p->blocks2 = t.b2;
-  p->sweep.ph = ph;
-  p->sweep2.ph = ph;
+  for (int d = 0; d < kMaxDepth; ++d) {
+    p->sw[d] = t.a[d];
+    p->bl[d] = t.b[d];
+  }
 }
 
 // waves that can be resident at once for the sweep kernel of this plan
-static int64_t resident_waves(dl_plan p, int mode, bool x2) {
+static int64_t resident_waves(dl_plan p, int mode, int depth) {
   if (p->waves_per_cu > 0) return int64_t(p->cu_count) * p->waves_per_cu;
-  int occ = p->dry ? 0 : sweep_occupancy(p->fp64, p->g.ndim, axes_code(p->g), mode, x2);
+  int occ = p->dry ? 0 : sweep_occupancy(p->fp64, p->g.ndim, axes_code(p->g), mode, depth);
   if (occ <= 0) occ = 2;
   return int64_t(occ) * 4 * p->cu_count;
 }
 
 static int plan_tiling(dl_plan p) {
+  // fused steps per pass: 1-D and 2-D grids only; a periodic 2-D pass reaches
+  // `depth` rows beyond a segment on each side and wraps once, so the box
+  // needs at least 2 * depth rows
+  int depth = 1;
+  if (p->g.ndim <= 2) {
+    depth = std::min(p->depth_limit, max_depth(p->fp64));
+    if (p->g.ndim == 2 && p->bc == DL_BC_PERIODIC)
+      while (depth > 1 && p->g.n[1] < 2 * depth) --depth;
+  }
+  p->depth = depth;
   for (int mode = 0; mode < 3; ++mode) {
     PlanTiling& t = p->tiling[mode];
     if (p->g.ndim == 3) {
-      make_tiling3d(p->g, p->fp64 ? kTY3D_F64 : kTY3D_F32, resident_waves(p, mode, false),
-                    p->seg_override, t.a1, t.b1);
+      make_tiling3d(p->g, p->fp64 ? kTY3D_F64 : kTY3D_F32, resident_waves(p, mode, 1),
+                    p->seg_override, t.a[0], t.b[0]);
     } else {
-      make_tiling(p->g, resident_waves(p, mode, false), p->seg_override, t.a1, t.b1, 64);
-      make_tiling(p->g, resident_waves(p, mode, true), p->seg_override, t.a2, t.b2, 62);
+      for (int d = 1; d <= depth; ++d)
+        make_tiling(p->g, resident_waves(p, mode, d), p->seg_override, t.a[d - 1], t.b[d - 1],
+                    strip_width(d));
     }
-    t.a1.periodic = t.a2.periodic = (p->bc == DL_BC_PERIODIC);
+    for (int d = 0; d < kMaxDepth; ++d) t.a[d].periodic = (p->bc == DL_BC_PERIODIC);
   }
   select_tiling(p, 2);
-  // two steps per pass for 1-D and 2-D grids
-  p->x2 = p->allow_x2 && p->g.ndim <= 2;
   // resident 1-D path: the whole line in one workgroup (4 cells per thread)
   p->resident = false;
   if (p->g.ndim == 1 && p->allow_resident) {
@@ -327,36 +334,35 @@ int check_f64_ptr(const void* ptr, const char* name, bool nullable) {
   return DL_OK;
 }
 
-// one full step src -> dst
-hipError_t sweep_once(dl_plan p, const void* src, void* dst, const double* V, hipStream_t st) {
-  if (p->g.ndim == 3) return launch_sweep3d(p->fp64, src, dst, V, p->sweep, p->blocks, st);
-  return launch_sweep2d(p->fp64, src, dst, V, p->sweep, p->blocks, st);
+// one pass of `depth` fused steps src -> dst with the current phase and tiling
+hipError_t launch_pass(dl_plan p, int depth, const void* src, void* dst, const double* V,
+                       hipStream_t st) {
+  if (p->g.ndim == 3) {
+    SweepArgs a = p->sw[0];
+    a.ph = p->ph;
+    return launch_sweep3d(p->fp64, src, dst, V, a, p->bl[0], st);
+  }
+  SweepArgs a = p->sw[depth - 1];
+  a.ph = p->ph;
+  return launch_sweep2d(p->fp64, depth, src, dst, V, a, p->bl[depth - 1], st);
 }
 
 // enqueue `nsteps` steps ping-ponging between psi and the plan's tmp buffer,
-// starting from psi (two steps per launch where the plan allows it); returns
-// the buffer that holds the result
+// starting from psi, in passes of the plan's depth (the remainder in
+// shallower passes); returns the buffer that holds the result
 hipError_t enqueue_steps(dl_plan p, void* psi, const double* V, int64_t nsteps, hipStream_t st,
                          void** result) {
   void* a = psi;
   void* b = p->tmp;
-  int64_t s = 0;
-  if (p->x2) {
-    p->sweep2.ph = p->sweep.ph;
-    for (; s + 2 <= nsteps; s += 2) {
-      hipError_t e = launch_sweep2d_x2(p->fp64, a, b, V, p->sweep2, p->blocks2, st);
+  int64_t left = nsteps;
+  for (int d = p->depth; d >= 1; --d) {
+    for (; left >= d; left -= d) {
+      hipError_t e = launch_pass(p, d, a, b, V, st);
       if (e != hipSuccess) return e;
       void* t = a;
       a = b;
       b = t;
     }
-  }
-  for (; s < nsteps; ++s) {
-    hipError_t e = sweep_once(p, a, b, V, st);
-    if (e != hipSuccess) return e;
-    void* t = a;
-    a = b;
-    b = t;
   }
   *result = a;
   return hipSuccess;
@@ -367,7 +373,7 @@ hipError_t enqueue_steps(dl_plan p, void* psi, const double* V, int64_t nsteps, 
 static hipError_t graph_for(dl_plan p, void* psi, const double* V, int64_t pairs,
                             hipGraphExec_t* exec) {
   for (auto& ge : p->graphs) {
-    if (ge.psi == psi && ge.V == V && ge.pairs == pairs && ge.mode == p->sweep.ph.mode) {
+    if (ge.psi == psi && ge.V == V && ge.pairs == pairs && ge.mode == p->ph.mode) {
       *exec = ge.exec;
       return hipSuccess;
     }
@@ -392,7 +398,7 @@ static hipError_t graph_for(dl_plan p, void* psi, const double* V, int64_t pairs
   (void)hipGraphDestroy(graph);
   if (e != hipSuccess) return e;
   if (p->graphs.size() >= 8) p->drop_graphs();
-  p->graphs.push_back(GraphEntry{psi, V, pairs, p->sweep.ph.mode, ex});
+  p->graphs.push_back(GraphEntry{psi, V, pairs, p->ph.mode, ex});
   *exec = ex;
   return hipSuccess;
 }
@@ -406,14 +412,14 @@ extern "C" int dl_step(dl_plan p, void* psi, const double* V, int64_t nsteps, vo
   if (nsteps == 0) return DL_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int mode = phase_mode(p->m, V);
-  p->sweep.ph = make_phase(p->g.ndim, p->dt, p->c, p->m, mode, p->fp64);
+  p->ph = make_phase(p->g.ndim, p->dt, p->c, p->m, mode, p->fp64);
   select_tiling(p, mode);
   if (p->resident) {
     ResidentArgs ra{};
     ra.n = p->g.n[0];
     ra.nsteps = nsteps;
     ra.periodic = (p->bc == DL_BC_PERIODIC);
-    ra.ph = p->sweep.ph;
+    ra.ph = p->ph;
     hipError_t e = launch_resident1d(p->fp64, p->g.axis[0], psi, V, ra, 4, p->res_threads, st);
     return e == hipSuccess ? DL_OK : hip_fail(e, "resident 1-D sweep launch");
   }
@@ -451,35 +457,48 @@ extern "C" int dl_step_out(dl_plan p, const void* src, void* dst, const double* 
   if (a < b + p->state_bytes && b < a + p->state_bytes)
     return fail(DL_ERR_ARG, "src and dst overlap");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  p->sweep.ph = make_phase(p->g.ndim, p->dt, p->c, p->m, phase_mode(p->m, V), p->fp64);
-  select_tiling(p, p->sweep.ph.mode);
-  hipError_t e = sweep_once(p, src, dst, V, st);
+  p->ph = make_phase(p->g.ndim, p->dt, p->c, p->m, phase_mode(p->m, V), p->fp64);
+  select_tiling(p, p->ph.mode);
+  hipError_t e = launch_pass(p, 1, src, dst, V, st);
   return e == hipSuccess ? DL_OK : hip_fail(e, "sweep launch");
 }
 
-extern "C" int dl_step_pair_out(dl_plan p, const void* src, void* dst, const double* V,
-                                void* stream) {
+extern "C" int dl_step_fused_out(dl_plan p, const void* src, void* dst, const double* V,
+                                 int64_t nsteps, void* stream) {
   int rc = check_live(p);
   if (rc) return rc;
   if ((rc = check_state_ptr(src, "src"))) return rc;
   if ((rc = check_state_ptr(dst, "dst"))) return rc;
   if ((rc = check_f64_ptr(V, "V", true))) return rc;
+  if (nsteps < 1) return fail(DL_ERR_ARG, "nsteps = %lld < 1", static_cast<long long>(nsteps));
   const char* a = static_cast<const char*>(src);
   const char* b = static_cast<const char*>(dst);
   if (a < b + p->state_bytes && b < a + p->state_bytes)
     return fail(DL_ERR_ARG, "src and dst overlap");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  p->sweep.ph = make_phase(p->g.ndim, p->dt, p->c, p->m, phase_mode(p->m, V), p->fp64);
-  select_tiling(p, p->sweep.ph.mode);
-  hipError_t e;
-  if (p->x2) {
-    p->sweep2.ph = p->sweep.ph;
-    e = launch_sweep2d_x2(p->fp64, src, dst, V, p->sweep2, p->blocks2, st);
-  } else {
-    e = sweep_once(p, src, p->tmp, V, st);
-    if (e == hipSuccess) e = sweep_once(p, p->tmp, dst, V, st);
+  p->ph = make_phase(p->g.ndim, p->dt, p->c, p->m, phase_mode(p->m, V), p->fp64);
+  select_tiling(p, p->ph.mode);
+  // passes deepest first; they alternate between dst and the plan's buffer
+  // so that the last one writes dst
+  int64_t passes = 0;
+  {
+    int64_t left = nsteps;
+    for (int d = p->depth; d >= 1; --d) {
+      passes += left / d;
+      left %= d;
+    }
   }
-  return e == hipSuccess ? DL_OK : hip_fail(e, "sweep launch");
+  const void* in = src;
+  int64_t i = 0, left = nsteps;
+  for (int d = p->depth; d >= 1; --d) {
+    for (; left >= d; left -= d, ++i) {
+      void* out = ((passes - 1 - i) % 2 == 0) ? dst : p->tmp;
+      hipError_t e = launch_pass(p, d, in, out, V, st);
+      if (e != hipSuccess) return hip_fail(e, "sweep launch");
+      in = out;
+    }
+  }
+  return DL_OK;
 }
 
 extern "C" int dl_observables(dl_plan p, const void* psi, double x_b, double out[5],
@@ -527,18 +546,20 @@ extern "C" int dl_plan_set_tiling(dl_plan p, int waves_per_cu, int seg_len, int 
   return plan_tiling(p);
 }
 
-extern "C" int dl_plan_set_x2(dl_plan p, int enable) {
+extern "C" int dl_plan_set_depth(dl_plan p, int depth) {
   if (!p) return fail(DL_ERR_ARG, "plan is NULL");
-  p->allow_x2 = enable != 0;
+  if (depth < 1 || depth > kMaxDepth) return fail(DL_ERR_ARG, "depth %d not in 1..%d", depth, kMaxDepth);
+  p->depth_limit = depth;
   if (!p->dry) p->drop_graphs();
   return plan_tiling(p);
 }
 
 extern "C" int dl_plan_info(dl_plan p, int64_t* info, int n) {
   if (!p || !info) return fail(DL_ERR_ARG, "NULL argument");
-  const int64_t vals[] = {p->blocks,         p->sweep.H,      p->sweep.nseg, p->sweep.nstrips,
-                          p->sweep.ntiles,   p->resident,     p->res_threads, p->waves_per_cu,
-                          p->sweep.xcd_remap, p->graph_pairs, p->x2,        p->blocks2};
+  const SweepArgs& t = p->sw[p->depth - 1];  // tiling of the deepest pass in use
+  const int64_t vals[] = {p->bl[p->depth - 1], t.H,          t.nseg,         t.nstrips,
+                          t.ntiles,            p->resident,  p->res_threads, p->waves_per_cu,
+                          t.xcd_remap,         p->graph_pairs, p->depth,     p->bl[0]};
   const int nv = static_cast<int>(sizeof vals / sizeof vals[0]);
   for (int i = 0; i < n && i < nv; ++i) info[i] = vals[i];
   return DL_OK;

@@ -5,11 +5,9 @@
 // eq:sol_dis_4), reading psi once and writing it once.
 //
 // Work decomposition (2-D, and 1-D as the one-row case):
-//   * a wave64 owns a strip of 64 consecutive x cells; lane l holds cell x0+l;
-//   * the x transport takes the left neighbour's right movers and the right
-//     neighbour's left movers with DPP wave shifts; lane 0 loads the cell left
-//     of the strip, lane 63 the cell right of it (or the lane just past the
-//     last cell stands for the cell beyond the wall);
+//   * a wave64 holds 64 consecutive x cells (lane l: cell xs + l) and writes
+//     the 62 middle ones; their x neighbours all sit in the wave, so the x
+//     transport is a DPP wave shift with no halo loads;
 //   * the wave marches along y over a segment of H rows, keeping the y movers
 //     of the two previous rows in registers, so every row of psi is loaded
 //     once per segment (plus one halo row at each end);
@@ -18,6 +16,8 @@
 //     (both at their start or both at their end) and hit in L2;
 //   * blocks are remapped so that each XCD receives a contiguous band of
 //     segments (workgroups are dealt to the 8 XCDs round-robin).
+// The two-step pass (temporal blocking) writes the 60 middle cells of a wave
+// and advances them by two full steps per read and write of psi.
 // 3-D marches along z with a plane tile of 64 x cells by TY y rows per wave,
 // the y transport rolling over the rows of the tile and the z transport
 // rolling over planes.
@@ -27,46 +27,26 @@
 
 namespace dirac {
 
-template <typename T, int AX0, int AX1, int MODE>
+// K full steps per launch on a 1-D line or a 2-D plane (64 - 2K output
+// columns per wave, march segments of H rows in 2-D)
+template <typename T, int K, int AX0, int AX1, int MODE>
 __global__ __launch_bounds__(256) void k_sweep2d(const T* __restrict__ src, T* __restrict__ dst,
                                                  const double* __restrict__ V, SweepArgs a) {
   const int lane = threadIdx.x & 63;
   int64_t blk = blockIdx.x;
   if (a.xcd_remap) blk = (blk % 8) * (gridDim.x / 8) + blk / 8;
-  const int64_t tile = blk * 4 + (threadIdx.x >> 6);
+  const int64_t tile = blk * 4 + wave_in_block();
   if (tile >= a.ntiles) return;
   const int64_t strip = tile % a.nstrips;
   const int64_t seg = tile / a.nstrips;
-  const int64_t x0 = strip * 64;
+  const int64_t xs = strip * strip_width(K) - K;  // lanes K .. 63 - K are written
   if constexpr (AX1 < 0) {
-    one_row<T, AX0, MODE>(src, dst, V, a, x0, lane);  // 1-D: one row, no march
+    one_row<T, K, AX0, MODE>(src, dst, V, a, xs, lane);  // 1-D: one row, no march
   } else {
     const int64_t jb = seg * a.H;
     const int64_t je = (jb + a.H < a.ny) ? jb + a.H : a.ny;
     // even segments march up, odd ones down
-    march_dir<T, AX0, AX1, MODE>(src, dst, V, a, x0, lane, jb, je, (seg & 1) == 0);
-  }
-}
-
-// two steps per launch (1-D / 2-D): waves of 62 output columns
-template <typename T, int AX0, int AX1, int MODE>
-__global__ __launch_bounds__(256) void k_sweep2d_x2(const T* __restrict__ src,
-                                                    T* __restrict__ dst,
-                                                    const double* __restrict__ V, SweepArgs a) {
-  const int lane = threadIdx.x & 63;
-  int64_t blk = blockIdx.x;
-  if (a.xcd_remap) blk = (blk % 8) * (gridDim.x / 8) + blk / 8;
-  const int64_t tile = blk * 4 + (threadIdx.x >> 6);
-  if (tile >= a.ntiles) return;
-  const int64_t strip = tile % a.nstrips;
-  const int64_t seg = tile / a.nstrips;
-  const int64_t xs = strip * 62 - 1;
-  if constexpr (AX1 < 0) {
-    one_row_x2<T, AX0, MODE>(src, dst, V, a, xs, lane);
-  } else {
-    const int64_t jb = seg * a.H;
-    const int64_t je = (jb + a.H < a.ny) ? jb + a.H : a.ny;
-    march_dir_x2<T, AX0, AX1, MODE>(src, dst, V, a, xs, lane, jb, je, (seg & 1) == 0);
+    march_dir<T, K, AX0, AX1, MODE>(src, dst, V, a, xs, lane, jb, je, (seg & 1) == 0);
   }
 }
 
@@ -171,7 +151,7 @@ __global__ __launch_bounds__(256) void k_sweep3d(const T* __restrict__ src, T* _
   const int lane = threadIdx.x & 63;
   int64_t blk = blockIdx.x;
   if (a.xcd_remap) blk = (blk % 8) * (gridDim.x / 8) + blk / 8;
-  const int64_t tile = blk * 4 + (threadIdx.x >> 6);
+  const int64_t tile = blk * 4 + wave_in_block();
   if (tile >= a.ntiles) return;
   // tile order: x strips fastest, then y row blocks, then z segments
   const int64_t strip = tile % a.nstrips;
@@ -262,145 +242,85 @@ __global__ __launch_bounds__(1024) void k_resident1d(T* __restrict__ psi,
 }
 
 // ---------------------------------------------------------------------------
-// launchers
+// launchers: the 1-D / 2-D kernel for (type, depth, axes, phase mode)
 // ---------------------------------------------------------------------------
-template <typename T, int AX0, int AX1, int MODE>
-static hipError_t launch2d_t(const T* src, T* dst, const double* V, const SweepArgs& a,
-                             int blocks, hipStream_t st) {
-  hipLaunchKernelGGL((k_sweep2d<T, AX0, AX1, MODE>), dim3(blocks), dim3(256), 0, st, src, dst, V,
-                     a);
-  return hipGetLastError();
-}
-
-template <typename T, int AX0, int AX1>
-static hipError_t launch2d_mode(const T* src, T* dst, const double* V, const SweepArgs& a,
-                                int blocks, hipStream_t st) {
-  switch (a.ph.mode) {
-    case 0: return launch2d_t<T, AX0, AX1, 0>(src, dst, V, a, blocks, st);
-    case 1: return launch2d_t<T, AX0, AX1, 1>(src, dst, V, a, blocks, st);
-    default: return launch2d_t<T, AX0, AX1, 2>(src, dst, V, a, blocks, st);
+template <typename T, int K, int AX0, int AX1>
+static const void* kernel2d_mode(int mode) {
+  switch (mode) {
+    case 0: return reinterpret_cast<const void*>(&k_sweep2d<T, K, AX0, AX1, 0>);
+    case 1: return reinterpret_cast<const void*>(&k_sweep2d<T, K, AX0, AX1, 1>);
+    default: return reinterpret_cast<const void*>(&k_sweep2d<T, K, AX0, AX1, 2>);
   }
 }
 
-template <typename T>
-static hipError_t launch2d_axes(const T* src, T* dst, const double* V, const SweepArgs& a,
-                                int blocks, hipStream_t st) {
-  switch (a.axes_code) {
-    case 0: return launch2d_mode<T, 0, -1>(src, dst, V, a, blocks, st);
-    case 1: return launch2d_mode<T, 1, -1>(src, dst, V, a, blocks, st);
-    case 2: return launch2d_mode<T, 2, -1>(src, dst, V, a, blocks, st);
-    case 10: return launch2d_mode<T, 0, 1>(src, dst, V, a, blocks, st);
-    case 20: return launch2d_mode<T, 0, 2>(src, dst, V, a, blocks, st);
-    case 21: return launch2d_mode<T, 1, 2>(src, dst, V, a, blocks, st);
-    default: return hipErrorInvalidValue;
+template <typename T, int K>
+static const void* kernel2d_axes(int axes_code, int mode) {
+  switch (axes_code) {
+    case 0: return kernel2d_mode<T, K, 0, -1>(mode);
+    case 1: return kernel2d_mode<T, K, 1, -1>(mode);
+    case 2: return kernel2d_mode<T, K, 2, -1>(mode);
+    case 10: return kernel2d_mode<T, K, 0, 1>(mode);
+    case 20: return kernel2d_mode<T, K, 0, 2>(mode);
+    case 21: return kernel2d_mode<T, K, 1, 2>(mode);
+    default: return nullptr;
   }
 }
 
-template <typename T, int AX0, int AX1, int MODE>
-static hipError_t launch2x_t(const T* src, T* dst, const double* V, const SweepArgs& a,
-                             int blocks, hipStream_t st) {
-  hipLaunchKernelGGL((k_sweep2d_x2<T, AX0, AX1, MODE>), dim3(blocks), dim3(256), 0, st, src, dst,
-                     V, a);
-  return hipGetLastError();
-}
-
-template <typename T, int AX0, int AX1>
-static hipError_t launch2x_mode(const T* src, T* dst, const double* V, const SweepArgs& a,
-                                int blocks, hipStream_t st) {
-  switch (a.ph.mode) {
-    case 0: return launch2x_t<T, AX0, AX1, 0>(src, dst, V, a, blocks, st);
-    case 1: return launch2x_t<T, AX0, AX1, 1>(src, dst, V, a, blocks, st);
-    default: return launch2x_t<T, AX0, AX1, 2>(src, dst, V, a, blocks, st);
+// nullptr for combinations that are not built (FP64 deeper than 2)
+static const void* kernel2d(bool fp64, int depth, int axes_code, int mode) {
+  if (fp64) {
+    switch (depth) {
+      case 1: return kernel2d_axes<double, 1>(axes_code, mode);
+      case 2: return kernel2d_axes<double, 2>(axes_code, mode);
+      default: return nullptr;
+    }
+  }
+  switch (depth) {
+    case 1: return kernel2d_axes<float, 1>(axes_code, mode);
+    case 2: return kernel2d_axes<float, 2>(axes_code, mode);
+    case 3: return kernel2d_axes<float, 3>(axes_code, mode);
+    case 4: return kernel2d_axes<float, 4>(axes_code, mode);
+    case 5: return kernel2d_axes<float, 5>(axes_code, mode);
+    default: return nullptr;
   }
 }
 
-template <typename T>
-static hipError_t launch2x_axes(const T* src, T* dst, const double* V, const SweepArgs& a,
-                                int blocks, hipStream_t st) {
-  switch (a.axes_code) {
-    case 0: return launch2x_mode<T, 0, -1>(src, dst, V, a, blocks, st);
-    case 1: return launch2x_mode<T, 1, -1>(src, dst, V, a, blocks, st);
-    case 2: return launch2x_mode<T, 2, -1>(src, dst, V, a, blocks, st);
-    case 10: return launch2x_mode<T, 0, 1>(src, dst, V, a, blocks, st);
-    case 20: return launch2x_mode<T, 0, 2>(src, dst, V, a, blocks, st);
-    case 21: return launch2x_mode<T, 1, 2>(src, dst, V, a, blocks, st);
-    default: return hipErrorInvalidValue;
-  }
+hipError_t launch_sweep2d(bool fp64, int depth, const void* src, void* dst, const double* V,
+                          const SweepArgs& a, int blocks, hipStream_t st) {
+  const void* fn = kernel2d(fp64, depth, a.axes_code, a.ph.mode);
+  if (!fn || blocks <= 0) return hipErrorInvalidValue;
+  SweepArgs args = a;
+  void* kargs[] = {const_cast<void**>(&src), &dst, const_cast<double**>(&V), &args};
+  return hipLaunchKernel(fn, dim3(blocks), dim3(256), kargs, 0, st);
 }
 
 // ---- occupancy queries (resident 256-thread blocks per CU) -------------------
-template <typename K>
-static int occ_of(K kernel) {
+static int occ_of(const void* kernel) {
+  if (!kernel) return 0;
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(kernel), 256,
-                                                   0) != hipSuccess) {
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, 256, 0) != hipSuccess) {
     (void)hipGetLastError();
     return 0;
   }
   return n;
 }
 
-template <typename T, int AX0, int AX1, int MODE>
-static int occ2d_t(bool x2) {
-  return x2 ? occ_of(&k_sweep2d_x2<T, AX0, AX1, MODE>) : occ_of(&k_sweep2d<T, AX0, AX1, MODE>);
-}
-
-template <typename T, int AX0, int AX1>
-static int occ2d_mode(int mode, bool x2) {
-  switch (mode) {
-    case 0: return occ2d_t<T, AX0, AX1, 0>(x2);
-    case 1: return occ2d_t<T, AX0, AX1, 1>(x2);
-    default: return occ2d_t<T, AX0, AX1, 2>(x2);
-  }
-}
-
-template <typename T>
-static int occ2d_axes(int axes_code, int mode, bool x2) {
-  switch (axes_code) {
-    case 0: return occ2d_mode<T, 0, -1>(mode, x2);
-    case 1: return occ2d_mode<T, 1, -1>(mode, x2);
-    case 2: return occ2d_mode<T, 2, -1>(mode, x2);
-    case 10: return occ2d_mode<T, 0, 1>(mode, x2);
-    case 20: return occ2d_mode<T, 0, 2>(mode, x2);
-    case 21: return occ2d_mode<T, 1, 2>(mode, x2);
-    default: return 0;
-  }
-}
-
-int sweep_occupancy(bool fp64, int ndim, int axes_code, int mode, bool x2) {
+int sweep_occupancy(bool fp64, int ndim, int axes_code, int mode, int depth) {
   if (ndim == 3) {
     if (fp64) {
       switch (mode) {
-        case 0: return occ_of(&k_sweep3d<double, kTY3D_F64, 0>);
-        case 1: return occ_of(&k_sweep3d<double, kTY3D_F64, 1>);
-        default: return occ_of(&k_sweep3d<double, kTY3D_F64, 2>);
+        case 0: return occ_of(reinterpret_cast<const void*>(&k_sweep3d<double, kTY3D_F64, 0>));
+        case 1: return occ_of(reinterpret_cast<const void*>(&k_sweep3d<double, kTY3D_F64, 1>));
+        default: return occ_of(reinterpret_cast<const void*>(&k_sweep3d<double, kTY3D_F64, 2>));
       }
     }
     switch (mode) {
-      case 0: return occ_of(&k_sweep3d<float, kTY3D_F32, 0>);
-      case 1: return occ_of(&k_sweep3d<float, kTY3D_F32, 1>);
-      default: return occ_of(&k_sweep3d<float, kTY3D_F32, 2>);
+      case 0: return occ_of(reinterpret_cast<const void*>(&k_sweep3d<float, kTY3D_F32, 0>));
+      case 1: return occ_of(reinterpret_cast<const void*>(&k_sweep3d<float, kTY3D_F32, 1>));
+      default: return occ_of(reinterpret_cast<const void*>(&k_sweep3d<float, kTY3D_F32, 2>));
     }
   }
-  return fp64 ? occ2d_axes<double>(axes_code, mode, x2) : occ2d_axes<float>(axes_code, mode, x2);
-}
-
-hipError_t launch_sweep2d_x2(bool fp64, const void* src, void* dst, const double* V,
-                             const SweepArgs& a, int blocks, hipStream_t st) {
-  if (fp64)
-    return launch2x_axes<double>(static_cast<const double*>(src), static_cast<double*>(dst), V,
-                                 a, blocks, st);
-  return launch2x_axes<float>(static_cast<const float*>(src), static_cast<float*>(dst), V, a,
-                              blocks, st);
-}
-
-hipError_t launch_sweep2d(bool fp64, const void* src, void* dst, const double* V,
-                          const SweepArgs& a, int blocks, hipStream_t st) {
-  if (fp64)
-    return launch2d_axes<double>(static_cast<const double*>(src), static_cast<double*>(dst), V,
-                                 a, blocks, st);
-  return launch2d_axes<float>(static_cast<const float*>(src), static_cast<float*>(dst), V, a,
-                              blocks, st);
+  return occ_of(kernel2d(fp64, depth, axes_code, mode));
 }
 
 template <typename T, int TY>

@@ -24,7 +24,7 @@ DL_BC_ZERO, DL_BC_PERIODIC = 0, 1
 DL_DRY, DL_GRAPH = 1, 2
 
 # every entry point of include/libdirac.h
-EXPORTS = ("dl_plan_create", "dl_plan_destroy", "dl_step", "dl_step_out", "dl_step_pair_out",
+EXPORTS = ("dl_plan_create", "dl_plan_destroy", "dl_step", "dl_step_out", "dl_step_fused_out",
            "dl_observables", "dl_seed_adjoint",
            "dl_grad_step", "dl_project", "dl_expand", "dl_batch_create", "dl_batch_step", "dl_last_error",
            "dl_version")
@@ -59,8 +59,8 @@ def load() -> ctypes.CDLL:
         "dl_plan_destroy": [vp],
         "dl_step": [vp, vp, vp, i64, vp],
         "dl_step_out": [vp, vp, vp, vp, vp],
-        "dl_step_pair_out": [vp, vp, vp, vp, vp],
-        "dl_plan_set_x2": [vp, ci],
+        "dl_step_fused_out": [vp, vp, vp, vp, i64, vp],
+        "dl_plan_set_depth": [vp, ci],
         "dl_observables": [vp, vp, dbl, P(dbl), vp],
         "dl_seed_adjoint": [vp, vp, dbl, vp, vp, vp],
         "dl_grad_step": [vp, vp, vp, vp, vp, i64, vp],
@@ -178,14 +178,15 @@ class Plan:
                                    self._cells(V, "V"), _stream_handle()))
         return dst
 
-    def step_pair_out(self, src, dst, V=None):
-        check(self.lib.dl_step_pair_out(self.handle, self._state(src, "src"),
-                                        self._state(dst, "dst"), self._cells(V, "V"),
-                                        _stream_handle()))
+    def step_fused_out(self, src, dst, V=None, nsteps=2):
+        check(self.lib.dl_step_fused_out(self.handle, self._state(src, "src"),
+                                         self._state(dst, "dst"), self._cells(V, "V"),
+                                         int(nsteps), _stream_handle()))
         return dst
 
-    def set_x2(self, enable=True):
-        check(self.lib.dl_plan_set_x2(self.handle, int(bool(enable))))
+    def set_depth(self, depth):
+        """Cap on the steps fused into one pass over memory (1 .. 5)."""
+        check(self.lib.dl_plan_set_depth(self.handle, int(depth)))
 
     def observables(self, psi, x_b=0.0) -> np.ndarray:
         out = (ctypes.c_double * 5)()
@@ -240,7 +241,7 @@ class Plan:
         buf = (ctypes.c_int64 * 12)()
         check(self.lib.dl_plan_info(self.handle, buf, 12))
         keys = ("blocks", "seg_len", "nseg", "nstrips", "ntiles", "resident", "res_threads",
-                "waves_per_cu", "xcd_remap", "graph_pairs", "two_steps_per_pass", "blocks_x2")
+                "waves_per_cu", "xcd_remap", "graph_pairs", "depth", "blocks_1")
         return dict(zip(keys, buf[:]))
 
     def close(self):

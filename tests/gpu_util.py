@@ -13,7 +13,7 @@ def announce(msg):
 
 
 def gpu_step(psi, V, *, dx, dt, c, m, nsteps, axes=None, bc="zero", dtype="c128", tiling=None,
-             graph=False, chunks=None, x2=True):
+             graph=False, chunks=None, depth=None):
     """Run dl_step on a copy of psi (numpy, (..., 4)); returns numpy."""
     import torch
     shape = tuple(reversed(psi.shape[:-1]))
@@ -23,8 +23,8 @@ def gpu_step(psi, V, *, dx, dt, c, m, nsteps, axes=None, bc="zero", dtype="c128"
     with L.Plan(shape, dx, dt, c, m, dtype=dtype, bc=bc, axes=axes, graph=graph) as p:
         if tiling:
             p.set_tiling(**tiling)
-        if not x2:
-            p.set_x2(False)
+        if depth is not None:
+            p.set_depth(depth)
         if chunks:
             for k in chunks:
                 p.step(t, tV, k)

@@ -71,35 +71,46 @@ def test_graph_replay_and_resume(dtype):
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
 @pytest.mark.parametrize("shape,axes,bc", [((300, 260), (0, 1), "zero"), ((130, 45), (0, 2), "periodic"),
                                            ((5000,), (1,), "zero"), ((4099,), (0,), "periodic"),
-                                           ((63, 70), (1, 2), "periodic"), ((62, 9), (0, 1), "zero")])
-def test_two_steps_per_pass_same_bits(dtype, shape, axes, bc):
-    """The fused two-step pass gives the bits of two single steps (odd and even
-    counts, tilings, walls and wrap-around)."""
-    announce(f"two steps per pass {shape} {axes} {bc} {dtype}")
+                                           ((63, 70), (1, 2), "periodic"), ((62, 9), (0, 1), "zero"),
+                                           ((57, 8), (0, 1), "periodic"), ((200, 7), (0, 1), "periodic")])
+def test_fused_passes_same_bits(dtype, shape, axes, bc):
+    """Passes of 2 to 5 fused steps give the bits of single steps (counts
+    that are and are not multiples of the depth, tilings, walls, wrap-around,
+    periodic boxes too thin for the deepest pass)."""
+    announce(f"fused passes {shape} {axes} {bc} {dtype}")
     psi = random_spinor(shape[::-1], seed=21)
     V = _V(shape, seed=22)
     kw = dict(dx=DX, dt=DT, c=C, m=1.0, axes=axes, bc=bc, dtype=dtype,
               tiling={"allow_resident": False})
-    for n in (1, 2, 7, 20):
-        single = gpu_step(psi, V, nsteps=n, x2=False, **kw)
-        fused = gpu_step(psi, V, nsteps=n, x2=True, **kw)
-        assert same_bits(single, fused), n
-    massless = gpu_step(psi, None, nsteps=9, x2=True, **{**kw, "m": 0.0})
-    assert same_bits(massless, gpu_step(psi, None, nsteps=9, x2=False, **{**kw, "m": 0.0}))
+    depths = (2, 3, 4, 5) if dtype == "c64" else (2,)
+    for n in (1, 2, 3, 7, 20):
+        single = gpu_step(psi, V, nsteps=n, depth=1, **kw)
+        for d in depths:
+            assert same_bits(single, gpu_step(psi, V, nsteps=n, depth=d, **kw)), (n, d)
+    massless = gpu_step(psi, None, nsteps=9, depth=1, **{**kw, "m": 0.0})
+    for d in depths:
+        assert same_bits(massless, gpu_step(psi, None, nsteps=9, depth=d, **{**kw, "m": 0.0}))
 
 
-def test_step_pair_out_matches_two_single_steps():
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_step_fused_out_matches_single_steps(dtype):
     import torch
     from paper_1107_4650_amd import libdirac as L
-    announce("step_pair_out")
+    announce(f"step_fused_out {dtype}")
     shape = (257, 130)
-    psi = random_spinor(shape[::-1], seed=5).astype(np.complex64)
+    tdt = torch.complex64 if dtype == "c64" else torch.complex128
+    psi = torch.from_numpy(random_spinor(shape[::-1], seed=5)).to(tdt)
     V = torch.from_numpy(_V(shape)).to("cuda")
-    with L.Plan(shape, DX, DT, C, 1.0, dtype="c64") as p:
-        a = torch.from_numpy(psi).to("cuda")
-        b, c2, d = torch.empty_like(a), torch.empty_like(a), torch.empty_like(a)
-        p.step_out(a, b, V)
-        p.step_out(b, c2, V)
-        p.step_pair_out(a, d, V)
-        torch.cuda.synchronize()
-    assert same_bits(c2.cpu().numpy(), d.cpu().numpy())
+    with L.Plan(shape, DX, DT, C, 1.0, dtype=dtype) as p:
+        a = psi.to("cuda")
+        ref = [a]
+        for _ in range(11):
+            nxt = torch.empty_like(a)
+            p.step_out(ref[-1], nxt, V)
+            ref.append(nxt)
+        for k in range(1, 12):
+            d = torch.empty_like(a)
+            p.step_fused_out(a, d, V, k)
+            torch.cuda.synchronize()
+            assert same_bits(ref[k].cpu().numpy(), d.cpu().numpy()), k
+        assert same_bits(a.cpu().numpy(), psi.numpy())  # src untouched

@@ -167,3 +167,30 @@ def test_3d_fp64_vs_oracle():
     got32 = gpu_step(psi.astype(np.complex64), V, dx=0.02, dt=dt, c=C, m=1.0, nsteps=20,
                      axes=(0, 1, 2), dtype="c64")
     assert rel_l2(got32, ref) <= 3e-6
+
+
+THIN = [((130, 45), (0, 1), "zero"), ((61, 3), (0, 1), "periodic"), ((61, 4), (0, 2), "periodic"),
+        ((200, 2), (1, 2), "zero"), ((2, 50), (0, 1), "periodic"), ((3000,), (0,), "zero")]
+
+
+@pytest.mark.parametrize("shape,axes,bc", THIN, ids=[f"{_ids(s)}-{b}" for s, _, b in THIN])
+def test_thin_boxes_and_far_phase_arguments(shape, axes, bc):
+    """Boxes a few cells thin (rows that wrap once, two columns) and phase
+    angles beyond the fast argument reduction (|V dt| > 2^20 for 2 % of the
+    cells), in both precisions.  An odd step count runs the two-step pass and
+    one single step; the 1-D line also runs without the resident kernel."""
+    announce(f"thin box / far phases {shape} {axes} {bc}")
+    psi = random_spinor(shape[::-1], seed=31 + sum(shape))
+    rng = np.random.default_rng(11)
+    V = rng.uniform(-3, 3, size=shape[::-1]) * C * C
+    flat = V.reshape(-1)
+    idx = rng.choice(flat.size, size=max(1, flat.size // 50), replace=False)
+    flat[idx] = rng.choice([-1.0, 1.0], idx.size) * 1e12
+    nsteps = 9
+    ref = O.step(psi, V, dt=DT, c=C, m=1.0, nsteps=nsteps, axes=axes, bc=bc)
+    for tiling in (None, {"allow_resident": False}):
+        kw = dict(dx=DX, dt=DT, c=C, m=1.0, nsteps=nsteps, axes=axes, bc=bc, tiling=tiling)
+        got64 = gpu_step(psi, V, dtype="c128", **kw)
+        assert rel_l2(got64, ref) <= 1e-12, tiling
+        got32 = gpu_step(psi.astype(np.complex64), V, dtype="c64", **kw)
+        assert rel_l2(got32, ref) <= 5e-6, tiling
