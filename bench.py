@@ -93,9 +93,10 @@ def rel_l2(a, b):
     return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
 
 
-def load_traffic(kernel_name):
-    """HBM bytes per launch from committed rocprofv3 PMC summaries, if they were
-    taken on the current kernel source; None otherwise."""
+def load_profile(kernel_name):
+    """Counter figures for one kernel from the committed rocprofv3 PMC summaries
+    (HBM bytes per launch, VALU busy fraction), if they were taken on the
+    current kernel source; None otherwise."""
     path = os.path.join(PROFILES, "traffic.json")
     if not os.path.exists(path):
         return None
@@ -104,7 +105,7 @@ def load_traffic(kernel_name):
     ent = t.get(kernel_name)
     if not ent or ent.get("source_hash") != kernel_source_hash():
         return None
-    return ent.get("bytes_per_launch")
+    return ent
 
 
 def bench_main(args):
@@ -149,7 +150,8 @@ def bench_main(args):
     # writing psi once: 72 B per cell per launch, 72 / d32 B per site-update
     achieved = BYTES_F32 * sites / (per32 * 1e-3) / 1e9
     kname = f"sweep2d_d{d32}_f32_2048"
-    traffic = load_traffic(kname)
+    prof = load_profile(kname)
+    traffic = prof.get("bytes_per_launch") if prof else None
     line = {
         "metric": METRIC,
         "value": sites * n32 / wall32,
@@ -174,7 +176,12 @@ def bench_main(args):
                      "kernel": f"k_sweep2d<float,{d32},0,1,2>",
                      "bytes_per_launch_per_cell": BYTES_F32,
                      "bytes_per_site_update": BYTES_F32 / d32,
-                     "per_launch_ms": per32, "site_updates_per_launch": d32 * sites},
+                     "per_launch_ms": per32, "site_updates_per_launch": d32 * sites,
+                     # the fused pass recomputes halo cells and converts to FP64 for the
+                     # phase; rocprofv3 counters (SQ_INSTS_VALU) show the SIMDs' VALU
+                     # issue as the limiter of the five-step pass
+                     "valu_busy": prof.get("valu_busy") if prof else None,
+                     "profile": prof.get("summary") if prof else None},
         "fp64": {"value": sites * n64 / wall64, "unit": "site-updates/s",
                  "ms_per_step": wall64 * 1e3 / n64, "per_launch_ms": per64,
                  "steps_per_launch": d64,

@@ -30,7 +30,7 @@ namespace dirac {
 // K full steps per launch on a 1-D line or a 2-D plane (64 - 2K output
 // columns per wave, march segments of H rows in 2-D)
 template <typename T, int K, int AX0, int AX1, int MODE>
-__global__ __launch_bounds__(256) void k_sweep2d(const T* __restrict__ src, T* __restrict__ dst,
+__global__ __launch_bounds__(256, 2) void k_sweep2d(const T* __restrict__ src, T* __restrict__ dst,
                                                  const double* __restrict__ V, SweepArgs a) {
   const int lane = threadIdx.x & 63;
   int64_t blk = blockIdx.x;

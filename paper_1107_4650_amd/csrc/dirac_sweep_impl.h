@@ -166,16 +166,16 @@ __device__ __forceinline__ Lanes lanes_of(int64_t nx, int periodic, int64_t xs, 
 // register copies are needed to advance it.  Memory accesses sit outside
 // branches: rows and columns beyond a wall are read at a clamped address and
 // zeroed where they are consumed, rows past the segment end are read and
-// ignored, and the loop runs whole unrolled trips (surplus iterations store
-// nothing), so the loads of later rows stay in flight while the current row
-// is computed.
+// ignored, and the only branch that leaves the loop is a wave-uniform exit
+// after the last row, so the loads of later rows stay in flight while the
+// current row is computed.
 // ---------------------------------------------------------------------------
 template <int K> struct MarchShape;  // L: rows in flight; U: unroll
 template <> struct MarchShape<1> { static constexpr int L = 3, U = 4; };
 template <> struct MarchShape<2> { static constexpr int L = 2, U = 6; };
 template <> struct MarchShape<3> { static constexpr int L = 3, U = 4; };
 template <> struct MarchShape<4> { static constexpr int L = 4, U = 10; };
-template <> struct MarchShape<5> { static constexpr int L = 5, U = 6; };
+template <> struct MarchShape<5> { static constexpr int L = 2, U = 6; };
 
 template <typename T, int K, int AX0, int AX1, bool UP, int MODE>
 __device__ __forceinline__ void march2d(const T* __restrict__ src, T* __restrict__ dst,
@@ -221,11 +221,12 @@ __device__ __forceinline__ void march2d(const T* __restrict__ src, T* __restrict
     zero(mv[q][0]);
     zero(mv[q][1]);
   }
-  const int trips = (nit + U - 1) / U;
-  for (int trip = 0; trip < trips; ++trip) {
+  for (int trip = 0;; ++trip) {
 #pragma unroll
     for (int k = 0; k < U; ++k) {
       const int it = trip * U + k;
+      // wave-uniform exit; the loads issued for later rows are simply dropped
+      if (it >= nit) return;
       Site<T> cur = ring[k % RS];
       const double vcur = vr[k % RS];
       load_in(it + L, ring[(k + L) % RS], vr[(k + L) % RS]);
@@ -256,7 +257,7 @@ __device__ __forceinline__ void march2d(const T* __restrict__ src, T* __restrict
         }
         cur = o;
       }
-      if (it >= 2 * K && it < nit && own) store_site(dst + (out_row(it, K) * nx + c.x) * 8, cur);
+      if (it >= 2 * K && own) store_site(dst + (out_row(it, K) * nx + c.x) * 8, cur);
       factors_fix<MODE, TWO>(fnew, vcur, a.ph);
     }
   }
