@@ -26,6 +26,12 @@
  *         psi_c <- psi_c * (cos th_c - i sin th_c),
  *         th_c = (V + beta_cc m c^2) dt,
  *     with V the potential energy sampled at cell centres.
+ *   - One time step of the second-order (Strang) splitting of Sec. 2.4 with
+ *     the simplifications that section states for 1-D and 2-D grids: the
+ *     transports over dt/2 in the order A, B, C, the local step D over dt,
+ *     then the transports over dt/2 in the reverse order.  Each half-step
+ *     transport is the same one-cell characteristic shift, i.e. the grid
+ *     obeys c*(dt/2) = a.
  *   - Observables: norm, mean coordinates and the probability beyond x_b
  *     (Sec. 5.2.1, R/T integrals), as sequential Neumaier sums in FP64.
  *   - The discrete adjoint of the step (derived from eq:sol_dis_1-4) by
@@ -302,6 +308,28 @@ static void step_once(const grid_t *g, zd *psi, zd *tmp, const double *V,
     local_step(g, psi, V, dt, c, m, -1.0);
 }
 
+/* One second-order step (Sec. 2.4, 1-D and 2-D):
+ *   T_first(dt/2) ... T_last(dt/2), D(dt), T_last(dt/2) ... T_first(dt/2),
+ * each T over dt/2 being the one-cell shift of eq:sol_dis_1-3 (c dt/2 = a). */
+static void step_once_strang(const grid_t *g, zd *psi, zd *tmp, const double *V,
+                             double dt, double c, double m)
+{
+    int order[3];
+    const int k = transport_order(g, order);
+    const int64_t bytes = nsites(g) * 4 * (int64_t)sizeof(zd);
+    for (int t = 0; t < k; ++t) {
+        const int a = g->axis[order[t]];
+        transport_d(g, order[t], PROJ[a][0], PROJ[a][1], psi, tmp);
+        memcpy(psi, tmp, (size_t)bytes);
+    }
+    local_step(g, psi, V, dt, c, m, -1.0);
+    for (int t = k - 1; t >= 0; --t) {
+        const int a = g->axis[order[t]];
+        transport_d(g, order[t], PROJ[a][0], PROJ[a][1], psi, tmp);
+        memcpy(psi, tmp, (size_t)bytes);
+    }
+}
+
 /* One adjoint step S^H = T_first^H ... T_last^H D^H (D^H applied first). */
 static void adjoint_once(const grid_t *g, zd *lam, zd *tmp, const double *V,
                          double dt, double c, double m)
@@ -334,6 +362,22 @@ int oracle_step(int ndim, const int64_t *n, const int *axis, int bc,
     zd *tmp = (zd *)malloc((size_t)nsites(&g) * 4 * sizeof(zd));
     if (!tmp) return -2;
     for (int64_t s = 0; s < nsteps; ++s) step_once(&g, (zd *)psi, tmp, V, dt, c, m);
+    free(tmp);
+    return 0;
+}
+
+/* nsteps second-order steps (1-D and 2-D grids only; dt is the full step). */
+int oracle_step_strang(int ndim, const int64_t *n, const int *axis, int bc,
+                       double dt, double c, double m, const double *V,
+                       double *psi, int64_t nsteps, int nthreads)
+{
+    grid_t g;
+    if (ndim > 2 || grid_from_args(&g, ndim, n, axis, bc) || nsteps < 0) return -1;
+    build_matrices();
+    set_threads(nthreads);
+    zd *tmp = (zd *)malloc((size_t)nsites(&g) * 4 * sizeof(zd));
+    if (!tmp) return -2;
+    for (int64_t s = 0; s < nsteps; ++s) step_once_strang(&g, (zd *)psi, tmp, V, dt, c, m);
     free(tmp);
     return 0;
 }

@@ -49,6 +49,7 @@ def _load():
                                     ctypes.c_double, ctypes.c_double, dp, dp, ctypes.c_int64,
                                     ctypes.c_int]
         lib.oracle_adjoint_step.argtypes = lib.oracle_step.argtypes
+        lib.oracle_step_strang.argtypes = lib.oracle_step.argtypes
         lib.oracle_stream_f32.argtypes = [ctypes.c_int, i64p, ip, ctypes.c_int, dp,
                                           ctypes.c_int64, ctypes.c_int]
         lib.oracle_observables.argtypes = [ctypes.c_int, i64p, ctypes.c_double, dp, dp,
@@ -59,7 +60,8 @@ def _load():
                                     ctypes.c_int]
         lib.oracle_dirac_matrices.argtypes = [dp]
         lib.oracle_max_threads.restype = ctypes.c_int
-        for f in (lib.oracle_step, lib.oracle_adjoint_step, lib.oracle_stream_f32,
+        for f in (lib.oracle_step, lib.oracle_adjoint_step, lib.oracle_step_strang,
+                  lib.oracle_stream_f32,
                   lib.oracle_observables, lib.oracle_grad):
             f.restype = ctypes.c_int
         _lib = lib
@@ -105,6 +107,21 @@ def step(psi, V=None, *, dt, c, m, nsteps, axes=None, bc="zero", threads=0):
                              None if V is None else _ptr(V), _ptr(psi), int(nsteps), int(threads))
     if rc:
         raise RuntimeError(f"oracle_step failed ({rc})")
+    return psi
+
+
+def step_strang(psi, V=None, *, dt, c, m, nsteps, axes=None, bc="zero", threads=0):
+    """Return psi after `nsteps` second-order steps (Sec. 2.4, 1-D and 2-D):
+    half-step transports in the order A, B, C, D over dt, half-step transports
+    in the reverse order; each half step is a one-cell shift (c dt = 2a)."""
+    psi = np.array(psi, dtype=np.complex128, order="C", copy=True)
+    V = _check_V(V, psi)
+    ndim, n, ax = _grid_args(psi, axes)
+    rc = _load().oracle_step_strang(ndim, n, ax, _bc(bc), dt, c, m,
+                                    None if V is None else _ptr(V), _ptr(psi), int(nsteps),
+                                    int(threads))
+    if rc:
+        raise RuntimeError(f"oracle_step_strang failed ({rc})")
     return psi
 
 
