@@ -13,6 +13,7 @@ adjoint).
   python bench.py [--steps K] [--warmup W] [--gpus 1]
   python bench.py --only sweep --steps 20     # kernel loop only (profiling)
   python bench.py --calibrate-copy            # a plain copy of known size
+  python bench.py --only klein                # the paper's 2-D Klein run alone
 """
 from __future__ import annotations
 
@@ -223,7 +224,57 @@ def bench_extras(args, line):
     ex["adjoint_1024"] = bench_adjoint(args)
     # batch of 256 uneven instances vs the same instances one at a time
     ex["batch_256"] = bench_batch(args)
+    if args.klein_steps > 0:
+        ex["klein2d_24576x8192_strang"] = bench_klein2d(args)
     line["extras"] = ex
+
+
+def bench_klein2d(args):
+    """The paper's 2-D Klein run (Sec. 5.2.2): 24576 x 8192 cells in the x-z
+    plane, second-order steps, 12000 steps to t = 0.214, complex64 state; the
+    transmitted probability beyond x = 0 against the paper's numeric 0.2407
+    and the analytic 0.2621.  Inputs are assembled on the device from their
+    separable 1-D pieces (input generation only)."""
+    import torch
+    from paper_1107_4650_amd import libdirac as L
+    from paper_1107_4650_amd.inputs import klein2d_factors, C_LIGHT, M_E
+    nx, nz = 24576, 8192
+    f = klein2d_factors(nx, nz)
+    gx = torch.from_numpy(f["gx"]).to("cuda")
+    gz = torch.from_numpy(f["gz"]).to("cuda")
+    u = torch.from_numpy(f["u"]).to("cuda")
+    psi = torch.empty((nz, nx, 4), dtype=torch.complex64, device="cuda")
+    for k0 in range(0, nz, 512):  # row blocks keep the complex128 temporaries small
+        k1 = min(nz, k0 + 512)
+        psi[k0:k1] = (gz[k0:k1, None, None] * gx[None, :, None] * u).to(torch.complex64)
+    V = torch.from_numpy(f["Vx"]).to("cuda")[None, :].expand(nz, nx).contiguous()
+    del gx, gz
+    steps = args.klein_steps
+    with L.Plan((nx, nz), f["dx"], f["dt"], C_LIGHT, M_E, dtype="c64", axes=(0, 2),
+                xmin=f["xmin"], scheme="strang") as p:
+        obs0 = p.observables(psi, 0.0)
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        s.record()
+        p.step(psi, V, steps)
+        e.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = s.elapsed_time(e)
+        obs = p.observables(psi, 0.0)
+        depth = p.info()["depth"]
+    del psi, V
+    torch.cuda.empty_cache()
+    sites = nx * nz
+    T = obs[4] / obs[0]
+    log(f"2-D Klein 24576x8192 strang: {steps} steps in {ms / 1e3:.2f} s, T = {T:.4f}")
+    return {"grid": [nx, nz], "steps": steps, "t_final": steps * f["dt"], "scheme": "strang",
+            "dtype": "c64", "steps_per_pass": depth, "seconds": ms / 1e3, "wall_s": wall,
+            "site_updates_per_s": sites * steps / (ms * 1e-3),
+            "norm_initial": obs0[0], "norm_final": obs[0],
+            "T": T, "R": 1.0 - T, "T_paper_numeric": 0.2407, "T_analytic": 0.2621,
+            "paper_seconds": 22 * 3600, "paper_processors": 256}
 
 
 def bench_3d(args):
@@ -407,7 +458,9 @@ def main():
     ap.add_argument("--steps3d", type=int, default=50)
     ap.add_argument("--adjoint-steps", type=int, default=4000)
     ap.add_argument("--batch-steps", type=int, default=500)
-    ap.add_argument("--only", choices=["all", "sweep", "main"], default="all")
+    ap.add_argument("--klein-steps", type=int, default=12000,
+                    help="steps of the paper's 2-D Klein run (0 skips it)")
+    ap.add_argument("--only", choices=["all", "sweep", "main", "klein"], default="all")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
     args = ap.parse_args()
@@ -418,6 +471,9 @@ def main():
         sys.exit(2)
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.only == "klein":
+        print(json.dumps(bench_klein2d(args)), flush=True)
         return
     line = bench_main(args)
     if line is None:

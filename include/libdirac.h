@@ -48,7 +48,7 @@ typedef struct dl_plan_s *dl_plan;
 typedef enum {
     DL_OK = 0,
     DL_ERR_ARG = -1,    /* null pointer, bad size, bad enum, nsteps < 0 ... */
-    DL_ERR_CFL = -2,    /* c dt differs from the cell size (relative 1e-12) */
+    DL_ERR_CFL = -2,    /* c dt differs from the cell size (twice it with DL_STRANG), relative 1e-12 */
     DL_ERR_DTYPE = -3,  /* unknown dtype, or call not valid for the plan's dtype */
     DL_ERR_ALIGN = -4,  /* a pointer is not aligned as required */
     DL_ERR_NOMEM = -5,  /* device allocation failed */
@@ -66,6 +66,13 @@ typedef enum { DL_BC_ZERO = 0, DL_BC_PERIODIC = 1 } dl_bc;
 #define DL_DRY 1u    /* validate only: no HIP call, no allocation; every other
                         entry point then returns DL_ERR_STATE */
 #define DL_GRAPH 2u  /* replay long step sequences from captured hipGraphs */
+#define DL_STRANG 4u /* second-order steps (Sec. 2.4), 1-D and 2-D grids only:
+                        each step applies the transports over dt/2 in the order
+                        A, B, C, the local step over dt, then the transports
+                        over dt/2 in the reverse order.  Every transport is the
+                        one-cell shift, so the plan needs c*dt = 2*dx
+                        (DL_ERR_CFL otherwise).  The adjoint entry points
+                        refuse such a plan (DL_ERR_ARG). */
 
 /* Grid of P0 cells (Sec. 2.3).  n[d] cells along grid dimension d, n[0]
  * fastest.  axis[d] is the Dirac matrix carried by dimension d (0 = alpha_x,

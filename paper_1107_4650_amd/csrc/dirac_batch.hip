@@ -66,12 +66,12 @@ __global__ __launch_bounds__(256) void k_batch(const BatchInst* __restrict__ ins
   const int64_t x0 = static_cast<int64_t>(t.strip) * strip_width(1) - 1;  // lanes 1 .. 62 written
   const bool up = t.up != 0;
   switch (I.axes_code) {
-    case 0: one_row<T, 1, 0, -1>(src, dst, I.V, a, x0, lane); break;
-    case 1: one_row<T, 1, 1, -1>(src, dst, I.V, a, x0, lane); break;
-    case 2: one_row<T, 1, 2, -1>(src, dst, I.V, a, x0, lane); break;
-    case 10: march_dir<T, 1, 0, 1, -1>(src, dst, I.V, a, x0, lane, t.jb, t.je, up); break;
-    case 20: march_dir<T, 1, 0, 2, -1>(src, dst, I.V, a, x0, lane, t.jb, t.je, up); break;
-    case 21: march_dir<T, 1, 1, 2, -1>(src, dst, I.V, a, x0, lane, t.jb, t.je, up); break;
+    case 0: one_row<T, LieStep, 1, 0, -1>(src, dst, I.V, a, x0, lane); break;
+    case 1: one_row<T, LieStep, 1, 1, -1>(src, dst, I.V, a, x0, lane); break;
+    case 2: one_row<T, LieStep, 1, 2, -1>(src, dst, I.V, a, x0, lane); break;
+    case 10: march_dir<T, LieStep, 1, 0, 1, -1>(src, dst, I.V, a, x0, lane, t.jb, t.je, up); break;
+    case 20: march_dir<T, LieStep, 1, 0, 2, -1>(src, dst, I.V, a, x0, lane, t.jb, t.je, up); break;
+    case 21: march_dir<T, LieStep, 1, 1, 2, -1>(src, dst, I.V, a, x0, lane, t.jb, t.je, up); break;
     default: break;
   }
 }
@@ -280,7 +280,7 @@ extern "C" int dl_batch_create(dl_plan* out, const dl_grid* grids, const double*
   if (!grids || !dx || !dt || !c || !m) return set_error(DL_ERR_ARG, "NULL parameter array");
   if (count < 1 || count > (1 << 20)) return set_error(DL_ERR_ARG, "count out of range");
   for (int k = 0; k < count; ++k) {
-    int rc = validate_grid(&grids[k], dx[k], dt[k], c[k], m[k], dtype, bc, 2);
+    int rc = validate_grid(&grids[k], dx[k], dt[k], c[k], m[k], dtype, bc, 2, 1);
     if (rc) return rc;
     if (grids[k].n[0] > (int64_t(1) << 30) || (grids[k].ndim > 1 && grids[k].n[1] > (1 << 30)))
       return set_error(DL_ERR_ARG, "instance too large for a batch");

@@ -10,12 +10,19 @@ namespace dirac {
 
 constexpr int kTY3D_F32 = 4;  // y rows per wave in the 3-D plane tile
 constexpr int kTY3D_F64 = 2;
-// 1-D / 2-D passes fuse up to kMaxDepth full steps (FP64 state: 2; deeper
-// passes would not fit the registers of two waves per SIMD); a wave of 64
-// lanes then writes 64 - 2 * depth columns
+// 1-D / 2-D passes fuse up to kMaxDepth full lowest-order steps (FP64 state:
+// 2; deeper passes would not fit the registers of two waves per SIMD), or up
+// to 2 second-order steps (FP64: 1).  A wave of 64 lanes writes 64 - 2X
+// columns, X being the x transports of the pass (one per lowest-order step,
+// two per second-order step).
 constexpr int kMaxDepth = 5;
-__host__ __device__ constexpr int max_depth(bool fp64) { return fp64 ? 2 : kMaxDepth; }
-__host__ __device__ constexpr int strip_width(int depth) { return 64 - 2 * depth; }
+__host__ __device__ constexpr int max_depth(bool fp64, bool strang) {
+  return strang ? (fp64 ? 1 : 2) : (fp64 ? 2 : kMaxDepth);
+}
+__host__ __device__ constexpr int strip_width(int xlanes) { return 64 - 2 * xlanes; }
+__host__ __device__ constexpr int pass_xlanes(bool strang, int depth) {
+  return strang ? 2 * depth : depth;
+}
 
 struct SweepArgs {
   int64_t nx, ny, nz;  // cells along grid dims 0, 1, 2 (1 where absent)
@@ -45,16 +52,17 @@ struct ObsArgs {
   double x_b;
 };
 
-// `depth` full steps src -> dst in one pass over a 1-D / 2-D grid (tiling
-// made for strip_width(depth)); `blocks` 256-thread workgroups
-hipError_t launch_sweep2d(bool fp64, int depth, const void* src, void* dst, const double* V,
-                          const SweepArgs& a, int blocks, hipStream_t st);
+// `depth` full steps (second order if `strang`) src -> dst in one pass over
+// a 1-D / 2-D grid (tiling made for strip_width(pass_xlanes(strang, depth)));
+// `blocks` 256-thread workgroups
+hipError_t launch_sweep2d(bool fp64, bool strang, int depth, const void* src, void* dst,
+                          const double* V, const SweepArgs& a, int blocks, hipStream_t st);
 // one full step src -> dst on a 3-D grid
 hipError_t launch_sweep3d(bool fp64, const void* src, void* dst, const double* V,
                           const SweepArgs& a, int blocks, hipStream_t st);
 // resident 256-thread blocks per CU of the sweep kernel for this layout,
 // phase mode and depth (0 if the runtime cannot tell)
-int sweep_occupancy(bool fp64, int ndim, int axes_code, int mode, int depth);
+int sweep_occupancy(bool fp64, bool strang, int ndim, int axes_code, int mode, int depth);
 // nsteps in place in one workgroup of `threads` threads, `spt` cells each
 hipError_t launch_resident1d(bool fp64, int axis, void* psi, const double* V,
                              const ResidentArgs& a, int spt, int threads, hipStream_t st);

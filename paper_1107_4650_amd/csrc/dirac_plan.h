@@ -34,6 +34,7 @@ struct dl_plan_s {
   bool fp64 = false;
   bool dry = false;
   bool use_graph = false;
+  bool strang = false;         // second-order steps (Sec. 2.4)
   int64_t cells = 0;
   size_t state_bytes = 0;
   int device = 0;
@@ -72,8 +73,11 @@ namespace dirac {
 
 int set_error(int code, const char* msg);
 int set_hip_error(hipError_t e, const char* what);
+int transports_per_step(dl_plan p);
+// shift: cells per one-cell-transport step, c dt = shift * dx (2 for the
+// second-order step, whose transports run over dt / 2)
 int validate_grid(const dl_grid* g, double dx, double dt, double c, double m, int dtype, int bc,
-                  int max_ndim);
+                  int max_ndim, int shift);
 PhaseK make_phase(int ntransports, double dt, double c, double m, int mode, bool two_angles);
 int phase_mode(double m, const double* V);
 int axes_code(const dl_grid& g);
@@ -82,7 +86,6 @@ void make_tiling(const dl_grid& g, int64_t target, int seg_override, SweepArgs& 
 int check_live(dl_plan p);
 int check_state_ptr(const void* ptr, const char* name);
 int check_f64_ptr(const void* ptr, const char* name, bool nullable);
-hipError_t sweep_once(dl_plan p, const void* src, void* dst, const double* V, hipStream_t st);
 void destroy_batch(dl_plan p);
 
 }  // namespace dirac

@@ -43,7 +43,7 @@ int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
 int set_hip_error(hipError_t e, const char* what) { return hip_fail(e, what); }
 
 int validate_grid(const dl_grid* g, double dx, double dt, double c, double m, int dtype, int bc,
-                  int max_ndim) {
+                  int max_ndim, int shift) {
   if (!g) return fail(DL_ERR_ARG, "grid is NULL");
   if (g->ndim < 1 || g->ndim > max_ndim) return fail(DL_ERR_ARG, "ndim must be 1..%d", max_ndim);
   for (int d = 0; d < g->ndim; ++d) {
@@ -66,8 +66,9 @@ int validate_grid(const dl_grid* g, double dx, double dt, double c, double m, in
   if (dtype != DL_C64 && dtype != DL_C128) return fail(DL_ERR_DTYPE, "unknown dtype %d", dtype);
   if (bc != DL_BC_ZERO && bc != DL_BC_PERIODIC) return fail(DL_ERR_ARG, "unknown bc %d", bc);
   const double K = c * dt / dx;
-  if (!(std::fabs(K - 1.0) <= 1e-12))
-    return fail(DL_ERR_CFL, "c*dt/dx = %.17g: the characteristic shift needs c*dt = dx", K);
+  if (!(std::fabs(K - shift) <= 1e-12 * shift))
+    return fail(DL_ERR_CFL, "c*dt/dx = %.17g: the characteristic shift needs c*dt = %d dx", K,
+                shift);
   return DL_OK;
 }
 
@@ -172,6 +173,10 @@ void make_tiling3d(const dl_grid& g, int ty, int64_t target, int seg_override, S
 // plan
 // ===========================================================================
 
+// one-cell transports per step: one per axis (Sec. 2.1), or two per axis for
+// the second-order step (Sec. 2.4)
+int dirac::transports_per_step(dl_plan p) { return (p->strang ? 2 : 1) * p->g.ndim; }
+
 // make the tilings of phase mode `mode` current
 static void select_tiling(dl_plan p, int mode) {
   const PlanTiling& t = p->tiling[mode < 0 || mode > 2 ? 2 : mode];
@@ -184,20 +189,23 @@ static void select_tiling(dl_plan p, int mode) {
 // waves that can be resident at once for the sweep kernel of this plan
 static int64_t resident_waves(dl_plan p, int mode, int depth) {
   if (p->waves_per_cu > 0) return int64_t(p->cu_count) * p->waves_per_cu;
-  int occ = p->dry ? 0 : sweep_occupancy(p->fp64, p->g.ndim, axes_code(p->g), mode, depth);
+  int occ = p->dry ? 0
+                   : sweep_occupancy(p->fp64, p->strang, p->g.ndim, axes_code(p->g), mode, depth);
   if (occ <= 0) occ = 2;
   return int64_t(occ) * 4 * p->cu_count;
 }
 
 static int plan_tiling(dl_plan p) {
   // fused steps per pass: 1-D and 2-D grids only; a periodic 2-D pass reaches
-  // `depth` rows beyond a segment on each side and wraps once, so the box
-  // needs at least 2 * depth rows
+  // one row per stage (one per lowest-order step, two per second-order step)
+  // beyond a segment on each side and wraps once, so the box needs at least
+  // twice that many rows
   int depth = 1;
   if (p->g.ndim <= 2) {
-    depth = std::min(p->depth_limit, max_depth(p->fp64));
+    depth = std::min(p->depth_limit, max_depth(p->fp64, p->strang));
+    const int stages_per_step = p->strang ? 2 : 1;
     if (p->g.ndim == 2 && p->bc == DL_BC_PERIODIC)
-      while (depth > 1 && p->g.n[1] < 2 * depth) --depth;
+      while (depth > 1 && p->g.n[1] < 2 * stages_per_step * depth) --depth;
   }
   p->depth = depth;
   for (int mode = 0; mode < 3; ++mode) {
@@ -208,14 +216,14 @@ static int plan_tiling(dl_plan p) {
     } else {
       for (int d = 1; d <= depth; ++d)
         make_tiling(p->g, resident_waves(p, mode, d), p->seg_override, t.a[d - 1], t.b[d - 1],
-                    strip_width(d));
+                    strip_width(pass_xlanes(p->strang, d)));
     }
     for (int d = 0; d < kMaxDepth; ++d) t.a[d].periodic = (p->bc == DL_BC_PERIODIC);
   }
   select_tiling(p, 2);
   // resident 1-D path: the whole line in one workgroup (4 cells per thread)
   p->resident = false;
-  if (p->g.ndim == 1 && p->allow_resident) {
+  if (p->g.ndim == 1 && p->allow_resident && !p->strang) {
     const int64_t n = p->g.n[0];
     const int64_t threads = ((n + 4 * 64 - 1) / (4 * 64)) * 64;
     if (threads <= 1024 && (p->bc == DL_BC_ZERO || threads * 4 == n)) {
@@ -230,7 +238,8 @@ extern "C" int dl_plan_create(dl_plan* out, const dl_grid* g, double dx, double 
                               double m, dl_dtype dtype, dl_bc bc, unsigned flags) {
   if (!out) return fail(DL_ERR_ARG, "out is NULL");
   *out = nullptr;
-  int rc = validate_grid(g, dx, dt, c, m, dtype, bc, 3);
+  const bool strang = (flags & DL_STRANG) != 0;
+  int rc = validate_grid(g, dx, dt, c, m, dtype, bc, strang ? 2 : 3, strang ? 2 : 1);
   if (rc) return rc;
   if (g->ndim == 3 && !(g->axis[0] == 0 && g->axis[1] == 1 && g->axis[2] == 2))
     return fail(DL_ERR_ARG, "3-D grids carry alpha_x, alpha_y, alpha_z in order");
@@ -255,6 +264,7 @@ extern "C" int dl_plan_create(dl_plan* out, const dl_grid* g, double dx, double 
   p->state_bytes = static_cast<size_t>(p->cells) * 4 * (p->fp64 ? 16 : 8);
   p->dry = (flags & DL_DRY) != 0;
   p->use_graph = (flags & DL_GRAPH) != 0;
+  p->strang = strang;
   plan_tiling(p);
   if (p->dry) {
     *out = p;
@@ -344,7 +354,7 @@ hipError_t launch_pass(dl_plan p, int depth, const void* src, void* dst, const d
   }
   SweepArgs a = p->sw[depth - 1];
   a.ph = p->ph;
-  return launch_sweep2d(p->fp64, depth, src, dst, V, a, p->bl[depth - 1], st);
+  return launch_sweep2d(p->fp64, p->strang, depth, src, dst, V, a, p->bl[depth - 1], st);
 }
 
 // enqueue `nsteps` steps ping-ponging between psi and the plan's tmp buffer,
@@ -412,7 +422,7 @@ extern "C" int dl_step(dl_plan p, void* psi, const double* V, int64_t nsteps, vo
   if (nsteps == 0) return DL_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int mode = phase_mode(p->m, V);
-  p->ph = make_phase(p->g.ndim, p->dt, p->c, p->m, mode, p->fp64);
+  p->ph = make_phase(transports_per_step(p), p->dt, p->c, p->m, mode, p->fp64);
   select_tiling(p, mode);
   if (p->resident) {
     ResidentArgs ra{};
@@ -457,7 +467,7 @@ extern "C" int dl_step_out(dl_plan p, const void* src, void* dst, const double* 
   if (a < b + p->state_bytes && b < a + p->state_bytes)
     return fail(DL_ERR_ARG, "src and dst overlap");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  p->ph = make_phase(p->g.ndim, p->dt, p->c, p->m, phase_mode(p->m, V), p->fp64);
+  p->ph = make_phase(transports_per_step(p), p->dt, p->c, p->m, phase_mode(p->m, V), p->fp64);
   select_tiling(p, p->ph.mode);
   hipError_t e = launch_pass(p, 1, src, dst, V, st);
   return e == hipSuccess ? DL_OK : hip_fail(e, "sweep launch");
@@ -476,7 +486,7 @@ extern "C" int dl_step_fused_out(dl_plan p, const void* src, void* dst, const do
   if (a < b + p->state_bytes && b < a + p->state_bytes)
     return fail(DL_ERR_ARG, "src and dst overlap");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  p->ph = make_phase(p->g.ndim, p->dt, p->c, p->m, phase_mode(p->m, V), p->fp64);
+  p->ph = make_phase(transports_per_step(p), p->dt, p->c, p->m, phase_mode(p->m, V), p->fp64);
   select_tiling(p, p->ph.mode);
   // passes deepest first; they alternate between dst and the plan's buffer
   // so that the last one writes dst

@@ -27,11 +27,13 @@
 
 namespace dirac {
 
-// K full steps per launch on a 1-D line or a 2-D plane (64 - 2K output
-// columns per wave, march segments of H rows in 2-D)
-template <typename T, int K, int AX0, int AX1, int MODE>
+// K full steps of scheme S per launch on a 1-D line or a 2-D plane (64 - 2X
+// output columns per wave, X = x transports of the pass; march segments of
+// H rows in 2-D)
+template <typename T, class S, int K, int AX0, int AX1, int MODE>
 __global__ __launch_bounds__(256, 2) void k_sweep2d(const T* __restrict__ src, T* __restrict__ dst,
-                                                 const double* __restrict__ V, SweepArgs a) {
+                                                    const double* __restrict__ V, SweepArgs a) {
+  constexpr int X = halo_lanes<S>(K);
   const int lane = threadIdx.x & 63;
   int64_t blk = blockIdx.x;
   if (a.xcd_remap) blk = (blk % 8) * (gridDim.x / 8) + blk / 8;
@@ -39,14 +41,14 @@ __global__ __launch_bounds__(256, 2) void k_sweep2d(const T* __restrict__ src, T
   if (tile >= a.ntiles) return;
   const int64_t strip = tile % a.nstrips;
   const int64_t seg = tile / a.nstrips;
-  const int64_t xs = strip * strip_width(K) - K;  // lanes K .. 63 - K are written
+  const int64_t xs = strip * strip_width(X) - X;  // lanes X .. 63 - X are written
   if constexpr (AX1 < 0) {
-    one_row<T, K, AX0, MODE>(src, dst, V, a, xs, lane);  // 1-D: one row, no march
+    one_row<T, S, K, AX0, MODE>(src, dst, V, a, xs, lane);  // 1-D: one row, no march
   } else {
     const int64_t jb = seg * a.H;
     const int64_t je = (jb + a.H < a.ny) ? jb + a.H : a.ny;
     // even segments march up, odd ones down
-    march_dir<T, K, AX0, AX1, MODE>(src, dst, V, a, xs, lane, jb, je, (seg & 1) == 0);
+    march_dir<T, S, K, AX0, AX1, MODE>(src, dst, V, a, xs, lane, jb, je, (seg & 1) == 0);
   }
 }
 
@@ -244,50 +246,58 @@ __global__ __launch_bounds__(1024) void k_resident1d(T* __restrict__ psi,
 // ---------------------------------------------------------------------------
 // launchers: the 1-D / 2-D kernel for (type, depth, axes, phase mode)
 // ---------------------------------------------------------------------------
-template <typename T, int K, int AX0, int AX1>
+template <typename T, class S, int K, int AX0, int AX1>
 static const void* kernel2d_mode(int mode) {
   switch (mode) {
-    case 0: return reinterpret_cast<const void*>(&k_sweep2d<T, K, AX0, AX1, 0>);
-    case 1: return reinterpret_cast<const void*>(&k_sweep2d<T, K, AX0, AX1, 1>);
-    default: return reinterpret_cast<const void*>(&k_sweep2d<T, K, AX0, AX1, 2>);
+    case 0: return reinterpret_cast<const void*>(&k_sweep2d<T, S, K, AX0, AX1, 0>);
+    case 1: return reinterpret_cast<const void*>(&k_sweep2d<T, S, K, AX0, AX1, 1>);
+    default: return reinterpret_cast<const void*>(&k_sweep2d<T, S, K, AX0, AX1, 2>);
   }
 }
 
-template <typename T, int K>
+template <typename T, class S, int K>
 static const void* kernel2d_axes(int axes_code, int mode) {
   switch (axes_code) {
-    case 0: return kernel2d_mode<T, K, 0, -1>(mode);
-    case 1: return kernel2d_mode<T, K, 1, -1>(mode);
-    case 2: return kernel2d_mode<T, K, 2, -1>(mode);
-    case 10: return kernel2d_mode<T, K, 0, 1>(mode);
-    case 20: return kernel2d_mode<T, K, 0, 2>(mode);
-    case 21: return kernel2d_mode<T, K, 1, 2>(mode);
+    case 0: return kernel2d_mode<T, S, K, 0, -1>(mode);
+    case 1: return kernel2d_mode<T, S, K, 1, -1>(mode);
+    case 2: return kernel2d_mode<T, S, K, 2, -1>(mode);
+    case 10: return kernel2d_mode<T, S, K, 0, 1>(mode);
+    case 20: return kernel2d_mode<T, S, K, 0, 2>(mode);
+    case 21: return kernel2d_mode<T, S, K, 1, 2>(mode);
     default: return nullptr;
   }
 }
 
-// nullptr for combinations that are not built (FP64 deeper than 2)
-static const void* kernel2d(bool fp64, int depth, int axes_code, int mode) {
+// nullptr for combinations that are not built (depths beyond max_depth)
+static const void* kernel2d(bool fp64, bool strang, int depth, int axes_code, int mode) {
+  if (strang) {
+    if (fp64) return depth == 1 ? kernel2d_axes<double, StrangStep, 1>(axes_code, mode) : nullptr;
+    switch (depth) {
+      case 1: return kernel2d_axes<float, StrangStep, 1>(axes_code, mode);
+      case 2: return kernel2d_axes<float, StrangStep, 2>(axes_code, mode);
+      default: return nullptr;
+    }
+  }
   if (fp64) {
     switch (depth) {
-      case 1: return kernel2d_axes<double, 1>(axes_code, mode);
-      case 2: return kernel2d_axes<double, 2>(axes_code, mode);
+      case 1: return kernel2d_axes<double, LieStep, 1>(axes_code, mode);
+      case 2: return kernel2d_axes<double, LieStep, 2>(axes_code, mode);
       default: return nullptr;
     }
   }
   switch (depth) {
-    case 1: return kernel2d_axes<float, 1>(axes_code, mode);
-    case 2: return kernel2d_axes<float, 2>(axes_code, mode);
-    case 3: return kernel2d_axes<float, 3>(axes_code, mode);
-    case 4: return kernel2d_axes<float, 4>(axes_code, mode);
-    case 5: return kernel2d_axes<float, 5>(axes_code, mode);
+    case 1: return kernel2d_axes<float, LieStep, 1>(axes_code, mode);
+    case 2: return kernel2d_axes<float, LieStep, 2>(axes_code, mode);
+    case 3: return kernel2d_axes<float, LieStep, 3>(axes_code, mode);
+    case 4: return kernel2d_axes<float, LieStep, 4>(axes_code, mode);
+    case 5: return kernel2d_axes<float, LieStep, 5>(axes_code, mode);
     default: return nullptr;
   }
 }
 
-hipError_t launch_sweep2d(bool fp64, int depth, const void* src, void* dst, const double* V,
-                          const SweepArgs& a, int blocks, hipStream_t st) {
-  const void* fn = kernel2d(fp64, depth, a.axes_code, a.ph.mode);
+hipError_t launch_sweep2d(bool fp64, bool strang, int depth, const void* src, void* dst,
+                          const double* V, const SweepArgs& a, int blocks, hipStream_t st) {
+  const void* fn = kernel2d(fp64, strang, depth, a.axes_code, a.ph.mode);
   if (!fn || blocks <= 0) return hipErrorInvalidValue;
   SweepArgs args = a;
   void* kargs[] = {const_cast<void**>(&src), &dst, const_cast<double**>(&V), &args};
@@ -305,7 +315,7 @@ static int occ_of(const void* kernel) {
   return n;
 }
 
-int sweep_occupancy(bool fp64, int ndim, int axes_code, int mode, int depth) {
+int sweep_occupancy(bool fp64, bool strang, int ndim, int axes_code, int mode, int depth) {
   if (ndim == 3) {
     if (fp64) {
       switch (mode) {
@@ -320,7 +330,7 @@ int sweep_occupancy(bool fp64, int ndim, int axes_code, int mode, int depth) {
       default: return occ_of(reinterpret_cast<const void*>(&k_sweep3d<float, kTY3D_F32, 2>));
     }
   }
-  return occ_of(kernel2d(fp64, depth, axes_code, mode));
+  return occ_of(kernel2d(fp64, strang, depth, axes_code, mode));
 }
 
 template <typename T, int TY>

@@ -138,31 +138,39 @@ __device__ __forceinline__ Lanes lanes_of(int64_t nx, int periodic, int64_t xs, 
 // ---------------------------------------------------------------------------
 // 1-D / 2-D fused pass of K full steps (temporal blocking).
 //
+// A step is a sequence of stages, each holding one y transport and row-local
+// work before and after it (the scheme, below):
+//   Lie (Sec. 2.1):    T_x, T_y, D                 -- one stage per step;
+//   Strang (Sec. 2.4): T_x, T_y, D | T_y, T_x      -- two stages per step,
+// every transport a one-cell shift.  A pass of K steps runs NS = K * stages
+// per step.
+//
 // A wave holds 64 consecutive columns (lane l: column xs + l) and writes the
-// middle 64 - 2K of them.  Step s (1..K) is valid on lanes s .. 63 - s: every
-// x neighbour it needs sits in the wave, so the neighbour exchange is a plain
+// middle 64 - 2X of them, X being the x transports of the pass: each x
+// transport is valid one lane further in from both ends, and every x
+// neighbour it needs sits in the wave, so the neighbour exchange is a plain
 // DPP shift and no lane loads a halo cell.  In 2-D the wave marches along y
-// over a segment of H rows.  Iteration it reads input row in_row(it); step s
-// then completes the row s behind it, from the step-(s-1) rows two behind,
-// one behind and current, keeping the y movers of two previous rows per step
-// in registers.  Each row is read once per segment (plus K halo rows at each
-// end) and written once, whatever K.
+// over a segment of H rows.  Iteration it reads input row in_row(it); stage
+// st (0-based) then completes the row st + 1 behind it, from the stage-(st-1)
+// rows two behind, one behind and current, keeping the y movers of two
+// previous rows per stage in registers.  Each row is read once per segment
+// (plus NS halo rows at each end) and written once, whatever K.
 //
 // Each intermediate state is rounded to T exactly as a stored single step, so
 // a pass of K steps gives the same bits as K passes of one step.  With zero
 // walls the intermediate states are forced to zero outside the box, as the
-// transports of the next step require.
+// transports of the next stage require.
 //
 // The potential of a row arrives with the row; its phase factors are formed
-// once, in the iteration that reads it, and applied by all K steps in the K
-// following iterations, so the dependent sine/cosine chain overlaps the
-// transports of other rows.  MODE (0: scale only, 1: constant mass phases,
-// 2: potential; < 0: read at run time) is a template parameter so that the
-// block has no mode branches.
+// once, in the iteration that reads it, and applied by every stage with a
+// local step in the following iterations, so the dependent sine/cosine chain
+// overlaps the transports of other rows.  MODE (0: scale only, 1: constant
+// mass phases, 2: potential; < 0: read at run time) is a template parameter
+// so that the block has no mode branches.
 //
 // Rolling state lives in register slots indexed by the iteration modulo
 // their period (row ring: L + 1 slots for L rows in flight, y movers: 2 per
-// step, factors: K + 1) and the loop is unrolled by a common multiple, so no
+// stage, factors: P) and the loop is unrolled by a common multiple, so no
 // register copies are needed to advance it.  Memory accesses sit outside
 // branches: rows and columns beyond a wall are read at a clamped address and
 // zeroed where they are consumed, rows past the segment end are read and
@@ -170,32 +178,64 @@ __device__ __forceinline__ Lanes lanes_of(int64_t nx, int periodic, int64_t xs, 
 // after the last row, so the loads of later rows stay in flight while the
 // current row is computed.
 // ---------------------------------------------------------------------------
-template <int K> struct MarchShape;  // L: rows in flight; U: unroll
-template <> struct MarchShape<1> { static constexpr int L = 3, U = 4; };
-template <> struct MarchShape<2> { static constexpr int L = 2, U = 6; };
-template <> struct MarchShape<3> { static constexpr int L = 3, U = 4; };
-template <> struct MarchShape<4> { static constexpr int L = 4, U = 10; };
-template <> struct MarchShape<5> { static constexpr int L = 2, U = 6; };
+struct LieStep {  // T_x, T_y, D
+  static constexpr int kStages = 1;  // stages per step
+  static constexpr int kXPerStep = 1;
+  static constexpr bool pre_x(int) { return true; }
+  static constexpr bool phase(int) { return true; }
+  static constexpr bool post_x(int) { return false; }
+};
+struct StrangStep {  // T_x, T_y, D, T_y, T_x (half-step transports)
+  static constexpr int kStages = 2;
+  static constexpr int kXPerStep = 2;
+  static constexpr bool pre_x(int st) { return st % 2 == 0; }
+  static constexpr bool phase(int st) { return st % 2 == 0; }
+  static constexpr bool post_x(int st) { return st % 2 == 1; }
+};
 
-template <typename T, int K, int AX0, int AX1, bool UP, int MODE>
+// x transports of a pass of K steps: lanes lost at each end of the wave
+template <class S> __host__ __device__ constexpr int halo_lanes(int K) { return K * S::kXPerStep; }
+
+template <class S, int K> struct MarchShape;  // L: rows in flight; U: unroll
+template <> struct MarchShape<LieStep, 1> { static constexpr int L = 3, U = 4; };
+template <> struct MarchShape<LieStep, 2> { static constexpr int L = 2, U = 6; };
+template <> struct MarchShape<LieStep, 3> { static constexpr int L = 3, U = 4; };
+template <> struct MarchShape<LieStep, 4> { static constexpr int L = 4, U = 10; };
+template <> struct MarchShape<LieStep, 5> { static constexpr int L = 2, U = 6; };
+template <> struct MarchShape<StrangStep, 1> { static constexpr int L = 3, U = 4; };
+template <> struct MarchShape<StrangStep, 2> { static constexpr int L = 3, U = 4; };
+
+// factor slots: rows from the newest read to the oldest still to be phased
+template <class S> constexpr int factor_slots(int NS) {
+  int last = 0;
+  for (int st = 0; st < NS; ++st)
+    if (S::phase(st)) last = st;
+  return last + 2;
+}
+
+template <typename T, class S, int K, int AX0, int AX1, bool UP, int MODE>
 __device__ __forceinline__ void march2d(const T* __restrict__ src, T* __restrict__ dst,
                                         const double* __restrict__ V, const SweepArgs& a,
                                         int64_t xs, int lane, int64_t jb, int64_t je) {
   constexpr bool TWO = sizeof(T) == 8;
-  constexpr int L = MarchShape<K>::L;  // rows in flight
-  constexpr int RS = L + 1;            // ring slots
-  constexpr int P = K + 1;             // factor slots
-  constexpr int U = MarchShape<K>::U;
+  constexpr int NS = K * S::kStages;          // stages of the pass
+  constexpr int X = halo_lanes<S>(K);         // x transports of the pass
+  constexpr int L = MarchShape<S, K>::L;      // rows in flight
+  constexpr int RS = L + 1;                   // ring slots
+  constexpr int P = factor_slots<S>(NS);      // factor slots
+  constexpr int U = MarchShape<S, K>::U;
   static_assert(U % RS == 0 && U % 2 == 0 && U % P == 0, "unroll must cover every period");
   const int64_t nx = a.nx, ny = a.ny;
-  const int nit = static_cast<int>(je - jb) + 2 * K;  // iterations with work
+  const int nit = static_cast<int>(je - jb) + 2 * NS;  // iterations with work
   const Lanes c = lanes_of(nx, a.periodic, xs, lane);
-  const bool own = c.inside && lane >= K && lane <= 63 - K;
+  const bool own = c.inside && lane >= X && lane <= 63 - X;
   const bool read_v = (MODE == 2) || (MODE < 0 && a.ph.mode == 2);
   const bool zero_walls = !a.periodic;
-  // input row of iteration it; step s completes row in_row(it) -+ s
-  auto in_row = [&](int it) -> int64_t { return UP ? jb - K + it : je - 1 + K - it; };
-  auto out_row = [&](int it, int st) -> int64_t { return UP ? in_row(it) - st : in_row(it) + st; };
+  // input row of iteration it; stage st completes row in_row(it) -+ (st + 1)
+  auto in_row = [&](int it) -> int64_t { return UP ? jb - NS + it : je - 1 + NS - it; };
+  auto out_row = [&](int it, int done) -> int64_t {
+    return UP ? in_row(it) - done : in_row(it) + done;
+  };
   auto load_in = [&](int it, Site<T>& m, double& v) {
     const int64_t r = read_row(in_row(it), ny, a.periodic);
     load_site(src + (r * nx + c.col) * 8, m);
@@ -207,17 +247,17 @@ __device__ __forceinline__ void march2d(const T* __restrict__ src, T* __restrict
   double vr[RS];
 #pragma unroll
   for (int k = 0; k < L; ++k) load_in(k, ring[k], vr[k]);
-  // slot it % P: phase factors of in_row(it); step s of iteration it uses
-  // slot (it - s) % P.  Slots of rows before the first input row feed only
-  // results that are not stored.
+  // slot it % P: phase factors of in_row(it); stage st of iteration it uses
+  // slot (it - st - 1) % P.  Slots of rows before the first input row feed
+  // only results that are not stored.
   Factors f[P];
 #pragma unroll
   for (int q = 0; q < P; ++q) f[q] = const_factors(a.ph);
-  // y movers of step s (index s - 1), slot it % 2: the step's input row two
-  // iterations back (r movers when marching up, l movers when down)
-  Mov<T> mv[K][2];
+  // y movers of stage st, slot it % 2: the stage's input row two iterations
+  // back (r movers when marching up, l movers when down)
+  Mov<T> mv[NS][2];
 #pragma unroll
-  for (int q = 0; q < K; ++q) {
+  for (int q = 0; q < NS; ++q) {
     zero(mv[q][0]);
     zero(mv[q][1]);
   }
@@ -238,39 +278,49 @@ __device__ __forceinline__ void march2d(const T* __restrict__ src, T* __restrict
       Factors& fnew = f[k % P];
       fnew = factors_of<MODE, TWO>(vcur, a.ph);
 #pragma unroll
-      for (int st = 1; st <= K; ++st) {
-        Site<T> phi;
-        x_transport_inner<T, AX0>(cur, phi);
+      for (int st = 0; st < NS; ++st) {
+        if (S::pre_x(st)) {
+          Site<T> phi;
+          x_transport_inner<T, AX0>(cur, phi);
+          cur = phi;
+        }
         Mov<T> ry, ly;
-        Axis<AX1, T>::movers(phi, ry, ly);
+        Axis<AX1, T>::movers(cur, ry, ly);
         Site<T> o;
         if (UP)
-          Axis<AX1, T>::combine(mv[st - 1][k % 2], ly, o);
+          Axis<AX1, T>::combine(mv[st][k % 2], ly, o);
         else
-          Axis<AX1, T>::combine(ry, mv[st - 1][k % 2], o);
-        mv[st - 1][k % 2] = UP ? ry : ly;
-        apply_local<MODE>(o, f[((k - st) % P + P) % P], a.ph);
-        if (st < K && zero_walls) {
-          const int64_t r = out_row(it, st);
+          Axis<AX1, T>::combine(ry, mv[st][k % 2], o);
+        mv[st][k % 2] = UP ? ry : ly;
+        if (S::phase(st)) apply_local<MODE>(o, f[((k - st - 1) % P + P) % P], a.ph);
+        if (S::post_x(st)) {
+          Site<T> phi;
+          x_transport_inner<T, AX0>(o, phi);
+          o = phi;
+        }
+        if (st < NS - 1 && zero_walls) {
+          const int64_t r = out_row(it, st + 1);
           if (r < 0 || r >= ny) zero(o);
           if (!c.full && !c.inside) zero(o);
         }
         cur = o;
       }
-      if (it >= 2 * K && own) store_site(dst + (out_row(it, K) * nx + c.x) * 8, cur);
+      if (it >= 2 * NS && own) store_site(dst + (out_row(it, NS) * nx + c.x) * 8, cur);
       factors_fix<MODE, TWO>(fnew, vcur, a.ph);
     }
   }
 }
 
-// K steps of a 1-D line for the 64 - 2K output cells of the wave
-template <typename T, int K, int AX, int MODE>
+// K steps of a 1-D line for the 64 - 2X output cells of the wave
+template <typename T, class S, int K, int AX, int MODE>
 __device__ __forceinline__ void one_row(const T* __restrict__ src, T* __restrict__ dst,
                                         const double* __restrict__ V, const SweepArgs& a,
                                         int64_t xs, int lane) {
   constexpr bool TWO = sizeof(T) == 8;
+  constexpr int X = halo_lanes<S>(K);
   const Lanes c = lanes_of(a.nx, a.periodic, xs, lane);
-  const bool own = c.inside && lane >= K && lane <= 63 - K;
+  const bool own = c.inside && lane >= X && lane <= 63 - X;
+  const bool walls = !a.periodic && !c.inside;  // this lane's cell lies beyond a wall
   Site<T> m;
   load_site(src + c.col * 8, m);
   if (c.out) zero(m);
@@ -279,25 +329,33 @@ __device__ __forceinline__ void one_row(const T* __restrict__ src, T* __restrict
   Factors f = factors_of<MODE, TWO>(v, a.ph);
   factors_fix<MODE, TWO>(f, v, a.ph);
 #pragma unroll
-  for (int st = 1; st <= K; ++st) {
-    Site<T> o;
-    x_transport_inner<T, AX>(m, o);
-    apply_local<MODE>(o, f, a.ph);
-    if (st < K && !a.periodic && !c.inside) zero(o);
-    m = o;
+  for (int s = 0; s < K * S::kStages; ++s) {
+    if (S::pre_x(s)) {
+      Site<T> o;
+      x_transport_inner<T, AX>(m, o);
+      m = o;
+      if (walls) zero(m);
+    }
+    if (S::phase(s)) apply_local<MODE>(m, f, a.ph);
+    if (S::post_x(s)) {
+      Site<T> o;
+      x_transport_inner<T, AX>(m, o);
+      m = o;
+      if (walls) zero(m);
+    }
   }
   if (own) store_site(dst + c.x * 8, m);
 }
 
 // march a 2-D segment upwards (up = true) or downwards
-template <typename T, int K, int AX0, int AX1, int MODE>
+template <typename T, class S, int K, int AX0, int AX1, int MODE>
 __device__ __forceinline__ void march_dir(const T* __restrict__ src, T* __restrict__ dst,
                                           const double* __restrict__ V, const SweepArgs& a,
                                           int64_t xs, int lane, int64_t jb, int64_t je, bool up) {
   if (up)
-    march2d<T, K, AX0, AX1, true, MODE>(src, dst, V, a, xs, lane, jb, je);
+    march2d<T, S, K, AX0, AX1, true, MODE>(src, dst, V, a, xs, lane, jb, je);
   else
-    march2d<T, K, AX0, AX1, false, MODE>(src, dst, V, a, xs, lane, jb, je);
+    march2d<T, S, K, AX0, AX1, false, MODE>(src, dst, V, a, xs, lane, jb, je);
 }
 
 }  // namespace dirac

@@ -243,6 +243,50 @@ def config_batch(count=256, nsteps=5000, seed=0, dx=0.01, sides=(256, 512, 1024)
     return out
 
 
+# The 2-D Klein run of Sec. 5.2.2: x-z plane, box x in [-15, 15], z in [-5, 5],
+# packet k0 = 100 along x with Delta = 1 and spinor (1, 0, 0, C), Sauter step
+# of thickness L = 0.0025 at x = 0, second-order steps with c dt = 2a.  The
+# paper's grid is 24576 x 8192 cells and 12000 steps (t = 0.214).  Readings:
+# the height is V0 = 2 m c^2 + 1e4 (the printed m c^2 + 1e4 lies in the total
+# reflection window; 2 m c^2 + 1e4 gives the printed analytic T = 0.2621), and
+# the packet starts at (x0, z0) = (-10, 0) as in the 1-D run.
+KLEIN2D = dict(x_half=15.0, z_half=5.0, k0=100.0, delta=1.0, L=0.0025, x0=-10.0, z0=0.0,
+               extra_height=1.0e4)
+
+
+def klein2d_factors(nx=24576, nz=8192, c=C_LIGHT, m=M_E):
+    """Separable pieces of the 2-D Klein inputs (so that large grids can be
+    assembled on the device): cell-centre coordinates, the normalised 1-D
+    envelopes along x and z, the spinor, the potential along x, dx and dt."""
+    k = KLEIN2D
+    dx = 2.0 * k["x_half"] / nx
+    if abs(2.0 * k["z_half"] / nz - dx) > 1e-15 * dx:
+        raise ValueError("the x and z cells must be equal: nx / nz = 3")
+    xs = centres(nx, dx, -k["x_half"])
+    zs = centres(nz, dx, -k["z_half"])
+    gx = np.exp(1j * k["k0"] * xs) * np.exp(-((xs - k["x0"]) ** 2) / (4.0 * k["delta"] ** 2))
+    gz = np.exp(-((zs - k["z0"]) ** 2) / (4.0 * k["delta"] ** 2)).astype(np.complex128)
+    u = spinor_u([k["k0"], 0.0, 0.0], c, m)
+    # dV sum |gz gx u|^2 = 1
+    gx = gx / math.sqrt(dx * float(np.sum(np.abs(gx) ** 2)))
+    gz = gz / math.sqrt(dx * float(np.sum(np.abs(gz) ** 2)) * float(np.sum(np.abs(u) ** 2)))
+    V0 = 2.0 * m * c * c + k["extra_height"]
+    Vx = 0.5 * V0 * (1.0 + np.tanh(xs / k["L"]))
+    return dict(dx=dx, dt=2.0 * dx / c, xs=xs, zs=zs, gx=gx, gz=gz, u=u, Vx=Vx, V0=V0,
+                xmin=[-k["x_half"], -k["z_half"]])
+
+
+def klein2d_workload(nx=24576, nz=8192, nsteps=12000) -> Workload:
+    """The 2-D Klein run as host arrays (for grids small enough to hold)."""
+    c, m = C_LIGHT, M_E
+    f = klein2d_factors(nx, nz, c, m)
+    psi = (f["gz"][:, None, None] * f["gx"][None, :, None]) * f["u"][None, None, :]
+    V = np.ascontiguousarray(np.broadcast_to(f["Vx"][None, :], (nz, nx)))
+    return Workload(f"klein2d-{nx}x{nz}", (nx, nz), f["dx"], f["dt"], c, m, nsteps,
+                    np.ascontiguousarray(psi), V, (0, 2), "zero", f["xmin"],
+                    {"V0": f["V0"], "scheme": "strang"})
+
+
 def random_spinor(shape_arr, seed=0, dtype=np.complex128, scale=1.0) -> np.ndarray:
     """Uniform random complex spinor field in [-scale, scale] (re and im), for
     parity checks that must not depend on smoothness."""

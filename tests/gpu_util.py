@@ -13,14 +13,15 @@ def announce(msg):
 
 
 def gpu_step(psi, V, *, dx, dt, c, m, nsteps, axes=None, bc="zero", dtype="c128", tiling=None,
-             graph=False, chunks=None, depth=None):
+             graph=False, chunks=None, depth=None, scheme="lie"):
     """Run dl_step on a copy of psi (numpy, (..., 4)); returns numpy."""
     import torch
     shape = tuple(reversed(psi.shape[:-1]))
     tdt = torch.complex128 if dtype == "c128" else torch.complex64
     t = torch.from_numpy(np.ascontiguousarray(psi)).to("cuda").to(tdt).contiguous()
     tV = None if V is None else torch.from_numpy(np.ascontiguousarray(V, dtype=np.float64)).to("cuda")
-    with L.Plan(shape, dx, dt, c, m, dtype=dtype, bc=bc, axes=axes, graph=graph) as p:
+    with L.Plan(shape, dx, dt, c, m, dtype=dtype, bc=bc, axes=axes, graph=graph,
+                scheme=scheme) as p:
         if tiling:
             p.set_tiling(**tiling)
         if depth is not None:

@@ -43,9 +43,9 @@ def test_library_exports_every_declared_symbol(lib):
     assert lib.dl_version() == 1
 
 
-def dry(shape, dx=0.01, dt=None, c=C, m=1.0, dtype="c64", bc="zero", axes=None):
+def dry(shape, dx=0.01, dt=None, c=C, m=1.0, dtype="c64", bc="zero", axes=None, scheme="lie"):
     return L.Plan(shape, dx, dx / c if dt is None else dt, c, m, dtype=dtype, bc=bc, axes=axes,
-                  dry=True)
+                  dry=True, scheme=scheme)
 
 
 def code_of(fn):
@@ -65,7 +65,7 @@ def test_dry_plan_accepts_valid_grids(lib):
 
 def test_dry_plan_rejections(lib):
     assert code_of(lambda: dry((64,), dt=0.0101 / C)) == L.DL_ERR_CFL
-    assert code_of(lambda: dry((64,), dt=2 * 0.01 / C)) == L.DL_ERR_CFL      # K = 2 not built
+    assert code_of(lambda: dry((64,), dt=2 * 0.01 / C)) == L.DL_ERR_CFL      # two-cell shifts: Strang only
     assert code_of(lambda: dry((64,), dt=0.01 / C * (1 + 1e-9))) == L.DL_ERR_CFL
     assert code_of(lambda: dry((1,))) == L.DL_ERR_ARG
     assert code_of(lambda: dry((8, 8, 8, 8))) == L.DL_ERR_ARG
@@ -77,6 +77,19 @@ def test_dry_plan_rejections(lib):
     assert code_of(lambda: dry((64,), m=float("nan"))) == L.DL_ERR_ARG
     assert code_of(lambda: dry((64,), dx=-0.01)) == L.DL_ERR_ARG
     assert code_of(lambda: dry((64,), c=0.0, dt=1.0)) == L.DL_ERR_ARG
+
+
+def test_dry_strang_plans(lib):
+    """Second-order plans: c dt = 2 dx, 1-D and 2-D grids only."""
+    for shape, axes in (((64,), (0,)), ((32, 16), (0, 2)), ((32, 16), (0, 1)), ((32, 16), (1, 2))):
+        for dtype in ("c64", "c128"):
+            p = dry(shape, dtype=dtype, axes=axes, dt=2 * 0.01 / C, scheme="strang")
+            p.close()
+    assert code_of(lambda: dry((64,), dt=0.01 / C, scheme="strang")) == L.DL_ERR_CFL
+    assert code_of(lambda: dry((64,), dt=2 * 0.01 / C * (1 + 1e-9), scheme="strang")) == L.DL_ERR_CFL
+    assert code_of(lambda: dry((8, 8, 8), dt=2 * 0.01 / C, scheme="strang")) == L.DL_ERR_ARG
+    with pytest.raises(ValueError):
+        dry((64,), scheme="rk4")
 
 
 def test_raw_abi_argument_errors(lib):

@@ -1,0 +1,75 @@
+"""Second-order (Strang) steps of Sec. 2.4 on the GPU against the oracle.
+
+Bars as for the lowest-order step: pure streaming bit-exact in FP64; full
+steps to relative L2 1e-12 in FP64 and within the FP32 rounding budget;
+passes of two fused steps give the bits of single steps.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1107_4650_amd.inputs import random_spinor, C_LIGHT
+from tests.gpu_util import announce, gpu_step, rel_l2, same_bits
+
+pytestmark = pytest.mark.gpu
+
+C = C_LIGHT
+DX = 0.01
+DT = 2 * DX / C  # each half-step transport moves one cell
+
+LAYOUTS = [((300,), (0,)), ((257,), (1,)), ((4099,), (2,)),
+           ((150, 37), (0, 1)), ((130, 45), (0, 2)), ((70, 33), (1, 2)), ((64, 64), (0, 1)),
+           ((61, 9), (0, 2))]
+
+
+def _ids(v):
+    return "x".join(str(int(s)) for s in v)
+
+
+@pytest.mark.parametrize("shape,axes", LAYOUTS, ids=[f"{_ids(s)}-ax{_ids(a)}" for s, a in LAYOUTS])
+@pytest.mark.parametrize("bc", ["zero", "periodic"])
+def test_strang_streaming_bit_exact_and_full_step(shape, axes, bc):
+    announce(f"strang {shape} axes={axes} bc={bc}")
+    psi = random_spinor(shape[::-1], seed=11 + sum(shape))
+    kw = dict(dx=DX, dt=DT, c=C, axes=axes, bc=bc, scheme="strang")
+    ref0 = O.step_strang(psi, None, dt=DT, c=C, m=0.0, nsteps=41, axes=axes, bc=bc)
+    assert same_bits(gpu_step(psi, None, m=0.0, nsteps=41, dtype="c128", **kw), ref0)
+    V = np.random.default_rng(4).uniform(-3, 3, size=shape[::-1]) * C * C
+    ref = O.step_strang(psi, V, dt=DT, c=C, m=1.0, nsteps=33, axes=axes, bc=bc)
+    got64 = gpu_step(psi, V, m=1.0, nsteps=33, dtype="c128", **kw)
+    assert rel_l2(got64, ref) <= 1e-12
+    got32 = gpu_step(psi.astype(np.complex64), V, m=1.0, nsteps=33, dtype="c64", **kw)
+    assert rel_l2(got32, ref) <= 5e-6
+    refm = O.step_strang(psi, None, dt=DT, c=C, m=1.0, nsteps=5, axes=axes, bc=bc)
+    gotm = gpu_step(psi, None, m=1.0, nsteps=5, dtype="c128", **kw)
+    assert rel_l2(gotm, refm) <= 1e-13
+
+
+@pytest.mark.parametrize("shape,axes,bc", [((300, 260), (0, 2), "zero"), ((130, 45), (0, 1), "periodic"),
+                                           ((5000,), (0,), "zero"), ((4099,), (2,), "periodic"),
+                                           ((57, 8), (1, 2), "periodic"), ((200, 7), (0, 2), "periodic")])
+def test_strang_fused_passes_same_bits(shape, axes, bc):
+    announce(f"strang fused {shape} {axes} {bc}")
+    psi = random_spinor(shape[::-1], seed=5).astype(np.complex64)
+    V = np.random.default_rng(6).uniform(-2, 2, size=shape[::-1]) * C * C
+    kw = dict(dx=DX, dt=DT, c=C, m=1.0, axes=axes, bc=bc, dtype="c64", scheme="strang",
+              tiling={"allow_resident": False})
+    for n in (1, 2, 3, 8):
+        single = gpu_step(psi, V, nsteps=n, depth=1, **kw)
+        assert same_bits(single, gpu_step(psi, V, nsteps=n, depth=2, **kw)), n
+
+
+def test_strang_klein_setup_small():
+    """The 2-D Klein run's physics (x-z plane, Sauter step V0 = 2mc^2 + 1e4,
+    k0 = 100) on a coarse 768 x 256 grid of the same box, 240 steps, FP64 and
+    FP32 against the oracle."""
+    from paper_1107_4650_amd.inputs import klein2d_workload
+    w = klein2d_workload(nx=768, nz=256, nsteps=240)
+    announce("strang klein small")
+    ref = O.step_strang(w.psi0, w.V, dt=w.dt, c=w.c, m=w.m, nsteps=w.nsteps, axes=w.axes)
+    got = gpu_step(w.psi0, w.V, dx=w.dx, dt=w.dt, c=w.c, m=w.m, nsteps=w.nsteps, axes=w.axes,
+                   scheme="strang")
+    assert rel_l2(got, ref) <= 1e-12
+    got32 = gpu_step(w.psi0.astype(np.complex64), w.V, dx=w.dx, dt=w.dt, c=w.c, m=w.m,
+                     nsteps=w.nsteps, axes=w.axes, dtype="c64", scheme="strang")
+    assert rel_l2(got32, ref) <= 2e-5
