@@ -32,6 +32,12 @@
  *     then the transports over dt/2 in the reverse order.  Each half-step
  *     transport is the same one-cell characteristic shift, i.e. the grid
  *     obeys c*(dt/2) = a.
+ *   - D with a vector potential (eq:sol_dis_4 with the closed form of the
+ *     exponential of Dirac matrices, Sec. 2.3): psi <- U exp(-i Vtilde) psi,
+ *     U = cos(A) + i (-beta m c^2 dt + alpha . Atilde) sin(A) / A,
+ *     A = sqrt((m c^2 dt)^2 + Atilde . Atilde), written as the printed 4x4
+ *     matrix; Atilde (the field integral e int A dtau over the step,
+ *     eq:field_dis1) is given per cell.
  *   - Observables: norm, mean coordinates and the probability beyond x_b
  *     (Sec. 5.2.1, R/T integrals), as sequential Neumaier sums in FP64.
  *   - The discrete adjoint of the step (derived from eq:sol_dis_1-4) by
@@ -269,6 +275,47 @@ static void local_step(const grid_t *g, zd *psi, const double *V,
     }
 }
 
+/* D with a vector potential: psi <- U(i) exp(-i V(i) dt) psi with U the
+ * printed 4x4 matrix of Sec. 2.3 (entries in terms of c(A), s(A), m c^2 dt
+ * and the components of Atilde).  Atil is planar: Atil[d * ns + s] is the
+ * component d (x, y, z) at site s, or NULL for no field.  For A = 0
+ * (massless, no field) sin(A)/A is its limit 1. */
+static void local_step_field(const grid_t *g, zd *psi, const double *V, const double *Atil,
+                             double dt, double c, double m)
+{
+    const int64_t ns = nsites(g);
+    const double mu = m * c * c * dt;
+    #pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < ns; ++s) {
+        const double ax = Atil ? Atil[s] : 0.0;
+        const double ay = Atil ? Atil[ns + s] : 0.0;
+        const double az = Atil ? Atil[2 * ns + s] : 0.0;
+        const double A = sqrt(mu * mu + ax * ax + ay * ay + az * az);
+        const double cA = cos(A);
+        const double sA = (A > 0.0) ? sin(A) / A : 1.0;  /* s(A) / A */
+        zd U[4][4];
+        memset(U, 0, sizeof U);
+        U[0][0] = CMPLX(cA, -mu * sA);
+        U[1][1] = CMPLX(cA, -mu * sA);
+        U[2][2] = CMPLX(cA, mu * sA);
+        U[3][3] = CMPLX(cA, mu * sA);
+        U[0][2] = CMPLX(0.0, az * sA);
+        U[0][3] = CMPLX(ay * sA, ax * sA);
+        U[1][2] = CMPLX(-ay * sA, ax * sA);
+        U[1][3] = CMPLX(0.0, -az * sA);
+        U[2][0] = CMPLX(0.0, az * sA);
+        U[2][1] = CMPLX(ay * sA, ax * sA);
+        U[3][0] = CMPLX(-ay * sA, ax * sA);
+        U[3][1] = CMPLX(0.0, -az * sA);
+        const double th = (V ? V[s] : 0.0) * dt;
+        const zd ph = CMPLX(cos(th), -sin(th));
+        zd v[4], out[4];
+        for (int k = 0; k < 4; ++k) v[k] = psi[4 * s + k] * ph;
+        matvec_d(U, v, out);
+        for (int k = 0; k < 4; ++k) psi[4 * s + k] = out[k];
+    }
+}
+
 /* ------------------------------------------------------------------ */
 /* Public entry points (called through ctypes by the tests)             */
 /* ------------------------------------------------------------------ */
@@ -378,6 +425,44 @@ int oracle_step_strang(int ndim, const int64_t *n, const int *axis, int bc,
     zd *tmp = (zd *)malloc((size_t)nsites(&g) * 4 * sizeof(zd));
     if (!tmp) return -2;
     for (int64_t s = 0; s < nsteps; ++s) step_once_strang(&g, (zd *)psi, tmp, V, dt, c, m);
+    free(tmp);
+    return 0;
+}
+
+/* nsteps steps with a vector potential: the lowest-order step (scheme 0) or
+ * the second-order step of Sec. 2.4 (scheme 1, 1-D and 2-D), with D
+ * replaced by local_step_field. */
+int oracle_step_field(int ndim, const int64_t *n, const int *axis, int bc, int scheme,
+                      double dt, double c, double m, const double *V, const double *Atil,
+                      double *psi, int64_t nsteps, int nthreads)
+{
+    grid_t g;
+    if ((scheme == 1 && ndim > 2) || scheme < 0 || scheme > 1 ||
+        grid_from_args(&g, ndim, n, axis, bc) || nsteps < 0)
+        return -1;
+    build_matrices();
+    set_threads(nthreads);
+    zd *tmp = (zd *)malloc((size_t)nsites(&g) * 4 * sizeof(zd));
+    if (!tmp) return -2;
+    int order[3];
+    const int k = transport_order(&g, order);
+    const int64_t bytes = nsites(&g) * 4 * (int64_t)sizeof(zd);
+    zd *p = (zd *)psi;
+    for (int64_t st = 0; st < nsteps; ++st) {
+        for (int t = 0; t < k; ++t) {
+            const int a = g.axis[order[t]];
+            transport_d(&g, order[t], PROJ[a][0], PROJ[a][1], p, tmp);
+            memcpy(p, tmp, (size_t)bytes);
+        }
+        local_step_field(&g, p, V, Atil, dt, c, m);
+        if (scheme == 1) {
+            for (int t = k - 1; t >= 0; --t) {
+                const int a = g.axis[order[t]];
+                transport_d(&g, order[t], PROJ[a][0], PROJ[a][1], p, tmp);
+                memcpy(p, tmp, (size_t)bytes);
+            }
+        }
+    }
     free(tmp);
     return 0;
 }

@@ -50,6 +50,9 @@ def _load():
                                     ctypes.c_int]
         lib.oracle_adjoint_step.argtypes = lib.oracle_step.argtypes
         lib.oracle_step_strang.argtypes = lib.oracle_step.argtypes
+        lib.oracle_step_field.argtypes = [ctypes.c_int, i64p, ip, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_double, ctypes.c_double, ctypes.c_double, dp,
+                                          dp, dp, ctypes.c_int64, ctypes.c_int]
         lib.oracle_stream_f32.argtypes = [ctypes.c_int, i64p, ip, ctypes.c_int, dp,
                                           ctypes.c_int64, ctypes.c_int]
         lib.oracle_observables.argtypes = [ctypes.c_int, i64p, ctypes.c_double, dp, dp,
@@ -61,6 +64,7 @@ def _load():
         lib.oracle_dirac_matrices.argtypes = [dp]
         lib.oracle_max_threads.restype = ctypes.c_int
         for f in (lib.oracle_step, lib.oracle_adjoint_step, lib.oracle_step_strang,
+                  lib.oracle_step_field,
                   lib.oracle_stream_f32,
                   lib.oracle_observables, lib.oracle_grad):
             f.restype = ctypes.c_int
@@ -122,6 +126,27 @@ def step_strang(psi, V=None, *, dt, c, m, nsteps, axes=None, bc="zero", threads=
                                     int(threads))
     if rc:
         raise RuntimeError(f"oracle_step_strang failed ({rc})")
+    return psi
+
+
+def step_field(psi, V=None, A=None, *, dt, c, m, nsteps, axes=None, bc="zero", scheme="lie",
+               threads=0):
+    """Return psi after `nsteps` steps whose local step carries a vector
+    potential: D = U exp(-i V dt) with the 4x4 U of Sec. 2.3.  A: the field
+    integral Atilde per cell, shape (3,) + grid (x, y, z components), or None."""
+    psi = np.array(psi, dtype=np.complex128, order="C", copy=True)
+    V = _check_V(V, psi)
+    if A is not None:
+        A = np.ascontiguousarray(A, dtype=np.float64)
+        if A.shape != (3,) + psi.shape[:-1]:
+            raise ValueError("A must have shape (3,) + grid")
+    ndim, n, ax = _grid_args(psi, axes)
+    rc = _load().oracle_step_field(ndim, n, ax, _bc(bc), {"lie": 0, "strang": 1}[scheme], dt, c,
+                                   m, None if V is None else _ptr(V),
+                                   None if A is None else _ptr(A), _ptr(psi), int(nsteps),
+                                   int(threads))
+    if rc:
+        raise RuntimeError(f"oracle_step_field failed ({rc})")
     return psi
 
 
