@@ -224,9 +224,44 @@ def bench_extras(args, line):
     ex["adjoint_1024"] = bench_adjoint(args)
     # batch of 256 uneven instances vs the same instances one at a time
     ex["batch_256"] = bench_batch(args)
+    # local step with a static vector potential on the 2048^2 FP32 workload
+    ex["field_2048_f32"] = bench_field(args)
     if args.klein_steps > 0:
         ex["klein2d_24576x8192_strang"] = bench_klein2d(args)
     line["extras"] = ex
+
+
+def bench_field(args, steps=400):
+    """The 2-D 2048^2 tanh-step workload with a static vector potential in the
+    local step (field integral At_y = 0.05 sin(2 pi x / 5) per step, a
+    synthetic smooth field), complex64 state: dl_step_field, passes of 2."""
+    import torch
+    from paper_1107_4650_amd import libdirac as L
+    from paper_1107_4650_amd.inputs import config_2d_tanh, coord_mesh
+    w = config_2d_tanh(n=2048, nsteps=steps)
+    X = coord_mesh(w.shape, w.dx)[0]
+    A = np.zeros((3,) + w.shape[::-1])
+    A[1] = np.broadcast_to(0.05 * np.sin(2 * np.pi * X / 5.0), w.shape[::-1])
+    V, At = to_dev(w.V), to_dev(A)
+    with L.Plan(w.shape, w.dx, w.dt, w.c, w.m, dtype="c64", xmin=w.xmin) as p:
+        psi = to_dev(w.psi0, torch.complex64)
+        p.step_field(psi, V, At, 20)
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        p.step_field(psi, V, At, steps)
+        e.record()
+        torch.cuda.synchronize()
+        ms = s.elapsed_time(e)
+        norm = p.observables(psi, 0.0)[0]
+    del psi, V, At
+    torch.cuda.empty_cache()
+    # per pass of 2 steps: psi read + written (64 B), V (8 B), At (24 B) per cell
+    return {"steps": steps, "ms_per_step": ms / steps, "steps_per_pass": 2,
+            "site_updates_per_s": w.sites * steps / (ms * 1e-3),
+            "bytes_per_site_update": 96 / 2,
+            "hbm_frac": 96 * w.sites / (2 * ms / steps * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "norm": norm}
 
 
 def bench_klein2d(args):

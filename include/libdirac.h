@@ -108,6 +108,21 @@ int dl_step(dl_plan p, void *psi, const double *V, int64_t nsteps, void *stream)
  * fewer than twice that many rows; the remainder of nsteps runs in
  * shallower passes.  The bits do not depend on this grouping.) */
 
+/* dl_step with a vector potential in the local step (eq:sol_dis_4 and the
+ * closed-form exponential of Dirac matrices of Sec. 2.3):
+ *     D psi = U exp(-i V dt) psi,
+ *     U = cos(A) + i (-beta m c^2 dt + alpha . At) sin(A) / A,
+ *     A = sqrt((m c^2 dt)^2 + At . At)   (sin(A)/A -> 1 as A -> 0).
+ * A: device array of 3 * cells doubles, planar: the x, y and z components of
+ * the field integral At = e int A dtau over one step (eq:field_dis1) at the
+ * cell centres, each block in psi's cell order; held fixed for the nsteps
+ * steps of the call (a time-dependent field is applied by calls over shorter
+ * spans).  A = NULL is dl_step.  1-D and 2-D grids (DL_ERR_ARG on 3-D), both
+ * splittings; passes fuse at most 2 steps (1 with complex128 state or
+ * DL_STRANG).  Same buffers and copy rule as dl_step. */
+int dl_step_field(dl_plan p, void *psi, const double *V, const double *A, int64_t nsteps,
+                  void *stream);
+
 /* One step out of place: dst = S src (same step as dl_step with nsteps = 1).
  * src and dst must not overlap; src is left unchanged.  Lets a caller keep
  * both time levels, or alternate two buffers without the copy dl_step makes

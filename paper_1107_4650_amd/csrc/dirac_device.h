@@ -423,6 +423,102 @@ __device__ __forceinline__ void factors_fix(Factors& f, double V, const PhaseK& 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Local step with a vector potential (eq:sol_dis_4 with the closed-form
+// exponential of Dirac matrices, Sec. 2.3):
+//   D = U exp(-i V dt),  U = cos(A) + i (-beta mu + alpha . At) sin(A) / A,
+//   mu = m c^2 dt, A = sqrt(mu^2 + At . At), At the field integral of the
+//   step at the cell.
+// In the Dirac representation U has the blocks
+//   [[ (cos A - i mu sA) I,   i sA sigma.At ],
+//    [ i sA sigma.At,         (cos A + i mu sA) I ]],   sA = sin(A) / A,
+// so per cell three complex numbers (times s exp(-i V dt)) and At suffice.
+// ---------------------------------------------------------------------------
+struct FieldFactors {
+  double ur, ui;      // s e^{-iVdt} (cos A - i mu sA): components a, b
+  double dr, di;      // s e^{-iVdt} (cos A + i mu sA): components c, d
+  double qr, qi;      // s e^{-iVdt} i sA: both off-diagonal blocks
+  double ax, ay, az;  // At
+};
+
+template <bool TWO>
+__device__ __forceinline__ bool field_far(double V, double ax, double ay, double az,
+                                          const PhaseK& k) {
+  const double mu = k.mc2 * k.dt;
+  return far_arg(sqrt(mu * mu + ax * ax + ay * ay + az * az)) || far_arg(V * k.dt);
+}
+
+template <bool TWO, bool ANY>
+__device__ __forceinline__ FieldFactors field_factors(double V, double ax, double ay, double az,
+                                                      const PhaseK& k) {
+  constexpr int ACC = TWO ? 2 : 1;
+  const double mu = k.mc2 * k.dt;
+  const double A = sqrt(mu * mu + ax * ax + ay * ay + az * az);
+  double sA, cA, sv, cv;
+  if constexpr (ANY) {
+    sincos_any<ACC>(A, &sA, &cA);
+    sincos_any<ACC>(V * k.dt, &sv, &cv);
+  } else {
+    sincos_fast<ACC>(A, &sA, &cA);
+    sincos_fast<ACC>(V * k.dt, &sv, &cv);
+  }
+  const double sa = (A > 0.0) ? sA / A : 1.0;
+  // ph = s e^{-i V dt}
+  const double pr = k.scale * cv, pi = -k.scale * sv;
+  const double ms = mu * sa;
+  FieldFactors f;
+  f.ur = fma(pr, cA, pi * ms);   // ph * (cA - i ms)
+  f.ui = fma(pi, cA, -pr * ms);
+  f.dr = fma(pr, cA, -pi * ms);  // ph * (cA + i ms)
+  f.di = fma(pi, cA, pr * ms);
+  f.qr = -pi * sa;               // ph * (i sa)
+  f.qi = pr * sa;
+  f.ax = ax;
+  f.ay = ay;
+  f.az = az;
+  return f;
+}
+
+// if any lane of the wave has an angle outside the fast reduction range,
+// recompute the wave's factors with the library fallback (a rare branch)
+template <bool TWO>
+__device__ __forceinline__ void field_fix(FieldFactors& f, double V, double ax, double ay,
+                                          double az, const PhaseK& k) {
+  if (__any(field_far<TWO>(V, ax, ay, az, k))) f = field_factors<TWO, true>(V, ax, ay, az, k);
+}
+
+// psi <- U e^{-i V dt} psi (with the deferred scale), promoted to FP64 and
+// rounded once per component
+template <typename T>
+__device__ __forceinline__ void apply_field(Site<T>& s, const FieldFactors& f) {
+  const double ar = s.v[0], ai = s.v[1], br = s.v[2], bi = s.v[3];
+  const double cr = s.v[4], ci = s.v[5], dr = s.v[6], di = s.v[7];
+  // sigma.At (x, y):  (az x0 + (ax - i ay) x1,  (ax + i ay) x0 - az x1)
+  auto sig = [&](double x0r, double x0i, double x1r, double x1i, double& o0r, double& o0i,
+                 double& o1r, double& o1i) {
+    o0r = fma(f.az, x0r, fma(f.ax, x1r, f.ay * x1i));
+    o0i = fma(f.az, x0i, fma(f.ax, x1i, -f.ay * x1r));
+    o1r = fma(f.ax, x0r, fma(-f.ay, x0i, -f.az * x1r));
+    o1i = fma(f.ax, x0i, fma(f.ay, x0r, -f.az * x1i));
+  };
+  double t1r, t1i, t2r, t2i, t3r, t3i, t4r, t4i;
+  sig(cr, ci, dr, di, t1r, t1i, t2r, t2i);  // acts on the lower pair
+  sig(ar, ai, br, bi, t3r, t3i, t4r, t4i);  // acts on the upper pair
+  // x' = diag * x + q * t
+  auto mix = [&](double xr, double xi, double gr, double gi, double tr, double ti, T& oR, T& oI) {
+    oR = static_cast<T>(fma(gr, xr, fma(-gi, xi, fma(f.qr, tr, -f.qi * ti))));
+    oI = static_cast<T>(fma(gr, xi, fma(gi, xr, fma(f.qr, ti, f.qi * tr))));
+  };
+  mix(ar, ai, f.ur, f.ui, t1r, t1i, s.v[0], s.v[1]);
+  mix(br, bi, f.ur, f.ui, t2r, t2i, s.v[2], s.v[3]);
+  mix(cr, ci, f.dr, f.di, t3r, t3i, s.v[4], s.v[5]);
+  mix(dr, di, f.dr, f.di, t4r, t4i, s.v[6], s.v[7]);
+}
+
+// Phase factors of a cell for phase mode MODE (3: with a vector potential)
+template <int MODE> struct FactorOf { using type = Factors; };
+template <> struct FactorOf<3> { using type = FieldFactors; };
+
 // Full local step on one site (V ignored unless mode == 2).
 template <typename T>
 __device__ __forceinline__ void local_step(Site<T>& s, double V, const PhaseK& k) {

@@ -19,6 +19,11 @@ constexpr int kMaxDepth = 5;
 __host__ __device__ constexpr int max_depth(bool fp64, bool strang) {
   return strang ? (fp64 ? 1 : 2) : (fp64 ? 2 : kMaxDepth);
 }
+// passes whose local step carries a vector potential (phase mode 3) hold
+// nine doubles of factors per row in flight: they fuse at most 2 steps
+__host__ __device__ constexpr int field_max_depth(bool fp64, bool strang) {
+  return (fp64 || strang) ? 1 : 2;
+}
 __host__ __device__ constexpr int strip_width(int xlanes) { return 64 - 2 * xlanes; }
 __host__ __device__ constexpr int pass_xlanes(bool strang, int depth) {
   return strang ? 2 * depth : depth;
@@ -35,6 +40,9 @@ struct SweepArgs {
   int xcd_remap;       // blocks dealt XCD-contiguously (grid a multiple of 8)
   int axes_code;       // 1-D: axis; 2-D: 10*axis0 + axis1 with axis1 > axis0 ... see plan
   PhaseK ph;
+  // phase mode 3: field integrals At, planar (x, y, z blocks of `cells`)
+  const double* At;
+  int64_t cells;
 };
 
 struct ResidentArgs {

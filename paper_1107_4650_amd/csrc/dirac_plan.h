@@ -47,7 +47,9 @@ struct dl_plan_s {
   int depth = 1;                        // fused steps per pass in use
   int waves_per_cu = 0;        // 0: size the grid from the kernels' occupancy
   int cu_count = 256;
-  dirac::PlanTiling tiling[3];  // per phase mode
+  dirac::PlanTiling tiling[4];  // per phase mode (3: with a vector potential)
+  int depth_field = 1;          // fused steps per pass with a vector potential
+  const double* field = nullptr;  // field integrals of the current call (mode 3)
   int seg_override = 0;
   bool allow_resident = true;
   bool resident = false;

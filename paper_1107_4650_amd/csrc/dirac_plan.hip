@@ -179,7 +179,7 @@ int dirac::transports_per_step(dl_plan p) { return (p->strang ? 2 : 1) * p->g.nd
 
 // make the tilings of phase mode `mode` current
 static void select_tiling(dl_plan p, int mode) {
-  const PlanTiling& t = p->tiling[mode < 0 || mode > 2 ? 2 : mode];
+  const PlanTiling& t = p->tiling[mode < 0 || mode > 3 ? 2 : mode];
   for (int d = 0; d < kMaxDepth; ++d) {
     p->sw[d] = t.a[d];
     p->bl[d] = t.b[d];
@@ -208,13 +208,15 @@ static int plan_tiling(dl_plan p) {
       while (depth > 1 && p->g.n[1] < 2 * stages_per_step * depth) --depth;
   }
   p->depth = depth;
-  for (int mode = 0; mode < 3; ++mode) {
+  p->depth_field = std::min(depth, field_max_depth(p->fp64, p->strang));
+  for (int mode = 0; mode < 4; ++mode) {
     PlanTiling& t = p->tiling[mode];
     if (p->g.ndim == 3) {
+      if (mode == 3) continue;  // no vector potential on 3-D grids
       make_tiling3d(p->g, p->fp64 ? kTY3D_F64 : kTY3D_F32, resident_waves(p, mode, 1),
                     p->seg_override, t.a[0], t.b[0]);
     } else {
-      for (int d = 1; d <= depth; ++d)
+      for (int d = 1; d <= (mode == 3 ? p->depth_field : depth); ++d)
         make_tiling(p->g, resident_waves(p, mode, d), p->seg_override, t.a[d - 1], t.b[d - 1],
                     strip_width(pass_xlanes(p->strang, d)));
     }
@@ -354,6 +356,8 @@ hipError_t launch_pass(dl_plan p, int depth, const void* src, void* dst, const d
   }
   SweepArgs a = p->sw[depth - 1];
   a.ph = p->ph;
+  a.At = p->field;
+  a.cells = p->cells;
   return launch_sweep2d(p->fp64, p->strang, depth, src, dst, V, a, p->bl[depth - 1], st);
 }
 
@@ -365,7 +369,8 @@ hipError_t enqueue_steps(dl_plan p, void* psi, const double* V, int64_t nsteps, 
   void* a = psi;
   void* b = p->tmp;
   int64_t left = nsteps;
-  for (int d = p->depth; d >= 1; --d) {
+  const int dmax = (p->ph.mode == 3) ? p->depth_field : p->depth;
+  for (int d = dmax; d >= 1; --d) {
     for (; left >= d; left -= d) {
       hipError_t e = launch_pass(p, d, a, b, V, st);
       if (e != hipSuccess) return e;
@@ -423,6 +428,7 @@ extern "C" int dl_step(dl_plan p, void* psi, const double* V, int64_t nsteps, vo
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int mode = phase_mode(p->m, V);
   p->ph = make_phase(transports_per_step(p), p->dt, p->c, p->m, mode, p->fp64);
+  p->field = nullptr;
   select_tiling(p, mode);
   if (p->resident) {
     ResidentArgs ra{};
@@ -455,6 +461,32 @@ extern "C" int dl_step(dl_plan p, void* psi, const double* V, int64_t nsteps, vo
   return DL_OK;
 }
 
+extern "C" int dl_step_field(dl_plan p, void* psi, const double* V, const double* A,
+                             int64_t nsteps, void* stream) {
+  int rc = check_live(p);
+  if (rc) return rc;
+  if (!A) return dl_step(p, psi, V, nsteps, stream);
+  if ((rc = check_state_ptr(psi, "psi"))) return rc;
+  if ((rc = check_f64_ptr(V, "V", true))) return rc;
+  if ((rc = check_f64_ptr(A, "A", false))) return rc;
+  if (p->g.ndim > 2) return fail(DL_ERR_ARG, "the vector potential is built for 1-D and 2-D grids");
+  if (nsteps < 0) return fail(DL_ERR_ARG, "nsteps = %lld < 0", static_cast<long long>(nsteps));
+  if (nsteps == 0) return DL_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  p->ph = make_phase(transports_per_step(p), p->dt, p->c, p->m, 3, p->fp64);
+  p->field = A;
+  select_tiling(p, 3);
+  void* res = nullptr;
+  hipError_t e = enqueue_steps(p, psi, V, nsteps, st, &res);
+  p->field = nullptr;
+  if (e != hipSuccess) return hip_fail(e, "sweep launch");
+  if (res != psi) {
+    e = hipMemcpyAsync(psi, res, p->state_bytes, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+  }
+  return DL_OK;
+}
+
 extern "C" int dl_step_out(dl_plan p, const void* src, void* dst, const double* V,
                            void* stream) {
   int rc = check_live(p);
@@ -468,6 +500,7 @@ extern "C" int dl_step_out(dl_plan p, const void* src, void* dst, const double* 
     return fail(DL_ERR_ARG, "src and dst overlap");
   hipStream_t st = static_cast<hipStream_t>(stream);
   p->ph = make_phase(transports_per_step(p), p->dt, p->c, p->m, phase_mode(p->m, V), p->fp64);
+  p->field = nullptr;
   select_tiling(p, p->ph.mode);
   hipError_t e = launch_pass(p, 1, src, dst, V, st);
   return e == hipSuccess ? DL_OK : hip_fail(e, "sweep launch");
@@ -487,6 +520,7 @@ extern "C" int dl_step_fused_out(dl_plan p, const void* src, void* dst, const do
     return fail(DL_ERR_ARG, "src and dst overlap");
   hipStream_t st = static_cast<hipStream_t>(stream);
   p->ph = make_phase(transports_per_step(p), p->dt, p->c, p->m, phase_mode(p->m, V), p->fp64);
+  p->field = nullptr;
   select_tiling(p, p->ph.mode);
   // passes deepest first; they alternate between dst and the plan's buffer
   // so that the last one writes dst

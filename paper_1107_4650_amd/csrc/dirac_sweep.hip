@@ -25,6 +25,8 @@
 #include "dirac_launch.h"
 #include "dirac_sweep_impl.h"
 
+#include <type_traits>
+
 namespace dirac {
 
 // K full steps of scheme S per launch on a 1-D line or a 2-D plane (64 - 2X
@@ -248,10 +250,18 @@ __global__ __launch_bounds__(1024) void k_resident1d(T* __restrict__ psi,
 // ---------------------------------------------------------------------------
 template <typename T, class S, int K, int AX0, int AX1>
 static const void* kernel2d_mode(int mode) {
+  constexpr bool kField =
+      K <= field_max_depth(sizeof(T) == 8, std::is_same<S, StrangStep>::value);
   switch (mode) {
     case 0: return reinterpret_cast<const void*>(&k_sweep2d<T, S, K, AX0, AX1, 0>);
     case 1: return reinterpret_cast<const void*>(&k_sweep2d<T, S, K, AX0, AX1, 1>);
-    default: return reinterpret_cast<const void*>(&k_sweep2d<T, S, K, AX0, AX1, 2>);
+    case 2: return reinterpret_cast<const void*>(&k_sweep2d<T, S, K, AX0, AX1, 2>);
+    case 3:
+      if constexpr (kField)
+        return reinterpret_cast<const void*>(&k_sweep2d<T, S, K, AX0, AX1, 3>);
+      else
+        return nullptr;
+    default: return nullptr;
   }
 }
 

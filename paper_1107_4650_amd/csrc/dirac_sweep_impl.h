@@ -229,30 +229,44 @@ __device__ __forceinline__ void march2d(const T* __restrict__ src, T* __restrict
   const int nit = static_cast<int>(je - jb) + 2 * NS;  // iterations with work
   const Lanes c = lanes_of(nx, a.periodic, xs, lane);
   const bool own = c.inside && lane >= X && lane <= 63 - X;
-  const bool read_v = (MODE == 2) || (MODE < 0 && a.ph.mode == 2);
+  constexpr bool FIELD = MODE == 3;             // local step with a vector potential
+  using FT = typename FactorOf<MODE>::type;
+  const bool read_v = (MODE == 2) || (FIELD && V != nullptr) || (MODE < 0 && a.ph.mode == 2);
   const bool zero_walls = !a.periodic;
   // input row of iteration it; stage st completes row in_row(it) -+ (st + 1)
   auto in_row = [&](int it) -> int64_t { return UP ? jb - NS + it : je - 1 + NS - it; };
   auto out_row = [&](int it, int done) -> int64_t {
     return UP ? in_row(it) - done : in_row(it) + done;
   };
-  auto load_in = [&](int it, Site<T>& m, double& v) {
+  auto load_in = [&](int it, Site<T>& m, double& v, double* at) {
     const int64_t r = read_row(in_row(it), ny, a.periodic);
     load_site(src + (r * nx + c.col) * 8, m);
     v = read_v ? V[r * nx + c.col] : 0.0;
+    if constexpr (FIELD) {
+      const int64_t q = r * nx + c.col;
+      at[0] = a.At[q];
+      at[1] = a.At[a.cells + q];
+      at[2] = a.At[2 * a.cells + q];
+    }
   };
 
-  // ring slot it % RS: input row of iteration it and its potential
+  // ring slot it % RS: input row of iteration it, its potential (and field)
   Site<T> ring[RS];
   double vr[RS];
+  double ar[RS][FIELD ? 3 : 1];
 #pragma unroll
-  for (int k = 0; k < L; ++k) load_in(k, ring[k], vr[k]);
+  for (int k = 0; k < L; ++k) load_in(k, ring[k], vr[k], ar[k]);
   // slot it % P: phase factors of in_row(it); stage st of iteration it uses
   // slot (it - st - 1) % P.  Slots of rows before the first input row feed
   // only results that are not stored.
-  Factors f[P];
+  FT f[P];
 #pragma unroll
-  for (int q = 0; q < P; ++q) f[q] = const_factors(a.ph);
+  for (int q = 0; q < P; ++q) {
+    if constexpr (FIELD)
+      f[q] = FT{};
+    else
+      f[q] = const_factors(a.ph);
+  }
   // y movers of stage st, slot it % 2: the stage's input row two iterations
   // back (r movers when marching up, l movers when down)
   Mov<T> mv[NS][2];
@@ -269,14 +283,23 @@ __device__ __forceinline__ void march2d(const T* __restrict__ src, T* __restrict
       if (it >= nit) return;
       Site<T> cur = ring[k % RS];
       const double vcur = vr[k % RS];
-      load_in(it + L, ring[(k + L) % RS], vr[(k + L) % RS]);
+      double acur[3] = {0.0, 0.0, 0.0};
+      if constexpr (FIELD) {
+        acur[0] = ar[k % RS][0];
+        acur[1] = ar[k % RS][1];
+        acur[2] = ar[k % RS][2];
+      }
+      load_in(it + L, ring[(k + L) % RS], vr[(k + L) % RS], ar[(k + L) % RS]);
       if (zero_walls) {  // cells beyond a wall read as zero
         const int64_t r = in_row(it);
         if (r < 0 || r >= ny) zero(cur);
         if (!c.full && c.out) zero(cur);
       }
-      Factors& fnew = f[k % P];
-      fnew = factors_of<MODE, TWO>(vcur, a.ph);
+      FT& fnew = f[k % P];
+      if constexpr (FIELD)
+        fnew = field_factors<TWO, false>(vcur, acur[0], acur[1], acur[2], a.ph);
+      else
+        fnew = factors_of<MODE, TWO>(vcur, a.ph);
 #pragma unroll
       for (int st = 0; st < NS; ++st) {
         if (S::pre_x(st)) {
@@ -292,7 +315,12 @@ __device__ __forceinline__ void march2d(const T* __restrict__ src, T* __restrict
         else
           Axis<AX1, T>::combine(ry, mv[st][k % 2], o);
         mv[st][k % 2] = UP ? ry : ly;
-        if (S::phase(st)) apply_local<MODE>(o, f[((k - st - 1) % P + P) % P], a.ph);
+        if (S::phase(st)) {
+          if constexpr (FIELD)
+            apply_field(o, f[((k - st - 1) % P + P) % P]);
+          else
+            apply_local<MODE>(o, f[((k - st - 1) % P + P) % P], a.ph);
+        }
         if (S::post_x(st)) {
           Site<T> phi;
           x_transport_inner<T, AX0>(o, phi);
@@ -306,7 +334,10 @@ __device__ __forceinline__ void march2d(const T* __restrict__ src, T* __restrict
         cur = o;
       }
       if (it >= 2 * NS && own) store_site(dst + (out_row(it, NS) * nx + c.x) * 8, cur);
-      factors_fix<MODE, TWO>(fnew, vcur, a.ph);
+      if constexpr (FIELD)
+        field_fix<TWO>(fnew, vcur, acur[0], acur[1], acur[2], a.ph);
+      else
+        factors_fix<MODE, TWO>(fnew, vcur, a.ph);
     }
   }
 }
@@ -324,10 +355,18 @@ __device__ __forceinline__ void one_row(const T* __restrict__ src, T* __restrict
   Site<T> m;
   load_site(src + c.col * 8, m);
   if (c.out) zero(m);
-  const bool read_v = (MODE == 2) || (MODE < 0 && a.ph.mode == 2);
+  constexpr bool FIELD = MODE == 3;
+  const bool read_v = (MODE == 2) || (FIELD && V != nullptr) || (MODE < 0 && a.ph.mode == 2);
   const double v = read_v ? V[c.col] : 0.0;
-  Factors f = factors_of<MODE, TWO>(v, a.ph);
-  factors_fix<MODE, TWO>(f, v, a.ph);
+  typename FactorOf<MODE>::type f;
+  if constexpr (FIELD) {
+    const double ax = a.At[c.col], ay = a.At[a.cells + c.col], az = a.At[2 * a.cells + c.col];
+    f = field_factors<TWO, false>(v, ax, ay, az, a.ph);
+    field_fix<TWO>(f, v, ax, ay, az, a.ph);
+  } else {
+    f = factors_of<MODE, TWO>(v, a.ph);
+    factors_fix<MODE, TWO>(f, v, a.ph);
+  }
 #pragma unroll
   for (int s = 0; s < K * S::kStages; ++s) {
     if (S::pre_x(s)) {
@@ -336,7 +375,12 @@ __device__ __forceinline__ void one_row(const T* __restrict__ src, T* __restrict
       m = o;
       if (walls) zero(m);
     }
-    if (S::phase(s)) apply_local<MODE>(m, f, a.ph);
+    if (S::phase(s)) {
+      if constexpr (FIELD)
+        apply_field(m, f);
+      else
+        apply_local<MODE>(m, f, a.ph);
+    }
     if (S::post_x(s)) {
       Site<T> o;
       x_transport_inner<T, AX>(m, o);

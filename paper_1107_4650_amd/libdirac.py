@@ -24,7 +24,8 @@ DL_BC_ZERO, DL_BC_PERIODIC = 0, 1
 DL_DRY, DL_GRAPH, DL_STRANG = 1, 2, 4
 
 # every entry point of include/libdirac.h
-EXPORTS = ("dl_plan_create", "dl_plan_destroy", "dl_step", "dl_step_out", "dl_step_fused_out",
+EXPORTS = ("dl_plan_create", "dl_plan_destroy", "dl_step", "dl_step_field", "dl_step_out",
+           "dl_step_fused_out",
            "dl_observables", "dl_seed_adjoint",
            "dl_grad_step", "dl_project", "dl_expand", "dl_batch_create", "dl_batch_step", "dl_last_error",
            "dl_version")
@@ -59,6 +60,7 @@ def load() -> ctypes.CDLL:
         "dl_plan_destroy": [vp],
         "dl_step": [vp, vp, vp, i64, vp],
         "dl_step_out": [vp, vp, vp, vp, vp],
+        "dl_step_field": [vp, vp, vp, vp, i64, vp],
         "dl_step_fused_out": [vp, vp, vp, vp, i64, vp],
         "dl_plan_set_depth": [vp, ci],
         "dl_observables": [vp, vp, dbl, P(dbl), vp],
@@ -177,6 +179,23 @@ class Plan:
         check(self.lib.dl_step(self.handle, self._state(psi), self._cells(V, "V"), int(nsteps),
                                _stream_handle()))
         return psi
+
+    def step_field(self, psi, V=None, A=None, nsteps=1):
+        """dl_step with the field integrals A (float64, shape (3,) + grid) in
+        the local step."""
+        check(self.lib.dl_step_field(self.handle, self._state(psi), self._cells(V, "V"),
+                                     self._field(A), int(nsteps), _stream_handle()))
+        return psi
+
+    def _field(self, A):
+        import torch
+        if A is None:
+            return None
+        if not isinstance(A, torch.Tensor) or A.device.type != "cuda" or A.dtype != torch.float64:
+            raise TypeError("A must be a float64 CUDA tensor")
+        if tuple(A.shape) != (3,) + self.tshape[:-1] or not A.is_contiguous():
+            raise ValueError(f"A must be contiguous with shape {(3,) + self.tshape[:-1]}")
+        return ctypes.c_void_p(A.data_ptr())
 
     def step_out(self, src, dst, V=None):
         check(self.lib.dl_step_out(self.handle, self._state(src, "src"), self._state(dst, "dst"),

@@ -13,7 +13,7 @@ def announce(msg):
 
 
 def gpu_step(psi, V, *, dx, dt, c, m, nsteps, axes=None, bc="zero", dtype="c128", tiling=None,
-             graph=False, chunks=None, depth=None, scheme="lie"):
+             graph=False, chunks=None, depth=None, scheme="lie", A=None):
     """Run dl_step on a copy of psi (numpy, (..., 4)); returns numpy."""
     import torch
     shape = tuple(reversed(psi.shape[:-1]))
@@ -26,7 +26,10 @@ def gpu_step(psi, V, *, dx, dt, c, m, nsteps, axes=None, bc="zero", dtype="c128"
             p.set_tiling(**tiling)
         if depth is not None:
             p.set_depth(depth)
-        if chunks:
+        if A is not None:
+            tA = torch.from_numpy(np.ascontiguousarray(A, dtype=np.float64)).to("cuda")
+            p.step_field(t, tV, tA, nsteps)
+        elif chunks:
             for k in chunks:
                 p.step(t, tV, k)
         else:
