@@ -1,15 +1,17 @@
 // dirac_batch.hip -- many independent 1-D / 2-D instances advanced together.
 //
-// One launch performs one time step of every active instance: the grid is a
-// flat table of tiles (instance, 62-cell strip, march segment), ordered
-// longest first (2-D segments of H rows before single 1-D rows) so that the
-// workgroup dispatcher's in-order assignment is a longest-processing-time
-// list schedule.  Each tile runs exactly the per-cell code of the single-plan
-// sweep (x transport / y march / local step), so every instance
-// ends bit-identical to dl_step on its own plan.  Consecutive steps are
-// ordered by the launch boundary (no cross-workgroup waits inside a kernel);
-// long runs are replayed from a captured hipGraph.  The segment length is
-// chosen by timing candidates on the batch itself (dl_batch_autotune).
+// One launch performs one pass of D fused steps (then, for the remainder of
+// each instance's count, single steps) of every active instance: the grid is
+// a flat table of tiles (instance, strip of 64 - 2D cells, march segment),
+// ordered longest first (2-D segments of H rows before single 1-D rows) so
+// that the workgroup dispatcher's in-order assignment is a
+// longest-processing-time list schedule.  Each tile runs exactly the per-cell
+// code of the single-plan sweep (x transport / y march / local step, the
+// phase mode read at run time), so every instance ends bit-identical to
+// dl_step on its own plan.  Consecutive passes are ordered by the launch
+// boundary (no cross-workgroup waits inside a kernel); long runs are replayed
+// from a captured hipGraph.  The segment length is chosen by timing
+// candidates on the batch itself (dl_batch_autotune).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -32,6 +34,8 @@ struct BatchInst {
   const double* V;    // per call
   int64_t nx, ny;
   int64_t nsteps;     // per call
+  int64_t passes;     // per call: passes of the batch's depth ...
+  int64_t rem;        // ... then this many single steps
   int periodic;
   int axes_code;
   PhaseK ph;          // per call (mode depends on V)
@@ -44,17 +48,31 @@ struct BatchTile {
   int up;             // march direction (alternates between segments)
 };
 
-template <typename T>
+// One launch advances every instance still due by one pass of K steps.
+// phase 0: the index-th pass of the batch's depth D = K (instances with more
+// passes skip); phase 1: the index-th single step (K = 1) of the remainder.
+// Tiles are strips of 64 - 2D columns (lanes D .. 63 - D are written), valid
+// for every K <= D.  An instance's buffers alternate with the passes it has
+// done, so its parity is computed here from its own counts.
+template <typename T, int K>
 __global__ __launch_bounds__(256) void k_batch(const BatchInst* __restrict__ insts,
                                                const BatchTile* __restrict__ tiles, int ntiles,
-                                               int64_t step, int parity) {
+                                               int phase, int64_t index, int depth) {
   const int lane = threadIdx.x & 63;
   const int tile = __builtin_amdgcn_readfirstlane(static_cast<int>(blockIdx.x) * 4 +
                                                   static_cast<int>(threadIdx.x >> 6));
   if (tile >= ntiles) return;
   const BatchTile t = tiles[tile];
   const BatchInst& I = insts[t.inst];
-  if (step >= I.nsteps) return;
+  int64_t done;  // passes this instance has completed before this launch
+  if (phase == 0) {
+    if (index >= I.passes) return;
+    done = index;
+  } else {
+    if (index >= I.rem) return;
+    done = I.passes + index;
+  }
+  const int parity = static_cast<int>(done & 1);
   const T* src = static_cast<const T*>(parity ? I.b : I.a);
   T* dst = static_cast<T*>(parity ? I.a : I.b);
   SweepArgs a{};
@@ -63,18 +81,29 @@ __global__ __launch_bounds__(256) void k_batch(const BatchInst* __restrict__ ins
   a.nz = 1;
   a.periodic = I.periodic;
   a.ph = I.ph;
-  const int64_t x0 = static_cast<int64_t>(t.strip) * strip_width(1) - 1;  // lanes 1 .. 62 written
+  const int64_t xs = static_cast<int64_t>(t.strip) * strip_width(depth) - depth;
   const bool up = t.up != 0;
   switch (I.axes_code) {
-    case 0: one_row<T, LieStep, 1, 0, -1>(src, dst, I.V, a, x0, lane); break;
-    case 1: one_row<T, LieStep, 1, 1, -1>(src, dst, I.V, a, x0, lane); break;
-    case 2: one_row<T, LieStep, 1, 2, -1>(src, dst, I.V, a, x0, lane); break;
-    case 10: march_dir<T, LieStep, 1, 0, 1, -1>(src, dst, I.V, a, x0, lane, t.jb, t.je, up); break;
-    case 20: march_dir<T, LieStep, 1, 0, 2, -1>(src, dst, I.V, a, x0, lane, t.jb, t.je, up); break;
-    case 21: march_dir<T, LieStep, 1, 1, 2, -1>(src, dst, I.V, a, x0, lane, t.jb, t.je, up); break;
+    case 0: one_row<T, LieStep, K, 0, -1>(src, dst, I.V, a, xs, lane, depth); break;
+    case 1: one_row<T, LieStep, K, 1, -1>(src, dst, I.V, a, xs, lane, depth); break;
+    case 2: one_row<T, LieStep, K, 2, -1>(src, dst, I.V, a, xs, lane, depth); break;
+    case 10:
+      march_dir<T, LieStep, K, 0, 1, -1>(src, dst, I.V, a, xs, lane, t.jb, t.je, up, depth);
+      break;
+    case 20:
+      march_dir<T, LieStep, K, 0, 2, -1>(src, dst, I.V, a, xs, lane, t.jb, t.je, up, depth);
+      break;
+    case 21:
+      march_dir<T, LieStep, K, 1, 2, -1>(src, dst, I.V, a, xs, lane, t.jb, t.je, up, depth);
+      break;
     default: break;
   }
 }
+
+// depth of the batch's passes (steps fused per launch); a periodic batch
+// lowers it until every 2-D instance has at least 2 * depth rows
+constexpr int kBatchDepthF32 = 4;
+constexpr int kBatchDepthF64 = 2;
 
 }  // namespace dirac
 
@@ -90,6 +119,7 @@ struct Batch {
   int bc = DL_BC_ZERO;
   bool use_graph = true;
   int seg_len = 32;                 // 2-D march segment length (autotuned)
+  int depth = 1;                    // steps fused per pass
   int64_t graph_pairs = 16;
   std::vector<size_t> bytes;        // state bytes per instance
   void* scratch = nullptr;          // second buffers of all instances
@@ -118,7 +148,7 @@ std::vector<BatchTile> make_tiles(const Batch& B) {
   std::vector<BatchTile> two, one;
   for (int k = 0; k < B.count; ++k) {
     const dl_grid& g = B.grids[k];
-    const int64_t nstrips = (g.n[0] + strip_width(1) - 1) / strip_width(1);
+    const int64_t nstrips = (g.n[0] + strip_width(B.depth) - 1) / strip_width(B.depth);
     if (g.ndim == 1) {
       for (int64_t s = 0; s < nstrips; ++s)
         one.push_back(BatchTile{k, static_cast<int>(s), 0, 1, 1});
@@ -166,15 +196,38 @@ void drop_graph(Batch& B) {
   B.graph_tiles = -1;
 }
 
-hipError_t launch_step(const Batch& B, int64_t step, int parity, hipStream_t st) {
+template <typename T>
+hipError_t launch_pass_t(const Batch& B, int K, int phase, int64_t index, hipStream_t st) {
   const int blocks = (B.ntiles + 3) / 4;
-  if (B.fp64)
-    hipLaunchKernelGGL(k_batch<double>, dim3(blocks), dim3(256), 0, st, B.d_insts, B.d_tiles,
-                       B.ntiles, step, parity);
-  else
-    hipLaunchKernelGGL(k_batch<float>, dim3(blocks), dim3(256), 0, st, B.d_insts, B.d_tiles,
-                       B.ntiles, step, parity);
+  const int D = B.depth;
+  switch (K) {
+    case 1: hipLaunchKernelGGL((k_batch<T, 1>), dim3(blocks), dim3(256), 0, st, B.d_insts,
+                               B.d_tiles, B.ntiles, phase, index, D); break;
+    case 2: hipLaunchKernelGGL((k_batch<T, 2>), dim3(blocks), dim3(256), 0, st, B.d_insts,
+                               B.d_tiles, B.ntiles, phase, index, D); break;
+    default:
+      if constexpr (sizeof(T) == 4) {  // deeper passes for FP32 state only
+        if (K == 3)
+          hipLaunchKernelGGL((k_batch<T, 3>), dim3(blocks), dim3(256), 0, st, B.d_insts,
+                             B.d_tiles, B.ntiles, phase, index, D);
+        else if (K == 4)
+          hipLaunchKernelGGL((k_batch<T, 4>), dim3(blocks), dim3(256), 0, st, B.d_insts,
+                             B.d_tiles, B.ntiles, phase, index, D);
+        else
+          return hipErrorInvalidValue;
+      } else {
+        return hipErrorInvalidValue;
+      }
+  }
   return hipGetLastError();
+}
+
+// phase 0: the index-th pass of the batch's depth; phase 1: the index-th
+// single step of the remainder
+hipError_t launch_pass(const Batch& B, int phase, int64_t index, hipStream_t st) {
+  const int K = phase == 0 ? B.depth : 1;
+  return B.fp64 ? launch_pass_t<double>(B, K, phase, index, st)
+                : launch_pass_t<float>(B, K, phase, index, st);
 }
 
 // fill per-call descriptors (pointers, step counts, phase mode) and upload
@@ -188,6 +241,8 @@ int prepare(Batch& B, void* const* psi, const double* const* V, const int64_t* n
     I.a = psi[k];
     I.V = V ? V[k] : nullptr;
     I.nsteps = nsteps[k];
+    I.passes = nsteps[k] / B.depth;
+    I.rem = nsteps[k] % B.depth;
     I.ph = make_phase(B.grids[k].ndim, B.dt[k], B.c[k], B.m[k], phase_mode(B.m[k], I.V), B.fp64);
   }
   hipError_t e = hipMemcpyAsync(B.d_insts, B.h_insts.data(), B.count * sizeof(BatchInst),
@@ -195,16 +250,18 @@ int prepare(Batch& B, void* const* psi, const double* const* V, const int64_t* n
   return e == hipSuccess ? DL_OK : set_hip_error(e, "descriptor upload");
 }
 
-// run steps [0, max nsteps); the kernel skips instances whose count is reached
+// run every instance's passes of the batch's depth, then its remaining
+// single steps; the kernel skips instances whose count is reached
 int run(Batch& B, const int64_t* nsteps, hipStream_t st) {
-  int64_t nmax = 0, nmin = INT64_MAX;
+  int64_t pmax = 0, pmin = INT64_MAX, rmax = 0;
   for (int k = 0; k < B.count; ++k) {
-    nmax = std::max(nmax, nsteps[k]);
-    nmin = std::min(nmin, nsteps[k]);
+    pmax = std::max(pmax, nsteps[k] / B.depth);
+    pmin = std::min(pmin, nsteps[k] / B.depth);
+    rmax = std::max(rmax, nsteps[k] % B.depth);
   }
-  int64_t s = 0;
-  // steps [0, nmin) have every instance active: replay a graph of 2*pairs steps
-  if (B.use_graph && nmin >= 2 * B.graph_pairs) {
+  int64_t q = 0;
+  // passes [0, pmin) have every instance active: replay a graph of 2*pairs passes
+  if (B.use_graph && pmin >= 2 * B.graph_pairs) {
     // the launches read pointers and counts from the device descriptor table,
     // so one captured graph serves every call with the same tile table
     if (!B.graph || B.graph_seg != B.seg_len || B.graph_tiles != B.ntiles) {
@@ -217,8 +274,9 @@ int run(Batch& B, const int64_t* nsteps, hipStream_t st) {
       hipError_t e = hipStreamBeginCapture(B.cap_stream, hipStreamCaptureModeThreadLocal);
       if (e != hipSuccess) return set_hip_error(e, "begin capture");
       hipError_t e2 = hipSuccess;
-      for (int64_t q = 0; q < 2 * B.graph_pairs && e2 == hipSuccess; ++q)
-        e2 = launch_step(B, 0, static_cast<int>(q & 1), B.cap_stream);
+      // pass indices 0 .. 2*pairs-1: the parity of an all-active pass is its index's
+      for (int64_t i = 0; i < 2 * B.graph_pairs && e2 == hipSuccess; ++i)
+        e2 = launch_pass(B, 0, i, B.cap_stream);
       e = hipStreamEndCapture(B.cap_stream, &g);
       if (e2 != hipSuccess || e != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
@@ -230,20 +288,24 @@ int run(Batch& B, const int64_t* nsteps, hipStream_t st) {
       B.graph_seg = B.seg_len;
       B.graph_tiles = B.ntiles;
     }
-    const int64_t reps = nmin / (2 * B.graph_pairs);
+    const int64_t reps = pmin / (2 * B.graph_pairs);
     for (int64_t r = 0; r < reps; ++r) {
       hipError_t e = hipGraphLaunch(B.graph, st);
       if (e != hipSuccess) return set_hip_error(e, "graph launch");
     }
-    s = reps * 2 * B.graph_pairs;
+    q = reps * 2 * B.graph_pairs;
   }
-  for (; s < nmax; ++s) {
-    hipError_t e = launch_step(B, s, static_cast<int>(s & 1), st);
+  for (; q < pmax; ++q) {
+    hipError_t e = launch_pass(B, 0, q, st);
+    if (e != hipSuccess) return set_hip_error(e, "batch pass launch");
+  }
+  for (int64_t r = 0; r < rmax; ++r) {
+    hipError_t e = launch_pass(B, 1, r, st);
     if (e != hipSuccess) return set_hip_error(e, "batch step launch");
   }
-  // odd counts end in the second buffer
+  // an odd number of passes ends in the second buffer
   for (int k = 0; k < B.count; ++k) {
-    if (nsteps[k] & 1) {
+    if ((nsteps[k] / B.depth + nsteps[k] % B.depth) & 1) {
       hipError_t e = hipMemcpyAsync(B.h_insts[k].a, B.h_insts[k].b, B.bytes[k],
                                     hipMemcpyDeviceToDevice, st);
       if (e != hipSuccess) return set_hip_error(e, "hipMemcpyAsync");
@@ -298,6 +360,10 @@ extern "C" int dl_batch_create(dl_plan* out, const dl_grid* grids, const double*
   p->bc = bc;
   p->fp64 = (dtype == DL_C128);
   p->dry = (flags & DL_DRY) != 0;
+  B->depth = p->fp64 ? kBatchDepthF64 : kBatchDepthF32;
+  if (bc == DL_BC_PERIODIC)
+    for (int k = 0; k < count; ++k)
+      while (grids[k].ndim == 2 && B->depth > 1 && grids[k].n[1] < 2 * B->depth) --B->depth;
   B->count = count;
   B->fp64 = p->fp64;
   B->bc = bc;

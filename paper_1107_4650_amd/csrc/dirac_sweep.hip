@@ -45,12 +45,12 @@ __global__ __launch_bounds__(256, 2) void k_sweep2d(const T* __restrict__ src, T
   const int64_t seg = tile / a.nstrips;
   const int64_t xs = strip * strip_width(X) - X;  // lanes X .. 63 - X are written
   if constexpr (AX1 < 0) {
-    one_row<T, S, K, AX0, MODE>(src, dst, V, a, xs, lane);  // 1-D: one row, no march
+    one_row<T, S, K, AX0, MODE>(src, dst, V, a, xs, lane, X);  // 1-D: one row, no march
   } else {
     const int64_t jb = seg * a.H;
     const int64_t je = (jb + a.H < a.ny) ? jb + a.H : a.ny;
     // even segments march up, odd ones down
-    march_dir<T, S, K, AX0, AX1, MODE>(src, dst, V, a, xs, lane, jb, je, (seg & 1) == 0);
+    march_dir<T, S, K, AX0, AX1, MODE>(src, dst, V, a, xs, lane, jb, je, (seg & 1) == 0, X);
   }
 }
 

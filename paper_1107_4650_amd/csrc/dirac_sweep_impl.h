@@ -216,7 +216,8 @@ template <class S> constexpr int factor_slots(int NS) {
 template <typename T, class S, int K, int AX0, int AX1, bool UP, int MODE>
 __device__ __forceinline__ void march2d(const T* __restrict__ src, T* __restrict__ dst,
                                         const double* __restrict__ V, const SweepArgs& a,
-                                        int64_t xs, int lane, int64_t jb, int64_t je) {
+                                        int64_t xs, int lane, int64_t jb, int64_t je,
+                                        int wlane) {
   constexpr bool TWO = sizeof(T) == 8;
   constexpr int NS = K * S::kStages;          // stages of the pass
   constexpr int X = halo_lanes<S>(K);         // x transports of the pass
@@ -228,7 +229,7 @@ __device__ __forceinline__ void march2d(const T* __restrict__ src, T* __restrict
   const int64_t nx = a.nx, ny = a.ny;
   const int nit = static_cast<int>(je - jb) + 2 * NS;  // iterations with work
   const Lanes c = lanes_of(nx, a.periodic, xs, lane);
-  const bool own = c.inside && lane >= X && lane <= 63 - X;
+  const bool own = c.inside && lane >= wlane && lane <= 63 - wlane;  // wlane >= X
   constexpr bool FIELD = MODE == 3;             // local step with a vector potential
   using FT = typename FactorOf<MODE>::type;
   const bool read_v = (MODE == 2) || (FIELD && V != nullptr) || (MODE < 0 && a.ph.mode == 2);
@@ -342,15 +343,16 @@ __device__ __forceinline__ void march2d(const T* __restrict__ src, T* __restrict
   }
 }
 
-// K steps of a 1-D line for the 64 - 2X output cells of the wave
+// K steps of a 1-D line; the wave writes lanes wlane .. 63 - wlane (the
+// 64 - 2X lanes where all K steps are valid, or fewer)
 template <typename T, class S, int K, int AX, int MODE>
 __device__ __forceinline__ void one_row(const T* __restrict__ src, T* __restrict__ dst,
                                         const double* __restrict__ V, const SweepArgs& a,
-                                        int64_t xs, int lane) {
+                                        int64_t xs, int lane, int wlane) {
   constexpr bool TWO = sizeof(T) == 8;
   constexpr int X = halo_lanes<S>(K);
   const Lanes c = lanes_of(a.nx, a.periodic, xs, lane);
-  const bool own = c.inside && lane >= X && lane <= 63 - X;
+  const bool own = c.inside && lane >= wlane && lane <= 63 - wlane;  // wlane >= X
   const bool walls = !a.periodic && !c.inside;  // this lane's cell lies beyond a wall
   Site<T> m;
   load_site(src + c.col * 8, m);
@@ -391,15 +393,17 @@ __device__ __forceinline__ void one_row(const T* __restrict__ src, T* __restrict
   if (own) store_site(dst + c.x * 8, m);
 }
 
-// march a 2-D segment upwards (up = true) or downwards
+// march a 2-D segment upwards (up = true) or downwards, writing lanes
+// wlane .. 63 - wlane (wlane >= the pass's x transports)
 template <typename T, class S, int K, int AX0, int AX1, int MODE>
 __device__ __forceinline__ void march_dir(const T* __restrict__ src, T* __restrict__ dst,
                                           const double* __restrict__ V, const SweepArgs& a,
-                                          int64_t xs, int lane, int64_t jb, int64_t je, bool up) {
+                                          int64_t xs, int lane, int64_t jb, int64_t je, bool up,
+                                          int wlane) {
   if (up)
-    march2d<T, S, K, AX0, AX1, true, MODE>(src, dst, V, a, xs, lane, jb, je);
+    march2d<T, S, K, AX0, AX1, true, MODE>(src, dst, V, a, xs, lane, jb, je, wlane);
   else
-    march2d<T, S, K, AX0, AX1, false, MODE>(src, dst, V, a, xs, lane, jb, je);
+    march2d<T, S, K, AX0, AX1, false, MODE>(src, dst, V, a, xs, lane, jb, je, wlane);
 }
 
 }  // namespace dirac

@@ -70,3 +70,59 @@ def test_autotune_leaves_inputs_and_keeps_bits():
         torch.cuda.synchronize()
     for w, t in zip(ws, psis):
         assert same_bits(t.cpu().numpy(), _alone(w, 40, "c64"))
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_batch_graph_replay_of_fused_passes(dtype):
+    """Every instance long enough for graph replay of whole passes, counts
+    that are and are not multiples of the pass depth, some instances
+    without a potential."""
+    import torch
+    announce(f"batch graph replay {dtype}")
+    ws = _instances(9, seed=11)
+    nsteps = [70, 71, 72, 73, 150, 99, 64, 65, 131]
+    tdt = torch.complex64 if dtype == "c64" else torch.complex128
+    psis = [torch.from_numpy(w.psi0).to("cuda").to(tdt) for w in ws]
+    Vs = [None if k % 3 == 2 else torch.from_numpy(w.V).to("cuda") for k, w in enumerate(ws)]
+    with L.Batch([w.shape for w in ws], [w.dx for w in ws], [w.dt for w in ws],
+                 [w.c for w in ws], [w.m for w in ws], dtype=dtype, graph=True) as b:
+        b.set(seg_len=32, graph_pairs=4)
+        b.step(psis, Vs, nsteps)
+        torch.cuda.synchronize()
+    for k, (w, n, t) in enumerate(zip(ws, nsteps, psis)):
+        ref = _alone(w, n, dtype) if Vs[k] is not None else _alone_noV(w, n, dtype)
+        assert same_bits(t.cpu().numpy(), ref), (w.name, w.shape, n)
+
+
+def _alone_noV(w, nsteps, dtype):
+    import torch
+    tdt = torch.complex64 if dtype == "c64" else torch.complex128
+    psi = torch.from_numpy(w.psi0).to("cuda").to(tdt)
+    with L.Plan(w.shape, w.dx, w.dt, w.c, w.m, dtype=dtype, axes=w.axes) as p:
+        p.step(psi, None, nsteps)
+        torch.cuda.synchronize()
+    return psi.cpu().numpy()
+
+
+def test_batch_periodic_thin_instances():
+    """A periodic batch with 2-D instances of few rows (the pass depth drops so
+    that each wraps once) against single periodic runs."""
+    import torch
+    from paper_1107_4650_amd.inputs import random_spinor
+    announce("batch periodic thin")
+    shapes = [(100, 5), (64, 3), (300,), (80, 40), (70, 9)]
+    dx, c = 0.01, C_LIGHT
+    psis0 = [random_spinor(s[::-1], seed=k).astype(np.complex64) for k, s in enumerate(shapes)]
+    Vs0 = [np.random.default_rng(k).uniform(-2, 2, s[::-1]) * c * c for k, s in enumerate(shapes)]
+    nsteps = [13, 8, 21, 10, 9]
+    psis = [torch.from_numpy(p).to("cuda") for p in psis0]
+    Vs = [torch.from_numpy(v).to("cuda") for v in Vs0]
+    with L.Batch(shapes, dx, dx / c, c, 1.0, dtype="c64", bc="periodic") as b:
+        b.step(psis, Vs, nsteps)
+        torch.cuda.synchronize()
+    for s, p0, v0, n, t in zip(shapes, psis0, Vs0, nsteps, psis):
+        psi = torch.from_numpy(p0).to("cuda")
+        with L.Plan(s, dx, dx / c, c, 1.0, dtype="c64", bc="periodic") as p:
+            p.step(psi, torch.from_numpy(v0).to("cuda"), n)
+            torch.cuda.synchronize()
+        assert same_bits(t.cpu().numpy(), psi.cpu().numpy()), (s, n)
