@@ -216,6 +216,18 @@ def bench_extras(args, line):
     ex["1d_4096_c128"] = {"steps": w.nsteps, "ms": ms,
                           "site_updates_per_s": w.sites * w.nsteps / (ms * 1e-3)}
     log(f"1-D 4096 x {w.nsteps}: {ms:.3f} ms")
+    # the same line as a two-component state (the packet lives in (psi_1, psi_4))
+    with L.Plan(w.shape, w.dx, w.dt, w.c, w.m, dtype="c128", xmin=w.xmin, bispinor=True) as p:
+        psi2 = to_dev(np.ascontiguousarray(w.psi0[:, [0, 3]]))
+        p.step(psi2, V, 10)
+        torch.cuda.synchronize()
+        s.record()
+        p.step(psi2, V, w.nsteps)
+        e.record()
+        torch.cuda.synchronize()
+        ms2 = s.elapsed_time(e)
+    ex["1d_4096_c128"]["bispinor_ms"] = ms2
+    ex["1d_line_4M_f32"] = bench_long_line()
     # 3-D 512^3 FP32 and FP64, a prefix of the 2000-step run
     ex["3d_512"] = bench_3d(args)
     # observables pass on the 2048^2 FP32 state
@@ -229,6 +241,40 @@ def bench_extras(args, line):
     if args.klein_steps > 0:
         ex["klein2d_24576x8192_strang"] = bench_klein2d(args)
     line["extras"] = ex
+
+
+def bench_long_line(n=1 << 22, steps=400):
+    """A long 1-D line (4M cells, the 1-D workload's packet and step potential
+    stretched over a 41.9 a.u. box), complex64: the four-component state vs
+    the two-component one, passes of 5 steps each."""
+    import torch
+    from paper_1107_4650_amd import libdirac as L
+    from paper_1107_4650_amd.inputs import packet, potential_step, C_LIGHT, M_E
+    dx = 0.01
+    shape = (n,)
+    psi = packet(shape, dx, delta=2.0, p0=[50.0], r0=[-10.0])
+    V = to_dev(potential_step(shape, dx, 2.0 * M_E * C_LIGHT ** 2))
+    out = {"cells": n, "steps": steps}
+    for name, nc in (("four_component", 4), ("two_component", 2)):
+        src = psi if nc == 4 else np.ascontiguousarray(psi[:, [0, 3]])
+        with L.Plan(shape, dx, dx / C_LIGHT, C_LIGHT, M_E, dtype="c64", bispinor=(nc == 2)) as p:
+            t = to_dev(src, torch.complex64)
+            p.step(t, V, 20)
+            torch.cuda.synchronize()
+            s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            s.record()
+            p.step(t, V, steps)
+            e.record()
+            torch.cuda.synchronize()
+            ms = s.elapsed_time(e)
+            depth = p.info()["depth"]
+        out[name] = {"ms_per_step": ms / steps, "site_updates_per_s": n * steps / (ms * 1e-3),
+                     "steps_per_pass": depth, "bytes_per_cell_per_pass": 8 * 2 * nc + 8}
+        del t
+    torch.cuda.empty_cache()
+    log(f"1-D 4M line: {out['four_component']['ms_per_step'] * 1e3:.1f} vs "
+        f"{out['two_component']['ms_per_step'] * 1e3:.1f} us/step (4 vs 2 components)")
+    return out
 
 
 def bench_field(args, steps=400):

@@ -3,7 +3,9 @@
  *
  * The library advances a four-component complex spinor field on a regular
  * grid with the lowest-order operator splitting of the time-dependent Dirac
- * equation in coordinate space (Fillion-Gourdeau, Lorin, Bandrauk, Sec. 2):
+ * equation in coordinate space (Fillion-Gourdeau, Lorin, Bandrauk, Sec. 2;
+ * the second-order splitting of Sec. 2.4 with DL_STRANG, a vector potential
+ * with dl_step_field, two-component 1-D lines with DL_BISPINOR):
  * per time step, for every active grid axis d in the order x, y, z, the exact
  * characteristic transport
  *
@@ -21,8 +23,9 @@
  *  - Pointers named psi, lam, V, Q, G are DEVICE pointers owned by the caller;
  *    the library never frees them.  Arrays are C-contiguous with grid
  *    dimension 0 (x) fastest and the spinor component last:
- *    psi[((k * n1 + j) * n0 + i) * 4 + comp], each component an interleaved
- *    (re, im) pair of float (DL_C64) or double (DL_C128).  V, Q and G hold
+ *    psi[((k * n1 + j) * n0 + i) * 4 + comp] (a DL_BISPINOR plan: 2 stored
+ *    components per cell), each component an interleaved (re, im) pair of
+ *    float (DL_C64) or double (DL_C128).  V, Q and G hold
  *    one double per cell in the same cell order.
  *  - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued
  *    on it and the call returns without waiting, except where noted.
@@ -73,6 +76,15 @@ typedef enum { DL_BC_ZERO = 0, DL_BC_PERIODIC = 1 } dl_bc;
                         one-cell shift, so the plan needs c*dt = 2*dx
                         (DL_ERR_CFL otherwise).  The adjoint entry points
                         refuse such a plan (DL_ERR_ARG). */
+#define DL_BISPINOR 8u /* two-component state, 1-D grids only (Sec. 2.4): with
+                        one transport axis the pair of components that contains
+                        psi_1 -- (psi_1, psi_4) for alpha_x and alpha_y,
+                        (psi_1, psi_3) for alpha_z -- evolves on its own; the
+                        state then holds that pair, 2 complex numbers per cell
+                        (layout (n, 2)), and the other pair is taken as zero.
+                        Results equal those components of the four-component
+                        step.  dl_step_field and the adjoint refuse such a plan
+                        (DL_ERR_ARG); the observables read the pair. */
 
 /* Grid of P0 cells (Sec. 2.3).  n[d] cells along grid dimension d, n[0]
  * fastest.  axis[d] is the Dirac matrix carried by dimension d (0 = alpha_x,

@@ -424,6 +424,7 @@ static int check_adjoint_plan(dl_plan p) {
   if (rc) return rc;
   if (p->g.ndim > 2) return set_error(DL_ERR_ARG, "the adjoint supports 1-D and 2-D grids");
   if (p->strang) return set_error(DL_ERR_ARG, "the adjoint is built for lowest-order steps only");
+  if (p->nc != 4) return set_error(DL_ERR_ARG, "the adjoint is built for four-component states");
   return DL_OK;
 }
 

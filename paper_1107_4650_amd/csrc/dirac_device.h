@@ -69,6 +69,58 @@ __device__ __forceinline__ void store_site(double* __restrict__ p, const Site<do
 }
 
 // ---------------------------------------------------------------------------
+// Two-component storage of 1-D lines.  With a single transport axis the four
+// components pair up -- alpha_x and alpha_y couple a with d (and b with c),
+// alpha_z couples a with c (and b with d), beta is diagonal -- and each pair
+// evolves on its own (Sec. 2.4 notes the two-component reduction in 1-D).  A
+// two-component state (NC = 2) stores the pair that contains a, as two
+// complex numbers per cell; the other pair is taken as zero.
+// ---------------------------------------------------------------------------
+template <int AX> __host__ __device__ constexpr int pair_second() { return AX == 2 ? 2 : 3; }
+
+__device__ __forceinline__ void load_pair(const float* __restrict__ p, float& a0, float& a1,
+                                          float& b0, float& b1) {
+  const float4 q = *reinterpret_cast<const float4*>(p);
+  a0 = q.x; a1 = q.y; b0 = q.z; b1 = q.w;
+}
+__device__ __forceinline__ void load_pair(const double* __restrict__ p, double& a0, double& a1,
+                                          double& b0, double& b1) {
+  const double2 q0 = reinterpret_cast<const double2*>(p)[0];
+  const double2 q1 = reinterpret_cast<const double2*>(p)[1];
+  a0 = q0.x; a1 = q0.y; b0 = q1.x; b1 = q1.y;
+}
+__device__ __forceinline__ void store_pair(float* __restrict__ p, float a0, float a1, float b0,
+                                           float b1) {
+  *reinterpret_cast<float4*>(p) = make_float4(a0, a1, b0, b1);
+}
+__device__ __forceinline__ void store_pair(double* __restrict__ p, double a0, double a1,
+                                           double b0, double b1) {
+  reinterpret_cast<double2*>(p)[0] = make_double2(a0, a1);
+  reinterpret_cast<double2*>(p)[1] = make_double2(b0, b1);
+}
+
+// load / store cell `cell` of a state with NC stored components per cell
+template <int NC, int AX, typename T>
+__device__ __forceinline__ void load_cell(const T* __restrict__ base, int64_t cell, Site<T>& s) {
+  if constexpr (NC == 4) {
+    load_site(base + cell * 8, s);
+  } else {
+    constexpr int j = pair_second<AX>();
+    zero(s);
+    load_pair(base + cell * 4, s.v[0], s.v[1], s.v[2 * j], s.v[2 * j + 1]);
+  }
+}
+template <int NC, int AX, typename T>
+__device__ __forceinline__ void store_cell(T* __restrict__ base, int64_t cell, const Site<T>& s) {
+  if constexpr (NC == 4) {
+    store_site(base + cell * 8, s);
+  } else {
+    constexpr int j = pair_second<AX>();
+    store_pair(base + cell * 4, s.v[0], s.v[1], s.v[2 * j], s.v[2 * j + 1]);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // wave64 neighbour exchange with DPP (wave_shr:1 / wave_shl:1).  Lanes whose
 // source lies outside the wave (lane 0 for shr, lane 63 for shl) keep `old`.
 // ---------------------------------------------------------------------------

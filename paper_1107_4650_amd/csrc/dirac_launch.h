@@ -43,6 +43,7 @@ struct SweepArgs {
   // phase mode 3: field integrals At, planar (x, y, z blocks of `cells`)
   const double* At;
   int64_t cells;
+  int nc;              // components stored per cell: 4, or 2 (two-component 1-D line)
 };
 
 struct ResidentArgs {
@@ -50,11 +51,13 @@ struct ResidentArgs {
   int64_t nsteps;
   int periodic;
   PhaseK ph;
+  int nc;              // components stored per cell: 4 or 2
 };
 
 struct ObsArgs {
   int64_t n0, n1, n2;
   int ndim;
+  int nc;              // components stored per cell: 4 or 2
   double dx;
   double xmin0, xmin1, xmin2;
   double x_b;
@@ -70,7 +73,8 @@ hipError_t launch_sweep3d(bool fp64, const void* src, void* dst, const double* V
                           const SweepArgs& a, int blocks, hipStream_t st);
 // resident 256-thread blocks per CU of the sweep kernel for this layout,
 // phase mode and depth (0 if the runtime cannot tell)
-int sweep_occupancy(bool fp64, bool strang, int ndim, int axes_code, int mode, int depth);
+int sweep_occupancy(bool fp64, bool strang, int ndim, int axes_code, int mode, int depth,
+                    int nc);
 // nsteps in place in one workgroup of `threads` threads, `spt` cells each
 hipError_t launch_resident1d(bool fp64, int axis, void* psi, const double* V,
                              const ResidentArgs& a, int spt, int threads, hipStream_t st);

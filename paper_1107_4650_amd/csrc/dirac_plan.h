@@ -35,6 +35,7 @@ struct dl_plan_s {
   bool dry = false;
   bool use_graph = false;
   bool strang = false;         // second-order steps (Sec. 2.4)
+  int nc = 4;                  // components stored per cell (2: two-component 1-D line)
   int64_t cells = 0;
   size_t state_bytes = 0;
   int device = 0;

@@ -190,7 +190,8 @@ static void select_tiling(dl_plan p, int mode) {
 static int64_t resident_waves(dl_plan p, int mode, int depth) {
   if (p->waves_per_cu > 0) return int64_t(p->cu_count) * p->waves_per_cu;
   int occ = p->dry ? 0
-                   : sweep_occupancy(p->fp64, p->strang, p->g.ndim, axes_code(p->g), mode, depth);
+                   : sweep_occupancy(p->fp64, p->strang, p->g.ndim, axes_code(p->g), mode, depth,
+                                     p->nc);
   if (occ <= 0) occ = 2;
   return int64_t(occ) * 4 * p->cu_count;
 }
@@ -245,6 +246,8 @@ extern "C" int dl_plan_create(dl_plan* out, const dl_grid* g, double dx, double 
   if (rc) return rc;
   if (g->ndim == 3 && !(g->axis[0] == 0 && g->axis[1] == 1 && g->axis[2] == 2))
     return fail(DL_ERR_ARG, "3-D grids carry alpha_x, alpha_y, alpha_z in order");
+  const bool pair = (flags & DL_BISPINOR) != 0;
+  if (pair && g->ndim != 1) return fail(DL_ERR_ARG, "two-component states are 1-D lines");
   dl_plan p = new (std::nothrow) dl_plan_s();
   if (!p) return fail(DL_ERR_NOMEM, "host allocation failed");
   p->g = *g;
@@ -263,7 +266,8 @@ extern "C" int dl_plan_create(dl_plan* out, const dl_grid* g, double dx, double 
   p->fp64 = (dtype == DL_C128);
   p->cells = 1;
   for (int d = 0; d < g->ndim; ++d) p->cells *= g->n[d];
-  p->state_bytes = static_cast<size_t>(p->cells) * 4 * (p->fp64 ? 16 : 8);
+  p->nc = pair ? 2 : 4;
+  p->state_bytes = static_cast<size_t>(p->cells) * p->nc * (p->fp64 ? 16 : 8);
   p->dry = (flags & DL_DRY) != 0;
   p->use_graph = (flags & DL_GRAPH) != 0;
   p->strang = strang;
@@ -358,6 +362,7 @@ hipError_t launch_pass(dl_plan p, int depth, const void* src, void* dst, const d
   a.ph = p->ph;
   a.At = p->field;
   a.cells = p->cells;
+  a.nc = p->nc;
   return launch_sweep2d(p->fp64, p->strang, depth, src, dst, V, a, p->bl[depth - 1], st);
 }
 
@@ -436,6 +441,7 @@ extern "C" int dl_step(dl_plan p, void* psi, const double* V, int64_t nsteps, vo
     ra.nsteps = nsteps;
     ra.periodic = (p->bc == DL_BC_PERIODIC);
     ra.ph = p->ph;
+    ra.nc = p->nc;
     hipError_t e = launch_resident1d(p->fp64, p->g.axis[0], psi, V, ra, 4, p->res_threads, st);
     return e == hipSuccess ? DL_OK : hip_fail(e, "resident 1-D sweep launch");
   }
@@ -470,6 +476,7 @@ extern "C" int dl_step_field(dl_plan p, void* psi, const double* V, const double
   if ((rc = check_f64_ptr(V, "V", true))) return rc;
   if ((rc = check_f64_ptr(A, "A", false))) return rc;
   if (p->g.ndim > 2) return fail(DL_ERR_ARG, "the vector potential is built for 1-D and 2-D grids");
+  if (p->nc != 4) return fail(DL_ERR_ARG, "a vector potential couples all four components");
   if (nsteps < 0) return fail(DL_ERR_ARG, "nsteps = %lld < 0", static_cast<long long>(nsteps));
   if (nsteps == 0) return DL_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -563,6 +570,7 @@ extern "C" int dl_observables(dl_plan p, const void* psi, double x_b, double out
   a.xmin1 = p->g.xmin[1];
   a.xmin2 = p->g.xmin[2];
   a.x_b = x_b;
+  a.nc = p->nc;
   hipError_t e = launch_observables(p->fp64, psi, a, p->partials, p->dres, st);
   if (e != hipSuccess) return hip_fail(e, "observables launch");
   e = hipMemcpyAsync(p->hres, p->dres, 5 * sizeof(double), hipMemcpyDeviceToHost, st);

@@ -65,7 +65,7 @@ __device__ void block_reduce(NSum (&acc)[NQ], NSum (*lds)[4]) {
   }
 }
 
-template <typename T>
+template <typename T, int NC>
 __global__ __launch_bounds__(256) void k_obs_partial(const T* __restrict__ psi, ObsArgs a,
                                                      double* __restrict__ partials) {
   __shared__ NSum lds[kQ][4];
@@ -76,12 +76,21 @@ __global__ __launch_bounds__(256) void k_obs_partial(const T* __restrict__ psi, 
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
   for (int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; c < ncell;
        c += stride) {
-    Site<T> s;
-    load_site(psi + c * 8, s);
+    // |psi|^2 over the stored components (a two-component line stores a pair
+    // whose partners are zero, so the sum is the same)
+    T s[2 * NC];
+    if constexpr (NC == 4) {
+      Site<T> q;
+      load_site(psi + c * 8, q);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) s[k] = q.v[k];
+    } else {
+      load_pair(psi + c * 4, s[0], s[1], s[2], s[3]);
+    }
     double rho = 0.0;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const double v = static_cast<double>(s.v[k]);
+    for (int k = 0; k < 2 * NC; ++k) {
+      const double v = static_cast<double>(s[k]);
       rho = fma(v, v, rho);
     }
     const int64_t i0 = c % a.n0;
@@ -134,12 +143,21 @@ __global__ __launch_bounds__(256) void k_obs_final(const double* __restrict__ pa
 
 hipError_t launch_observables(bool fp64, const void* psi, const ObsArgs& a, double* partials,
                               double* out5, hipStream_t st) {
-  if (fp64)
-    hipLaunchKernelGGL(k_obs_partial<double>, dim3(kObsBlocks), dim3(256), 0, st,
-                       static_cast<const double*>(psi), a, partials);
-  else
-    hipLaunchKernelGGL(k_obs_partial<float>, dim3(kObsBlocks), dim3(256), 0, st,
-                       static_cast<const float*>(psi), a, partials);
+  if (fp64) {
+    if (a.nc == 2)
+      hipLaunchKernelGGL((k_obs_partial<double, 2>), dim3(kObsBlocks), dim3(256), 0, st,
+                         static_cast<const double*>(psi), a, partials);
+    else
+      hipLaunchKernelGGL((k_obs_partial<double, 4>), dim3(kObsBlocks), dim3(256), 0, st,
+                         static_cast<const double*>(psi), a, partials);
+  } else {
+    if (a.nc == 2)
+      hipLaunchKernelGGL((k_obs_partial<float, 2>), dim3(kObsBlocks), dim3(256), 0, st,
+                         static_cast<const float*>(psi), a, partials);
+    else
+      hipLaunchKernelGGL((k_obs_partial<float, 4>), dim3(kObsBlocks), dim3(256), 0, st,
+                         static_cast<const float*>(psi), a, partials);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_obs_final, dim3(1), dim3(256), 0, st, partials, kObsBlocks, a, out5);

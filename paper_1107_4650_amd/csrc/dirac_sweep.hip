@@ -32,9 +32,10 @@ namespace dirac {
 // K full steps of scheme S per launch on a 1-D line or a 2-D plane (64 - 2X
 // output columns per wave, X = x transports of the pass; march segments of
 // H rows in 2-D)
-template <typename T, class S, int K, int AX0, int AX1, int MODE>
+template <typename T, class S, int K, int AX0, int AX1, int MODE, int NC = 4>
 __global__ __launch_bounds__(256, 2) void k_sweep2d(const T* __restrict__ src, T* __restrict__ dst,
                                                     const double* __restrict__ V, SweepArgs a) {
+  static_assert(NC == 4 || AX1 < 0, "two-component states are 1-D lines");
   constexpr int X = halo_lanes<S>(K);
   const int lane = threadIdx.x & 63;
   int64_t blk = blockIdx.x;
@@ -45,7 +46,7 @@ __global__ __launch_bounds__(256, 2) void k_sweep2d(const T* __restrict__ src, T
   const int64_t seg = tile / a.nstrips;
   const int64_t xs = strip * strip_width(X) - X;  // lanes X .. 63 - X are written
   if constexpr (AX1 < 0) {
-    one_row<T, S, K, AX0, MODE>(src, dst, V, a, xs, lane, X);  // 1-D: one row, no march
+    one_row<T, S, K, AX0, MODE, NC>(src, dst, V, a, xs, lane, X);  // 1-D: one row, no march
   } else {
     const int64_t jb = seg * a.H;
     const int64_t je = (jb + a.H < a.ny) ? jb + a.H : a.ny;
@@ -177,7 +178,7 @@ __global__ __launch_bounds__(256) void k_sweep3d(const T* __restrict__ src, T* _
 // through LDS.  Thread t holds cells [t*SPT, (t+1)*SPT).  The per-cell
 // arithmetic is the same as in k_sweep2d, so results are bit-identical.
 // ---------------------------------------------------------------------------
-template <typename T, int AX, int SPT>
+template <typename T, int AX, int SPT, int NC>
 __global__ __launch_bounds__(1024) void k_resident1d(T* __restrict__ psi,
                                                      const double* __restrict__ V,
                                                      ResidentArgs a) {
@@ -192,7 +193,7 @@ __global__ __launch_bounds__(1024) void k_resident1d(T* __restrict__ psi,
   for (int k = 0; k < SPT; ++k) {
     const int64_t x = static_cast<int64_t>(t) * SPT + k;
     if (x < n) {
-      load_site(psi + x * 8, s[k]);
+      load_cell<NC, AX>(psi, x, s[k]);
       f[k] = phase_factors((a.ph.mode == 2) ? V[x] : 0.0, a.ph);
     } else {
       zero(s[k]);
@@ -241,24 +242,24 @@ __global__ __launch_bounds__(1024) void k_resident1d(T* __restrict__ psi,
 #pragma unroll
   for (int k = 0; k < SPT; ++k) {
     const int64_t x = static_cast<int64_t>(t) * SPT + k;
-    if (x < n) store_site(psi + x * 8, s[k]);
+    if (x < n) store_cell<NC, AX>(psi, x, s[k]);
   }
 }
 
 // ---------------------------------------------------------------------------
 // launchers: the 1-D / 2-D kernel for (type, depth, axes, phase mode)
 // ---------------------------------------------------------------------------
-template <typename T, class S, int K, int AX0, int AX1>
+template <typename T, class S, int K, int AX0, int AX1, int NC>
 static const void* kernel2d_mode(int mode) {
-  constexpr bool kField =
+  constexpr bool kField = NC == 4 &&
       K <= field_max_depth(sizeof(T) == 8, std::is_same<S, StrangStep>::value);
   switch (mode) {
-    case 0: return reinterpret_cast<const void*>(&k_sweep2d<T, S, K, AX0, AX1, 0>);
-    case 1: return reinterpret_cast<const void*>(&k_sweep2d<T, S, K, AX0, AX1, 1>);
-    case 2: return reinterpret_cast<const void*>(&k_sweep2d<T, S, K, AX0, AX1, 2>);
+    case 0: return reinterpret_cast<const void*>(&k_sweep2d<T, S, K, AX0, AX1, 0, NC>);
+    case 1: return reinterpret_cast<const void*>(&k_sweep2d<T, S, K, AX0, AX1, 1, NC>);
+    case 2: return reinterpret_cast<const void*>(&k_sweep2d<T, S, K, AX0, AX1, 2, NC>);
     case 3:
       if constexpr (kField)
-        return reinterpret_cast<const void*>(&k_sweep2d<T, S, K, AX0, AX1, 3>);
+        return reinterpret_cast<const void*>(&k_sweep2d<T, S, K, AX0, AX1, 3, NC>);
       else
         return nullptr;
     default: return nullptr;
@@ -266,48 +267,56 @@ static const void* kernel2d_mode(int mode) {
 }
 
 template <typename T, class S, int K>
-static const void* kernel2d_axes(int axes_code, int mode) {
+static const void* kernel2d_axes(int axes_code, int mode, int nc) {
+  if (nc == 2) {  // two-component 1-D lines
+    switch (axes_code) {
+      case 0: return kernel2d_mode<T, S, K, 0, -1, 2>(mode);
+      case 1: return kernel2d_mode<T, S, K, 1, -1, 2>(mode);
+      case 2: return kernel2d_mode<T, S, K, 2, -1, 2>(mode);
+      default: return nullptr;
+    }
+  }
   switch (axes_code) {
-    case 0: return kernel2d_mode<T, S, K, 0, -1>(mode);
-    case 1: return kernel2d_mode<T, S, K, 1, -1>(mode);
-    case 2: return kernel2d_mode<T, S, K, 2, -1>(mode);
-    case 10: return kernel2d_mode<T, S, K, 0, 1>(mode);
-    case 20: return kernel2d_mode<T, S, K, 0, 2>(mode);
-    case 21: return kernel2d_mode<T, S, K, 1, 2>(mode);
+    case 0: return kernel2d_mode<T, S, K, 0, -1, 4>(mode);
+    case 1: return kernel2d_mode<T, S, K, 1, -1, 4>(mode);
+    case 2: return kernel2d_mode<T, S, K, 2, -1, 4>(mode);
+    case 10: return kernel2d_mode<T, S, K, 0, 1, 4>(mode);
+    case 20: return kernel2d_mode<T, S, K, 0, 2, 4>(mode);
+    case 21: return kernel2d_mode<T, S, K, 1, 2, 4>(mode);
     default: return nullptr;
   }
 }
 
 // nullptr for combinations that are not built (depths beyond max_depth)
-static const void* kernel2d(bool fp64, bool strang, int depth, int axes_code, int mode) {
+static const void* kernel2d(bool fp64, bool strang, int depth, int axes_code, int mode, int nc) {
   if (strang) {
-    if (fp64) return depth == 1 ? kernel2d_axes<double, StrangStep, 1>(axes_code, mode) : nullptr;
+    if (fp64) return depth == 1 ? kernel2d_axes<double, StrangStep, 1>(axes_code, mode, nc) : nullptr;
     switch (depth) {
-      case 1: return kernel2d_axes<float, StrangStep, 1>(axes_code, mode);
-      case 2: return kernel2d_axes<float, StrangStep, 2>(axes_code, mode);
+      case 1: return kernel2d_axes<float, StrangStep, 1>(axes_code, mode, nc);
+      case 2: return kernel2d_axes<float, StrangStep, 2>(axes_code, mode, nc);
       default: return nullptr;
     }
   }
   if (fp64) {
     switch (depth) {
-      case 1: return kernel2d_axes<double, LieStep, 1>(axes_code, mode);
-      case 2: return kernel2d_axes<double, LieStep, 2>(axes_code, mode);
+      case 1: return kernel2d_axes<double, LieStep, 1>(axes_code, mode, nc);
+      case 2: return kernel2d_axes<double, LieStep, 2>(axes_code, mode, nc);
       default: return nullptr;
     }
   }
   switch (depth) {
-    case 1: return kernel2d_axes<float, LieStep, 1>(axes_code, mode);
-    case 2: return kernel2d_axes<float, LieStep, 2>(axes_code, mode);
-    case 3: return kernel2d_axes<float, LieStep, 3>(axes_code, mode);
-    case 4: return kernel2d_axes<float, LieStep, 4>(axes_code, mode);
-    case 5: return kernel2d_axes<float, LieStep, 5>(axes_code, mode);
+    case 1: return kernel2d_axes<float, LieStep, 1>(axes_code, mode, nc);
+    case 2: return kernel2d_axes<float, LieStep, 2>(axes_code, mode, nc);
+    case 3: return kernel2d_axes<float, LieStep, 3>(axes_code, mode, nc);
+    case 4: return kernel2d_axes<float, LieStep, 4>(axes_code, mode, nc);
+    case 5: return kernel2d_axes<float, LieStep, 5>(axes_code, mode, nc);
     default: return nullptr;
   }
 }
 
 hipError_t launch_sweep2d(bool fp64, bool strang, int depth, const void* src, void* dst,
                           const double* V, const SweepArgs& a, int blocks, hipStream_t st) {
-  const void* fn = kernel2d(fp64, strang, depth, a.axes_code, a.ph.mode);
+  const void* fn = kernel2d(fp64, strang, depth, a.axes_code, a.ph.mode, a.nc);
   if (!fn || blocks <= 0) return hipErrorInvalidValue;
   SweepArgs args = a;
   void* kargs[] = {const_cast<void**>(&src), &dst, const_cast<double**>(&V), &args};
@@ -325,7 +334,8 @@ static int occ_of(const void* kernel) {
   return n;
 }
 
-int sweep_occupancy(bool fp64, bool strang, int ndim, int axes_code, int mode, int depth) {
+int sweep_occupancy(bool fp64, bool strang, int ndim, int axes_code, int mode, int depth,
+                    int nc) {
   if (ndim == 3) {
     if (fp64) {
       switch (mode) {
@@ -340,7 +350,7 @@ int sweep_occupancy(bool fp64, bool strang, int ndim, int axes_code, int mode, i
       default: return occ_of(reinterpret_cast<const void*>(&k_sweep3d<float, kTY3D_F32, 2>));
     }
   }
-  return occ_of(kernel2d(fp64, strang, depth, axes_code, mode));
+  return occ_of(kernel2d(fp64, strang, depth, axes_code, mode, nc));
 }
 
 template <typename T, int TY>
@@ -371,8 +381,12 @@ hipError_t launch_sweep3d(bool fp64, const void* src, void* dst, const double* V
 template <typename T, int AX, int SPT>
 static hipError_t launch_res_t(void* psi, const double* V, const ResidentArgs& a, int threads,
                                hipStream_t st) {
-  hipLaunchKernelGGL((k_resident1d<T, AX, SPT>), dim3(1), dim3(threads), 0, st,
-                     static_cast<T*>(psi), V, a);
+  if (a.nc == 2)
+    hipLaunchKernelGGL((k_resident1d<T, AX, SPT, 2>), dim3(1), dim3(threads), 0, st,
+                       static_cast<T*>(psi), V, a);
+  else
+    hipLaunchKernelGGL((k_resident1d<T, AX, SPT, 4>), dim3(1), dim3(threads), 0, st,
+                       static_cast<T*>(psi), V, a);
   return hipGetLastError();
 }
 
@@ -383,7 +397,6 @@ static hipError_t launch_res_spt(void* psi, const double* V, const ResidentArgs&
     case 1: return launch_res_t<T, AX, 1>(psi, V, a, threads, st);
     case 2: return launch_res_t<T, AX, 2>(psi, V, a, threads, st);
     case 4: return launch_res_t<T, AX, 4>(psi, V, a, threads, st);
-    case 8: return launch_res_t<T, AX, 8>(psi, V, a, threads, st);
     default: return hipErrorInvalidValue;
   }
 }

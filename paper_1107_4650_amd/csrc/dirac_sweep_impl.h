@@ -344,8 +344,9 @@ __device__ __forceinline__ void march2d(const T* __restrict__ src, T* __restrict
 }
 
 // K steps of a 1-D line; the wave writes lanes wlane .. 63 - wlane (the
-// 64 - 2X lanes where all K steps are valid, or fewer)
-template <typename T, class S, int K, int AX, int MODE>
+// 64 - 2X lanes where all K steps are valid, or fewer).  NC: components
+// stored per cell (4, or 2 for the two-component line)
+template <typename T, class S, int K, int AX, int MODE, int NC = 4>
 __device__ __forceinline__ void one_row(const T* __restrict__ src, T* __restrict__ dst,
                                         const double* __restrict__ V, const SweepArgs& a,
                                         int64_t xs, int lane, int wlane) {
@@ -355,7 +356,7 @@ __device__ __forceinline__ void one_row(const T* __restrict__ src, T* __restrict
   const bool own = c.inside && lane >= wlane && lane <= 63 - wlane;  // wlane >= X
   const bool walls = !a.periodic && !c.inside;  // this lane's cell lies beyond a wall
   Site<T> m;
-  load_site(src + c.col * 8, m);
+  load_cell<NC, AX>(src, c.col, m);
   if (c.out) zero(m);
   constexpr bool FIELD = MODE == 3;
   const bool read_v = (MODE == 2) || (FIELD && V != nullptr) || (MODE < 0 && a.ph.mode == 2);
@@ -390,7 +391,7 @@ __device__ __forceinline__ void one_row(const T* __restrict__ src, T* __restrict
       if (walls) zero(m);
     }
   }
-  if (own) store_site(dst + c.x * 8, m);
+  if (own) store_cell<NC, AX>(dst, c.x, m);
 }
 
 // march a 2-D segment upwards (up = true) or downwards, writing lanes

@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "DL_OK", -1: "DL_ERR_ARG", -2: "DL_ERR_CFL", -3: "DL_ERR_DTYP
                 -4: "DL_ERR_ALIGN", -5: "DL_ERR_NOMEM", -6: "DL_ERR_HIP", -7: "DL_ERR_STATE"}
 DL_C64, DL_C128 = 0, 1
 DL_BC_ZERO, DL_BC_PERIODIC = 0, 1
-DL_DRY, DL_GRAPH, DL_STRANG = 1, 2, 4
+DL_DRY, DL_GRAPH, DL_STRANG, DL_BISPINOR = 1, 2, 4, 8
 
 # every entry point of include/libdirac.h
 EXPORTS = ("dl_plan_create", "dl_plan_destroy", "dl_step", "dl_step_field", "dl_step_out",
@@ -131,20 +131,21 @@ class Plan:
     """A libdirac plan for one grid (see include/libdirac.h)."""
 
     def __init__(self, shape, dx, dt, c, m, dtype="c64", bc="zero", axes=None, xmin=None,
-                 dry=False, graph=False, scheme="lie"):
+                 dry=False, graph=False, scheme="lie", bispinor=False):
         """scheme: "lie" (lowest order, c dt = dx) or "strang" (second order,
-        c dt = 2 dx; 1-D and 2-D grids)."""
+        c dt = 2 dx; 1-D and 2-D grids).  bispinor: 1-D line stored as the
+        pair of components that contains psi_1 (tensor shape (n, 2))."""
         if scheme not in ("lie", "strang"):
             raise ValueError(f"unknown scheme {scheme!r}")
         self.lib = load()
         self.shape = tuple(int(s) for s in shape)           # x first
-        self.tshape = tuple(reversed(self.shape)) + (4,)    # tensor shape
+        self.tshape = tuple(reversed(self.shape)) + (2 if bispinor else 4,)  # tensor shape
         self.dtype_code = _dtype_code(dtype)
         self.dx, self.dt, self.c, self.m = float(dx), float(dt), float(c), float(m)
         self.bc = bc
         self.grid = make_grid(self.shape, axes, xmin, dx)
         flags = ((DL_DRY if dry else 0) | (DL_GRAPH if graph else 0)
-                 | (DL_STRANG if scheme == "strang" else 0))
+                 | (DL_STRANG if scheme == "strang" else 0) | (DL_BISPINOR if bispinor else 0))
         h = ctypes.c_void_p()
         check(self.lib.dl_plan_create(ctypes.byref(h), ctypes.byref(self.grid), self.dx, self.dt,
                                       self.c, self.m, self.dtype_code, _bc_code(bc), flags))

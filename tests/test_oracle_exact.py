@@ -137,3 +137,24 @@ def test_local_step_equals_matrix_exponential(oracle):
         U = scipy.linalg.expm(-1j * (beta * m * c * c + V[i] * np.eye(4)) * dt)
         ref = U @ psi[i - 1]
         assert np.max(np.abs(out[i] - ref)) <= 1e-15 * max(1.0, np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("bc", ["zero", "periodic"])
+def test_one_axis_pairs_decouple(oracle, axis, bc):
+    """With one transport axis the components split into two pairs that never
+    mix (alpha_x, alpha_y: (1,4) and (2,3); alpha_z: (1,3) and (2,4); beta is
+    diagonal): a zero pair stays exactly zero, and the other pair evolves the
+    same whatever the zero pair held."""
+    n = 300
+    first = [0, 3] if axis < 2 else [0, 2]
+    other = [k for k in range(4) if k not in first]
+    psi = random_spinor((n,), seed=axis)
+    V = np.random.default_rng(9).uniform(-2, 2, n) * 137.036 ** 2
+    kw = dict(dt=0.01 / 137.036, c=137.036, m=1.0, nsteps=40, axes=(axis,), bc=bc)
+    full = oracle.step(psi, V, **kw)
+    half = psi.copy()
+    half[:, other] = 0
+    out = oracle.step(half, V, **kw)
+    assert np.all(out[:, other] == 0)
+    assert np.max(np.abs(out[:, first] - full[:, first])) <= 1e-15 * np.max(np.abs(full))
