@@ -10,6 +10,14 @@ namespace dirac {
 
 constexpr int kTY3D_F32 = 4;  // y rows per wave in the 3-D plane tile
 constexpr int kTY3D_F64 = 2;
+// two-step 3-D pass: y rows per wave, and one wave per SIMD (its working set
+// spills into the accumulation registers of a wave that has the SIMD alone)
+constexpr int kTY3D2_F32 = 4;
+constexpr int kMinBlocks3D2 = 1;
+// 3-D passes fuse at most two lowest-order steps (FP64 state: one), on rows
+// of fewer than 2^28 cells (per-lane offsets are 32-bit)
+__host__ __device__ constexpr int max_depth3d(bool fp64) { return fp64 ? 1 : 2; }
+constexpr int64_t kMaxRow3DFused = int64_t(1) << 28;
 // 1-D / 2-D passes fuse up to kMaxDepth full lowest-order steps (FP64 state:
 // 2; deeper passes would not fit the registers of two waves per SIMD), or up
 // to 2 second-order steps (FP64: 1).  A wave of 64 lanes writes 64 - 2X
@@ -68,8 +76,9 @@ struct ObsArgs {
 // `blocks` 256-thread workgroups
 hipError_t launch_sweep2d(bool fp64, bool strang, int depth, const void* src, void* dst,
                           const double* V, const SweepArgs& a, int blocks, hipStream_t st);
-// one full step src -> dst on a 3-D grid
-hipError_t launch_sweep3d(bool fp64, const void* src, void* dst, const double* V,
+// `depth` (1 or 2) full steps src -> dst in one pass over a 3-D grid (tiling
+// made by the 3-D tiler for that depth)
+hipError_t launch_sweep3d(bool fp64, int depth, const void* src, void* dst, const double* V,
                           const SweepArgs& a, int blocks, hipStream_t st);
 // resident 256-thread blocks per CU of the sweep kernel for this layout,
 // phase mode and depth (0 if the runtime cannot tell)

@@ -141,22 +141,36 @@ void make_tiling(const dl_grid& g, int64_t target, int seg_override, SweepArgs& 
   a.axes_code = axes_code(g);
 }
 
-void make_tiling3d(const dl_grid& g, int ty, int64_t target, int seg_override, SweepArgs& a,
-                   int& blocks) {
+// 3-D tiling: strips of `strip_width` x cells by blocks of `ty` y rows, march
+// segments along z.  A wave of a segment of H planes runs H + halo plane
+// iterations; with `target` waves resident at once, the segment count is the
+// one that minimises (rounds of resident waves) x (H + halo).
+void make_tiling3d(const dl_grid& g, int ty, int strip_width, int halo, int64_t target,
+                   int seg_override, SweepArgs& a, int& blocks) {
   a.nx = g.n[0];
   a.ny = g.n[1];
   a.nz = g.n[2];
-  a.nstrips = (a.nx + 63) / 64;
+  a.nstrips = (a.nx + strip_width - 1) / strip_width;
   a.nyblk = (a.ny + ty - 1) / ty;
   const int64_t per_seg = a.nstrips * a.nyblk;
   int64_t H;
   if (seg_override > 0) {
     H = seg_override;
   } else {
-    int64_t nseg = target / per_seg;
-    if (nseg < 1) nseg = 1;
-    H = (a.nz + nseg - 1) / nseg;
-    if (H < 4) H = 4;
+    if (target < 1) target = 1;
+    H = a.nz;
+    int64_t best = -1;
+    for (int64_t ns = 1; ns <= 4096 && ns <= a.nz; ++ns) {
+      const int64_t h = (a.nz + ns - 1) / ns;
+      if (h < 4 && ns > 1) break;
+      const int64_t nseg = (a.nz + h - 1) / h;
+      const int64_t rounds = (per_seg * nseg + target - 1) / target;
+      const int64_t cost = rounds * (h + halo);
+      if (best < 0 || cost < best) {
+        best = cost;
+        H = h;
+      }
+    }
   }
   if (H > a.nz) H = a.nz;
   a.H = static_cast<int>(H);
@@ -197,12 +211,16 @@ static int64_t resident_waves(dl_plan p, int mode, int depth) {
 }
 
 static int plan_tiling(dl_plan p) {
-  // fused steps per pass: 1-D and 2-D grids only; a periodic 2-D pass reaches
-  // one row per stage (one per lowest-order step, two per second-order step)
-  // beyond a segment on each side and wraps once, so the box needs at least
-  // twice that many rows
+  // fused steps per pass.  A periodic 2-D pass reaches one row per stage (one
+  // per lowest-order step, two per second-order step) beyond a segment on each
+  // side and wraps once, so the box needs at least twice that many rows.  A
+  // 3-D pass fuses at most two steps; the rows and planes its stored cells
+  // depend on lie at most two beyond the box, which one wrap reaches for any
+  // box of two or more cells per axis.
   int depth = 1;
-  if (p->g.ndim <= 2) {
+  if (p->g.ndim == 3) {
+    if (p->g.n[0] < kMaxRow3DFused) depth = std::min(p->depth_limit, max_depth3d(p->fp64));
+  } else {
     depth = std::min(p->depth_limit, max_depth(p->fp64, p->strang));
     const int stages_per_step = p->strang ? 2 : 1;
     if (p->g.ndim == 2 && p->bc == DL_BC_PERIODIC)
@@ -214,8 +232,11 @@ static int plan_tiling(dl_plan p) {
     PlanTiling& t = p->tiling[mode];
     if (p->g.ndim == 3) {
       if (mode == 3) continue;  // no vector potential on 3-D grids
-      make_tiling3d(p->g, p->fp64 ? kTY3D_F64 : kTY3D_F32, resident_waves(p, mode, 1),
+      make_tiling3d(p->g, p->fp64 ? kTY3D_F64 : kTY3D_F32, 64, 2, resident_waves(p, mode, 1),
                     p->seg_override, t.a[0], t.b[0]);
+      if (depth >= 2)
+        make_tiling3d(p->g, kTY3D2_F32, strip_width(2), 4, resident_waves(p, mode, 2),
+                      p->seg_override, t.a[1], t.b[1]);
     } else {
       for (int d = 1; d <= (mode == 3 ? p->depth_field : depth); ++d)
         make_tiling(p->g, resident_waves(p, mode, d), p->seg_override, t.a[d - 1], t.b[d - 1],
@@ -354,9 +375,9 @@ int check_f64_ptr(const void* ptr, const char* name, bool nullable) {
 hipError_t launch_pass(dl_plan p, int depth, const void* src, void* dst, const double* V,
                        hipStream_t st) {
   if (p->g.ndim == 3) {
-    SweepArgs a = p->sw[0];
+    SweepArgs a = p->sw[depth - 1];
     a.ph = p->ph;
-    return launch_sweep3d(p->fp64, src, dst, V, a, p->bl[0], st);
+    return launch_sweep3d(p->fp64, depth, src, dst, V, a, p->bl[depth - 1], st);
   }
   SweepArgs a = p->sw[depth - 1];
   a.ph = p->ph;

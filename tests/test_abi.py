@@ -92,6 +92,28 @@ def test_dry_strang_plans(lib):
         dry((64,), scheme="rk4")
 
 
+def test_dry_3d_pass_depth(lib):
+    """FP32 3-D plans fuse two steps per pass (waves write 60 columns, row
+    blocks of 4); FP64 plans, rows of 2^28 cells or more and a depth cap of
+    one keep single steps."""
+    p = dry((64, 30, 16))
+    info = p.info()
+    assert info["depth"] == 2 and info["nstrips"] == 2
+    assert info["ntiles"] == 2 * 8 * info["nseg"]
+    p.set_depth(1)
+    assert p.info()["depth"] == 1 and p.info()["nstrips"] == 1
+    p.close()
+    p = dry((64, 30, 16), dtype="c128")
+    assert p.info()["depth"] == 1
+    p.close()
+    p = dry((1 << 28, 2, 2))
+    assert p.info()["depth"] == 1
+    p.close()
+    p = dry(((1 << 28) - 1, 2, 2))
+    assert p.info()["depth"] == 2
+    p.close()
+
+
 def test_raw_abi_argument_errors(lib):
     g = L.make_grid((64,), dx=0.01)
     h = ctypes.c_void_p()

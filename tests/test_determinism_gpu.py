@@ -92,6 +92,27 @@ def test_fused_passes_same_bits(dtype, shape, axes, bc):
         assert same_bits(massless, gpu_step(psi, None, nsteps=9, depth=d, **{**kw, "m": 0.0}))
 
 
+@pytest.mark.parametrize("shape,bc,seg", [((70, 13, 11), "zero", 0), ((130, 6, 21), "periodic", 4),
+                                          ((61, 9, 5), "zero", 2), ((64, 64, 40), "zero", 7),
+                                          ((3, 2, 2), "periodic", 0), ((2, 5, 3), "zero", 0),
+                                          ((121, 4, 9), "periodic", 3), ((2, 2, 7), "periodic", 2)])
+def test_fused_3d_passes_same_bits(shape, bc, seg):
+    """3-D passes of two fused steps (FP32 state) give the bits of single
+    steps: ragged strips and row blocks, segments marching up and down,
+    walls, wrap-around, boxes of two cells per axis; every phase mode."""
+    announce(f"fused 3-D passes {shape} {bc} seg={seg}")
+    psi = random_spinor(shape[::-1], seed=31)
+    V = _V(shape, seed=32)
+    kw = dict(dx=DX, dt=DT, c=C, axes=(0, 1, 2), bc=bc, dtype="c64",
+              tiling={"seg_len": seg} if seg else None)
+    for n in (1, 2, 3, 8):
+        single = gpu_step(psi, V, m=1.0, nsteps=n, depth=1, **kw)
+        assert same_bits(single, gpu_step(psi, V, m=1.0, nsteps=n, depth=2, **kw)), n
+    for m in (0.0, 1.0):
+        single = gpu_step(psi, None, m=m, nsteps=5, depth=1, **kw)
+        assert same_bits(single, gpu_step(psi, None, m=m, nsteps=5, depth=2, **kw)), m
+
+
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
 def test_step_fused_out_matches_single_steps(dtype):
     import torch
