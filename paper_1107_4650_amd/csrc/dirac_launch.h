@@ -84,6 +84,8 @@ hipError_t launch_sweep3d(bool fp64, int depth, const void* src, void* dst, cons
 // phase mode and depth (0 if the runtime cannot tell)
 int sweep_occupancy(bool fp64, bool strang, int ndim, int axes_code, int mode, int depth,
                     int nc);
+// the same for the 3-D kernels
+int occupancy3d(bool fp64, int mode, int depth);
 // nsteps in place in one workgroup of `threads` threads, `spt` cells each
 hipError_t launch_resident1d(bool fp64, int axis, void* psi, const double* V,
                              const ResidentArgs& a, int spt, int threads, hipStream_t st);

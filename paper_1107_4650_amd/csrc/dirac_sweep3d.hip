@@ -1,0 +1,357 @@
+// dirac_sweep3d.hip -- the Dirac sweep on 3-D grids (gfx950).
+//
+// A full lowest-order step (Sec. 2.1) on a 3-D grid: T_x, T_y, T_z, then the
+// local step.  A wave marches along z with a plane tile of 64 x cells by TY y
+// rows, the y transport rolling over the rows of the tile and the z
+// transport rolling over planes.  With FP32 state a pass advances two steps
+// (60 output columns, two halo rows in y and two halo planes in z).
+#include "dirac_device.h"
+#include "dirac_launch.h"
+#include "dirac_sweep_impl.h"
+
+namespace dirac {
+
+// ---------------------------------------------------------------------------
+// 3-D fused step: march along z, plane tile 64 x TY per wave.  The potential
+// of the TY output rows is loaded one plane ahead, so each plane starts with
+// the TY independent phase-factor chains, which run while the plane's rows
+// are still in flight.
+// ---------------------------------------------------------------------------
+template <typename T, int TY, bool UP, int MODE>
+__device__ __forceinline__ void march3d(const T* __restrict__ src, T* __restrict__ dst,
+                                        const double* __restrict__ V, const SweepArgs& a,
+                                        int64_t x0, int lane, int64_t y0, int64_t kb,
+                                        int64_t ke) {
+  constexpr bool TWO = sizeof(T) == 8;
+  const int64_t nx = a.nx, ny = a.ny, nz = a.nz;
+  const int64_t plane_cells = nx * ny;
+  const int nit = static_cast<int>(ke - kb) + 2;
+  const int64_t x = x0 + lane;
+  const int64_t xv = x < nx ? x : nx - 1;
+  const bool read_v = (MODE == 2);
+  auto kout_of = [&](int it) -> int64_t { return UP ? kb - 2 + it : ke - it + 1; };
+  auto load_v = [&](int it, double* v) {
+    int64_t k = kout_of(it);
+    k = k < 0 ? 0 : (k >= nz ? nz - 1 : k);
+#pragma unroll
+    for (int t = 0; t < TY; ++t) {
+      const int64_t y = (y0 + t < ny) ? y0 + t : ny - 1;
+      v[t] = read_v ? V[(k * ny + y) * nx + xv] : 0.0;
+    }
+  };
+  Mov<T> zs1[TY], zs2[TY];
+#pragma unroll
+  for (int t = 0; t < TY; ++t) {
+    zero(zs1[t]);
+    zero(zs2[t]);
+  }
+  double vcur[TY];
+  load_v(0, vcur);
+  for (int it = 0; it < nit; ++it) {
+    const int64_t kin = UP ? kb - 1 + it : ke - it;
+    const int64_t kout = kout_of(it);
+    const int64_t kr = wrap_or_neg(kin, nz, a.periodic);
+    // loads of this plane tile (rows y0-1 .. y0+TY) and of the next plane's potential
+    Row<T> rows[TY + 2];
+#pragma unroll
+    for (int t = 0; t < TY + 2; ++t) {
+      if (kr >= 0) {
+        load_row(src + kr * plane_cells * 8, nx, ny, a.periodic, x0, lane, y0 - 1 + t, rows[t]);
+      } else {
+        zero(rows[t].m);
+        zero(rows[t].h);
+      }
+    }
+    double vnext[TY];
+    load_v(it + 1, vnext);
+    Factors fac[TY];
+#pragma unroll
+    for (int t = 0; t < TY; ++t) fac[t] = factors_of<MODE, TWO>(vcur[t], a.ph);
+#pragma unroll
+    for (int t = 0; t < TY; ++t) factors_fix<MODE, TWO>(fac[t], vcur[t], a.ph);
+    // x transport of every row, y transport rolling over the rows
+    Mov<T> ry1, ry2;
+    zero(ry1);
+    zero(ry2);
+#pragma unroll
+    for (int t = 0; t < TY + 2; ++t) {
+      Site<T> phi;
+      x_transport<T, 0>(rows[t], phi);
+      Mov<T> ry, ly;
+      Axis<1, T>::movers(phi, ry, ly);
+      if (t >= 2) {
+        const int ty = t - 2;  // output row y0 + ty
+        Site<T> psi2;
+        Axis<1, T>::combine(ry2, ly, psi2);
+        Mov<T> rz, lz;
+        Axis<2, T>::movers(psi2, rz, lz);
+        if (it >= 2) {
+          Site<T> o;
+          if (UP)
+            Axis<2, T>::combine(zs2[ty], lz, o);
+          else
+            Axis<2, T>::combine(rz, zs2[ty], o);
+          apply_local<MODE>(o, fac[ty], a.ph);
+          const int64_t y = y0 + ty;
+          if (x < nx && y < ny) store_site(dst + ((kout * ny + y) * nx + x) * 8, o);
+        }
+        zs2[ty] = zs1[ty];
+        zs1[ty] = UP ? rz : lz;
+      }
+      ry2 = ry1;
+      ry1 = ry;
+    }
+#pragma unroll
+    for (int t = 0; t < TY; ++t) vcur[t] = vnext[t];
+  }
+}
+
+template <typename T, int TY, int MODE>
+__global__ __launch_bounds__(256) void k_sweep3d(const T* __restrict__ src, T* __restrict__ dst,
+                                                 const double* __restrict__ V, SweepArgs a) {
+  const int lane = threadIdx.x & 63;
+  int64_t blk = blockIdx.x;
+  if (a.xcd_remap) blk = (blk % 8) * (gridDim.x / 8) + blk / 8;
+  const int64_t tile = blk * 4 + wave_in_block();
+  if (tile >= a.ntiles) return;
+  // tile order: x strips fastest, then y row blocks, then z segments
+  const int64_t strip = tile % a.nstrips;
+  const int64_t rest = tile / a.nstrips;
+  const int64_t yblk = rest % a.nyblk;
+  const int64_t seg = rest / a.nyblk;
+  const int64_t x0 = strip * 64, y0 = yblk * TY;
+  const int64_t kb = seg * a.H;
+  const int64_t ke = (kb + a.H < a.nz) ? kb + a.H : a.nz;
+  if (seg & 1)
+    march3d<T, TY, false, MODE>(src, dst, V, a, x0, lane, y0, kb, ke);
+  else
+    march3d<T, TY, true, MODE>(src, dst, V, a, x0, lane, y0, kb, ke);
+}
+
+// ---------------------------------------------------------------------------
+// 3-D pass of two fused steps (temporal blocking).  A wave holds 64 x
+// columns (writing the middle 60) and a block of TY y rows, and marches along
+// z.  Each plane iteration reads TY + 4 rows of the input plane (two halo rows
+// on each side); the rows of the next plane and their potential are loaded
+// while the current plane computes.  The first step completes, in streaming
+// order, the TY + 2 rows y0 - 1 .. y0 + TY of the plane one behind (its own y
+// halo for the second step); each of those rows feeds the second step at
+// once, which completes the TY output rows of the plane two behind.  The z
+// movers of two previous planes are kept per step and row.  The phase
+// factors of a row are formed once, by the first step, and kept for the
+// second step, which reaches the same row and plane one iteration later.
+// Intermediate states are rounded as stored steps and zeroed outside the box
+// with zero walls, so the pass gives the bits of two single steps.
+// ---------------------------------------------------------------------------
+template <typename T, int TY, bool UP, int MODE>
+__device__ __forceinline__ void march3d_x2(const T* __restrict__ src, T* __restrict__ dst,
+                                           const double* __restrict__ V, const SweepArgs& a,
+                                           int64_t xs, int lane, int64_t y0, int64_t kb,
+                                           int64_t ke) {
+  constexpr bool TWO = sizeof(T) == 8;
+  constexpr int K = 2;
+  constexpr int R0 = TY + 4;  // rows read per plane
+  constexpr int R1 = TY + 2;  // rows completed by the first step
+  const int64_t nx = a.nx, ny = a.ny, nz = a.nz;
+  const int64_t plane_cells = nx * ny;
+  const int nit = static_cast<int>(ke - kb) + 2 * K;
+  const Lanes c = lanes_of(nx, a.periodic, xs, lane);
+  const bool own = c.inside && lane >= K && lane <= 63 - K;
+  // per-lane offsets fit 32 bits (a row holds fewer than 2^28 cells); row and
+  // plane bases are wave-uniform
+  const uint32_t cell_off = static_cast<uint32_t>(c.col) * 8u;
+  const uint32_t v_off = static_cast<uint32_t>(c.col);
+  const bool read_v = (MODE == 2);
+  const bool zero_walls = !a.periodic;
+  auto in_plane = [&](int it) -> int64_t { return UP ? kb - K + it : ke - 1 + K - it; };
+  auto plane_of = [&](int it, int st) -> int64_t {
+    return UP ? in_plane(it) - st : in_plane(it) + st;
+  };
+  auto out_of_box = [&](int64_t k, int64_t y) -> bool {
+    return k < 0 || k >= nz || y < 0 || y >= ny;
+  };
+  // input rows of iteration it (slot it % 2) and the V of its first-step rows;
+  // the plane of iteration it + 1 is loaded while iteration it computes
+  Site<T> buf[2][R0];
+  double vb[2][R1];
+  auto load_plane = [&](int it, Site<T>* rows, double* v) {
+    const int64_t kr = read_row(in_plane(it), nz, a.periodic);
+    const T* plane = src + kr * plane_cells * 8;
+#pragma unroll
+    for (int t = 0; t < R0; ++t)
+      load_site(plane + read_row(y0 - 2 + t, ny, a.periodic) * nx * 8 + cell_off, rows[t]);
+    const int64_t k1r = read_row(plane_of(it, 1), nz, a.periodic);
+#pragma unroll
+    for (int u = 0; u < R1; ++u)
+      v[u] = read_v ? (V + (k1r * ny + read_row(y0 - 1 + u, ny, a.periodic)) * nx)[v_off] : 0.0;
+  };
+  // z movers of two previous planes, per step and row (slot it % 2)
+  Mov<T> zm1[2][R1], zm2[2][TY];
+  // factors of the output rows, formed by the first step on plane k1 and used
+  // by the second step on the same plane one iteration later
+  Factors fc[TY];
+#pragma unroll
+  for (int w = 0; w < TY; ++w) fc[w] = Factors{};
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+#pragma unroll
+    for (int u = 0; u < R1; ++u) {
+      zero(zm1[q][u]);
+      vb[q][u] = 0.0;
+    }
+#pragma unroll
+    for (int w = 0; w < TY; ++w) zero(zm2[q][w]);
+  }
+  load_plane(0, buf[0], vb[0]);
+  for (int pair = 0;; ++pair) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int it = 2 * pair + k;
+      if (it >= nit) return;
+      const int64_t kin = in_plane(it);
+      const int64_t k1 = plane_of(it, 1), k2 = plane_of(it, 2);
+      load_plane(it + 1, buf[k ^ 1], vb[k ^ 1]);
+      Factors pend{};  // factors of the previous first-step row
+      // streaming over rows: first step (y movers of two rows back), then second
+      Mov<T> ya1, yb1, ya2, yb2;  // r movers of rows t - 1 and t - 2 (first, second step)
+      zero(ya1);
+      zero(yb1);
+      zero(ya2);
+      zero(yb2);
+#pragma unroll
+      for (int t = 0; t < R0; ++t) {
+        Site<T> in = buf[k][t];
+        if (zero_walls) {
+          if (out_of_box(kin, y0 - 2 + t)) zero(in);
+          if (!c.full && c.out) zero(in);
+        }
+        Site<T> phi;
+        x_transport_inner<T, 0>(in, phi);
+        Mov<T> ry, ly;
+        Axis<1, T>::movers(phi, ry, ly);
+        if (t >= 2) {
+          const int u = t - 2;  // first-step row y0 - 1 + u of plane k1
+          Site<T> py;
+          Axis<1, T>::combine(yb1, ly, py);
+          Mov<T> rz, lz;
+          Axis<2, T>::movers(py, rz, lz);
+          Site<T> o1;
+          if (UP)
+            Axis<2, T>::combine(zm1[k][u], lz, o1);
+          else
+            Axis<2, T>::combine(rz, zm1[k][u], o1);
+          zm1[k][u] = UP ? rz : lz;
+          Factors f1 = factors_of<MODE, TWO>(vb[k][u], a.ph);
+          factors_fix<MODE, TWO>(f1, vb[k][u], a.ph);
+          apply_local<MODE>(o1, f1, a.ph);
+          if (zero_walls) {
+            if (out_of_box(k1, y0 - 1 + u)) zero(o1);
+            if (!c.full && !c.inside) zero(o1);
+          }
+          // second step on first-step row u
+          Site<T> phi2;
+          x_transport_inner<T, 0>(o1, phi2);
+          Mov<T> ry2, ly2;
+          Axis<1, T>::movers(phi2, ry2, ly2);
+          if (u >= 2) {
+            const int w = u - 2;  // output row y0 + w of plane k2
+            Site<T> py2;
+            Axis<1, T>::combine(yb2, ly2, py2);
+            Mov<T> rz2, lz2;
+            Axis<2, T>::movers(py2, rz2, lz2);
+            Site<T> o2;
+            if (UP)
+              Axis<2, T>::combine(zm2[k][w], lz2, o2);
+            else
+              Axis<2, T>::combine(rz2, zm2[k][w], o2);
+            zm2[k][w] = UP ? rz2 : lz2;
+            apply_local<MODE>(o2, fc[w], a.ph);
+            const int64_t y = y0 + w;
+            if (it >= 2 * K && own && y < ny)
+              store_site(dst + (k2 * ny + y) * nx * 8 + cell_off, o2);
+            // row y0 + w of plane k1 takes these factors in the next iteration
+            fc[w] = pend;
+          }
+          pend = f1;
+          yb2 = ya2;
+          ya2 = ry2;
+        }
+        yb1 = ya1;
+        ya1 = ry;
+      }
+    }
+  }
+}
+
+template <typename T, int TY, int MODE>
+__global__ __launch_bounds__(256, kMinBlocks3D2) void k_sweep3d_x2(const T* __restrict__ src,
+                                                       T* __restrict__ dst,
+                                                       const double* __restrict__ V,
+                                                       SweepArgs a) {
+  const int lane = threadIdx.x & 63;
+  int64_t blk = blockIdx.x;
+  if (a.xcd_remap) blk = (blk % 8) * (gridDim.x / 8) + blk / 8;
+  const int64_t tile = blk * 4 + wave_in_block();
+  if (tile >= a.ntiles) return;
+  // tile order: x strips fastest, then y row blocks, then z segments
+  const int64_t strip = tile % a.nstrips;
+  const int64_t rest = tile / a.nstrips;
+  const int64_t yblk = rest % a.nyblk;
+  const int64_t seg = rest / a.nyblk;
+  const int64_t xs = strip * strip_width(2) - 2, y0 = yblk * TY;
+  const int64_t kb = seg * a.H;
+  const int64_t ke = (kb + a.H < a.nz) ? kb + a.H : a.nz;
+  if (seg & 1)
+    march3d_x2<T, TY, false, MODE>(src, dst, V, a, xs, lane, y0, kb, ke);
+  else
+    march3d_x2<T, TY, true, MODE>(src, dst, V, a, xs, lane, y0, kb, ke);
+}
+
+// ---- 3-D kernels: one step, or a pass of two fused steps ---------------------
+template <typename T>
+static const void* kernel3d(int depth, int mode) {
+  constexpr bool F64 = sizeof(T) == 8;
+  constexpr int TY1 = F64 ? kTY3D_F64 : kTY3D_F32;
+  if (depth == 2) {
+    if constexpr (F64) return nullptr;  // FP64: one step per pass (two would spill)
+    constexpr int TY2 = kTY3D2_F32;
+    switch (mode) {
+      case 0: return reinterpret_cast<const void*>(&k_sweep3d_x2<T, TY2, 0>);
+      case 1: return reinterpret_cast<const void*>(&k_sweep3d_x2<T, TY2, 1>);
+      default: return reinterpret_cast<const void*>(&k_sweep3d_x2<T, TY2, 2>);
+    }
+  }
+  if (depth != 1) return nullptr;
+  switch (mode) {
+    case 0: return reinterpret_cast<const void*>(&k_sweep3d<T, TY1, 0>);
+    case 1: return reinterpret_cast<const void*>(&k_sweep3d<T, TY1, 1>);
+    default: return reinterpret_cast<const void*>(&k_sweep3d<T, TY1, 2>);
+  }
+}
+
+static int occ_of(const void* kernel) {
+  if (!kernel) return 0;
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, 256, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return n;
+}
+
+int occupancy3d(bool fp64, int mode, int depth) {
+  const int m = mode < 0 || mode > 2 ? 2 : mode;
+  return occ_of(fp64 ? kernel3d<double>(depth, m) : kernel3d<float>(depth, m));
+}
+
+hipError_t launch_sweep3d(bool fp64, int depth, const void* src, void* dst, const double* V,
+                          const SweepArgs& a, int blocks, hipStream_t st) {
+  const int m = a.ph.mode < 0 || a.ph.mode > 2 ? 2 : a.ph.mode;
+  const void* fn = fp64 ? kernel3d<double>(depth, m) : kernel3d<float>(depth, m);
+  if (!fn || blocks <= 0) return hipErrorInvalidValue;
+  SweepArgs args = a;
+  void* kargs[] = {const_cast<void**>(&src), &dst, const_cast<double**>(&V), &args};
+  return hipLaunchKernel(fn, dim3(blocks), dim3(256), kargs, 0, st);
+}
+
+}  // namespace dirac
