@@ -175,7 +175,7 @@ def bench_main(args):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
-                     "kernel": f"k_sweep2d<float,{d32},0,1,2>",
+                     "kernel": f"k_sweep2d<float, LieStep, {d32}, 0, 1, 2, 4>",
                      "bytes_per_launch_per_cell": BYTES_F32,
                      "bytes_per_site_update": BYTES_F32 / d32,
                      "per_launch_ms": per32, "site_updates_per_launch": d32 * sites,
