@@ -10,22 +10,30 @@ namespace dirac {
 
 constexpr int kTY3D_F32 = 4;  // y rows per wave in the 3-D plane tile
 constexpr int kTY3D_F64 = 2;
-// two-step 3-D pass: y rows per wave, and one wave per SIMD (its working set
-// spills into the accumulation registers of a wave that has the SIMD alone)
+// two-step 3-D pass: y rows per wave (FP32, FP64 state), and one wave per SIMD
+// (its working set spills into the accumulation registers of a wave that has
+// the SIMD alone)
 constexpr int kTY3D2_F32 = 4;
+constexpr int kTY3D2_F64 = 2;
 constexpr int kMinBlocks3D2 = 1;
-// 3-D passes fuse at most two lowest-order steps (FP64 state: one), on rows
-// of fewer than 2^28 cells (per-lane offsets are 32-bit)
-__host__ __device__ constexpr int max_depth3d(bool fp64) { return fp64 ? 1 : 2; }
+// 3-D passes fuse at most two lowest-order steps, on rows of fewer than 2^28
+// cells (per-lane offsets are 32-bit)
+__host__ __device__ constexpr int max_depth3d(bool) { return 2; }
 constexpr int64_t kMaxRow3DFused = int64_t(1) << 28;
-// 1-D / 2-D passes fuse up to kMaxDepth full lowest-order steps (FP64 state:
-// 2; deeper passes would not fit the registers of two waves per SIMD), or up
-// to 2 second-order steps (FP64: 1).  A wave of 64 lanes writes 64 - 2X
-// columns, X being the x transports of the pass (one per lowest-order step,
-// two per second-order step).
+// 1-D / 2-D passes fuse up to kMaxDepth full lowest-order steps, or up to 2
+// second-order steps (FP64: 1).  A wave of 64 lanes writes 64 - 2X columns, X
+// being the x transports of the pass (one per lowest-order step, two per
+// second-order step).  FP64 passes of more than two steps need more registers
+// than two waves per SIMD have: they run one wave per SIMD, the compiler
+// parking part of the working set in the accumulation registers.
 constexpr int kMaxDepth = 5;
+constexpr int kMaxDepthF64 = 5;
 __host__ __device__ constexpr int max_depth(bool fp64, bool strang) {
-  return strang ? (fp64 ? 1 : 2) : (fp64 ? 2 : kMaxDepth);
+  return strang ? (fp64 ? 1 : 2) : (fp64 ? kMaxDepthF64 : kMaxDepth);
+}
+// resident 256-thread blocks per CU the 1-D / 2-D kernel is compiled for
+__host__ __device__ constexpr int sweep2d_min_blocks(bool fp64, int depth) {
+  return (fp64 && depth > 2) ? 1 : 2;
 }
 // passes whose local step carries a vector potential (phase mode 3) hold
 // nine doubles of factors per row in flight: they fuse at most 2 steps

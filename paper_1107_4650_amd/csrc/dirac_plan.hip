@@ -235,7 +235,8 @@ static int plan_tiling(dl_plan p) {
       make_tiling3d(p->g, p->fp64 ? kTY3D_F64 : kTY3D_F32, 64, 2, resident_waves(p, mode, 1),
                     p->seg_override, t.a[0], t.b[0]);
       if (depth >= 2)
-        make_tiling3d(p->g, kTY3D2_F32, strip_width(2), 4, resident_waves(p, mode, 2),
+        make_tiling3d(p->g, p->fp64 ? kTY3D2_F64 : kTY3D2_F32, strip_width(2), 4,
+                      resident_waves(p, mode, 2),
                       p->seg_override, t.a[1], t.b[1]);
     } else {
       for (int d = 1; d <= (mode == 3 ? p->depth_field : depth); ++d)

@@ -29,8 +29,9 @@ namespace dirac {
 // output columns per wave, X = x transports of the pass; march segments of
 // H rows in 2-D)
 template <typename T, class S, int K, int AX0, int AX1, int MODE, int NC = 4>
-__global__ __launch_bounds__(256, 2) void k_sweep2d(const T* __restrict__ src, T* __restrict__ dst,
-                                                    const double* __restrict__ V, SweepArgs a) {
+__global__ __launch_bounds__(256, sweep2d_min_blocks(sizeof(T) == 8, K))
+void k_sweep2d(const T* __restrict__ src, T* __restrict__ dst, const double* __restrict__ V,
+               SweepArgs a) {
   static_assert(NC == 4 || AX1 < 0, "two-component states are 1-D lines");
   constexpr int X = halo_lanes<S>(K);
   const int lane = threadIdx.x & 63;
@@ -177,9 +178,14 @@ static const void* kernel2d(bool fp64, bool strang, int depth, int axes_code, in
     }
   }
   if (fp64) {
+    static_assert(kMaxDepthF64 <= 5, "FP64 kernels are built for depths 1 to 5");
+    if (depth > kMaxDepthF64) return nullptr;
     switch (depth) {
       case 1: return kernel2d_axes<double, LieStep, 1>(axes_code, mode, nc);
       case 2: return kernel2d_axes<double, LieStep, 2>(axes_code, mode, nc);
+      case 3: return kernel2d_axes<double, LieStep, 3>(axes_code, mode, nc);
+      case 4: return kernel2d_axes<double, LieStep, 4>(axes_code, mode, nc);
+      case 5: return kernel2d_axes<double, LieStep, 5>(axes_code, mode, nc);
       default: return nullptr;
     }
   }

@@ -313,8 +313,7 @@ static const void* kernel3d(int depth, int mode) {
   constexpr bool F64 = sizeof(T) == 8;
   constexpr int TY1 = F64 ? kTY3D_F64 : kTY3D_F32;
   if (depth == 2) {
-    if constexpr (F64) return nullptr;  // FP64: one step per pass (two would spill)
-    constexpr int TY2 = kTY3D2_F32;
+    constexpr int TY2 = F64 ? kTY3D2_F64 : kTY3D2_F32;
     switch (mode) {
       case 0: return reinterpret_cast<const void*>(&k_sweep3d_x2<T, TY2, 0>);
       case 1: return reinterpret_cast<const void*>(&k_sweep3d_x2<T, TY2, 1>);

@@ -93,9 +93,9 @@ def test_dry_strang_plans(lib):
 
 
 def test_dry_3d_pass_depth(lib):
-    """FP32 3-D plans fuse two steps per pass (waves write 60 columns, row
-    blocks of 4); FP64 plans, rows of 2^28 cells or more and a depth cap of
-    one keep single steps."""
+    """3-D plans fuse two steps per pass (waves write 60 columns, row blocks
+    of 4 with FP32 state, 2 with FP64); rows of 2^28 cells or more and a
+    depth cap of one keep single steps."""
     p = dry((64, 30, 16))
     info = p.info()
     assert info["depth"] == 2 and info["nstrips"] == 2
@@ -104,7 +104,9 @@ def test_dry_3d_pass_depth(lib):
     assert p.info()["depth"] == 1 and p.info()["nstrips"] == 1
     p.close()
     p = dry((64, 30, 16), dtype="c128")
-    assert p.info()["depth"] == 1
+    info = p.info()
+    assert info["depth"] == 2 and info["nstrips"] == 2
+    assert info["ntiles"] == 2 * 15 * info["nseg"]  # row blocks of 2 with FP64 state
     p.close()
     p = dry((1 << 28, 2, 2))
     assert p.info()["depth"] == 1

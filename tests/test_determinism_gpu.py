@@ -82,7 +82,7 @@ def test_fused_passes_same_bits(dtype, shape, axes, bc):
     V = _V(shape, seed=22)
     kw = dict(dx=DX, dt=DT, c=C, m=1.0, axes=axes, bc=bc, dtype=dtype,
               tiling={"allow_resident": False})
-    depths = (2, 3, 4, 5) if dtype == "c64" else (2,)
+    depths = (2, 3, 4, 5)
     for n in (1, 2, 3, 7, 20):
         single = gpu_step(psi, V, nsteps=n, depth=1, **kw)
         for d in depths:
@@ -96,14 +96,15 @@ def test_fused_passes_same_bits(dtype, shape, axes, bc):
                                           ((61, 9, 5), "zero", 2), ((64, 64, 40), "zero", 7),
                                           ((3, 2, 2), "periodic", 0), ((2, 5, 3), "zero", 0),
                                           ((121, 4, 9), "periodic", 3), ((2, 2, 7), "periodic", 2)])
-def test_fused_3d_passes_same_bits(shape, bc, seg):
-    """3-D passes of two fused steps (FP32 state) give the bits of single
-    steps: ragged strips and row blocks, segments marching up and down,
-    walls, wrap-around, boxes of two cells per axis; every phase mode."""
-    announce(f"fused 3-D passes {shape} {bc} seg={seg}")
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_fused_3d_passes_same_bits(shape, bc, seg, dtype):
+    """3-D passes of two fused steps give the bits of single steps: ragged
+    strips and row blocks, segments marching up and down, walls,
+    wrap-around, boxes of two cells per axis; every phase mode."""
+    announce(f"fused 3-D passes {shape} {bc} seg={seg} {dtype}")
     psi = random_spinor(shape[::-1], seed=31)
     V = _V(shape, seed=32)
-    kw = dict(dx=DX, dt=DT, c=C, axes=(0, 1, 2), bc=bc, dtype="c64",
+    kw = dict(dx=DX, dt=DT, c=C, axes=(0, 1, 2), bc=bc, dtype=dtype,
               tiling={"seg_len": seg} if seg else None)
     for n in (1, 2, 3, 8):
         single = gpu_step(psi, V, m=1.0, nsteps=n, depth=1, **kw)
