@@ -455,13 +455,16 @@ def bench_adjoint(args):
         bwd_ms = ev[2].elapsed_time(ev[3])
         rec = rel_l2(psi, psi0)
         gn = float(torch.linalg.vector_norm(g))
+        K = p.info()["reverse_depth"]
     sites = w.sites * w.nsteps
     log(f"adjoint: fwd {fwd_ms:.2f} ms, bwd {bwd_ms:.2f} ms, reconstruction {rec:.2e}")
     return {"steps": w.nsteps, "forward_ms": fwd_ms, "backward_ms": bwd_ms,
             "forward_site_updates_per_s": sites / (fwd_ms * 1e-3),
             "backward_site_updates_per_s": sites / (bwd_ms * 1e-3),
-            "backward_bytes_per_site": 152,
-            "backward_roofline_frac": 152 * sites / (bwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            # a reverse pass reads psi, lambda, V, Q and writes psi, lambda, Q once
+            # per cell, 152 B, whatever its steps
+            "backward_steps_per_pass": K, "backward_bytes_per_cell_per_pass": 152,
+            "backward_roofline_frac": 152 / K * sites / (bwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "loss_P_T": L_T, "grad_norm": gn, "psi0_reconstruction_rel_l2": rec}
 
 

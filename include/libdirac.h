@@ -115,10 +115,11 @@ int dl_plan_destroy(dl_plan p);
  * exp(-i theta) is formed from the FP64 V and applied in FP64, then rounded
  * once to FP32.  nsteps = 0 is a no-op. */
 int dl_step(dl_plan p, void *psi, const double *V, int64_t nsteps, void *stream);
-/* (1-D and 2-D grids fuse several steps into one pass over memory: up to 5
- * with complex64 state, 2 with complex128, fewer on periodic 2-D boxes of
- * fewer than twice that many rows; the remainder of nsteps runs in
- * shallower passes.  The bits do not depend on this grouping.) */
+/* (Several steps are fused into one pass over memory: up to 5 on 1-D and
+ * 2-D grids, fewer on periodic 2-D boxes of fewer than twice that many rows,
+ * and 2 on 3-D grids with rows of fewer than 2^28 cells; the remainder of
+ * nsteps runs in shallower passes.  The bits do not depend on this grouping;
+ * dl_plan_set_depth caps it.) */
 
 /* dl_step with a vector potential in the local step (eq:sol_dis_4 and the
  * closed-form exponential of Dirac matrices of Sec. 2.3):
@@ -168,7 +169,10 @@ int dl_seed_adjoint(dl_plan p, const void *psi, double x_b, void *lam, double *Q
  * step.  S^H lam is exact for both boundary conditions; S^{-1} = S^H holds
  * exactly with DL_BC_PERIODIC (with zero walls it holds only while nothing has
  * left the box).  After N steps from (psi_N, lam_N = M psi_N, Q = 0), Q is
- * dL/dV and psi is the reconstructed psi_0. */
+ * dL/dV and psi is the reconstructed psi_0.  Up to 3 reverse steps (2 with
+ * complex128 state) are fused into one pass over psi, lam, V and Q, with the
+ * bits of single reverse steps (the terms of Q added in the same order).
+ * 1-D and 2-D grids, lowest-order four-component plans (DL_ERR_ARG else). */
 int dl_grad_step(dl_plan p, void *psi, void *lam, const double *V, double *Q,
                  int64_t nsteps, void *stream);
 
@@ -198,6 +202,50 @@ int dl_batch_create(dl_plan *out, const dl_grid *grids, const double *dx,
  * the same parameters. */
 int dl_batch_step(dl_plan b, void *const *psi, const double *const *V,
                   const int64_t *nsteps, void *stream);
+
+/* ---- tuning: tile shapes, fusion depth, and the batch autotuner -------- */
+
+/* Tiling of the plan's kernels.  waves_per_cu in 0..32: 0 sizes each launch
+ * from the kernel's occupancy (all march segments in one round of resident
+ * waves), otherwise that many waves per compute unit; seg_len >= 0: rows (or
+ * z planes) per march segment, 0 derives it from the grid size; allow_resident
+ * (0/1): let short 1-D lines run in one workgroup for all steps; graph_pairs
+ * >= 1: a captured graph (DL_GRAPH) holds 2 * graph_pairs steps.  Drops the
+ * plan's captured graphs.  The bits of every result are independent of these
+ * settings.  DL_ERR_ARG on values out of range. */
+int dl_plan_set_tiling(dl_plan p, int waves_per_cu, int seg_len, int allow_resident,
+                       int graph_pairs);
+
+/* Cap on the steps fused into one pass over memory, depth in 1..5: forward
+ * passes (dl_step and friends) and reverse passes (dl_grad_step) use at most
+ * this many steps, and never more than the kernels are built for (2-D and
+ * 1-D: 5; 3-D: 2; second-order steps: 2, complex128 1; vector potential: 2,
+ * complex128 1; reverse steps: 3, complex128 2).  The bits are independent of
+ * the grouping.  DL_ERR_ARG outside 1..5. */
+int dl_plan_set_depth(dl_plan p, int depth);
+
+/* Up to n values describing the deepest forward pass in use, written to the
+ * HOST array info: [0] workgroups, [1] rows per march segment, [2] segments,
+ * [3] x strips, [4] wave tiles, [5] resident 1-D path (0/1), [6] its threads,
+ * [7] waves_per_cu setting, [8] XCD-contiguous block order (0/1),
+ * [9] graph_pairs, [10] fused steps per pass, [11] workgroups of a
+ * single-step pass, [12] reverse steps per pass of dl_grad_step.  Works on
+ * DL_DRY plans. */
+int dl_plan_info(dl_plan p, int64_t *info, int n);
+
+/* Batch tiling: seg_len >= 1 rows per 2-D march segment of every instance,
+ * graph_pairs >= 1 as in dl_plan_set_tiling.  Results stay bit-identical. */
+int dl_batch_set(dl_plan b, int seg_len, int graph_pairs);
+
+/* Autotuner of the batch: times `trials` passes at each candidate segment
+ * length (8, 16, 32, 64, 128 rows) on a device copy of the states psi[k]
+ * (HOST array of count device pointers; V as in dl_batch_step), keeps the
+ * fastest and writes it to *chosen (HOST, may be NULL).  The caller's states
+ * are not modified.  Allocates a scratch copy of all states for the call;
+ * synchronises `stream`.  When the environment variable LIBDIRAC_TUNE_CACHE
+ * names a file, appends "f32|f64:count seg_len" to it. */
+int dl_batch_autotune(dl_plan b, void *const *psi, const double *const *V, int trials,
+                      int *chosen, void *stream);
 
 /* Thread-local message for the last non-OK status ("" if none). */
 const char *dl_last_error(void);

@@ -23,6 +23,7 @@
 // columns in full and do not store.
 #include "dirac_device.h"
 #include "dirac_plan.h"
+#include "dirac_sweep_impl.h"
 
 namespace dirac {
 
@@ -39,55 +40,16 @@ struct RevArgs {
   PhaseK ph;        // forward phase constants (conjugated here)
 };
 
-// conjugate factors: D^H = s exp(+i theta)
+// conjugate factors: D^H = s exp(+i theta).  The phase mode is read at run
+// time; the fast sine/cosine serves every lane unless some lane of the wave
+// has an angle beyond its range (a wave-uniform, rarely taken repair).
+template <bool TWO>
 __device__ __forceinline__ Factors adjoint_factors(double V, const PhaseK& k) {
-  Factors f = phase_factors(V, k);
+  Factors f = factors_of<-1, TWO>(V, k);
+  factors_fix<-1, TWO>(f, V, k);
   f.ui = -f.ui;
   f.di = -f.di;
   return f;
-}
-
-// load the cell at column x of row j (walls / wrap-around), zeros outside
-template <typename T>
-__device__ __forceinline__ void load_cell(const T* __restrict__ f, int64_t nx, int64_t ny,
-                                          int periodic, int64_t x, int64_t j, Site<T>& s,
-                                          bool& inside) {
-  zero(s);
-  inside = false;
-  if (j < 0 || j >= ny) {
-    if (!periodic) return;
-    j = (j < 0) ? j + ny : j - ny;
-  }
-  if (x < 0 || x >= nx) {
-    if (!periodic) return;
-    x = (x < 0) ? x + nx : x - nx;
-  }
-  inside = true;
-  load_site(f + (j * nx + x) * 8, s);
-}
-
-template <typename T> struct RevRow {
-  Site<T> p, l;  // psi and lambda at this lane's column
-  double v;      // potential at this lane's (possibly wrapped) column
-  bool inside;
-};
-
-template <typename T>
-__device__ __forceinline__ void load_rev_row(const T* psi, const T* lam, const double* V,
-                                             const RevArgs& a, int64_t x, int64_t j,
-                                             RevRow<T>& R) {
-  bool in2;
-  load_cell(psi, a.nx, a.ny, a.periodic, x, j, R.p, R.inside);
-  load_cell(lam, a.nx, a.ny, a.periodic, x, j, R.l, in2);
-  R.v = 0.0;
-  if (R.inside && a.ph.mode == 2) {
-    int64_t jj = j, xx = x;
-    if (jj < 0) jj += a.ny;
-    if (jj >= a.ny) jj -= a.ny;
-    if (xx < 0) xx += a.nx;
-    if (xx >= a.nx) xx -= a.nx;
-    R.v = V[jj * a.nx + xx];
-  }
 }
 
 // D^H on one site (scale folded in); mode 0 is the bare scale
@@ -113,92 +75,198 @@ __device__ __forceinline__ double im_dot(const Site<T>& l, const Site<T>& p) {
   return acc;
 }
 
-// backward x transport of a row held across the wave: right movers from the
-// right lane, left movers from the left lane (lanes 0 and 63 are halo lanes)
+// backward x transport inside the wave: right movers from the right lane,
+// left movers from the left lane (lanes 0 and 63 lack a neighbour and give
+// values that are not used)
 template <typename T, int AX>
 __device__ __forceinline__ void x_transport_adj(const Site<T>& in, Site<T>& out) {
   Mov<T> r, l, rR, lL;
   Axis<AX, T>::movers(in, r, l);
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    rR.v[k] = dpp_from_right(r.v[k], r.v[k]);
-    lL.v[k] = dpp_from_left(l.v[k], l.v[k]);
+    rR.v[k] = dpp_from_right_zero(r.v[k]);
+    lL.v[k] = dpp_from_left_zero(l.v[k]);
   }
   Axis<AX, T>::combine(rR, lL, out);
 }
 
-constexpr int PFR = 2;
+// resident 256-thread blocks per CU the reverse kernel is compiled for: a
+// single reverse step fits two waves per SIMD; fused passes carry two fields
+// through every stage and run one wave per SIMD, the compiler parking part of
+// the working set in the accumulation registers
+__host__ __device__ constexpr int rev_min_blocks(bool fp64, int depth) {
+  return (fp64 || depth > 1) ? 1 : 2;
+}
 
-template <typename T, int AX0, int AX1, bool UP>
+// one input row of the reverse march: psi, lambda, V and Q at this lane's
+// (wrapped or clamped) column
+template <typename T> struct RevIn {
+  Site<T> p, l;
+  double v, q;
+};
+
+// ---------------------------------------------------------------------------
+// K reverse steps per launch (temporal blocking of the adjoint).  Stage s
+// takes the row of time level n - s + 1 (psi and lambda): it adds that level's
+// term to dL/dV, applies D^H to both fields, and completes the row one behind
+// with T_y^H then T_x^H; that row is the input of stage s + 1.  The wave
+// holds 64 columns and writes the 64 - 2K middle ones (every stage narrows
+// the valid lanes by one on each side).  A row's factors and its dL/dV
+// accumulator are formed when the row is read and move one slot on per
+// iteration until the last stage has taken the row; the accumulator then goes back to
+// Q once per pass.  The K terms of a cell are added in the order of the
+// single steps, and intermediate rows are rounded and zeroed beyond walls
+// as stored steps are, so a pass gives the bits of K single reverse steps.
+// ---------------------------------------------------------------------------
+
+template <typename T, int K, int AX0, int AX1, bool UP>
 __device__ __forceinline__ void rev_march(T* __restrict__ psi_out, T* __restrict__ lam_out,
                                           const T* __restrict__ psi, const T* __restrict__ lam,
                                           const double* __restrict__ V, double* __restrict__ Q,
-                                          const RevArgs& a, int64_t x, bool own, int64_t jb,
-                                          int64_t je) {
-  const int nit = static_cast<int>(je - jb) + 2;
-  auto in_row = [&](int it) -> int64_t { return UP ? jb - 1 + it : je - it; };
-  auto out_row = [&](int it) -> int64_t { return UP ? jb - 2 + it : je - it + 1; };
-  RevRow<T> ring[PFR];
+                                          const RevArgs& a, const Lanes& c, bool own,
+                                          int64_t jb, int64_t je) {
+  constexpr int L = 2;  // rows in flight; the loop is unrolled by the same 2
+  const int64_t nx = a.nx, ny = a.ny;
+  const int nit = static_cast<int>(je - jb) + 2 * K;
+  const bool zero_walls = !a.periodic;
+  const bool read_v = (a.ph.mode == 2);
+  auto in_row = [&](int it) -> int64_t { return UP ? jb - K + it : je - 1 + K - it; };
+  auto load = [&](int it, RevIn<T>& R) {
+    const int64_t q = read_row(in_row(it), ny, a.periodic) * nx + c.col;
+    load_site(psi + q * 8, R.p);
+    load_site(lam + q * 8, R.l);
+    R.v = read_v ? V[q] : 0.0;
+    R.q = Q[q];
+  };
+  RevIn<T> ring[L];
 #pragma unroll
-  for (int k = 0; k < PFR; ++k)
-    if (k < nit) load_rev_row(psi, lam, V, a, x, in_row(k), ring[k]);
-  Mov<T> sp1, sp2, sl1, sl2;  // y movers of the two previous rows (psi, lambda)
-  zero(sp1); zero(sp2); zero(sl1); zero(sl2);
-  for (int base = 0; base < nit; base += PFR) {
+  for (int k = 0; k < L; ++k) load(k, ring[k]);
+  static_assert(L == 2, "the y mover slots alternate with the iteration");
+  Mov<T> mp[K][2], ml[K][2];  // stored y movers per stage (psi, lambda), slot it % 2
+  Factors fr[K];              // factors of the rows in flight: fr[s - 1] for stage s
+  double qa[K];               // their dL/dV accumulators
 #pragma unroll
-    for (int k = 0; k < PFR; ++k) {
+  for (int s = 0; s < K; ++s) {
+    zero(mp[s][0]);
+    zero(mp[s][1]);
+    zero(ml[s][0]);
+    zero(ml[s][1]);
+    qa[s] = 0.0;
+  }
+  for (int base = 0;; base += L) {
+#pragma unroll
+    for (int k = 0; k < L; ++k) {
       const int it = base + k;
-      if (it < nit) {
-        const RevRow<T> cur = ring[k];
-        if (it + PFR < nit) load_rev_row(psi, lam, V, a, x, in_row(it + PFR), ring[k]);
-        const int64_t jin = in_row(it);
-        // gradient accumulation at the input time level, owned cells only
-        if (own && jin >= jb && jin < je) {
-          double* q = Q + jin * a.nx + x;
-          *q = fma(a.qscale, im_dot(cur.l, cur.p), *q);
+      if (it >= nit) return;
+      RevIn<T> cur = ring[k % L];
+      load(it + L, ring[k % L]);  // rows past the segment are read and dropped
+      const int64_t jin = in_row(it);
+      if (zero_walls) {
+        if (jin < 0 || jin >= ny || (!c.full && c.out)) {
+          zero(cur.p);
+          zero(cur.l);
         }
-        // D^H on both fields
-        Site<T> p = cur.p, l = cur.l;
-        const Factors f = adjoint_factors(cur.v, a.ph);
-        adjoint_local(p, f, a.ph);
-        adjoint_local(l, f, a.ph);
+      }
+      // the rows in flight move one stage on; the new row enters stage 1
+#pragma unroll
+      for (int s = K - 1; s >= 1; --s) {
+        fr[s] = fr[s - 1];
+        qa[s] = qa[s - 1];
+      }
+      fr[0] = adjoint_factors<sizeof(T) == 8>(cur.v, a.ph);
+      qa[0] = cur.q;
+      Site<T> p = cur.p, l = cur.l;
+#pragma unroll
+      for (int s = 1; s <= K; ++s) {
+        const int slot = s - 1;  // the input row's factors and accumulator
+        const int64_t j = UP ? jin - (s - 1) : jin + (s - 1);  // input row of stage s
+        qa[slot] = fma(a.qscale, im_dot(l, p), qa[slot]);
+        adjoint_local(p, fr[slot], a.ph);
+        adjoint_local(l, fr[slot], a.ph);
         Mov<T> rp, lp, rl, ll;
         Axis<AX1, T>::movers(p, rp, lp);
         Axis<AX1, T>::movers(l, rl, ll);
-        if (it >= 2) {
-          // T_y^H: right movers from row j+1, left movers from row j-1
-          Site<T> yp, yl;
-          if (UP) {
-            Axis<AX1, T>::combine(rp, sp2, yp);
-            Axis<AX1, T>::combine(rl, sl2, yl);
-          } else {
-            Axis<AX1, T>::combine(sp2, lp, yp);
-            Axis<AX1, T>::combine(sl2, ll, yl);
-          }
-          Site<T> op, ol;
-          x_transport_adj<T, AX0>(yp, op);
-          x_transport_adj<T, AX0>(yl, ol);
-          if (own) {
-            const int64_t off = (out_row(it) * a.nx + x) * 8;
-            store_site(psi_out + off, op);
-            store_site(lam_out + off, ol);
-          }
+        // T_y^H: right movers from the row above, left movers from the row below
+        Site<T> yp, yl;
+        if (UP) {
+          Axis<AX1, T>::combine(rp, mp[s - 1][k % 2], yp);
+          Axis<AX1, T>::combine(rl, ml[s - 1][k % 2], yl);
+        } else {
+          Axis<AX1, T>::combine(mp[s - 1][k % 2], lp, yp);
+          Axis<AX1, T>::combine(ml[s - 1][k % 2], ll, yl);
         }
-        sp2 = sp1;
-        sl2 = sl1;
-        sp1 = UP ? lp : rp;
-        sl1 = UP ? ll : rl;
+        mp[s - 1][k % 2] = UP ? lp : rp;
+        ml[s - 1][k % 2] = UP ? ll : rl;
+        const int64_t jo = UP ? j - 1 : j + 1;  // output row of stage s
+        x_transport_adj<T, AX0>(yp, p);
+        x_transport_adj<T, AX0>(yl, l);
+        if (s < K) {
+          if (zero_walls) {
+            if (jo < 0 || jo >= ny || (!c.full && !c.inside)) {
+              zero(p);
+              zero(l);
+            }
+          }
+        } else {
+          if (it >= 2 * K && own) {
+            const int64_t off = (jo * nx + c.col) * 8;
+            store_site(psi_out + off, p);
+            store_site(lam_out + off, l);
+          }
+          // the last stage has added its term to row j
+          if (own && j >= jb && j < je) Q[j * nx + c.col] = qa[slot];
+        }
       }
     }
   }
 }
 
-template <typename T, int AX0, int AX1>
-__global__ __launch_bounds__(256) void k_reverse(T* __restrict__ psi_out, T* __restrict__ lam_out,
-                                                 const T* __restrict__ psi,
-                                                 const T* __restrict__ lam,
-                                                 const double* __restrict__ V,
-                                                 double* __restrict__ Q, RevArgs a) {
+// K reverse steps on a 1-D line: every stage in place on the one row
+template <typename T, int K, int AX0>
+__device__ __forceinline__ void rev_line(T* __restrict__ psi_out, T* __restrict__ lam_out,
+                                         const T* __restrict__ psi, const T* __restrict__ lam,
+                                         const double* __restrict__ V, double* __restrict__ Q,
+                                         const RevArgs& a, const Lanes& c, bool own) {
+  Site<T> p, l;
+  load_site(psi + c.col * 8, p);
+  load_site(lam + c.col * 8, l);
+  const bool zero_walls = !a.periodic;
+  if (zero_walls && !c.full && c.out) {
+    zero(p);
+    zero(l);
+  }
+  const double v = (a.ph.mode == 2) ? V[c.col] : 0.0;
+  double q = Q[c.col];
+  const Factors f = adjoint_factors<sizeof(T) == 8>(v, a.ph);
+#pragma unroll
+  for (int s = 1; s <= K; ++s) {
+    q = fma(a.qscale, im_dot(l, p), q);
+    adjoint_local(p, f, a.ph);
+    adjoint_local(l, f, a.ph);
+    Site<T> op, ol;
+    x_transport_adj<T, AX0>(p, op);
+    x_transport_adj<T, AX0>(l, ol);
+    p = op;
+    l = ol;
+    if (s < K && zero_walls && !c.full && !c.inside) {
+      zero(p);
+      zero(l);
+    }
+  }
+  if (own) {
+    store_site(psi_out + c.col * 8, p);
+    store_site(lam_out + c.col * 8, l);
+    Q[c.col] = q;
+  }
+}
+
+template <typename T, int K, int AX0, int AX1>
+__global__ __launch_bounds__(256, rev_min_blocks(sizeof(T) == 8, K)) void k_reverse(T* __restrict__ psi_out,
+                                                    T* __restrict__ lam_out,
+                                                    const T* __restrict__ psi,
+                                                    const T* __restrict__ lam,
+                                                    const double* __restrict__ V,
+                                                    double* __restrict__ Q, RevArgs a) {
   const int lane = threadIdx.x & 63;
   int64_t blk = blockIdx.x;
   if (a.xcd_remap) blk = (blk % 8) * (gridDim.x / 8) + blk / 8;
@@ -206,29 +274,18 @@ __global__ __launch_bounds__(256) void k_reverse(T* __restrict__ psi_out, T* __r
   if (tile >= a.ntiles) return;
   const int64_t strip = tile % a.nstrips;
   const int64_t seg = tile / a.nstrips;
-  const int64_t x = strip * 62 - 1 + lane;
-  const bool own = lane >= 1 && lane <= 62 && x >= 0 && x < a.nx;
+  const int64_t xs = strip * strip_width(K) - K;  // lanes K .. 63 - K are written
+  const Lanes c = lanes_of(a.nx, a.periodic, xs, lane);
+  const bool own = c.inside && lane >= K && lane <= 63 - K;
   if constexpr (AX1 < 0) {
-    RevRow<T> R;
-    load_rev_row(psi, lam, V, a, x, 0, R);
-    if (own) Q[x] = fma(a.qscale, im_dot(R.l, R.p), Q[x]);
-    const Factors f = adjoint_factors(R.v, a.ph);
-    adjoint_local(R.p, f, a.ph);
-    adjoint_local(R.l, f, a.ph);
-    Site<T> op, ol;
-    x_transport_adj<T, AX0>(R.p, op);
-    x_transport_adj<T, AX0>(R.l, ol);
-    if (own) {
-      store_site(psi_out + x * 8, op);
-      store_site(lam_out + x * 8, ol);
-    }
+    rev_line<T, K, AX0>(psi_out, lam_out, psi, lam, V, Q, a, c, own);
   } else {
     const int64_t jb = seg * a.H;
     const int64_t je = (jb + a.H < a.ny) ? jb + a.H : a.ny;
     if (seg & 1)
-      rev_march<T, AX0, AX1, false>(psi_out, lam_out, psi, lam, V, Q, a, x, own, jb, je);
+      rev_march<T, K, AX0, AX1, false>(psi_out, lam_out, psi, lam, V, Q, a, c, own, jb, je);
     else
-      rev_march<T, AX0, AX1, true>(psi_out, lam_out, psi, lam, V, Q, a, x, own, jb, je);
+      rev_march<T, K, AX0, AX1, true>(psi_out, lam_out, psi, lam, V, Q, a, c, own, jb, je);
   }
 }
 
@@ -334,42 +391,50 @@ __global__ __launch_bounds__(256) void k_expand(const double* __restrict__ G,
   V[c] = acc;
 }
 
-template <typename T, int AX0, int AX1>
-static hipError_t launch_rev_t(void* po, void* lo, const void* pi, const void* li,
-                               const double* V, double* Q, const RevArgs& a, int blocks,
-                               hipStream_t st) {
-  hipLaunchKernelGGL((k_reverse<T, AX0, AX1>), dim3(blocks), dim3(256), 0, st,
-                     static_cast<T*>(po), static_cast<T*>(lo), static_cast<const T*>(pi),
-                     static_cast<const T*>(li), V, Q, a);
-  return hipGetLastError();
-}
-
-template <typename T>
-static hipError_t launch_rev(void* po, void* lo, const void* pi, const void* li, const double* V,
-                             double* Q, const RevArgs& a, int blocks, hipStream_t st) {
-  switch (a.axes_code) {
-    case 0: return launch_rev_t<T, 0, -1>(po, lo, pi, li, V, Q, a, blocks, st);
-    case 1: return launch_rev_t<T, 1, -1>(po, lo, pi, li, V, Q, a, blocks, st);
-    case 2: return launch_rev_t<T, 2, -1>(po, lo, pi, li, V, Q, a, blocks, st);
-    case 10: return launch_rev_t<T, 0, 1>(po, lo, pi, li, V, Q, a, blocks, st);
-    case 20: return launch_rev_t<T, 0, 2>(po, lo, pi, li, V, Q, a, blocks, st);
-    case 21: return launch_rev_t<T, 1, 2>(po, lo, pi, li, V, Q, a, blocks, st);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-template <typename T>
-static int rev_occ(int axes_code) {
-  const void* k;
+template <typename T, int K>
+static const void* rev_kernel_k(int axes_code) {
   switch (axes_code) {
-    case 0: k = reinterpret_cast<const void*>(&k_reverse<T, 0, -1>); break;
-    case 1: k = reinterpret_cast<const void*>(&k_reverse<T, 1, -1>); break;
-    case 2: k = reinterpret_cast<const void*>(&k_reverse<T, 2, -1>); break;
-    case 10: k = reinterpret_cast<const void*>(&k_reverse<T, 0, 1>); break;
-    case 20: k = reinterpret_cast<const void*>(&k_reverse<T, 0, 2>); break;
-    case 21: k = reinterpret_cast<const void*>(&k_reverse<T, 1, 2>); break;
-    default: return 0;
+    case 0: return reinterpret_cast<const void*>(&k_reverse<T, K, 0, -1>);
+    case 1: return reinterpret_cast<const void*>(&k_reverse<T, K, 1, -1>);
+    case 2: return reinterpret_cast<const void*>(&k_reverse<T, K, 2, -1>);
+    case 10: return reinterpret_cast<const void*>(&k_reverse<T, K, 0, 1>);
+    case 20: return reinterpret_cast<const void*>(&k_reverse<T, K, 0, 2>);
+    case 21: return reinterpret_cast<const void*>(&k_reverse<T, K, 1, 2>);
+    default: return nullptr;
   }
+}
+
+// the reverse kernel of `depth` fused steps for this layout (nullptr if not built)
+static const void* rev_kernel(bool fp64, int depth, int axes_code) {
+  if (fp64) {
+    switch (depth) {
+      case 1: return rev_kernel_k<double, 1>(axes_code);
+      case 2: return rev_kernel_k<double, 2>(axes_code);
+      default: return nullptr;
+    }
+  }
+  switch (depth) {
+    case 1: return rev_kernel_k<float, 1>(axes_code);
+    case 2: return rev_kernel_k<float, 2>(axes_code);
+    case 3: return rev_kernel_k<float, 3>(axes_code);
+    default: return nullptr;
+  }
+}
+
+static hipError_t launch_rev(bool fp64, int depth, void* po, void* lo, const void* pi,
+                             const void* li, const double* V, double* Q, const RevArgs& a,
+                             int blocks, hipStream_t st) {
+  const void* fn = rev_kernel(fp64, depth, a.axes_code);
+  if (!fn || blocks <= 0) return hipErrorInvalidValue;
+  RevArgs args = a;
+  void* kargs[] = {&po, &lo, const_cast<void**>(&pi), const_cast<void**>(&li),
+                   const_cast<double**>(&V), &Q, &args};
+  return hipLaunchKernel(fn, dim3(blocks), dim3(256), kargs, 0, st);
+}
+
+static int rev_occ(bool fp64, int depth, int axes_code) {
+  const void* k = rev_kernel(fp64, depth, axes_code);
+  if (!k) return 0;
   int n = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, 256, 0) != hipSuccess) {
     (void)hipGetLastError();
@@ -382,16 +447,28 @@ static int rev_occ(int axes_code) {
 
 using namespace dirac;
 
-static void rev_tiling(dl_plan p, RevArgs& a, int& blocks) {
+// reverse steps fused per pass: FP32 up to 3, FP64 up to 2, within the plan's
+// depth cap; a periodic 2-D box needs at least 2 rows per fused step
+int dirac::reverse_depth(dl_plan p) {
+  if (p->g.ndim > 2 || p->strang || p->nc != 4) return 1;
+  int d = std::min(p->depth_limit, p->fp64 ? kMaxRevDepthF64 : kMaxRevDepthF32);
+  if (p->g.ndim == 2 && p->bc == DL_BC_PERIODIC)
+    while (d > 1 && p->g.n[1] < 2 * d) --d;
+  return d < 1 ? 1 : d;
+}
+
+static void rev_tiling(dl_plan p, int depth, RevArgs& a, int& blocks) {
   a.nx = p->g.n[0];
   a.ny = p->g.ndim > 1 ? p->g.n[1] : 1;
   a.periodic = (p->bc == DL_BC_PERIODIC);
-  a.nstrips = (a.nx + 61) / 62;
+  const int w = strip_width(depth);
+  a.nstrips = (a.nx + w - 1) / w;
+  a.axes_code = axes_code(p->g);
   int64_t target;
   if (p->waves_per_cu > 0) {
     target = int64_t(p->cu_count) * p->waves_per_cu;
   } else {
-    int occ = p->fp64 ? rev_occ<double>(axes_code(p->g)) : rev_occ<float>(axes_code(p->g));
+    int occ = rev_occ(p->fp64, depth, a.axes_code);
     if (occ <= 0) occ = 2;
     target = int64_t(occ) * 4 * p->cu_count;
   }
@@ -413,7 +490,6 @@ static void rev_tiling(dl_plan p, RevArgs& a, int& blocks) {
   a.ntiles = a.nstrips * a.nseg;
   blocks = static_cast<int>((a.ntiles + 3) / 4);
   a.xcd_remap = (blocks % 8 == 0) ? 1 : 0;
-  a.axes_code = axes_code(p->g);
   double dV = p->dx;
   for (int d = 1; d < p->g.ndim; ++d) dV *= p->dx;
   a.qscale = 2.0 * p->dt * dV;
@@ -469,20 +545,25 @@ extern "C" int dl_grad_step(dl_plan p, void* psi, void* lam, const double* V, do
       return set_error(DL_ERR_NOMEM, "allocation of the second adjoint buffer failed");
     }
   }
-  RevArgs a{};
-  int blocks = 0;
-  rev_tiling(p, a, blocks);
-  a.ph = make_phase(p->g.ndim, p->dt, p->c, p->m, phase_mode(p->m, V), p->fp64);
+  const int dmax = reverse_depth(p);
+  const PhaseK ph = make_phase(p->g.ndim, p->dt, p->c, p->m, phase_mode(p->m, V), p->fp64);
   void* pa = psi;
   void* la = lam;
   void* pb = p->tmp;
   void* lb = p->tmp2;
-  for (int64_t s = 0; s < nsteps; ++s) {
-    hipError_t e = p->fp64 ? launch_rev<double>(pb, lb, pa, la, V, Q, a, blocks, st)
-                           : launch_rev<float>(pb, lb, pa, la, V, Q, a, blocks, st);
-    if (e != hipSuccess) return set_hip_error(e, "reverse sweep launch");
-    void* t = pa; pa = pb; pb = t;
-    t = la; la = lb; lb = t;
+  int64_t left = nsteps;
+  for (int d = dmax; d >= 1; --d) {
+    if (left < d) continue;
+    RevArgs a{};
+    int blocks = 0;
+    rev_tiling(p, d, a, blocks);
+    a.ph = ph;
+    for (; left >= d; left -= d) {
+      hipError_t e = launch_rev(p->fp64, d, pb, lb, pa, la, V, Q, a, blocks, st);
+      if (e != hipSuccess) return set_hip_error(e, "reverse sweep launch");
+      void* t = pa; pa = pb; pb = t;
+      t = la; la = lb; lb = t;
+    }
   }
   if (pa != psi) {
     hipError_t e = hipMemcpyAsync(psi, pa, p->state_bytes, hipMemcpyDeviceToDevice, st);

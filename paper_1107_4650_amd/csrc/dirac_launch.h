@@ -35,6 +35,9 @@ __host__ __device__ constexpr int max_depth(bool fp64, bool strang) {
 __host__ __device__ constexpr int sweep2d_min_blocks(bool fp64, int depth) {
   return (fp64 && depth > 2) ? 1 : 2;
 }
+// reverse (adjoint) passes fuse up to this many reverse steps
+constexpr int kMaxRevDepthF32 = 3;
+constexpr int kMaxRevDepthF64 = 2;
 // passes whose local step carries a vector potential (phase mode 3) hold
 // nine doubles of factors per row in flight: they fuse at most 2 steps
 __host__ __device__ constexpr int field_max_depth(bool fp64, bool strang) {

@@ -90,5 +90,7 @@ int check_live(dl_plan p);
 int check_state_ptr(const void* ptr, const char* name);
 int check_f64_ptr(const void* ptr, const char* name, bool nullable);
 void destroy_batch(dl_plan p);
+// reverse steps fused per pass of dl_grad_step (1 where the adjoint is refused)
+int reverse_depth(dl_plan p);
 
 }  // namespace dirac

@@ -606,7 +606,7 @@ extern "C" int dl_observables(dl_plan p, const void* psi, double x_b, double out
 extern "C" const char* dl_last_error(void) { return g_err; }
 extern "C" int dl_version(void) { return LIBDIRAC_VERSION; }
 
-// ---- tuning hooks (not part of the public header; used by the autotuner) ----
+// ---- tuning: tiling, fusion depth, plan description ----
 extern "C" int dl_plan_set_tiling(dl_plan p, int waves_per_cu, int seg_len, int allow_resident,
                                   int graph_pairs) {
   if (!p) return fail(DL_ERR_ARG, "plan is NULL");
@@ -633,7 +633,8 @@ extern "C" int dl_plan_info(dl_plan p, int64_t* info, int n) {
   const SweepArgs& t = p->sw[p->depth - 1];  // tiling of the deepest pass in use
   const int64_t vals[] = {p->bl[p->depth - 1], t.H,          t.nseg,         t.nstrips,
                           t.ntiles,            p->resident,  p->res_threads, p->waves_per_cu,
-                          t.xcd_remap,         p->graph_pairs, p->depth,     p->bl[0]};
+                          t.xcd_remap,         p->graph_pairs, p->depth,     p->bl[0],
+                          reverse_depth(p)};
   const int nv = static_cast<int>(sizeof vals / sizeof vals[0]);
   for (int i = 0; i < n && i < nv; ++i) info[i] = vals[i];
   return DL_OK;

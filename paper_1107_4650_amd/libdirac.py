@@ -27,8 +27,9 @@ DL_DRY, DL_GRAPH, DL_STRANG, DL_BISPINOR = 1, 2, 4, 8
 EXPORTS = ("dl_plan_create", "dl_plan_destroy", "dl_step", "dl_step_field", "dl_step_out",
            "dl_step_fused_out",
            "dl_observables", "dl_seed_adjoint",
-           "dl_grad_step", "dl_project", "dl_expand", "dl_batch_create", "dl_batch_step", "dl_last_error",
-           "dl_version")
+           "dl_grad_step", "dl_project", "dl_expand", "dl_batch_create", "dl_batch_step",
+           "dl_plan_set_tiling", "dl_plan_set_depth", "dl_plan_info", "dl_batch_set",
+           "dl_batch_autotune", "dl_last_error", "dl_version")
 
 
 class DiracError(RuntimeError):
@@ -52,6 +53,10 @@ def load() -> ctypes.CDLL:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() first")
+    # The library must run on PyTorch's HIP runtime (the tensors it is handed
+    # are PyTorch's): importing torch first puts that runtime in the process's
+    # global scope, where libdirac's HIP symbols then resolve.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     vp, i64, dbl, ci = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
     P = ctypes.POINTER
@@ -263,10 +268,10 @@ class Plan:
                                           int(bool(allow_resident)), int(graph_pairs)))
 
     def info(self) -> dict:
-        buf = (ctypes.c_int64 * 12)()
-        check(self.lib.dl_plan_info(self.handle, buf, 12))
+        buf = (ctypes.c_int64 * 13)()
+        check(self.lib.dl_plan_info(self.handle, buf, 13))
         keys = ("blocks", "seg_len", "nseg", "nstrips", "ntiles", "resident", "res_threads",
-                "waves_per_cu", "xcd_remap", "graph_pairs", "depth", "blocks_1")
+                "waves_per_cu", "xcd_remap", "graph_pairs", "depth", "blocks_1", "reverse_depth")
         return dict(zip(keys, buf[:]))
 
     def close(self):

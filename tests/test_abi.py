@@ -40,6 +40,8 @@ def test_library_exports_every_declared_symbol(lib):
     for name in declared_functions():
         assert name in exported, name
         assert getattr(lib, name) is not None
+    # and nothing is exported that the header does not declare
+    assert exported == set(declared_functions()), exported ^ set(declared_functions())
     assert lib.dl_version() == 1
 
 
@@ -108,6 +110,10 @@ def test_dry_3d_pass_depth(lib):
     assert info["depth"] == 2 and info["nstrips"] == 2
     assert info["ntiles"] == 2 * 15 * info["nseg"]  # row blocks of 2 with FP64 state
     p.close()
+    assert dry((64, 30)).info()["reverse_depth"] == 3
+    assert dry((64, 30), dtype="c128").info()["reverse_depth"] == 2
+    assert dry((64, 6), bc="periodic").info()["reverse_depth"] == 3
+    assert dry((64, 30, 8)).info()["reverse_depth"] == 1
     p = dry((1 << 28, 2, 2))
     assert p.info()["depth"] == 1
     p.close()

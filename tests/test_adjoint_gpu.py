@@ -159,3 +159,46 @@ def test_autograd_function_and_finite_differences():
             fd.append(float((lp - lm) / (2 * h)))
     fd = np.array(fd)
     assert np.max(np.abs(g - fd)) < 1e-4 * np.max(np.abs(g))
+
+
+def _reverse(shape, axes, bc, dtype, psi, lam, V, Q0, nsteps, depth, seg=0):
+    import torch
+    tdt = torch.complex128 if dtype == "c128" else torch.complex64
+    with L.Plan(shape, 0.01, 0.01 / C, C, 1.0, dtype=dtype, bc=bc, axes=axes) as p:
+        p.set_tiling(seg_len=seg, allow_resident=False)
+        p.set_depth(depth)
+        tp, tl, tQ = dev(psi).to(tdt), dev(lam).to(tdt), dev(Q0)
+        p.grad_step(tp, tl, None if V is None else dev(V), tQ, nsteps)
+        torch.cuda.synchronize()
+        return tp.cpu().numpy(), tl.cpu().numpy(), tQ.cpu().numpy()
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("shape,axes,bc,seg", [((150, 37), (0, 1), "zero", 0),
+                                               ((130, 45), (0, 2), "periodic", 7),
+                                               ((70, 66), (1, 2), "zero", 9),
+                                               ((62, 9), (0, 1), "zero", 0),
+                                               ((57, 8), (0, 1), "periodic", 0),
+                                               ((200, 5), (0, 1), "periodic", 0),
+                                               ((257,), (0,), "periodic", 0),
+                                               ((5000,), (2,), "zero", 0)])
+def test_fused_reverse_passes_same_bits(dtype, shape, axes, bc, seg):
+    """Passes of several reverse steps give the bits of single reverse steps
+    for psi, lambda and the accumulated dL/dV (counts that are and are not
+    multiples of the depth, segments marching up and down, walls, wrap-around,
+    periodic boxes too thin for the deepest pass, every phase mode)."""
+    announce(f"fused reverse {shape} {axes} {bc} seg={seg} {dtype}")
+    psi = random_spinor(shape[::-1], seed=21)
+    lam = random_spinor(shape[::-1], seed=22)
+    rng = np.random.default_rng(23)
+    V = rng.uniform(-2, 2, shape[::-1]) * C * C
+    Q0 = rng.standard_normal(shape[::-1])
+    for n in (1, 2, 3, 7, 11):
+        single = _reverse(shape, axes, bc, dtype, psi, lam, V, Q0, n, 1, seg)
+        fused = _reverse(shape, axes, bc, dtype, psi, lam, V, Q0, n, 5, seg)
+        for a, b in zip(single, fused):
+            assert np.array_equal(a, b), n
+    single = _reverse(shape, axes, bc, dtype, psi, lam, None, Q0, 6, 1, seg)
+    fused = _reverse(shape, axes, bc, dtype, psi, lam, None, Q0, 6, 5, seg)
+    for a, b in zip(single, fused):
+        assert np.array_equal(a, b)
