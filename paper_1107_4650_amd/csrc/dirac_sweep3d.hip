@@ -293,11 +293,18 @@ __global__ __launch_bounds__(256, kMinBlocks3D2) void k_sweep3d_x2(const T* __re
   if (a.xcd_remap) blk = (blk % 8) * (gridDim.x / 8) + blk / 8;
   const int64_t tile = blk * 4 + wave_in_block();
   if (tile >= a.ntiles) return;
-  // tile order: x strips fastest, then y row blocks, then z segments
-  const int64_t strip = tile % a.nstrips;
-  const int64_t rest = tile / a.nstrips;
-  const int64_t yblk = rest % a.nyblk;
-  const int64_t seg = rest / a.nyblk;
+  // tile order: x strips fastest, then y row blocks, then z segments; with
+  // blocks of two rows (FP64), whose halo rows outnumber their own, y row
+  // blocks fastest, so that the waves of a workgroup share their halo rows
+  constexpr bool kYFast = TY <= 2;
+  const int64_t n0 = kYFast ? a.nyblk : a.nstrips;
+  const int64_t n1 = kYFast ? a.nstrips : a.nyblk;
+  const int64_t i0 = tile % n0;
+  const int64_t rest = tile / n0;
+  const int64_t i1 = rest % n1;
+  const int64_t seg = rest / n1;
+  const int64_t strip = kYFast ? i1 : i0;
+  const int64_t yblk = kYFast ? i0 : i1;
   const int64_t xs = strip * strip_width(2) - 2, y0 = yblk * TY;
   const int64_t kb = seg * a.H;
   const int64_t ke = (kb + a.H < a.nz) ? kb + a.H : a.nz;
