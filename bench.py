@@ -183,7 +183,13 @@ def bench_main(args):
                      # phase; rocprofv3 counters (SQ_INSTS_VALU) show the SIMDs' VALU
                      # issue as the limiter of the five-step pass
                      "valu_busy": prof.get("valu_busy") if prof else None,
-                     "profile": prof.get("summary") if prof else None},
+                     "profile": prof.get("summary") if prof else None,
+                     # a sweep that reads and writes psi (and reads V) once per step
+                     # cannot exceed 8 TB/s / 72 B site-updates/s; the fused pass
+                     # does fewer bytes per step, so its rate is compared with that
+                     "one_step_per_pass_ceiling": HBM_PEAK_GBS * 1e9 / BYTES_F32,
+                     "value_over_that_ceiling": (sites * n32 / wall32)
+                                                / (HBM_PEAK_GBS * 1e9 / BYTES_F32)},
         "fp64": {"value": sites * n64 / wall64, "unit": "site-updates/s",
                  "ms_per_step": wall64 * 1e3 / n64, "per_launch_ms": per64,
                  "steps_per_launch": d64,
