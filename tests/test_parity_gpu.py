@@ -154,6 +154,24 @@ def test_config_2d_fp32_vs_fp64_1e4_steps():
     assert err <= 1e-4
 
 
+def test_config_3d_full_size_few_steps():
+    """512^3 at the benchmark's launch configuration (two-step passes plus a
+    single-step remainder), every cell compared with the oracle."""
+    from paper_1107_4650_amd.inputs import config_3d_sphere
+    w = config_3d_sphere(n=512, nsteps=3)
+    announce("3-D 512^3 x 3 steps")
+    ref = O.step(w.psi0, w.V, dt=w.dt, c=w.c, m=w.m, nsteps=w.nsteps, axes=w.axes)
+    got = gpu_step(w.psi0, w.V, dx=w.dx, dt=w.dt, c=w.c, m=w.m, nsteps=w.nsteps, axes=w.axes)
+    err64 = rel_l2(got, ref)
+    del got
+    got32 = gpu_step(w.psi0.astype(np.complex64), w.V, dx=w.dx, dt=w.dt, c=w.c, m=w.m,
+                     nsteps=w.nsteps, axes=w.axes, dtype="c64")
+    err32 = rel_l2(got32, ref)
+    announce(f"rel-L2 FP64 {err64:.3e}, FP32 {err32:.3e}")
+    assert err64 <= 1e-12
+    assert err32 <= 2e-6
+
+
 def test_3d_fp64_vs_oracle():
     announce("3-D 96x80x72")
     shape = (96, 80, 72)
