@@ -209,7 +209,8 @@ int dl_batch_step(dl_plan b, void *const *psi, const double *const *V,
  * from the kernel's occupancy (all march segments in one round of resident
  * waves), otherwise that many waves per compute unit; seg_len >= 0: rows (or
  * z planes) per march segment, 0 derives it from the grid size; allow_resident
- * (0/1): let short 1-D lines run in one workgroup for all steps; graph_pairs
+ * (0/1): let 1-D lines of up to 4096 cells run in one workgroup for all steps
+ * when the plan fuses at most 2 steps per pass (dl_plan_set_depth); graph_pairs
  * >= 1: a captured graph (DL_GRAPH) holds 2 * graph_pairs steps.  Drops the
  * plan's captured graphs.  The bits of every result are independent of these
  * settings.  DL_ERR_ARG on values out of range. */

@@ -247,8 +247,11 @@ static int plan_tiling(dl_plan p) {
   }
   select_tiling(p, 2);
   // resident 1-D path: the whole line in one workgroup (4 cells per thread)
+  // for all steps of a call.  One workgroup issues every step, so it only
+  // beats the tiled passes when those pay a launch for every one or two
+  // steps: it is used for plans that fuse at most 2 steps per pass.
   p->resident = false;
-  if (p->g.ndim == 1 && p->allow_resident && !p->strang) {
+  if (p->g.ndim == 1 && p->allow_resident && !p->strang && depth <= 2) {
     const int64_t n = p->g.n[0];
     const int64_t threads = ((n + 4 * 64 - 1) / (4 * 64)) * 64;
     if (threads <= 1024 && (p->bc == DL_BC_ZERO || threads * 4 == n)) {

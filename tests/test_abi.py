@@ -122,6 +122,22 @@ def test_dry_3d_pass_depth(lib):
     p.close()
 
 
+def test_dry_resident_choice(lib):
+    """1-D lines of up to 4096 cells run on the one-workgroup kernel only when
+    the plan fuses at most two steps per pass."""
+    p = dry((4096,), dtype="c128")
+    assert p.info()["resident"] == 0 and p.info()["depth"] == 5
+    p.set_depth(2)
+    assert p.info()["resident"] == 1
+    p.set_tiling(allow_resident=False)
+    assert p.info()["resident"] == 0
+    p.close()
+    p = dry((4097,))
+    p.set_depth(1)
+    assert p.info()["resident"] == 0
+    p.close()
+
+
 def test_raw_abi_argument_errors(lib):
     g = L.make_grid((64,), dx=0.01)
     h = ctypes.c_void_p()

@@ -30,7 +30,9 @@ def _run(psi, V, *, n, axis, bc, dtype, scheme, nsteps, bispinor, resident=True)
     tV = torch.from_numpy(V).to("cuda")
     with L.Plan((n,), DX, dt, C, 1.0, dtype=dtype, bc=bc, axes=(axis,), scheme=scheme,
                 bispinor=bispinor) as p:
-        if not resident:
+        if resident:
+            p.set_depth(2)  # the resident kernel serves plans of at most 2 steps per pass
+        else:
             p.set_tiling(allow_resident=False)
         p.step(t, tV, nsteps)
         obs = p.observables(t, 0.3)

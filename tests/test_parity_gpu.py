@@ -92,7 +92,8 @@ def test_full_step_fp64_and_fp32(shape, axes, bc):
 
 
 def test_config_1d_full_run():
-    """1-D N = 4096, 2000 steps, complex128 (resident one-workgroup path)."""
+    """1-D N = 4096, 2000 steps, complex128, at the benchmark's launch
+    configuration (passes of five steps)."""
     w = config_1d_step()
     announce("1-D 4096 x 2000 steps")
     ref = O.step(w.psi0, w.V, dt=w.dt, c=w.c, m=w.m, nsteps=w.nsteps, axes=w.axes)
@@ -195,8 +196,8 @@ THIN = [((130, 45), (0, 1), "zero"), ((61, 3), (0, 1), "periodic"), ((61, 4), (0
 def test_thin_boxes_and_far_phase_arguments(shape, axes, bc):
     """Boxes a few cells thin (rows that wrap once, two columns) and phase
     angles beyond the fast argument reduction (|V dt| > 2^20 for 2 % of the
-    cells), in both precisions.  An odd step count runs the two-step pass and
-    one single step; the 1-D line also runs without the resident kernel."""
+    cells), in both precisions.  Passes of up to two steps (the 1-D line on
+    the resident kernel) and of the deepest depth without it."""
     announce(f"thin box / far phases {shape} {axes} {bc}")
     psi = random_spinor(shape[::-1], seed=31 + sum(shape))
     rng = np.random.default_rng(11)
@@ -206,8 +207,9 @@ def test_thin_boxes_and_far_phase_arguments(shape, axes, bc):
     flat[idx] = rng.choice([-1.0, 1.0], idx.size) * 1e12
     nsteps = 9
     ref = O.step(psi, V, dt=DT, c=C, m=1.0, nsteps=nsteps, axes=axes, bc=bc)
-    for tiling in (None, {"allow_resident": False}):
-        kw = dict(dx=DX, dt=DT, c=C, m=1.0, nsteps=nsteps, axes=axes, bc=bc, tiling=tiling)
+    for tiling, depth in ((None, 2), ({"allow_resident": False}, None)):
+        kw = dict(dx=DX, dt=DT, c=C, m=1.0, nsteps=nsteps, axes=axes, bc=bc, tiling=tiling,
+                  depth=depth)
         got64 = gpu_step(psi, V, dtype="c128", **kw)
         assert rel_l2(got64, ref) <= 1e-12, tiling
         got32 = gpu_step(psi.astype(np.complex64), V, dtype="c64", **kw)
