@@ -287,7 +287,7 @@ def bench_long_line(n=1 << 22, steps=400):
 def bench_field(args, steps=400):
     """The 2-D 2048^2 tanh-step workload with a static vector potential in the
     local step (field integral At_y = 0.05 sin(2 pi x / 5) per step, a
-    synthetic smooth field), complex64 state: dl_step_field, passes of 2."""
+    synthetic smooth field), complex64 state: dl_step_field at the plan's depth."""
     import torch
     from paper_1107_4650_amd import libdirac as L
     from paper_1107_4650_amd.inputs import config_2d_tanh, coord_mesh
@@ -307,13 +307,14 @@ def bench_field(args, steps=400):
         torch.cuda.synchronize()
         ms = s.elapsed_time(e)
         norm = p.observables(psi, 0.0)[0]
+        K = p.info()["field_depth"]
     del psi, V, At
     torch.cuda.empty_cache()
-    # per pass of 2 steps: psi read + written (64 B), V (8 B), At (24 B) per cell
-    return {"steps": steps, "ms_per_step": ms / steps, "steps_per_pass": 2,
+    # per pass of K steps: psi read + written (64 B), V (8 B), At (24 B) per cell
+    return {"steps": steps, "ms_per_step": ms / steps, "steps_per_pass": K,
             "site_updates_per_s": w.sites * steps / (ms * 1e-3),
-            "bytes_per_site_update": 96 / 2,
-            "hbm_frac": 96 * w.sites / (2 * ms / steps * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "bytes_per_site_update": 96 / K,
+            "hbm_frac": 96 * w.sites / (K * ms / steps * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "norm": norm}
 
 

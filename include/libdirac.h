@@ -131,8 +131,8 @@ int dl_step(dl_plan p, void *psi, const double *V, int64_t nsteps, void *stream)
  * cell centres, each block in psi's cell order; held fixed for the nsteps
  * steps of the call (a time-dependent field is applied by calls over shorter
  * spans).  A = NULL is dl_step.  1-D and 2-D grids (DL_ERR_ARG on 3-D), both
- * splittings; passes fuse at most 2 steps (1 with complex128 state or
- * DL_STRANG).  Same buffers and copy rule as dl_step. */
+ * splittings; passes fuse at most 3 steps (1 with DL_STRANG), with the bits
+ * of single steps.  Same buffers and copy rule as dl_step. */
 int dl_step_field(dl_plan p, void *psi, const double *V, const double *A, int64_t nsteps,
                   void *stream);
 
@@ -220,8 +220,8 @@ int dl_plan_set_tiling(dl_plan p, int waves_per_cu, int seg_len, int allow_resid
 /* Cap on the steps fused into one pass over memory, depth in 1..5: forward
  * passes (dl_step and friends) and reverse passes (dl_grad_step) use at most
  * this many steps, and never more than the kernels are built for (2-D and
- * 1-D: 5; 3-D: 2; second-order steps: 2, complex128 1; vector potential: 2,
- * complex128 1; reverse steps: 3, complex128 2).  The bits are independent of
+ * 1-D: 5; 3-D: 2; second-order steps: 2, complex128 1; vector potential: 3,
+ * second-order 1; reverse steps: 3, complex128 2).  The bits are independent of
  * the grouping.  DL_ERR_ARG outside 1..5. */
 int dl_plan_set_depth(dl_plan p, int depth);
 
@@ -230,8 +230,8 @@ int dl_plan_set_depth(dl_plan p, int depth);
  * [3] x strips, [4] wave tiles, [5] resident 1-D path (0/1), [6] its threads,
  * [7] waves_per_cu setting, [8] XCD-contiguous block order (0/1),
  * [9] graph_pairs, [10] fused steps per pass, [11] workgroups of a
- * single-step pass, [12] reverse steps per pass of dl_grad_step.  Works on
- * DL_DRY plans. */
+ * single-step pass, [12] reverse steps per pass of dl_grad_step, [13] steps
+ * per pass of dl_step_field.  Works on DL_DRY plans. */
 int dl_plan_info(dl_plan p, int64_t *info, int n);
 
 /* Batch tiling: seg_len >= 1 rows per 2-D march segment of every instance,

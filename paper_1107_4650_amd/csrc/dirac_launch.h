@@ -32,16 +32,18 @@ __host__ __device__ constexpr int max_depth(bool fp64, bool strang) {
   return strang ? (fp64 ? 1 : 2) : (fp64 ? kMaxDepthF64 : kMaxDepth);
 }
 // resident 256-thread blocks per CU the 1-D / 2-D kernel is compiled for
-__host__ __device__ constexpr int sweep2d_min_blocks(bool fp64, int depth) {
-  return (fp64 && depth > 2) ? 1 : 2;
+// (phase mode 3, the vector potential, carries more per row)
+__host__ __device__ constexpr int sweep2d_min_blocks(bool fp64, int depth, int mode) {
+  return ((fp64 && depth > 2) || (mode == 3 && depth > (fp64 ? 1 : 3))) ? 1 : 2;
 }
 // reverse (adjoint) passes fuse up to this many reverse steps
 constexpr int kMaxRevDepthF32 = 3;
 constexpr int kMaxRevDepthF64 = 2;
 // passes whose local step carries a vector potential (phase mode 3) hold
-// nine doubles of factors per row in flight: they fuse at most 2 steps
-__host__ __device__ constexpr int field_max_depth(bool fp64, bool strang) {
-  return (fp64 || strang) ? 1 : 2;
+// nine doubles of factors per row in flight: they fuse at most 3 lowest-order
+// steps (FP64 passes of 2 or 3 at one wave per SIMD), second-order ones 1
+__host__ __device__ constexpr int field_max_depth(bool /*fp64*/, bool strang) {
+  return strang ? 1 : 3;
 }
 __host__ __device__ constexpr int strip_width(int xlanes) { return 64 - 2 * xlanes; }
 __host__ __device__ constexpr int pass_xlanes(bool strang, int depth) {

@@ -637,7 +637,7 @@ extern "C" int dl_plan_info(dl_plan p, int64_t* info, int n) {
   const int64_t vals[] = {p->bl[p->depth - 1], t.H,          t.nseg,         t.nstrips,
                           t.ntiles,            p->resident,  p->res_threads, p->waves_per_cu,
                           t.xcd_remap,         p->graph_pairs, p->depth,     p->bl[0],
-                          reverse_depth(p)};
+                          reverse_depth(p),    p->depth_field};
   const int nv = static_cast<int>(sizeof vals / sizeof vals[0]);
   for (int i = 0; i < n && i < nv; ++i) info[i] = vals[i];
   return DL_OK;

@@ -29,7 +29,7 @@ namespace dirac {
 // output columns per wave, X = x transports of the pass; march segments of
 // H rows in 2-D)
 template <typename T, class S, int K, int AX0, int AX1, int MODE, int NC = 4>
-__global__ __launch_bounds__(256, sweep2d_min_blocks(sizeof(T) == 8, K))
+__global__ __launch_bounds__(256, sweep2d_min_blocks(sizeof(T) == 8, K, MODE))
 void k_sweep2d(const T* __restrict__ src, T* __restrict__ dst, const double* __restrict__ V,
                SweepArgs a) {
   static_assert(NC == 4 || AX1 < 0, "two-component states are 1-D lines");

@@ -114,6 +114,10 @@ def test_dry_3d_pass_depth(lib):
     assert dry((64, 30), dtype="c128").info()["reverse_depth"] == 2
     assert dry((64, 6), bc="periodic").info()["reverse_depth"] == 3
     assert dry((64, 30, 8)).info()["reverse_depth"] == 1
+    assert dry((64, 30)).info()["field_depth"] == 3
+    assert dry((64, 30), dtype="c128").info()["field_depth"] == 3
+    assert dry((64, 30), dt=2 * 0.01 / C, scheme="strang").info()["field_depth"] == 1
+    assert dry((64, 4), bc="periodic").info()["field_depth"] == 2
     p = dry((1 << 28, 2, 2))
     assert p.info()["depth"] == 1
     p.close()

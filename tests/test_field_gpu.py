@@ -65,10 +65,13 @@ def test_field_fused_passes_and_zero_field(shape, axes, bc):
     V, A = _fields(shape, 3)
     kw = dict(dx=DX, dt=DX / C, c=C, m=1.0, axes=axes, bc=bc, A=A,
               tiling={"allow_resident": False})
-    for n in (1, 2, 5):
-        single = gpu_step(psi.astype(np.complex64), V, nsteps=n, depth=1, dtype="c64", **kw)
-        fused = gpu_step(psi.astype(np.complex64), V, nsteps=n, dtype="c64", **kw)
-        assert same_bits(single, fused), n
+    for dtype in ("c64", "c128"):
+        p0 = psi.astype(np.complex64) if dtype == "c64" else psi
+        for n in (1, 2, 3, 5, 7, 11):
+            single = gpu_step(p0, V, nsteps=n, depth=1, dtype=dtype, **kw)
+            for depth in (2, 3, 4, 5):
+                fused = gpu_step(p0, V, nsteps=n, depth=depth, dtype=dtype, **kw)
+                assert same_bits(single, fused), (dtype, n, depth)
     zero = gpu_step(psi, V, nsteps=9, dtype="c128", **{**kw, "A": np.zeros_like(A)})
     plain = gpu_step(psi, V, nsteps=9, dtype="c128", **{**kw, "A": None})
     assert rel_l2(zero, plain) <= 1e-14
