@@ -220,7 +220,7 @@ int dl_plan_set_tiling(dl_plan p, int waves_per_cu, int seg_len, int allow_resid
 /* Cap on the steps fused into one pass over memory, depth in 1..5: forward
  * passes (dl_step and friends) and reverse passes (dl_grad_step) use at most
  * this many steps, and never more than the kernels are built for (2-D and
- * 1-D: 5; 3-D: 2; second-order steps: 2, complex128 1; vector potential: 3,
+ * 1-D: 5; 3-D: 2; second-order steps: 2; vector potential: 3,
  * second-order 1; reverse steps: 3, complex128 2).  The bits are independent of
  * the grouping.  DL_ERR_ARG outside 1..5. */
 int dl_plan_set_depth(dl_plan p, int depth);

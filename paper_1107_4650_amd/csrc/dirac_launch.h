@@ -21,20 +21,21 @@ constexpr int kMinBlocks3D2 = 1;
 __host__ __device__ constexpr int max_depth3d(bool) { return 2; }
 constexpr int64_t kMaxRow3DFused = int64_t(1) << 28;
 // 1-D / 2-D passes fuse up to kMaxDepth full lowest-order steps, or up to 2
-// second-order steps (FP64: 1).  A wave of 64 lanes writes 64 - 2X columns, X
+// second-order steps.  A wave of 64 lanes writes 64 - 2X columns, X
 // being the x transports of the pass (one per lowest-order step, two per
-// second-order step).  FP64 passes of more than two steps need more registers
-// than two waves per SIMD have: they run one wave per SIMD, the compiler
-// parking part of the working set in the accumulation registers.
+// second-order step).  FP64 passes of more than two stages need more
+// registers than two waves per SIMD have: they run one wave per SIMD, the
+// compiler parking part of the working set in the accumulation registers.
 constexpr int kMaxDepth = 5;
 constexpr int kMaxDepthF64 = 5;
 __host__ __device__ constexpr int max_depth(bool fp64, bool strang) {
-  return strang ? (fp64 ? 1 : 2) : (fp64 ? kMaxDepthF64 : kMaxDepth);
+  return strang ? 2 : (fp64 ? kMaxDepthF64 : kMaxDepth);
 }
-// resident 256-thread blocks per CU the 1-D / 2-D kernel is compiled for
-// (phase mode 3, the vector potential, carries more per row)
-__host__ __device__ constexpr int sweep2d_min_blocks(bool fp64, int depth, int mode) {
-  return ((fp64 && depth > 2) || (mode == 3 && depth > (fp64 ? 1 : 3))) ? 1 : 2;
+// resident 256-thread blocks per CU the 1-D / 2-D kernel is compiled for, by
+// the steps and stages (steps x stages per step) of its pass and its phase
+// mode (mode 3, the vector potential, carries more per row)
+__host__ __device__ constexpr int sweep2d_min_blocks(bool fp64, int depth, int stages, int mode) {
+  return ((fp64 && stages > 2) || (mode == 3 && (fp64 ? depth > 1 : stages > 3))) ? 1 : 2;
 }
 // reverse (adjoint) passes fuse up to this many reverse steps
 constexpr int kMaxRevDepthF32 = 3;

@@ -29,7 +29,7 @@ namespace dirac {
 // output columns per wave, X = x transports of the pass; march segments of
 // H rows in 2-D)
 template <typename T, class S, int K, int AX0, int AX1, int MODE, int NC = 4>
-__global__ __launch_bounds__(256, sweep2d_min_blocks(sizeof(T) == 8, K, MODE))
+__global__ __launch_bounds__(256, sweep2d_min_blocks(sizeof(T) == 8, K, K * S::kStages, MODE))
 void k_sweep2d(const T* __restrict__ src, T* __restrict__ dst, const double* __restrict__ V,
                SweepArgs a) {
   static_assert(NC == 4 || AX1 < 0, "two-component states are 1-D lines");
@@ -170,7 +170,13 @@ static const void* kernel2d_axes(int axes_code, int mode, int nc) {
 // nullptr for combinations that are not built (depths beyond max_depth)
 static const void* kernel2d(bool fp64, bool strang, int depth, int axes_code, int mode, int nc) {
   if (strang) {
-    if (fp64) return depth == 1 ? kernel2d_axes<double, StrangStep, 1>(axes_code, mode, nc) : nullptr;
+    if (fp64) {
+      switch (depth) {
+        case 1: return kernel2d_axes<double, StrangStep, 1>(axes_code, mode, nc);
+        case 2: return kernel2d_axes<double, StrangStep, 2>(axes_code, mode, nc);
+        default: return nullptr;
+      }
+    }
     switch (depth) {
       case 1: return kernel2d_axes<float, StrangStep, 1>(axes_code, mode, nc);
       case 2: return kernel2d_axes<float, StrangStep, 2>(axes_code, mode, nc);

@@ -48,11 +48,14 @@ def test_strang_streaming_bit_exact_and_full_step(shape, axes, bc):
 @pytest.mark.parametrize("shape,axes,bc", [((300, 260), (0, 2), "zero"), ((130, 45), (0, 1), "periodic"),
                                            ((5000,), (0,), "zero"), ((4099,), (2,), "periodic"),
                                            ((57, 8), (1, 2), "periodic"), ((200, 7), (0, 2), "periodic")])
-def test_strang_fused_passes_same_bits(shape, axes, bc):
-    announce(f"strang fused {shape} {axes} {bc}")
-    psi = random_spinor(shape[::-1], seed=5).astype(np.complex64)
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_strang_fused_passes_same_bits(shape, axes, bc, dtype):
+    announce(f"strang fused {shape} {axes} {bc} {dtype}")
+    psi = random_spinor(shape[::-1], seed=5)
+    if dtype == "c64":
+        psi = psi.astype(np.complex64)
     V = np.random.default_rng(6).uniform(-2, 2, size=shape[::-1]) * C * C
-    kw = dict(dx=DX, dt=DT, c=C, m=1.0, axes=axes, bc=bc, dtype="c64", scheme="strang",
+    kw = dict(dx=DX, dt=DT, c=C, m=1.0, axes=axes, bc=bc, dtype=dtype, scheme="strang",
               tiling={"allow_resident": False})
     for n in (1, 2, 3, 8):
         single = gpu_step(psi, V, nsteps=n, depth=1, **kw)
