@@ -476,9 +476,9 @@ def bench_adjoint(args):
 
 
 def bench_batch(args):
-    """256 uneven 1-D/2-D instances: one batched launch per pass of 4 fused
-    steps (graph replay) vs the same instances advanced one at a time with
-    their own plans."""
+    """256 uneven 1-D/2-D instances: one batched launch per pass of the batch's
+    fused steps (graph replay) vs the same instances advanced one at a time
+    with their own plans."""
     import torch
     from paper_1107_4650_amd import libdirac as L
     from paper_1107_4650_amd.inputs import config_batch
@@ -492,6 +492,7 @@ def bench_batch(args):
     with L.Batch([w.shape for w in ws], [w.dx for w in ws], [w.dt for w in ws],
                  [w.c for w in ws], [w.m for w in ws], dtype="c64", graph=True) as b:
         out["autotuned_seg_len"] = b.autotune(psis, Vs, trials=3)
+        K = b.depth()
         b.step(psis, Vs, [2] * len(ws))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -500,9 +501,9 @@ def bench_batch(args):
         tb = time.perf_counter() - t0
     out["batched_s"] = tb
     out["batched_site_updates_per_s"] = sites * steps / tb
-    # one pass of 4 steps reads and writes each state once and reads V once
-    out["batched_steps_per_pass"] = 4
-    out["batched_roofline_frac"] = BYTES_F32 / 4 * sites * steps / tb / 1e9 / HBM_PEAK_GBS
+    # one pass of K steps reads and writes each state once and reads V once
+    out["batched_steps_per_pass"] = K
+    out["batched_roofline_frac"] = BYTES_F32 / K * sites * steps / tb / 1e9 / HBM_PEAK_GBS
     plans = [L.Plan(w.shape, w.dx, w.dt, w.c, w.m, dtype="c64") for w in ws]
     for p, t, v in zip(plans, psis, Vs):
         p.step(t, v, 2)

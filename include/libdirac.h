@@ -231,7 +231,8 @@ int dl_plan_set_depth(dl_plan p, int depth);
  * [7] waves_per_cu setting, [8] XCD-contiguous block order (0/1),
  * [9] graph_pairs, [10] fused steps per pass, [11] workgroups of a
  * single-step pass, [12] reverse steps per pass of dl_grad_step, [13] steps
- * per pass of dl_step_field.  Works on DL_DRY plans. */
+ * per pass of dl_step_field.  Works on DL_DRY plans.  On a batch handle every
+ * value is 0 but [10], the steps fused per pass of the batch. */
 int dl_plan_info(dl_plan p, int64_t *info, int n);
 
 /* Batch tiling: seg_len >= 1 rows per 2-D march segment of every instance,

@@ -102,8 +102,8 @@ __global__ __launch_bounds__(256) void k_batch(const BatchInst* __restrict__ ins
 
 // depth of the batch's passes (steps fused per launch); a periodic batch
 // lowers it until every 2-D instance has at least 2 * depth rows
-constexpr int kBatchDepthF32 = 4;
-constexpr int kBatchDepthF64 = 2;
+constexpr int kBatchDepthF32 = 5;
+constexpr int kBatchDepthF64 = 5;  // passes of 3 or more run one wave per SIMD
 
 }  // namespace dirac
 
@@ -196,28 +196,22 @@ void drop_graph(Batch& B) {
   B.graph_tiles = -1;
 }
 
+template <typename T, int K>
+static void launch_k(const Batch& B, int phase, int64_t index, hipStream_t st) {
+  hipLaunchKernelGGL((k_batch<T, K>), dim3((B.ntiles + 3) / 4), dim3(256), 0, st, B.d_insts,
+                     B.d_tiles, B.ntiles, phase, index, B.depth);
+}
+
 template <typename T>
 hipError_t launch_pass_t(const Batch& B, int K, int phase, int64_t index, hipStream_t st) {
-  const int blocks = (B.ntiles + 3) / 4;
-  const int D = B.depth;
+  if (K < 1 || K > (sizeof(T) == 8 ? kBatchDepthF64 : kBatchDepthF32)) return hipErrorInvalidValue;
   switch (K) {
-    case 1: hipLaunchKernelGGL((k_batch<T, 1>), dim3(blocks), dim3(256), 0, st, B.d_insts,
-                               B.d_tiles, B.ntiles, phase, index, D); break;
-    case 2: hipLaunchKernelGGL((k_batch<T, 2>), dim3(blocks), dim3(256), 0, st, B.d_insts,
-                               B.d_tiles, B.ntiles, phase, index, D); break;
-    default:
-      if constexpr (sizeof(T) == 4) {  // deeper passes for FP32 state only
-        if (K == 3)
-          hipLaunchKernelGGL((k_batch<T, 3>), dim3(blocks), dim3(256), 0, st, B.d_insts,
-                             B.d_tiles, B.ntiles, phase, index, D);
-        else if (K == 4)
-          hipLaunchKernelGGL((k_batch<T, 4>), dim3(blocks), dim3(256), 0, st, B.d_insts,
-                             B.d_tiles, B.ntiles, phase, index, D);
-        else
-          return hipErrorInvalidValue;
-      } else {
-        return hipErrorInvalidValue;
-      }
+    case 1: launch_k<T, 1>(B, phase, index, st); break;
+    case 2: launch_k<T, 2>(B, phase, index, st); break;
+    case 3: launch_k<T, 3>(B, phase, index, st); break;
+    case 4: launch_k<T, 4>(B, phase, index, st); break;
+    case 5: launch_k<T, 5>(B, phase, index, st); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
@@ -326,6 +320,8 @@ void free_batch(Batch* B) {
 }
 
 }  // namespace
+
+int dirac::batch_depth(dl_plan b) { return as_batch(b)->depth; }
 
 namespace dirac {
 void destroy_batch(dl_plan p) {

@@ -92,5 +92,7 @@ int check_f64_ptr(const void* ptr, const char* name, bool nullable);
 void destroy_batch(dl_plan p);
 // reverse steps fused per pass of dl_grad_step (1 where the adjoint is refused)
 int reverse_depth(dl_plan p);
+// steps fused per pass of a batch
+int batch_depth(dl_plan b);
 
 }  // namespace dirac

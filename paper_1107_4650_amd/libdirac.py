@@ -355,6 +355,12 @@ class Batch:
     def set(self, seg_len=32, graph_pairs=16):
         check(self.lib.dl_batch_set(self.handle, int(seg_len), int(graph_pairs)))
 
+    def depth(self) -> int:
+        """Steps fused per pass of the batch."""
+        buf = (ctypes.c_int64 * 11)()
+        check(self.lib.dl_plan_info(self.handle, buf, 11))
+        return int(buf[10])
+
     def close(self):
         if getattr(self, "handle", None):
             self.lib.dl_plan_destroy(self.handle)

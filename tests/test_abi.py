@@ -142,6 +142,18 @@ def test_dry_resident_choice(lib):
     p.close()
 
 
+def test_dry_batch_depth(lib):
+    """Batches fuse 5 steps per pass; a periodic batch drops the depth until
+    every 2-D instance has at least twice as many rows."""
+    with L.Batch([(64,), (32, 16)], 0.01, 0.01 / C, C, 1.0, dtype="c64", dry=True) as b:
+        assert b.depth() == 5
+    with L.Batch([(64,), (32, 16)], 0.01, 0.01 / C, C, 1.0, dtype="c128", dry=True) as b:
+        assert b.depth() == 5
+    with L.Batch([(64,), (32, 7)], 0.01, 0.01 / C, C, 1.0, dtype="c64", bc="periodic",
+                 dry=True) as b:
+        assert b.depth() == 3
+
+
 def test_raw_abi_argument_errors(lib):
     g = L.make_grid((64,), dx=0.01)
     h = ctypes.c_void_p()
