@@ -92,6 +92,24 @@ def test_fused_passes_same_bits(dtype, shape, axes, bc):
         assert same_bits(massless, gpu_step(psi, None, nsteps=9, depth=d, **{**kw, "m": 0.0}))
 
 
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("shape,axes,scheme", [((64, 48, 40), (0, 1, 2), "lie"),
+                                               ((200, 150), (0, 2), "strang")])
+def test_graph_replay_of_3d_and_second_order_passes(dtype, shape, axes, scheme):
+    """Graph capture and replay of fused 3-D passes and of second-order
+    passes give the bits of the same steps run eagerly, over several calls
+    with eager work between the replays."""
+    announce(f"graph 3-D / strang {shape} {scheme} {dtype}")
+    psi = random_spinor(shape[::-1], seed=12)
+    V = _V(shape, seed=13)
+    dt = (2 if scheme == "strang" else 1) * DT
+    kw = dict(dx=DX, dt=dt, c=C, m=1.0, axes=axes, dtype=dtype, scheme=scheme)
+    eager = gpu_step(psi, V, nsteps=101, **kw)
+    graph = gpu_step(psi, V, nsteps=0, graph=True, tiling={"graph_pairs": 6},
+                     chunks=[30, 24, 47], **kw)
+    assert same_bits(eager, graph)
+
+
 @pytest.mark.parametrize("shape,bc,seg", [((70, 13, 11), "zero", 0), ((130, 6, 21), "periodic", 4),
                                           ((61, 9, 5), "zero", 2), ((64, 64, 40), "zero", 7),
                                           ((3, 2, 2), "periodic", 0), ((2, 5, 3), "zero", 0),
