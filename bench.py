@@ -536,10 +536,19 @@ def cpu_baseline(min_seconds=10.0, max_seconds=30.0):
         psi = O.step(psi, w.V, dt=w.dt, c=w.c, m=w.m, nsteps=chunk, axes=w.axes, threads=threads)
         t_used += time.perf_counter() - t0
         done += chunk
+    # the same oracle on one thread, a shorter sample
+    psi1, done1, t1 = w.psi0, 0, 0.0
+    while t1 < min_seconds / 2:
+        t0 = time.perf_counter()
+        psi1 = O.step(psi1, w.V, dt=w.dt, c=w.c, m=w.m, nsteps=1, axes=w.axes, threads=1)
+        t1 += time.perf_counter() - t0
+        done1 += 1
     return {"value": w.sites * done / t_used, "unit": "site-updates/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{done} FP64 steps of the 2048x2048 tanh-step workload "
-                      f"({w.sites * done:.3e} site-updates, {t_used:.1f} s, {threads} OpenMP threads)"}
+                      f"({w.sites * done:.3e} site-updates, {t_used:.1f} s, {threads} OpenMP threads)",
+            "single_thread": {"value": w.sites * done1 / t1, "unit": "site-updates/s",
+                              "sample": f"{done1} steps on one thread, {t1:.1f} s"}}
 
 
 def calibrate_copy(nbytes=1 << 30, reps=5):
