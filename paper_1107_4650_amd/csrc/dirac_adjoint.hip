@@ -16,11 +16,10 @@
 //     dL/dV = 2 dt dV sum_{n=1..N} Im(lambda_n^H psi_n),
 // accumulated in FP64 at the start of every reverse step.
 //
-// Work decomposition of the reverse step: the y transport precedes the x
-// transport, so a strip's edge columns need the y-transported values of the
-// columns beside the strip.  A wave therefore covers 64 columns starting one
-// column left of its 62 output columns; lanes 0 and 63 compute the halo
-// columns in full and do not store.
+// Work decomposition: a pass of K reverse steps gives each wave 64 columns
+// and writes the middle 64 - 2K (every backward x transport, the last
+// transport of a reverse step, narrows the valid lanes by one on each side),
+// and marches along y as the forward passes do.
 #include "dirac_device.h"
 #include "dirac_plan.h"
 #include "dirac_sweep_impl.h"
