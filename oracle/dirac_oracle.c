@@ -31,7 +31,9 @@
  *     transports over dt/2 in the order A, B, C, the local step D over dt,
  *     then the transports over dt/2 in the reverse order.  Each half-step
  *     transport is the same one-cell characteristic shift, i.e. the grid
- *     obeys c*(dt/2) = a.
+ *     obeys c*(dt/2) = a.  On a 3-D grid, the printed nine-part sequence
+ *     A(dt/4) B(dt/2) A(dt/4) C(dt/2) D C(dt/2) A(dt/4) B(dt/2) A(dt/4) with
+ *     c*(dt/4) = a: A shifts one cell, B and C two cells.
  *   - D with a vector potential (eq:sol_dis_4 with the closed form of the
  *     exponential of Dirac matrices, Sec. 2.3): psi <- U exp(-i Vtilde) psi,
  *     U = cos(A) + i (-beta m c^2 dt + alpha . Atilde) sin(A) / A,
@@ -201,10 +203,12 @@ static void matvec_f(zf P[4][4], const zf *v, zf *out)
     }
 }
 
-/* psi'(i) = Pm psi(i - e_d) + Pp psi(i + e_d).
+/* psi'(i) = Pm psi(i - s e_d) + Pp psi(i + s e_d): the characteristic
+ * solution over a time with c t = s a (s = 1 for every sub-step except the
+ * half-step y and z transports of the 3-D second-order step, s = 2).
  * Forward sub-step: Pm = 1/2(I + alpha), Pp = 1/2(I - alpha).
  * Its adjoint:      Pm = (1/2(I - alpha))^H, Pp = (1/2(I + alpha))^H. */
-static void transport_d(const grid_t *g, int d, zd Pm[4][4], zd Pp[4][4],
+static void transport_d(const grid_t *g, int d, int shift, zd Pm[4][4], zd Pp[4][4],
                         const zd *in, zd *out)
 {
     const int64_t rows = g->n[1] * g->n[2];
@@ -214,8 +218,8 @@ static void transport_d(const grid_t *g, int d, zd Pm[4][4], zd Pp[4][4],
         for (int64_t i0 = 0; i0 < g->n[0]; ++i0) {
             int64_t c[3] = {i0, i1, i2};
             int64_t cm[3] = {i0, i1, i2}, cp[3] = {i0, i1, i2};
-            cm[d] -= 1;
-            cp[d] += 1;
+            cm[d] -= shift;
+            cp[d] += shift;
             const int64_t sm = site_at(g, cm[0], cm[1], cm[2]);
             const int64_t sp = site_at(g, cp[0], cp[1], cp[2]);
             const zd zero4[4] = {0, 0, 0, 0};
@@ -349,7 +353,7 @@ static void step_once(const grid_t *g, zd *psi, zd *tmp, const double *V,
     for (int t = 0; t < k; ++t) {
         const int d = order[t];
         const int a = g->axis[d];
-        transport_d(g, d, PROJ[a][0], PROJ[a][1], psi, tmp);
+        transport_d(g, d, 1, PROJ[a][0], PROJ[a][1], psi, tmp);
         memcpy(psi, tmp, (size_t)bytes);
     }
     local_step(g, psi, V, dt, c, m, -1.0);
@@ -366,13 +370,38 @@ static void step_once_strang(const grid_t *g, zd *psi, zd *tmp, const double *V,
     const int64_t bytes = nsites(g) * 4 * (int64_t)sizeof(zd);
     for (int t = 0; t < k; ++t) {
         const int a = g->axis[order[t]];
-        transport_d(g, order[t], PROJ[a][0], PROJ[a][1], psi, tmp);
+        transport_d(g, order[t], 1, PROJ[a][0], PROJ[a][1], psi, tmp);
         memcpy(psi, tmp, (size_t)bytes);
     }
     local_step(g, psi, V, dt, c, m, -1.0);
     for (int t = k - 1; t >= 0; --t) {
         const int a = g->axis[order[t]];
-        transport_d(g, order[t], PROJ[a][0], PROJ[a][1], psi, tmp);
+        transport_d(g, order[t], 1, PROJ[a][0], PROJ[a][1], psi, tmp);
+        memcpy(psi, tmp, (size_t)bytes);
+    }
+}
+
+/* One second-order step on a 3-D grid, the sequence printed in Sec. 2.4:
+ *   A(dt/4) B(dt/2) A(dt/4) C(dt/2) D(dt) C(dt/2) A(dt/4) B(dt/2) A(dt/4).
+ * With c dt/4 = a every A is the one-cell shift and every B and C the
+ * two-cell shift of eq:sol_dis_1-3 (c dt/2 = 2a). */
+static void step_once_strang3(const grid_t *g, zd *psi, zd *tmp, const double *V,
+                              double dt, double c, double m)
+{
+    int order[3];
+    transport_order(g, order);
+    const int64_t bytes = nsites(g) * 4 * (int64_t)sizeof(zd);
+    /* the sub-steps in order: (grid dimension of A, B or C, cells), -1 for D */
+    const int seq[9][2] = {{order[0], 1}, {order[1], 2}, {order[0], 1}, {order[2], 2}, {-1, 0},
+                           {order[2], 2}, {order[0], 1}, {order[1], 2}, {order[0], 1}};
+    for (int t = 0; t < 9; ++t) {
+        const int d = seq[t][0];
+        if (d < 0) {
+            local_step(g, psi, V, dt, c, m, -1.0);
+            continue;
+        }
+        const int a = g->axis[d];
+        transport_d(g, d, seq[t][1], PROJ[a][0], PROJ[a][1], psi, tmp);
         memcpy(psi, tmp, (size_t)bytes);
     }
 }
@@ -390,7 +419,7 @@ static void adjoint_once(const grid_t *g, zd *lam, zd *tmp, const double *V,
         const int a = g->axis[d];
         /* adjoint of psi'(i) = P+ psi(i-1) + P- psi(i+1) is
          * lam'(i) = (P-)^H lam(i-1) + (P+)^H lam(i+1) */
-        transport_d(g, d, PROJ_H[a][1], PROJ_H[a][0], lam, tmp);
+        transport_d(g, d, 1, PROJ_H[a][1], PROJ_H[a][0], lam, tmp);
         memcpy(lam, tmp, (size_t)bytes);
     }
 }
@@ -413,18 +442,24 @@ int oracle_step(int ndim, const int64_t *n, const int *axis, int bc,
     return 0;
 }
 
-/* nsteps second-order steps (1-D and 2-D grids only; dt is the full step). */
+/* nsteps second-order steps; dt is the full step (1-D, 2-D: c dt = 2a;
+ * 3-D: c dt = 4a). */
 int oracle_step_strang(int ndim, const int64_t *n, const int *axis, int bc,
                        double dt, double c, double m, const double *V,
                        double *psi, int64_t nsteps, int nthreads)
 {
     grid_t g;
-    if (ndim > 2 || grid_from_args(&g, ndim, n, axis, bc) || nsteps < 0) return -1;
+    if (grid_from_args(&g, ndim, n, axis, bc) || nsteps < 0) return -1;
     build_matrices();
     set_threads(nthreads);
     zd *tmp = (zd *)malloc((size_t)nsites(&g) * 4 * sizeof(zd));
     if (!tmp) return -2;
-    for (int64_t s = 0; s < nsteps; ++s) step_once_strang(&g, (zd *)psi, tmp, V, dt, c, m);
+    for (int64_t s = 0; s < nsteps; ++s) {
+        if (ndim == 3)
+            step_once_strang3(&g, (zd *)psi, tmp, V, dt, c, m);
+        else
+            step_once_strang(&g, (zd *)psi, tmp, V, dt, c, m);
+    }
     free(tmp);
     return 0;
 }
@@ -451,14 +486,14 @@ int oracle_step_field(int ndim, const int64_t *n, const int *axis, int bc, int s
     for (int64_t st = 0; st < nsteps; ++st) {
         for (int t = 0; t < k; ++t) {
             const int a = g.axis[order[t]];
-            transport_d(&g, order[t], PROJ[a][0], PROJ[a][1], p, tmp);
+            transport_d(&g, order[t], 1, PROJ[a][0], PROJ[a][1], p, tmp);
             memcpy(p, tmp, (size_t)bytes);
         }
         local_step_field(&g, p, V, Atil, dt, c, m);
         if (scheme == 1) {
             for (int t = k - 1; t >= 0; --t) {
                 const int a = g.axis[order[t]];
-                transport_d(&g, order[t], PROJ[a][0], PROJ[a][1], p, tmp);
+                transport_d(&g, order[t], 1, PROJ[a][0], PROJ[a][1], p, tmp);
                 memcpy(p, tmp, (size_t)bytes);
             }
         }

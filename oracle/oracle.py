@@ -115,9 +115,11 @@ def step(psi, V=None, *, dt, c, m, nsteps, axes=None, bc="zero", threads=0):
 
 
 def step_strang(psi, V=None, *, dt, c, m, nsteps, axes=None, bc="zero", threads=0):
-    """Return psi after `nsteps` second-order steps (Sec. 2.4, 1-D and 2-D):
+    """Return psi after `nsteps` second-order steps (Sec. 2.4).  1-D and 2-D:
     half-step transports in the order A, B, C, D over dt, half-step transports
-    in the reverse order; each half step is a one-cell shift (c dt = 2a)."""
+    in the reverse order; each half step is a one-cell shift (c dt = 2a).
+    3-D: A(dt/4) B(dt/2) A(dt/4) C(dt/2) D C(dt/2) A(dt/4) B(dt/2) A(dt/4),
+    A a one-cell shift, B and C two-cell shifts (c dt = 4a)."""
     psi = np.array(psi, dtype=np.complex128, order="C", copy=True)
     V = _check_V(V, psi)
     ndim, n, ax = _grid_args(psi, axes)

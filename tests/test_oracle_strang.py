@@ -132,3 +132,77 @@ def test_strang_unitarity_and_walls(oracle):
         cur = oracle.step_strang(cur, V, dt=2 * 0.01 / C, c=C, m=1.0, nsteps=10, axes=(1, 2))
         norms.append(np.sum(np.abs(cur) ** 2))
     assert np.all(np.diff(norms) <= 1e-12 * n0)
+
+
+# ---- 3-D second-order step: A(dt/4) B(dt/2) A(dt/4) C(dt/2) D C B A pattern ----
+
+def test_strang3d_symbol_is_the_printed_product(oracle):
+    """On a periodic 3-D box every Fourier mode is multiplied by the product of
+    the sub-step symbols in the printed order, with one-cell A and two-cell B,
+    C shifts: E_A E_B E_A E_C D E_C E_A E_B E_A (rightmost first),
+    E_d(s) = expm(-i alpha_d k_d s a)."""
+    shape, dx, m = (8, 8, 8), 0.01, 1.0
+    dt = 4 * dx / C
+    D = scipy.linalg.expm(-1j * R.BETA * m * C * C * dt)
+    rng = np.random.default_rng(5)
+    modes = [list(rng.integers(0, 8, 3)) for _ in range(10)] + [[4, 0, 0], [0, 4, 0], [0, 0, 4],
+                                                                [1, 2, 3]]
+    for js in modes:
+        idx = np.meshgrid(*[np.arange(n) for n in shape[::-1]], indexing="ij")
+        turns = sum(((js[d] * idx[2 - d]) % shape[d]) / shape[d] for d in range(3))
+        phase = np.exp(2j * np.pi * turns)
+        M = np.zeros((4, 4), complex)
+        for col in range(4):
+            psi = np.zeros(shape[::-1] + (4,), complex)
+            psi[..., col] = phase
+            out = oracle.step_strang(psi, dt=dt, c=C, m=m, nsteps=1, axes=(0, 1, 2),
+                                     bc="periodic")
+            v = out / phase[..., None]
+            assert np.max(np.abs(v - v.reshape(-1, 4)[0])) < 1e-13
+            M[:, col] = v.reshape(-1, 4)[0]
+        k = [2 * np.pi * js[d] / shape[d] for d in range(3)]
+        E = lambda d, s: scipy.linalg.expm(-1j * R.dirac_alpha(d) * k[d] * s)
+        seq = [E(0, 1), E(1, 2), E(0, 1), E(2, 2), D, E(2, 2), E(0, 1), E(1, 2), E(0, 1)]
+        expect = np.eye(4, dtype=complex)
+        for f in seq:
+            expect = f @ expect
+        assert np.max(np.abs(M - expect)) < 1e-13, js
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_strang3d_massless_eigen_shift_is_four_cells(oracle, axis):
+    """Massless data varying along one axis only, in the +1 eigenspace of
+    that axis' alpha, move exactly four cells per step (four one-cell A or two
+    two-cell B / C shifts; the other transports leave uniform data alone)."""
+    n, steps, other = 64, 5, 4
+    rng = np.random.default_rng(10 + axis)
+    u = rng.uniform(-1, 1, (n, 2)) + 1j * rng.uniform(-1, 1, (n, 2))
+    pauli = [np.array([[0, 1], [1, 0]]), np.array([[0, -1j], [1j, 0]]),
+             np.array([[1, 0], [0, -1]])][axis]
+    line = np.zeros((n, 4), complex)
+    line[:, :2] = u
+    line[:, 2:] = u @ pauli.T
+    shape = [other, other, other]
+    shape[axis] = n
+    arr_shape = tuple(shape[::-1]) + (4,)
+    bshape = [1, 1, 1]
+    bshape[2 - axis] = n
+    psi = np.broadcast_to(line.reshape(tuple(bshape) + (4,)), arr_shape).copy()
+    out = oracle.step_strang(psi, dt=4 * 0.01 / C, c=C, m=0.0, nsteps=steps,
+                             axes=(0, 1, 2), bc="periodic")
+    assert np.array_equal(out, np.roll(psi, 4 * steps, axis=2 - axis))
+
+
+def test_strang3d_unitarity_and_walls(oracle):
+    shape = (12, 10, 9)
+    psi = random_spinor(shape[::-1], seed=19)
+    V = np.random.default_rng(4).uniform(-3, 3, shape[::-1]) * C * C
+    out = oracle.step_strang(psi, V, dt=4 * 0.01 / C, c=C, m=1.0, nsteps=20, axes=(0, 1, 2),
+                             bc="periodic")
+    n0 = np.sum(np.abs(psi) ** 2)
+    assert abs(np.sum(np.abs(out) ** 2) / n0 - 1) < 1e-12
+    norms, cur = [n0], psi
+    for _ in range(4):
+        cur = oracle.step_strang(cur, V, dt=4 * 0.01 / C, c=C, m=1.0, nsteps=3, axes=(0, 1, 2))
+        norms.append(np.sum(np.abs(cur) ** 2))
+    assert np.all(np.diff(norms) <= 1e-12 * n0)
