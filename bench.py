@@ -388,11 +388,25 @@ def bench_3d(args):
     del r2
     runs = (("f32", torch.complex64, BYTES_F32, None), ("f32_one_step_per_pass", torch.complex64,
                                                         BYTES_F32, 1),
-            ("f64", torch.complex128, BYTES_F64, None))
+            ("f64", torch.complex128, BYTES_F64, None),
+            ("f32_second_order", torch.complex64, None, None))
     for dt_name, tdt, bps, depth in runs:
         f = (gz[:, None, None] * gy[None, :, None] * gx[None, None, :])
         psi = (f[..., None] * u).to(tdt).contiguous()
         del f
+        strang = dt_name.endswith("second_order")
+        if strang:
+            # c dt = 4 dx: three passes per step, and four times the time per step
+            with L.Plan((n, n, n), dx, 4 * dx / c, c, m, dtype="complex64", scheme="strang") as p:
+                s2 = min(steps, 20)
+                wall, per, _, done = timed_sweep(p, psi, V, s2, 2)
+            out[dt_name] = {"steps": done, "ms_per_step": wall * 1e3 / done,
+                            "passes_per_step": 3, "dt_over_lowest_order_dt": 4,
+                            "site_updates_per_s": n ** 3 * done / wall}
+            log(f"3-D 512^3 {dt_name}: {wall * 1e3 / done:.3f} ms/step (c dt = 4 dx)")
+            del psi
+            torch.cuda.empty_cache()
+            continue
         with L.Plan((n, n, n), dx, dx / c, c, m, dtype=str(tdt).split(".")[1]) as p:
             if depth is not None:
                 p.set_depth(depth)

@@ -51,7 +51,8 @@ typedef struct dl_plan_s *dl_plan;
 typedef enum {
     DL_OK = 0,
     DL_ERR_ARG = -1,    /* null pointer, bad size, bad enum, nsteps < 0 ... */
-    DL_ERR_CFL = -2,    /* c dt differs from the cell size (twice it with DL_STRANG), relative 1e-12 */
+    DL_ERR_CFL = -2,    /* c dt differs from the cell size (with DL_STRANG: twice it, four
+                           times on 3-D grids), relative 1e-12 */
     DL_ERR_DTYPE = -3,  /* unknown dtype, or call not valid for the plan's dtype */
     DL_ERR_ALIGN = -4,  /* a pointer is not aligned as required */
     DL_ERR_NOMEM = -5,  /* device allocation failed */
@@ -69,13 +70,18 @@ typedef enum { DL_BC_ZERO = 0, DL_BC_PERIODIC = 1 } dl_bc;
 #define DL_DRY 1u    /* validate only: no HIP call, no allocation; every other
                         entry point then returns DL_ERR_STATE */
 #define DL_GRAPH 2u  /* replay long step sequences from captured hipGraphs */
-#define DL_STRANG 4u /* second-order steps (Sec. 2.4), 1-D and 2-D grids only:
-                        each step applies the transports over dt/2 in the order
+#define DL_STRANG 4u /* second-order steps (Sec. 2.4).  1-D and 2-D grids: each
+                        step applies the transports over dt/2 in the order
                         A, B, C, the local step over dt, then the transports
-                        over dt/2 in the reverse order.  Every transport is the
-                        one-cell shift, so the plan needs c*dt = 2*dx
-                        (DL_ERR_CFL otherwise).  The adjoint entry points
-                        refuse such a plan (DL_ERR_ARG). */
+                        over dt/2 in the reverse order; every transport is the
+                        one-cell shift, so the plan needs c*dt = 2*dx.  3-D
+                        grids: A(dt/4) B(dt/2) A(dt/4) C(dt/2) D(dt) C(dt/2)
+                        A(dt/4) B(dt/2) A(dt/4) with c*dt = 4*dx: A shifts one
+                        cell, B and C two (three passes over memory per step,
+                        one extra state buffer in the plan).  DL_ERR_CFL on any
+                        other c*dt.  The adjoint entry points and
+                        dl_step_field on 3-D grids refuse such a plan
+                        (DL_ERR_ARG). */
 #define DL_BISPINOR 8u /* two-component state, 1-D grids only (Sec. 2.4): with
                         one transport axis the pair of components that contains
                         psi_1 -- (psi_1, psi_4) for alpha_x and alpha_y,

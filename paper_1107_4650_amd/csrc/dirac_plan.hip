@@ -189,7 +189,10 @@ void make_tiling3d(const dl_grid& g, int ty, int strip_width, int halo, int64_t 
 
 // one-cell transports per step: one per axis (Sec. 2.1), or two per axis for
 // the second-order step (Sec. 2.4)
-int dirac::transports_per_step(dl_plan p) { return (p->strang ? 2 : 1) * p->g.ndim; }
+int dirac::transports_per_step(dl_plan p) {
+  if (p->strang && p->g.ndim == 3) return 8;  // A four times, B and C twice
+  return (p->strang ? 2 : 1) * p->g.ndim;
+}
 
 // make the tilings of phase mode `mode` current
 static void select_tiling(dl_plan p, int mode) {
@@ -219,7 +222,8 @@ static int plan_tiling(dl_plan p) {
   // box of two or more cells per axis.
   int depth = 1;
   if (p->g.ndim == 3) {
-    if (p->g.n[0] < kMaxRow3DFused) depth = std::min(p->depth_limit, max_depth3d(p->fp64));
+    if (p->g.n[0] < kMaxRow3DFused && !p->strang)
+      depth = std::min(p->depth_limit, max_depth3d(p->fp64));
   } else {
     depth = std::min(p->depth_limit, max_depth(p->fp64, p->strang));
     const int stages_per_step = p->strang ? 2 : 1;
@@ -267,7 +271,11 @@ extern "C" int dl_plan_create(dl_plan* out, const dl_grid* g, double dx, double 
   if (!out) return fail(DL_ERR_ARG, "out is NULL");
   *out = nullptr;
   const bool strang = (flags & DL_STRANG) != 0;
-  int rc = validate_grid(g, dx, dt, c, m, dtype, bc, strang ? 2 : 3, strang ? 2 : 1);
+  // characteristic shift per step: one cell (lowest order), two cells (the
+  // half steps of the 1-D / 2-D second-order step), four cells (the quarter
+  // steps of A in the 3-D second-order step)
+  const int shift = strang ? ((g && g->ndim == 3) ? 4 : 2) : 1;
+  int rc = validate_grid(g, dx, dt, c, m, dtype, bc, 3, shift);
   if (rc) return rc;
   if (g->ndim == 3 && !(g->axis[0] == 0 && g->axis[1] == 1 && g->axis[2] == 2))
     return fail(DL_ERR_ARG, "3-D grids carry alpha_x, alpha_y, alpha_z in order");
@@ -311,7 +319,9 @@ extern "C" int dl_plan_create(dl_plan* out, const dl_grid* g, double dx, double 
       ncu > 0)
     p->cu_count = ncu;
   plan_tiling(p);
+  const bool mid = strang && g->ndim == 3;  // the 3-D second-order step runs through a third buffer
   if (hipMalloc(&p->tmp, p->state_bytes) != hipSuccess ||
+      (mid && hipMalloc(&p->tmp2, p->state_bytes) != hipSuccess) ||
       hipMalloc(&p->partials, sizeof(double) * 2 * 8 * kObsBlocks) != hipSuccess ||
       hipMalloc(&p->dres, sizeof(double) * 64) != hipSuccess ||
       hipHostMalloc(&p->hres, sizeof(double) * 64, hipHostMallocDefault) != hipSuccess) {
@@ -381,6 +391,7 @@ hipError_t launch_pass(dl_plan p, int depth, const void* src, void* dst, const d
   if (p->g.ndim == 3) {
     SweepArgs a = p->sw[depth - 1];
     a.ph = p->ph;
+    if (p->strang) return launch_strang3d(p->fp64, src, dst, p->tmp2, V, a, st);
     return launch_sweep3d(p->fp64, depth, src, dst, V, a, p->bl[depth - 1], st);
   }
   SweepArgs a = p->sw[depth - 1];

@@ -314,6 +314,151 @@ __global__ __launch_bounds__(256, kMinBlocks3D2) void k_sweep3d_x2(const T* __re
     march3d_x2<T, TY, true, MODE>(src, dst, V, a, xs, lane, y0, kb, ke);
 }
 
+// ---------------------------------------------------------------------------
+// 3-D second-order step (Sec. 2.4): A(dt/4) B(dt/2) A(dt/4) C(dt/2) D(dt)
+// C(dt/2) A(dt/4) B(dt/2) A(dt/4), with c dt/4 = a: A is the one-cell x
+// shift, B and C the two-cell y and z shifts.  It runs as three passes over
+// memory: A B A on every (x, y) plane, C D C along z, A B A again.  The
+// factors 1/2 of the eight transports are deferred to the local step (scale
+// 2^-8), so the stored intermediate states carry exact powers of two.
+// ---------------------------------------------------------------------------
+
+// r wrapped into [0, n) around a periodic box, else clamped (cells beyond a
+// wall are zeroed where they are used)
+__device__ __forceinline__ int64_t wrap_or_clamp(int64_t r, int64_t n, int periodic) {
+  if (periodic) return ((r % n) + n) % n;
+  return r < 0 ? 0 : (r >= n ? n - 1 : r);
+}
+
+// A B A on row j of plane k: a wave holds 64 columns and writes the middle 60
+template <typename T>
+__global__ __launch_bounds__(256) void k_strang3d_aba(const T* __restrict__ src,
+                                                      T* __restrict__ dst, SweepArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int64_t tile = int64_t(blockIdx.x) * 4 + wave_in_block();
+  if (tile >= a.ntiles) return;
+  const int64_t nx = a.nx, ny = a.ny;
+  const int64_t strip = tile % a.nstrips;
+  const int64_t rest = tile / a.nstrips;
+  const int64_t j = rest % ny, k = rest / ny;
+  const Lanes c = lanes_of(nx, a.periodic, strip * strip_width(2) - 2, lane);
+  const bool walls = !a.periodic;
+  auto load = [&](int64_t r, Site<T>& s) {
+    load_site(src + ((k * ny + wrap_or_clamp(r, ny, a.periodic)) * nx + c.col) * 8, s);
+    if (walls && (r < 0 || r >= ny || (!c.full && c.out))) zero(s);
+  };
+  Site<T> lo, hi, alo, ahi;
+  load(j - 2, lo);
+  load(j + 2, hi);
+  x_transport_inner<T, 0>(lo, alo);
+  x_transport_inner<T, 0>(hi, ahi);
+  if (walls && !c.full && !c.inside) {
+    zero(alo);
+    zero(ahi);
+  }
+  // B: the +1 movers of row j - 2 and the -1 movers of row j + 2 reach row j
+  Mov<T> r1, l1, r2, l2;
+  Axis<1, T>::movers(alo, r1, l1);
+  Axis<1, T>::movers(ahi, r2, l2);
+  Site<T> b, o;
+  Axis<1, T>::combine(r1, l2, b);
+  if (walls && !c.full && !c.inside) zero(b);
+  x_transport_inner<T, 0>(b, o);
+  if (c.inside && lane >= 2 && lane <= 61) store_site(dst + ((k * ny + j) * nx + c.x) * 8, o);
+}
+
+// C D C on row j of plane k: planes k - 4, k and k + 4 give C at k - 2 and
+// k + 2, where D applies, and C again gives plane k.  64 columns per wave.
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void k_strang3d_cdc(const T* __restrict__ src,
+                                                      T* __restrict__ dst,
+                                                      const double* __restrict__ V,
+                                                      SweepArgs a) {
+  constexpr bool TWO = sizeof(T) == 8;
+  const int lane = threadIdx.x & 63;
+  const int64_t tile = int64_t(blockIdx.x) * 4 + wave_in_block();
+  if (tile >= a.ntiles) return;
+  const int64_t nx = a.nx, ny = a.ny, nz = a.nz;
+  const int64_t strip = tile % a.nstrips;
+  const int64_t rest = tile / a.nstrips;
+  const int64_t j = rest % ny, k = rest / ny;
+  const int64_t x = strip * 64 + lane;
+  const int64_t col = x < nx ? x : nx - 1;
+  const bool walls = !a.periodic;
+  auto outside = [&](int64_t p) { return walls && (p < 0 || p >= nz); };
+  auto cell = [&](int64_t p) { return (wrap_or_clamp(p, nz, a.periodic) * ny + j) * nx + col; };
+  Site<T> s0, s1, s2;
+  load_site(src + cell(k - 4) * 8, s0);
+  load_site(src + cell(k) * 8, s1);
+  load_site(src + cell(k + 4) * 8, s2);
+  if (outside(k - 4)) zero(s0);
+  if (outside(k + 4)) zero(s2);
+  Mov<T> r0, l0, r1, l1, r2, l2;
+  Axis<2, T>::movers(s0, r0, l0);
+  Axis<2, T>::movers(s1, r1, l1);
+  Axis<2, T>::movers(s2, r2, l2);
+  Site<T> cm, cp;
+  Axis<2, T>::combine(r0, l1, cm);  // C at plane k - 2
+  Axis<2, T>::combine(r1, l2, cp);  // C at plane k + 2
+  const double vm = (MODE == 2) ? V[cell(k - 2)] : 0.0;
+  const double vp = (MODE == 2) ? V[cell(k + 2)] : 0.0;
+  Factors fm = factors_of<MODE, TWO>(vm, a.ph), fp = factors_of<MODE, TWO>(vp, a.ph);
+  factors_fix<MODE, TWO>(fm, vm, a.ph);
+  factors_fix<MODE, TWO>(fp, vp, a.ph);
+  apply_local<MODE>(cm, fm, a.ph);
+  apply_local<MODE>(cp, fp, a.ph);
+  if (outside(k - 2)) zero(cm);
+  if (outside(k + 2)) zero(cp);
+  Mov<T> rm, lm, rp, lp;
+  Axis<2, T>::movers(cm, rm, lm);
+  Axis<2, T>::movers(cp, rp, lp);
+  Site<T> o;
+  Axis<2, T>::combine(rm, lp, o);
+  if (x < nx) store_site(dst + ((k * ny + j) * nx + x) * 8, o);
+}
+
+template <typename T>
+static hipError_t strang3d_t(const void* src, void* dst, void* mid, const double* V,
+                             const SweepArgs& a0, hipStream_t st) {
+  SweepArgs a = a0;
+  const T* s = static_cast<const T*>(src);
+  T* d = static_cast<T*>(dst);
+  T* m = static_cast<T*>(mid);
+  SweepArgs ab = a;
+  ab.nstrips = (a.nx + strip_width(2) - 1) / strip_width(2);
+  ab.ntiles = ab.nstrips * a.ny * a.nz;
+  SweepArgs cd = a;
+  cd.nstrips = (a.nx + 63) / 64;
+  cd.ntiles = cd.nstrips * a.ny * a.nz;
+  const int64_t bab = (ab.ntiles + 3) / 4, bcd = (cd.ntiles + 3) / 4;
+  if (bab > INT32_MAX || bcd > INT32_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_strang3d_aba<T>), dim3(static_cast<unsigned>(bab)), dim3(256), 0, st,
+                     s, d, ab);
+  switch (a.ph.mode) {
+    case 0:
+      hipLaunchKernelGGL((k_strang3d_cdc<T, 0>), dim3(static_cast<unsigned>(bcd)), dim3(256), 0,
+                         st, d, m, V, cd);
+      break;
+    case 1:
+      hipLaunchKernelGGL((k_strang3d_cdc<T, 1>), dim3(static_cast<unsigned>(bcd)), dim3(256), 0,
+                         st, d, m, V, cd);
+      break;
+    default:
+      hipLaunchKernelGGL((k_strang3d_cdc<T, 2>), dim3(static_cast<unsigned>(bcd)), dim3(256), 0,
+                         st, d, m, V, cd);
+      break;
+  }
+  hipLaunchKernelGGL((k_strang3d_aba<T>), dim3(static_cast<unsigned>(bab)), dim3(256), 0, st,
+                     m, d, ab);
+  return hipGetLastError();
+}
+
+hipError_t launch_strang3d(bool fp64, const void* src, void* dst, void* mid, const double* V,
+                           const SweepArgs& a, hipStream_t st) {
+  return fp64 ? strang3d_t<double>(src, dst, mid, V, a, st)
+              : strang3d_t<float>(src, dst, mid, V, a, st);
+}
+
 // ---- 3-D kernels: one step, or a pass of two fused steps ---------------------
 template <typename T>
 static const void* kernel3d(int depth, int mode) {

@@ -138,7 +138,7 @@ class Plan:
     def __init__(self, shape, dx, dt, c, m, dtype="c64", bc="zero", axes=None, xmin=None,
                  dry=False, graph=False, scheme="lie", bispinor=False):
         """scheme: "lie" (lowest order, c dt = dx) or "strang" (second order,
-        c dt = 2 dx; 1-D and 2-D grids).  bispinor: 1-D line stored as the
+        c dt = 2 dx on 1-D and 2-D grids, 4 dx on 3-D grids).  bispinor: 1-D line stored as the
         pair of components that contains psi_1 (tensor shape (n, 2))."""
         if scheme not in ("lie", "strang"):
             raise ValueError(f"unknown scheme {scheme!r}")

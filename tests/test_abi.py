@@ -82,14 +82,19 @@ def test_dry_plan_rejections(lib):
 
 
 def test_dry_strang_plans(lib):
-    """Second-order plans: c dt = 2 dx, 1-D and 2-D grids only."""
+    """Second-order plans: c dt = 2 dx on 1-D and 2-D grids, 4 dx on 3-D grids."""
     for shape, axes in (((64,), (0,)), ((32, 16), (0, 2)), ((32, 16), (0, 1)), ((32, 16), (1, 2))):
         for dtype in ("c64", "c128"):
             p = dry(shape, dtype=dtype, axes=axes, dt=2 * 0.01 / C, scheme="strang")
             p.close()
     assert code_of(lambda: dry((64,), dt=0.01 / C, scheme="strang")) == L.DL_ERR_CFL
     assert code_of(lambda: dry((64,), dt=2 * 0.01 / C * (1 + 1e-9), scheme="strang")) == L.DL_ERR_CFL
-    assert code_of(lambda: dry((8, 8, 8), dt=2 * 0.01 / C, scheme="strang")) == L.DL_ERR_ARG
+    assert code_of(lambda: dry((8, 8, 8), dt=2 * 0.01 / C, scheme="strang")) == L.DL_ERR_CFL
+    for dtype in ("c64", "c128"):
+        p = dry((8, 8, 8), dtype=dtype, dt=4 * 0.01 / C, scheme="strang")
+        assert p.info()["depth"] == 1
+        p.close()
+    assert code_of(lambda: dry((64,), dt=4 * 0.01 / C, scheme="strang")) == L.DL_ERR_CFL
     with pytest.raises(ValueError):
         dry((64,), scheme="rk4")
 

@@ -76,3 +76,67 @@ def test_strang_klein_setup_small():
     got32 = gpu_step(w.psi0.astype(np.complex64), w.V, dx=w.dx, dt=w.dt, c=w.c, m=w.m,
                      nsteps=w.nsteps, axes=w.axes, dtype="c64", scheme="strang")
     assert rel_l2(got32, ref) <= 2e-5
+
+
+# ---- 3-D second-order steps: c dt = 4 dx, three passes per step ------------------
+DT3 = 4 * DX / C
+SHAPES3 = [(37, 21, 13), (64, 8, 9), (70, 13, 11), (2, 3, 5)]
+
+
+@pytest.mark.parametrize("shape", SHAPES3, ids=[_ids(s) for s in SHAPES3])
+@pytest.mark.parametrize("bc", ["zero", "periodic"])
+def test_strang3d_vs_oracle(shape, bc):
+    """Pure streaming bit for bit (FP64), full steps to relative L2 1e-12
+    (FP64) and within the FP32 rounding budget, against the oracle's printed
+    nine-part sequence."""
+    announce(f"strang 3-D {shape} {bc}")
+    psi = random_spinor(shape[::-1], seed=sum(shape))
+    V = np.random.default_rng(3).uniform(-3, 3, size=shape[::-1]) * C * C
+    kw = dict(dx=DX, dt=DT3, c=C, axes=(0, 1, 2), bc=bc, scheme="strang")
+    ref0 = O.step_strang(psi, None, dt=DT3, c=C, m=0.0, nsteps=9, axes=(0, 1, 2), bc=bc)
+    assert same_bits(gpu_step(psi, None, m=0.0, nsteps=9, dtype="c128", **kw), ref0)
+    # four cells per step: a box of a few cells with zero walls empties in two steps
+    n = 7 if min(shape) > 4 or bc == "periodic" else 1
+
+    def close(got, ref, tol):
+        if np.linalg.norm(ref) == 0:
+            return np.max(np.abs(got)) <= tol * np.max(np.abs(psi))
+        return rel_l2(got, ref) <= tol
+
+    ref = O.step_strang(psi, V, dt=DT3, c=C, m=1.0, nsteps=n, axes=(0, 1, 2), bc=bc)
+    assert close(gpu_step(psi, V, m=1.0, nsteps=n, dtype="c128", **kw), ref, 1e-12)
+    got32 = gpu_step(psi.astype(np.complex64), V, m=1.0, nsteps=n, dtype="c64", **kw)
+    assert close(got32, ref, 5e-6)
+    refm = O.step_strang(psi, None, dt=DT3, c=C, m=1.0, nsteps=4, axes=(0, 1, 2), bc=bc)
+    assert close(gpu_step(psi, None, m=1.0, nsteps=4, dtype="c128", **kw), refm, 1e-13)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_strang3d_step_out_chain_and_graph(dtype):
+    """n steps in one call, n single out-of-place steps and a graph replay give
+    the same bits (the plan's three state buffers never alias)."""
+    import torch
+    from paper_1107_4650_amd import libdirac as L
+    announce(f"strang 3-D buffers {dtype}")
+    shape = (40, 24, 18)
+    psi = random_spinor(shape[::-1], seed=4)
+    V = np.random.default_rng(5).uniform(-2, 2, size=shape[::-1]) * C * C
+    kw = dict(dx=DX, dt=DT3, c=C, m=1.0, axes=(0, 1, 2), dtype=dtype, scheme="strang")
+    whole = gpu_step(psi, V, nsteps=13, **kw)
+    graph = gpu_step(psi, V, nsteps=0, graph=True, tiling={"graph_pairs": 2}, chunks=[5, 8], **kw)
+    assert same_bits(whole, graph)
+    tdt = torch.complex64 if dtype == "c64" else torch.complex128
+    with L.Plan(shape, DX, DT3, C, 1.0, dtype=dtype, scheme="strang") as p:
+        a = torch.from_numpy(psi).to("cuda").to(tdt)
+        src = a.clone()
+        tV = torch.from_numpy(V).to("cuda")
+        for _ in range(13):
+            b = torch.empty_like(a)
+            p.step_out(a, b, tV)
+            a = b
+        torch.cuda.synchronize()
+        assert same_bits(a.cpu().numpy(), whole)
+        d = torch.empty_like(src)
+        p.step_fused_out(src, d, tV, 13)
+        torch.cuda.synchronize()
+        assert same_bits(d.cpu().numpy(), whole)
