@@ -100,11 +100,11 @@ int sweep_occupancy(bool fp64, bool strang, int ndim, int axes_code, int mode, i
                     int nc);
 // the same for the 3-D kernels
 int occupancy3d(bool fp64, int mode, int depth);
-// one second-order step src -> dst on a 3-D grid (Sec. 2.4) in three passes,
-// through `mid` (a state buffer distinct from src and dst); a needs nx, ny,
-// nz, periodic and ph
+// nsteps >= 1 second-order steps src -> dst on a 3-D grid (Sec. 2.4) in
+// 2 nsteps + 1 passes, through `mid` (a state buffer distinct from src and
+// dst); a needs nx, ny, nz, periodic and ph
 hipError_t launch_strang3d(bool fp64, const void* src, void* dst, void* mid, const double* V,
-                           const SweepArgs& a, hipStream_t st);
+                           const SweepArgs& a, int64_t nsteps, hipStream_t st);
 // nsteps in place in one workgroup of `threads` threads, `spt` cells each
 hipError_t launch_resident1d(bool fp64, int axis, void* psi, const double* V,
                              const ResidentArgs& a, int spt, int threads, hipStream_t st);

@@ -222,7 +222,9 @@ static int plan_tiling(dl_plan p) {
   // box of two or more cells per axis.
   int depth = 1;
   if (p->g.ndim == 3) {
-    if (p->g.n[0] < kMaxRow3DFused && !p->strang)
+    if (p->strang)
+      depth = p->depth_limit;  // steps grouped per call of the second-order passes
+    else if (p->g.n[0] < kMaxRow3DFused)
       depth = std::min(p->depth_limit, max_depth3d(p->fp64));
   } else {
     depth = std::min(p->depth_limit, max_depth(p->fp64, p->strang));
@@ -389,9 +391,9 @@ int check_f64_ptr(const void* ptr, const char* name, bool nullable) {
 hipError_t launch_pass(dl_plan p, int depth, const void* src, void* dst, const double* V,
                        hipStream_t st) {
   if (p->g.ndim == 3) {
-    SweepArgs a = p->sw[depth - 1];
+    SweepArgs a = p->sw[p->strang ? 0 : depth - 1];  // second-order passes size their own grids
     a.ph = p->ph;
-    if (p->strang) return launch_strang3d(p->fp64, src, dst, p->tmp2, V, a, st);
+    if (p->strang) return launch_strang3d(p->fp64, src, dst, p->tmp2, V, a, depth, st);
     return launch_sweep3d(p->fp64, depth, src, dst, V, a, p->bl[depth - 1], st);
   }
   SweepArgs a = p->sw[depth - 1];
@@ -426,6 +428,15 @@ hipError_t enqueue_steps(dl_plan p, void* psi, const double* V, int64_t nsteps, 
 
 }  // namespace dirac
 
+// dst = src for n 16-byte words: a plain kernel rather than a copy node, so a
+// captured graph holds kernels only
+__global__ __launch_bounds__(256) void k_copy16(const uint4* __restrict__ src,
+                                                uint4* __restrict__ dst, int64_t n) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
+    dst[i] = src[i];
+}
+
 static hipError_t graph_for(dl_plan p, void* psi, const double* V, int64_t pairs,
                             hipGraphExec_t* exec) {
   for (auto& ge : p->graphs) {
@@ -443,6 +454,16 @@ static hipError_t graph_for(dl_plan p, void* psi, const double* V, int64_t pairs
   if (e != hipSuccess) return e;
   void* res = nullptr;
   hipError_t e2 = enqueue_steps(p, psi, V, 2 * pairs, p->cap_stream, &res);
+  if (e2 == hipSuccess && res != psi) {
+    // an odd number of passes ends in the plan's buffer: every replay must
+    // leave the state in psi, where the next one starts
+    const int64_t words = static_cast<int64_t>(p->state_bytes / 16);
+    const int64_t blocks = std::min<int64_t>((words + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_copy16, dim3(static_cast<unsigned>(blocks)), dim3(256), 0,
+                       p->cap_stream, static_cast<const uint4*>(res), static_cast<uint4*>(psi),
+                       words);
+    e2 = hipGetLastError();
+  }
   e = hipStreamEndCapture(p->cap_stream, &graph);
   if (e2 != hipSuccess) {
     if (graph) (void)hipGraphDestroy(graph);

@@ -317,8 +317,10 @@ __global__ __launch_bounds__(256, kMinBlocks3D2) void k_sweep3d_x2(const T* __re
 // ---------------------------------------------------------------------------
 // 3-D second-order step (Sec. 2.4): A(dt/4) B(dt/2) A(dt/4) C(dt/2) D(dt)
 // C(dt/2) A(dt/4) B(dt/2) A(dt/4), with c dt/4 = a: A is the one-cell x
-// shift, B and C the two-cell y and z shifts.  It runs as three passes over
-// memory: A B A on every (x, y) plane, C D C along z, A B A again.  The
+// shift, B and C the two-cell y and z shifts.  It runs as passes over
+// memory: A B A on every (x, y) plane, C D C along z, A B A again; within a
+// group of steps the trailing A B A of a step and the leading one of the
+// next share a pass.  The
 // factors 1/2 of the eight transports are deferred to the local step (scale
 // 2^-8), so the stored intermediate states carry exact powers of two.
 // ---------------------------------------------------------------------------
@@ -365,6 +367,59 @@ __global__ __launch_bounds__(256) void k_strang3d_aba(const T* __restrict__ src,
   if (walls && !c.full && !c.inside) zero(b);
   x_transport_inner<T, 0>(b, o);
   if (c.inside && lane >= 2 && lane <= 61) store_site(dst + ((k * ny + j) * nx + c.x) * 8, o);
+}
+
+// A B A A B A on row j of plane k: the last three transports of one step and
+// the first three of the next, in one pass.  Rows j - 4, j and j + 4 give the
+// first A B A at rows j - 2 and j + 2, from which the second gives row j; a
+// wave holds 64 columns and writes the middle 56.
+template <typename T>
+__global__ __launch_bounds__(256) void k_strang3d_abaaba(const T* __restrict__ src,
+                                                         T* __restrict__ dst, SweepArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int64_t tile = int64_t(blockIdx.x) * 4 + wave_in_block();
+  if (tile >= a.ntiles) return;
+  const int64_t nx = a.nx, ny = a.ny;
+  const int64_t strip = tile % a.nstrips;
+  const int64_t rest = tile / a.nstrips;
+  const int64_t j = rest % ny, k = rest / ny;
+  const Lanes c = lanes_of(nx, a.periodic, strip * strip_width(4) - 4, lane);
+  const bool walls = !a.periodic;
+  const bool lanes_out = walls && !c.full && !c.inside;
+  auto load = [&](int64_t r, Site<T>& s) {
+    load_site(src + ((k * ny + wrap_or_clamp(r, ny, a.periodic)) * nx + c.col) * 8, s);
+    if (walls && (r < 0 || r >= ny || (!c.full && c.out))) zero(s);
+  };
+  auto A = [&](const Site<T>& in, Site<T>& out) {
+    x_transport_inner<T, 0>(in, out);
+    if (lanes_out) zero(out);
+  };
+  // B at a row from the transported rows below and above it
+  auto B = [&](const Site<T>& below, const Site<T>& above, Site<T>& out) {
+    Mov<T> r1, l1, r2, l2;
+    Axis<1, T>::movers(below, r1, l1);
+    Axis<1, T>::movers(above, r2, l2);
+    Axis<1, T>::combine(r1, l2, out);
+    if (lanes_out) zero(out);
+  };
+  Site<T> p0, p1, p2, a0, a1, a2, t, ylo, yhi, clo, chi, o;
+  load(j - 4, p0);
+  load(j, p1);
+  load(j + 4, p2);
+  A(p0, a0);
+  A(p1, a1);
+  A(p2, a2);
+  B(a0, a1, t);  // first A B A at row j - 2
+  A(t, ylo);
+  if (walls && (j - 2 < 0 || j - 2 >= ny)) zero(ylo);
+  B(a1, a2, t);  // first A B A at row j + 2
+  A(t, yhi);
+  if (walls && (j + 2 < 0 || j + 2 >= ny)) zero(yhi);
+  A(ylo, clo);
+  A(yhi, chi);
+  B(clo, chi, t);
+  x_transport_inner<T, 0>(t, o);
+  if (c.inside && lane >= 4 && lane <= 59) store_site(dst + ((k * ny + j) * nx + c.x) * 8, o);
 }
 
 // C D C on row j of plane k: planes k - 4, k and k + 4 give C at k - 2 and
@@ -419,44 +474,49 @@ __global__ __launch_bounds__(256) void k_strang3d_cdc(const T* __restrict__ src,
 
 template <typename T>
 static hipError_t strang3d_t(const void* src, void* dst, void* mid, const double* V,
-                             const SweepArgs& a0, hipStream_t st) {
-  SweepArgs a = a0;
+                             const SweepArgs& a, int64_t nsteps, hipStream_t st) {
   const T* s = static_cast<const T*>(src);
   T* d = static_cast<T*>(dst);
   T* m = static_cast<T*>(mid);
-  SweepArgs ab = a;
-  ab.nstrips = (a.nx + strip_width(2) - 1) / strip_width(2);
-  ab.ntiles = ab.nstrips * a.ny * a.nz;
-  SweepArgs cd = a;
-  cd.nstrips = (a.nx + 63) / 64;
-  cd.ntiles = cd.nstrips * a.ny * a.nz;
-  const int64_t bab = (ab.ntiles + 3) / 4, bcd = (cd.ntiles + 3) / 4;
-  if (bab > INT32_MAX || bcd > INT32_MAX) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_strang3d_aba<T>), dim3(static_cast<unsigned>(bab)), dim3(256), 0, st,
-                     s, d, ab);
-  switch (a.ph.mode) {
-    case 0:
-      hipLaunchKernelGGL((k_strang3d_cdc<T, 0>), dim3(static_cast<unsigned>(bcd)), dim3(256), 0,
-                         st, d, m, V, cd);
-      break;
-    case 1:
-      hipLaunchKernelGGL((k_strang3d_cdc<T, 1>), dim3(static_cast<unsigned>(bcd)), dim3(256), 0,
-                         st, d, m, V, cd);
-      break;
-    default:
-      hipLaunchKernelGGL((k_strang3d_cdc<T, 2>), dim3(static_cast<unsigned>(bcd)), dim3(256), 0,
-                         st, d, m, V, cd);
-      break;
+  auto plane_grid = [&](int width, SweepArgs& t) {
+    t = a;
+    t.nstrips = (a.nx + width - 1) / width;
+    t.ntiles = t.nstrips * a.ny * a.nz;
+    return (t.ntiles + 3) / 4;
+  };
+  SweepArgs ab, abab, cd;
+  const int64_t bab = plane_grid(strip_width(2), ab);
+  const int64_t babab = plane_grid(strip_width(4), abab);
+  const int64_t bcd = plane_grid(64, cd);
+  if (bab > INT32_MAX || babab > INT32_MAX || bcd > INT32_MAX) return hipErrorInvalidValue;
+  auto cdc = [&](const T* in, T* out) {
+    const dim3 g(static_cast<unsigned>(bcd));
+    switch (a.ph.mode) {
+      case 0: hipLaunchKernelGGL((k_strang3d_cdc<T, 0>), g, dim3(256), 0, st, in, out, V, cd); break;
+      case 1: hipLaunchKernelGGL((k_strang3d_cdc<T, 1>), g, dim3(256), 0, st, in, out, V, cd); break;
+      default: hipLaunchKernelGGL((k_strang3d_cdc<T, 2>), g, dim3(256), 0, st, in, out, V, cd); break;
+    }
+  };
+  // A B A, then C D C, and between two steps the trailing A B A of one and
+  // the leading A B A of the next in one pass: 2 nsteps + 1 passes
+  hipLaunchKernelGGL((k_strang3d_aba<T>), dim3(static_cast<unsigned>(bab)), dim3(256), 0, st, s,
+                     d, ab);
+  cdc(d, m);
+  for (int64_t n = 1; n < nsteps; ++n) {
+    hipLaunchKernelGGL((k_strang3d_abaaba<T>), dim3(static_cast<unsigned>(babab)), dim3(256), 0,
+                       st, m, d, abab);
+    cdc(d, m);
   }
-  hipLaunchKernelGGL((k_strang3d_aba<T>), dim3(static_cast<unsigned>(bab)), dim3(256), 0, st,
-                     m, d, ab);
+  hipLaunchKernelGGL((k_strang3d_aba<T>), dim3(static_cast<unsigned>(bab)), dim3(256), 0, st, m,
+                     d, ab);
   return hipGetLastError();
 }
 
 hipError_t launch_strang3d(bool fp64, const void* src, void* dst, void* mid, const double* V,
-                           const SweepArgs& a, hipStream_t st) {
-  return fp64 ? strang3d_t<double>(src, dst, mid, V, a, st)
-              : strang3d_t<float>(src, dst, mid, V, a, st);
+                           const SweepArgs& a, int64_t nsteps, hipStream_t st) {
+  if (nsteps < 1) return hipErrorInvalidValue;
+  return fp64 ? strang3d_t<double>(src, dst, mid, V, a, nsteps, st)
+              : strang3d_t<float>(src, dst, mid, V, a, nsteps, st);
 }
 
 // ---- 3-D kernels: one step, or a pass of two fused steps ---------------------

@@ -92,6 +92,8 @@ def test_dry_strang_plans(lib):
     assert code_of(lambda: dry((8, 8, 8), dt=2 * 0.01 / C, scheme="strang")) == L.DL_ERR_CFL
     for dtype in ("c64", "c128"):
         p = dry((8, 8, 8), dtype=dtype, dt=4 * 0.01 / C, scheme="strang")
+        assert p.info()["depth"] == 5  # steps grouped per launch sequence
+        p.set_depth(1)
         assert p.info()["depth"] == 1
         p.close()
     assert code_of(lambda: dry((64,), dt=4 * 0.01 / C, scheme="strang")) == L.DL_ERR_CFL

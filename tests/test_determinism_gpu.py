@@ -92,6 +92,22 @@ def test_fused_passes_same_bits(dtype, shape, axes, bc):
         assert same_bits(massless, gpu_step(psi, None, nsteps=9, depth=d, **{**kw, "m": 0.0}))
 
 
+@pytest.mark.parametrize("pairs", [2, 7, 32])
+def test_graph_replay_with_odd_pass_counts(pairs):
+    """A captured group of 2 * pairs steps that takes an odd number of passes
+    (4 steps: one pass of 4; 14: 5 + 5 + 4) ends in the plan's buffer; every
+    replay must still leave the state where the next one starts."""
+    announce(f"graph odd passes pairs={pairs}")
+    shape = (130, 70)
+    psi = random_spinor(shape[::-1], seed=14)
+    V = _V(shape, seed=15)
+    kw = dict(dx=DX, dt=DT, c=C, m=1.0, axes=(0, 1), dtype="c64")
+    n = 4 * pairs + 3
+    eager = gpu_step(psi, V, nsteps=n, **kw)
+    graph = gpu_step(psi, V, nsteps=n, graph=True, tiling={"graph_pairs": pairs}, **kw)
+    assert same_bits(eager, graph)
+
+
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
 @pytest.mark.parametrize("shape,axes,scheme", [((64, 48, 40), (0, 1, 2), "lie"),
                                                ((200, 150), (0, 2), "strang")])

@@ -111,6 +111,25 @@ def test_strang3d_vs_oracle(shape, bc):
     assert close(gpu_step(psi, None, m=1.0, nsteps=4, dtype="c128", **kw), refm, 1e-13)
 
 
+@pytest.mark.parametrize("shape", [(37, 21, 13), (64, 9, 10), (3, 6, 5)])
+@pytest.mark.parametrize("bc", ["zero", "periodic"])
+def test_strang3d_grouped_steps_same_bits(shape, bc):
+    """Steps grouped so that consecutive A B A share a pass give the bits of
+    single steps (three passes each), for counts that are and are not
+    multiples of the group."""
+    announce(f"strang 3-D grouped {shape} {bc}")
+    psi = random_spinor(shape[::-1], seed=8)
+    V = np.random.default_rng(9).uniform(-2, 2, size=shape[::-1]) * C * C
+    kw = dict(dx=DX, dt=DT3, c=C, m=1.0, axes=(0, 1, 2), bc=bc, scheme="strang")
+    for dtype in ("c64", "c128"):
+        p0 = psi.astype(np.complex64) if dtype == "c64" else psi
+        for n in (2, 3, 7):
+            single = gpu_step(p0, V, nsteps=n, depth=1, dtype=dtype, **kw)
+            for depth in (2, 5):
+                assert same_bits(single, gpu_step(p0, V, nsteps=n, depth=depth, dtype=dtype,
+                                                  **kw)), (dtype, n, depth)
+
+
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
 def test_strang3d_step_out_chain_and_graph(dtype):
     """n steps in one call, n single out-of-place steps and a graph replay give
