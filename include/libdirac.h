@@ -79,8 +79,8 @@ typedef enum { DL_BC_ZERO = 0, DL_BC_PERIODIC = 1 } dl_bc;
                         A(dt/4) B(dt/2) A(dt/4) with c*dt = 4*dx: A shifts one
                         cell, B and C two (three passes over memory per step,
                         one extra state buffer in the plan).  DL_ERR_CFL on any
-                        other c*dt.  The adjoint entry points and
-                        dl_step_field on 3-D grids refuse such a plan
+                        other c*dt.  The adjoint entry points, and
+                        dl_step_field on 3-D grids, refuse such a plan
                         (DL_ERR_ARG). */
 #define DL_BISPINOR 8u /* two-component state, 1-D grids only (Sec. 2.4): with
                         one transport axis the pair of components that contains
@@ -136,9 +136,10 @@ int dl_step(dl_plan p, void *psi, const double *V, int64_t nsteps, void *stream)
  * the field integral At = e int A dtau over one step (eq:field_dis1) at the
  * cell centres, each block in psi's cell order; held fixed for the nsteps
  * steps of the call (a time-dependent field is applied by calls over shorter
- * spans).  A = NULL is dl_step.  1-D and 2-D grids (DL_ERR_ARG on 3-D), both
- * splittings; passes fuse at most 3 steps (1 with DL_STRANG), with the bits
- * of single steps.  Same buffers and copy rule as dl_step. */
+ * spans).  A = NULL is dl_step.  1-D and 2-D grids, both splittings, passes
+ * of at most 3 steps (1 with DL_STRANG) with the bits of single steps; 3-D
+ * grids, lowest-order steps one per pass (DL_ERR_ARG for 3-D DL_STRANG
+ * plans).  Same buffers and copy rule as dl_step. */
 int dl_step_field(dl_plan p, void *psi, const double *V, const double *A, int64_t nsteps,
                   void *stream);
 

@@ -233,11 +233,16 @@ static int plan_tiling(dl_plan p) {
       while (depth > 1 && p->g.n[1] < 2 * stages_per_step * depth) --depth;
   }
   p->depth = depth;
-  p->depth_field = std::min(depth, field_max_depth(p->fp64, p->strang));
+  p->depth_field = (p->g.ndim == 3) ? 1 : std::min(depth, field_max_depth(p->fp64, p->strang));
   for (int mode = 0; mode < 4; ++mode) {
     PlanTiling& t = p->tiling[mode];
     if (p->g.ndim == 3) {
-      if (mode == 3) continue;  // no vector potential on 3-D grids
+      if (mode == 3) {  // with a vector potential: one step per pass
+        make_tiling3d(p->g, p->fp64 ? kTY3D_F64 : kTY3D_F32, 64, 2, resident_waves(p, 3, 1),
+                      p->seg_override, t.a[0], t.b[0]);
+        for (int d = 0; d < kMaxDepth; ++d) t.a[d].periodic = (p->bc == DL_BC_PERIODIC);
+        continue;
+      }
       make_tiling3d(p->g, p->fp64 ? kTY3D_F64 : kTY3D_F32, 64, 2, resident_waves(p, mode, 1),
                     p->seg_override, t.a[0], t.b[0]);
       if (depth >= 2)
@@ -393,6 +398,8 @@ hipError_t launch_pass(dl_plan p, int depth, const void* src, void* dst, const d
   if (p->g.ndim == 3) {
     SweepArgs a = p->sw[p->strang ? 0 : depth - 1];  // second-order passes size their own grids
     a.ph = p->ph;
+    a.At = p->field;
+    a.cells = p->cells;
     if (p->strang) return launch_strang3d(p->fp64, src, dst, p->tmp2, V, a, depth, st);
     return launch_sweep3d(p->fp64, depth, src, dst, V, a, p->bl[depth - 1], st);
   }
@@ -532,7 +539,8 @@ extern "C" int dl_step_field(dl_plan p, void* psi, const double* V, const double
   if ((rc = check_state_ptr(psi, "psi"))) return rc;
   if ((rc = check_f64_ptr(V, "V", true))) return rc;
   if ((rc = check_f64_ptr(A, "A", false))) return rc;
-  if (p->g.ndim > 2) return fail(DL_ERR_ARG, "the vector potential is built for 1-D and 2-D grids");
+  if (p->g.ndim == 3 && p->strang)
+    return fail(DL_ERR_ARG, "the 3-D second-order step carries no vector potential");
   if (p->nc != 4) return fail(DL_ERR_ARG, "a vector potential couples all four components");
   if (nsteps < 0) return fail(DL_ERR_ARG, "nsteps = %lld < 0", static_cast<long long>(nsteps));
   if (nsteps == 0) return DL_OK;

@@ -23,20 +23,29 @@ __device__ __forceinline__ void march3d(const T* __restrict__ src, T* __restrict
                                         int64_t x0, int lane, int64_t y0, int64_t kb,
                                         int64_t ke) {
   constexpr bool TWO = sizeof(T) == 8;
+  constexpr bool FIELD = MODE == 3;  // local step with a vector potential
+  using FT = typename FactorOf<MODE>::type;
   const int64_t nx = a.nx, ny = a.ny, nz = a.nz;
   const int64_t plane_cells = nx * ny;
   const int nit = static_cast<int>(ke - kb) + 2;
   const int64_t x = x0 + lane;
   const int64_t xv = x < nx ? x : nx - 1;
-  const bool read_v = (MODE == 2);
+  const bool read_v = (MODE == 2) || (FIELD && V != nullptr);
   auto kout_of = [&](int it) -> int64_t { return UP ? kb - 2 + it : ke - it + 1; };
-  auto load_v = [&](int it, double* v) {
+  // the potential (and field integrals) of the TY output rows of iteration it
+  auto load_v = [&](int it, double* v, double (*at)[3]) {
     int64_t k = kout_of(it);
     k = k < 0 ? 0 : (k >= nz ? nz - 1 : k);
 #pragma unroll
     for (int t = 0; t < TY; ++t) {
       const int64_t y = (y0 + t < ny) ? y0 + t : ny - 1;
-      v[t] = read_v ? V[(k * ny + y) * nx + xv] : 0.0;
+      const int64_t q = (k * ny + y) * nx + xv;
+      v[t] = read_v ? V[q] : 0.0;
+      if constexpr (FIELD) {
+        at[t][0] = a.At[q];
+        at[t][1] = a.At[a.cells + q];
+        at[t][2] = a.At[2 * a.cells + q];
+      }
     }
   };
   Mov<T> zs1[TY], zs2[TY];
@@ -45,8 +54,8 @@ __device__ __forceinline__ void march3d(const T* __restrict__ src, T* __restrict
     zero(zs1[t]);
     zero(zs2[t]);
   }
-  double vcur[TY];
-  load_v(0, vcur);
+  double vcur[TY], acur[TY][3];
+  load_v(0, vcur, acur);
   for (int it = 0; it < nit; ++it) {
     const int64_t kin = UP ? kb - 1 + it : ke - it;
     const int64_t kout = kout_of(it);
@@ -62,13 +71,21 @@ __device__ __forceinline__ void march3d(const T* __restrict__ src, T* __restrict
         zero(rows[t].h);
       }
     }
-    double vnext[TY];
-    load_v(it + 1, vnext);
-    Factors fac[TY];
+    double vnext[TY], anext[TY][3];
+    load_v(it + 1, vnext, anext);
+    FT fac[TY];
+    if constexpr (FIELD) {
 #pragma unroll
-    for (int t = 0; t < TY; ++t) fac[t] = factors_of<MODE, TWO>(vcur[t], a.ph);
+      for (int t = 0; t < TY; ++t) {
+        fac[t] = field_factors<TWO, false>(vcur[t], acur[t][0], acur[t][1], acur[t][2], a.ph);
+        field_fix<TWO>(fac[t], vcur[t], acur[t][0], acur[t][1], acur[t][2], a.ph);
+      }
+    } else {
 #pragma unroll
-    for (int t = 0; t < TY; ++t) factors_fix<MODE, TWO>(fac[t], vcur[t], a.ph);
+      for (int t = 0; t < TY; ++t) fac[t] = factors_of<MODE, TWO>(vcur[t], a.ph);
+#pragma unroll
+      for (int t = 0; t < TY; ++t) factors_fix<MODE, TWO>(fac[t], vcur[t], a.ph);
+    }
     // x transport of every row, y transport rolling over the rows
     Mov<T> ry1, ry2;
     zero(ry1);
@@ -91,7 +108,10 @@ __device__ __forceinline__ void march3d(const T* __restrict__ src, T* __restrict
             Axis<2, T>::combine(zs2[ty], lz, o);
           else
             Axis<2, T>::combine(rz, zs2[ty], o);
-          apply_local<MODE>(o, fac[ty], a.ph);
+          if constexpr (FIELD)
+            apply_field(o, fac[ty]);
+          else
+            apply_local<MODE>(o, fac[ty], a.ph);
           const int64_t y = y0 + ty;
           if (x < nx && y < ny) store_site(dst + ((kout * ny + y) * nx + x) * 8, o);
         }
@@ -102,7 +122,14 @@ __device__ __forceinline__ void march3d(const T* __restrict__ src, T* __restrict
       ry1 = ry;
     }
 #pragma unroll
-    for (int t = 0; t < TY; ++t) vcur[t] = vnext[t];
+    for (int t = 0; t < TY; ++t) {
+      vcur[t] = vnext[t];
+      if constexpr (FIELD) {
+        acur[t][0] = anext[t][0];
+        acur[t][1] = anext[t][1];
+        acur[t][2] = anext[t][2];
+      }
+    }
   }
 }
 
@@ -524,19 +551,22 @@ template <typename T>
 static const void* kernel3d(int depth, int mode) {
   constexpr bool F64 = sizeof(T) == 8;
   constexpr int TY1 = F64 ? kTY3D_F64 : kTY3D_F32;
-  if (depth == 2) {
+  if (depth == 2) {  // phase modes 0 to 2
     constexpr int TY2 = F64 ? kTY3D2_F64 : kTY3D2_F32;
     switch (mode) {
       case 0: return reinterpret_cast<const void*>(&k_sweep3d_x2<T, TY2, 0>);
       case 1: return reinterpret_cast<const void*>(&k_sweep3d_x2<T, TY2, 1>);
-      default: return reinterpret_cast<const void*>(&k_sweep3d_x2<T, TY2, 2>);
+      case 2: return reinterpret_cast<const void*>(&k_sweep3d_x2<T, TY2, 2>);
+      default: return nullptr;
     }
   }
   if (depth != 1) return nullptr;
   switch (mode) {
     case 0: return reinterpret_cast<const void*>(&k_sweep3d<T, TY1, 0>);
     case 1: return reinterpret_cast<const void*>(&k_sweep3d<T, TY1, 1>);
-    default: return reinterpret_cast<const void*>(&k_sweep3d<T, TY1, 2>);
+    case 2: return reinterpret_cast<const void*>(&k_sweep3d<T, TY1, 2>);
+    case 3: return reinterpret_cast<const void*>(&k_sweep3d<T, TY1, 3>);
+    default: return nullptr;
   }
 }
 
@@ -551,13 +581,13 @@ static int occ_of(const void* kernel) {
 }
 
 int occupancy3d(bool fp64, int mode, int depth) {
-  const int m = mode < 0 || mode > 2 ? 2 : mode;
+  const int m = mode < 0 || mode > 3 ? 2 : mode;
   return occ_of(fp64 ? kernel3d<double>(depth, m) : kernel3d<float>(depth, m));
 }
 
 hipError_t launch_sweep3d(bool fp64, int depth, const void* src, void* dst, const double* V,
                           const SweepArgs& a, int blocks, hipStream_t st) {
-  const int m = a.ph.mode < 0 || a.ph.mode > 2 ? 2 : a.ph.mode;
+  const int m = a.ph.mode < 0 || a.ph.mode > 3 ? 2 : a.ph.mode;
   const void* fn = fp64 ? kernel3d<double>(depth, m) : kernel3d<float>(depth, m);
   if (!fn || blocks <= 0) return hipErrorInvalidValue;
   SweepArgs args = a;
