@@ -389,11 +389,34 @@ def bench_3d(args):
     runs = (("f32", torch.complex64, BYTES_F32, None), ("f32_one_step_per_pass", torch.complex64,
                                                         BYTES_F32, 1),
             ("f64", torch.complex128, BYTES_F64, None),
-            ("f32_second_order", torch.complex64, None, None))
+            ("f32_second_order", torch.complex64, None, None),
+            ("f32_vector_potential", torch.complex64, None, None))
     for dt_name, tdt, bps, depth in runs:
         f = (gz[:, None, None] * gy[None, :, None] * gx[None, None, :])
         psi = (f[..., None] * u).to(tdt).contiguous()
         del f
+        if dt_name.endswith("vector_potential"):
+            # a smooth static field integral along y, one step per pass
+            At = torch.zeros((3, n, n, n), dtype=torch.float64, device="cuda")
+            At[1] = (0.05 * torch.sin(2 * np.pi * x / 5.0))[None, None, :]
+            with L.Plan((n, n, n), dx, dx / c, c, m, dtype="complex64") as p:
+                p.step_field(psi, V, At, 2)
+                torch.cuda.synchronize()
+                s_, e_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                nf = min(steps, 10)
+                s_.record()
+                p.step_field(psi, V, At, nf)
+                e_.record()
+                torch.cuda.synchronize()
+                msf = s_.elapsed_time(e_) / nf
+            # psi read + written (64 B), V (8 B), At (24 B) per cell and step
+            out[dt_name] = {"steps": nf, "ms_per_step": msf, "steps_per_pass": 1,
+                            "site_updates_per_s": n ** 3 / (msf * 1e-3),
+                            "hbm_frac": 96 * n ** 3 / (msf * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            log(f"3-D 512^3 {dt_name}: {msf:.3f} ms/step")
+            del psi, At
+            torch.cuda.empty_cache()
+            continue
         strang = dt_name.endswith("second_order")
         if strang:
             # c dt = 4 dx: three passes per step, and four times the time per step
