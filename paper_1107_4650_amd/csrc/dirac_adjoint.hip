@@ -442,6 +442,159 @@ static int rev_occ(bool fp64, int depth, int axes_code) {
   return n;
 }
 
+// ---------------------------------------------------------------------------
+// 3-D reverse step, two passes.  The first adds the step's term to dL/dV at
+// every cell, applies D^H at the planes k - 1 and k + 1 and completes T_z^H at
+// plane k (right movers from k + 1, left movers from k - 1); the second
+// applies T_y^H and then T_x^H within the plane (62 columns per wave).
+// ---------------------------------------------------------------------------
+struct Rev3Args {
+  int64_t nx, ny, nz;
+  int periodic;
+  int64_t nstrips, ntiles;
+  double qscale;
+  PhaseK ph;
+};
+
+__device__ __forceinline__ int64_t rev_wrap(int64_t r, int64_t n, int periodic) {
+  if (periodic) return ((r % n) + n) % n;
+  return r < 0 ? 0 : (r >= n ? n - 1 : r);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_reverse3d_z(T* __restrict__ psi_out,
+                                                     T* __restrict__ lam_out,
+                                                     const T* __restrict__ psi,
+                                                     const T* __restrict__ lam,
+                                                     const double* __restrict__ V,
+                                                     double* __restrict__ Q, Rev3Args a) {
+  const int lane = threadIdx.x & 63;
+  const int64_t tile = int64_t(blockIdx.x) * 4 + wave_in_block();
+  if (tile >= a.ntiles) return;
+  const int64_t nx = a.nx, ny = a.ny, nz = a.nz;
+  const int64_t strip = tile % a.nstrips;
+  const int64_t rest = tile / a.nstrips;
+  const int64_t j = rest % ny, k = rest / ny;
+  const int64_t x = strip * 64 + lane;
+  const int64_t col = x < nx ? x : nx - 1;
+  const bool walls = !a.periodic;
+  auto cell = [&](int64_t p) { return (rev_wrap(p, nz, a.periodic) * ny + j) * nx + col; };
+  // the step's term of dL/dV at the input time level
+  const int64_t q = (k * ny + j) * nx + col;
+  Site<T> p0, l0;
+  load_site(psi + q * 8, p0);
+  load_site(lam + q * 8, l0);
+  const double qn = fma(a.qscale, im_dot(l0, p0), Q[q]);
+  // D^H at the neighbouring planes, then T_z^H
+  Site<T> pm, lm, pp, lp;
+  const int64_t qm = cell(k - 1), qp = cell(k + 1);
+  load_site(psi + qm * 8, pm);
+  load_site(lam + qm * 8, lm);
+  load_site(psi + qp * 8, pp);
+  load_site(lam + qp * 8, lp);
+  const bool read_v = (a.ph.mode == 2);
+  const Factors fm = adjoint_factors<sizeof(T) == 8>(read_v ? V[qm] : 0.0, a.ph);
+  const Factors fp = adjoint_factors<sizeof(T) == 8>(read_v ? V[qp] : 0.0, a.ph);
+  adjoint_local(pm, fm, a.ph);
+  adjoint_local(lm, fm, a.ph);
+  adjoint_local(pp, fp, a.ph);
+  adjoint_local(lp, fp, a.ph);
+  if (walls && k - 1 < 0) {
+    zero(pm);
+    zero(lm);
+  }
+  if (walls && k + 1 >= nz) {
+    zero(pp);
+    zero(lp);
+  }
+  Mov<T> rpm, lpm, rpp, lpp, rlm, llm, rlp, llp;
+  Axis<2, T>::movers(pm, rpm, lpm);
+  Axis<2, T>::movers(pp, rpp, lpp);
+  Axis<2, T>::movers(lm, rlm, llm);
+  Axis<2, T>::movers(lp, rlp, llp);
+  Site<T> op, ol;
+  Axis<2, T>::combine(rpp, lpm, op);
+  Axis<2, T>::combine(rlp, llm, ol);
+  if (x < nx) {
+    Q[q] = qn;
+    store_site(psi_out + q * 8, op);
+    store_site(lam_out + q * 8, ol);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_reverse3d_xy(T* __restrict__ psi_out,
+                                                      T* __restrict__ lam_out,
+                                                      const T* __restrict__ psi,
+                                                      const T* __restrict__ lam, Rev3Args a) {
+  const int lane = threadIdx.x & 63;
+  const int64_t tile = int64_t(blockIdx.x) * 4 + wave_in_block();
+  if (tile >= a.ntiles) return;
+  const int64_t nx = a.nx, ny = a.ny;
+  const int64_t strip = tile % a.nstrips;
+  const int64_t rest = tile / a.nstrips;
+  const int64_t j = rest % ny, k = rest / ny;
+  const Lanes c = lanes_of(nx, a.periodic, strip * strip_width(1) - 1, lane);
+  const bool walls = !a.periodic;
+  auto load = [&](const T* f, int64_t r, Site<T>& s) {
+    load_site(f + ((k * ny + rev_wrap(r, ny, a.periodic)) * nx + c.col) * 8, s);
+    if (walls && (r < 0 || r >= ny || (!c.full && c.out))) zero(s);
+  };
+  Site<T> pd, pu, ld, lu;
+  load(psi, j - 1, pd);
+  load(psi, j + 1, pu);
+  load(lam, j - 1, ld);
+  load(lam, j + 1, lu);
+  // T_y^H: right movers from row j + 1, left movers from row j - 1
+  Mov<T> r1, l1, r2, l2;
+  Site<T> yp, yl, op, ol;
+  Axis<1, T>::movers(pd, r1, l1);
+  Axis<1, T>::movers(pu, r2, l2);
+  Axis<1, T>::combine(r2, l1, yp);
+  Axis<1, T>::movers(ld, r1, l1);
+  Axis<1, T>::movers(lu, r2, l2);
+  Axis<1, T>::combine(r2, l1, yl);
+  if (walls && !c.full && !c.inside) {
+    zero(yp);
+    zero(yl);
+  }
+  x_transport_adj<T, 0>(yp, op);
+  x_transport_adj<T, 0>(yl, ol);
+  if (c.inside && lane >= 1 && lane <= 62) {
+    const int64_t off = ((k * ny + j) * nx + c.x) * 8;
+    store_site(psi_out + off, op);
+    store_site(lam_out + off, ol);
+  }
+}
+
+// one reverse step on a 3-D grid: (pi, li) -> (pb, lb) -> (pi, li)
+static hipError_t launch_rev3d(bool fp64, void* pi, void* li, void* pb, void* lb,
+                               const double* V, double* Q, Rev3Args a, hipStream_t st) {
+  Rev3Args az = a, axy = a;
+  az.nstrips = (a.nx + 63) / 64;
+  az.ntiles = az.nstrips * a.ny * a.nz;
+  axy.nstrips = (a.nx + strip_width(1) - 1) / strip_width(1);
+  axy.ntiles = axy.nstrips * a.ny * a.nz;
+  const int64_t bz = (az.ntiles + 3) / 4, bxy = (axy.ntiles + 3) / 4;
+  if (bz > INT32_MAX || bxy > INT32_MAX) return hipErrorInvalidValue;
+  if (fp64) {
+    hipLaunchKernelGGL(k_reverse3d_z<double>, dim3(static_cast<unsigned>(bz)), dim3(256), 0, st,
+                       static_cast<double*>(pb), static_cast<double*>(lb),
+                       static_cast<const double*>(pi), static_cast<const double*>(li), V, Q, az);
+    hipLaunchKernelGGL(k_reverse3d_xy<double>, dim3(static_cast<unsigned>(bxy)), dim3(256), 0,
+                       st, static_cast<double*>(pi), static_cast<double*>(li),
+                       static_cast<const double*>(pb), static_cast<const double*>(lb), axy);
+  } else {
+    hipLaunchKernelGGL(k_reverse3d_z<float>, dim3(static_cast<unsigned>(bz)), dim3(256), 0, st,
+                       static_cast<float*>(pb), static_cast<float*>(lb),
+                       static_cast<const float*>(pi), static_cast<const float*>(li), V, Q, az);
+    hipLaunchKernelGGL(k_reverse3d_xy<float>, dim3(static_cast<unsigned>(bxy)), dim3(256), 0, st,
+                       static_cast<float*>(pi), static_cast<float*>(li),
+                       static_cast<const float*>(pb), static_cast<const float*>(lb), axy);
+  }
+  return hipGetLastError();
+}
+
 }  // namespace dirac
 
 using namespace dirac;
@@ -497,7 +650,6 @@ static void rev_tiling(dl_plan p, int depth, RevArgs& a, int& blocks) {
 static int check_adjoint_plan(dl_plan p) {
   int rc = check_live(p);
   if (rc) return rc;
-  if (p->g.ndim > 2) return set_error(DL_ERR_ARG, "the adjoint supports 1-D and 2-D grids");
   if (p->strang) return set_error(DL_ERR_ARG, "the adjoint is built for lowest-order steps only");
   if (p->nc != 4) return set_error(DL_ERR_ARG, "the adjoint is built for four-component states");
   return DL_OK;
@@ -544,8 +696,22 @@ extern "C" int dl_grad_step(dl_plan p, void* psi, void* lam, const double* V, do
       return set_error(DL_ERR_NOMEM, "allocation of the second adjoint buffer failed");
     }
   }
-  const int dmax = reverse_depth(p);
   const PhaseK ph = make_phase(p->g.ndim, p->dt, p->c, p->m, phase_mode(p->m, V), p->fp64);
+  if (p->g.ndim == 3) {  // two passes per reverse step, ending in psi and lam
+    Rev3Args a{};
+    a.nx = p->g.n[0];
+    a.ny = p->g.n[1];
+    a.nz = p->g.n[2];
+    a.periodic = (p->bc == DL_BC_PERIODIC);
+    a.qscale = 2.0 * p->dt * p->dx * p->dx * p->dx;
+    a.ph = ph;
+    for (int64_t s = 0; s < nsteps; ++s) {
+      hipError_t e = launch_rev3d(p->fp64, psi, lam, p->tmp, p->tmp2, V, Q, a, st);
+      if (e != hipSuccess) return set_hip_error(e, "reverse sweep launch");
+    }
+    return DL_OK;
+  }
+  const int dmax = reverse_depth(p);
   void* pa = psi;
   void* la = lam;
   void* pb = p->tmp;
