@@ -118,7 +118,7 @@ template <typename T> struct RevIn {
 // as stored steps are, so a pass gives the bits of K single reverse steps.
 // ---------------------------------------------------------------------------
 
-template <typename T, int K, int AX0, int AX1, bool UP>
+template <typename T, int K, int AX0, int AX1, bool UP, bool EDGE>
 __device__ __forceinline__ void rev_march(T* __restrict__ psi_out, T* __restrict__ lam_out,
                                           const T* __restrict__ psi, const T* __restrict__ lam,
                                           const double* __restrict__ V, double* __restrict__ Q,
@@ -130,8 +130,19 @@ __device__ __forceinline__ void rev_march(T* __restrict__ psi_out, T* __restrict
   const bool zero_walls = !a.periodic;
   const bool read_v = (a.ph.mode == 2);
   auto in_row = [&](int it) -> int64_t { return UP ? jb - K + it : je - 1 + K - it; };
+  // row in_row(it) -+ s lies in the box iff lo <= it - s < hi: wave-uniform
+  // bounds clamped to 32 bits (it - s spans -K .. nit + L), so the wall tests
+  // of the loop are scalar compares
+  auto clamp_it = [&](int64_t e) -> int {
+    return static_cast<int>(e < -64 ? -64 : (e > nit + 64 ? nit + 64 : e));
+  };
+  const int64_t lo64 = UP ? K - jb : je + K - ny;
+  const int lo = clamp_it(lo64), hi = clamp_it(lo64 + ny);
+  auto row_in = [&](int e) -> bool { return e >= lo && e < hi; };
   auto load = [&](int it, RevIn<T>& R) {
-    const int64_t q = read_row(in_row(it), ny, a.periodic) * nx + c.col;
+    int64_t r = in_row(it);
+    if (!row_in(it)) r = read_row(r, ny, a.periodic);
+    const int64_t q = r * nx + c.col;
     load_site(psi + q * 8, R.p);
     load_site(lam + q * 8, R.l);
     R.v = read_v ? V[q] : 0.0;
@@ -161,7 +172,11 @@ __device__ __forceinline__ void rev_march(T* __restrict__ psi_out, T* __restrict
       load(it + L, ring[k % L]);  // rows past the segment are read and dropped
       const int64_t jin = in_row(it);
       if (zero_walls) {
-        if (jin < 0 || jin >= ny || (!c.full && c.out)) {
+        if (!row_in(it)) {
+          zero(cur.p);
+          zero(cur.l);
+        }
+        if (EDGE && !c.full && c.out) {
           zero(cur.p);
           zero(cur.l);
         }
@@ -196,12 +211,16 @@ __device__ __forceinline__ void rev_march(T* __restrict__ psi_out, T* __restrict
         }
         mp[s - 1][k % 2] = UP ? lp : rp;
         ml[s - 1][k % 2] = UP ? ll : rl;
-        const int64_t jo = UP ? j - 1 : j + 1;  // output row of stage s
+        const int64_t jo = UP ? j - 1 : j + 1;  // output row of stage s: in_row(it) -+ s
         x_transport_adj<T, AX0>(yp, p);
         x_transport_adj<T, AX0>(yl, l);
         if (s < K) {
           if (zero_walls) {
-            if (jo < 0 || jo >= ny || (!c.full && !c.inside)) {
+            if (!row_in(it - s)) {
+              zero(p);
+              zero(l);
+            }
+            if (EDGE && !c.full && !c.inside) {
               zero(p);
               zero(l);
             }
@@ -212,8 +231,9 @@ __device__ __forceinline__ void rev_march(T* __restrict__ psi_out, T* __restrict
             store_site(psi_out + off, p);
             store_site(lam_out + off, l);
           }
-          // the last stage has added its term to row j
-          if (own && j >= jb && j < je) Q[j * nx + c.col] = qa[slot];
+          // the last stage has added its term to row j, which lies in the
+          // segment [jb, je) exactly for 2K - 1 <= it < nit - 1
+          if (own && it >= 2 * K - 1 && it < nit - 1) Q[j * nx + c.col] = qa[slot];
         }
       }
     }
@@ -281,10 +301,22 @@ __global__ __launch_bounds__(256, rev_min_blocks(sizeof(T) == 8, K)) void k_reve
   } else {
     const int64_t jb = seg * a.H;
     const int64_t je = (jb + a.H < a.ny) ? jb + a.H : a.ny;
-    if (seg & 1)
-      rev_march<T, K, AX0, AX1, false>(psi_out, lam_out, psi, lam, V, Q, a, c, own, jb, je);
-    else
-      rev_march<T, K, AX0, AX1, true>(psi_out, lam_out, psi, lam, V, Q, a, c, own, jb, je);
+    // FP32: waves with a lane beyond a zero wall run a variant that zeroes
+    // those lanes at every stage, the others one without that work; FP64
+    // keeps one variant per direction (its code is twice as long)
+    if (sizeof(T) == 8 || !c.full) {
+      if (seg & 1)
+        rev_march<T, K, AX0, AX1, false, true>(psi_out, lam_out, psi, lam, V, Q, a, c, own, jb, je);
+      else
+        rev_march<T, K, AX0, AX1, true, true>(psi_out, lam_out, psi, lam, V, Q, a, c, own, jb, je);
+    } else {
+      if (seg & 1)
+        rev_march<T, K, AX0, AX1, false, false>(psi_out, lam_out, psi, lam, V, Q, a, c, own, jb,
+                                                je);
+      else
+        rev_march<T, K, AX0, AX1, true, false>(psi_out, lam_out, psi, lam, V, Q, a, c, own, jb,
+                                               je);
+    }
   }
 }
 

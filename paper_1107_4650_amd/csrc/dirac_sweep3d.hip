@@ -170,7 +170,7 @@ __global__ __launch_bounds__(256) void k_sweep3d(const T* __restrict__ src, T* _
 // Intermediate states are rounded as stored steps and zeroed outside the box
 // with zero walls, so the pass gives the bits of two single steps.
 // ---------------------------------------------------------------------------
-template <typename T, int TY, bool UP, int MODE>
+template <typename T, int TY, bool UP, int MODE, bool EDGE>
 __device__ __forceinline__ void march3d_x2(const T* __restrict__ src, T* __restrict__ dst,
                                            const double* __restrict__ V, const SweepArgs& a,
                                            int64_t xs, int lane, int64_t y0, int64_t kb,
@@ -194,9 +194,20 @@ __device__ __forceinline__ void march3d_x2(const T* __restrict__ src, T* __restr
   auto plane_of = [&](int it, int st) -> int64_t {
     return UP ? in_plane(it) - st : in_plane(it) + st;
   };
-  auto out_of_box = [&](int64_t k, int64_t y) -> bool {
-    return k < 0 || k >= nz || y < 0 || y >= ny;
+  // wall tests as wave-uniform 32-bit compares: plane plane_of(it, st) lies
+  // in the box iff klo <= it - st < khi (it - st spans -K .. nit), and bit t
+  // of ymask says whether row y0 - 2 + t does
+  auto clamp_it = [&](int64_t e) -> int {
+    return static_cast<int>(e < -64 ? -64 : (e > nit + 64 ? nit + 64 : e));
   };
+  const int64_t klo64 = UP ? K - kb : ke + K - nz;
+  const int klo = clamp_it(klo64), khi = clamp_it(klo64 + nz);
+  auto plane_in = [&](int e) -> bool { return e >= klo && e < khi; };
+  uint32_t ymask = 0;
+#pragma unroll
+  for (int t = 0; t < R0; ++t)
+    if (y0 - 2 + t >= 0 && y0 - 2 + t < ny) ymask |= 1u << t;
+  ymask = __builtin_amdgcn_readfirstlane(ymask);
   // input rows of iteration it (slot it % 2) and the V of its first-step rows;
   // the plane of iteration it + 1 is loaded while iteration it computes
   Site<T> buf[2][R0];
@@ -235,8 +246,7 @@ __device__ __forceinline__ void march3d_x2(const T* __restrict__ src, T* __restr
     for (int k = 0; k < 2; ++k) {
       const int it = 2 * pair + k;
       if (it >= nit) return;
-      const int64_t kin = in_plane(it);
-      const int64_t k1 = plane_of(it, 1), k2 = plane_of(it, 2);
+      const int64_t k2 = plane_of(it, 2);
       load_plane(it + 1, buf[k ^ 1], vb[k ^ 1]);
       Factors pend{};  // factors of the previous first-step row
       // streaming over rows: first step (y movers of two rows back), then second
@@ -249,8 +259,8 @@ __device__ __forceinline__ void march3d_x2(const T* __restrict__ src, T* __restr
       for (int t = 0; t < R0; ++t) {
         Site<T> in = buf[k][t];
         if (zero_walls) {
-          if (out_of_box(kin, y0 - 2 + t)) zero(in);
-          if (!c.full && c.out) zero(in);
+          if (!plane_in(it) || !((ymask >> t) & 1u)) zero(in);
+          if (EDGE && c.out) zero(in);
         }
         Site<T> phi;
         x_transport_inner<T, 0>(in, phi);
@@ -272,8 +282,8 @@ __device__ __forceinline__ void march3d_x2(const T* __restrict__ src, T* __restr
           factors_fix<MODE, TWO>(f1, vb[k][u], a.ph);
           apply_local<MODE>(o1, f1, a.ph);
           if (zero_walls) {
-            if (out_of_box(k1, y0 - 1 + u)) zero(o1);
-            if (!c.full && !c.inside) zero(o1);
+            if (!plane_in(it - 1) || !((ymask >> (u + 1)) & 1u)) zero(o1);
+            if (EDGE && !c.inside) zero(o1);
           }
           // second step on first-step row u
           Site<T> phi2;
@@ -335,10 +345,20 @@ __global__ __launch_bounds__(256, kMinBlocks3D2) void k_sweep3d_x2(const T* __re
   const int64_t xs = strip * strip_width(2) - 2, y0 = yblk * TY;
   const int64_t kb = seg * a.H;
   const int64_t ke = (kb + a.H < a.nz) ? kb + a.H : a.nz;
-  if (seg & 1)
-    march3d_x2<T, TY, false, MODE>(src, dst, V, a, xs, lane, y0, kb, ke);
-  else
-    march3d_x2<T, TY, true, MODE>(src, dst, V, a, xs, lane, y0, kb, ke);
+  // waves with a lane beyond a zero wall zero those lanes at every step;
+  // the others skip that work
+  const bool edge = !lanes_of(a.nx, a.periodic, xs, 0).full;
+  if (edge) {
+    if (seg & 1)
+      march3d_x2<T, TY, false, MODE, true>(src, dst, V, a, xs, lane, y0, kb, ke);
+    else
+      march3d_x2<T, TY, true, MODE, true>(src, dst, V, a, xs, lane, y0, kb, ke);
+  } else {
+    if (seg & 1)
+      march3d_x2<T, TY, false, MODE, false>(src, dst, V, a, xs, lane, y0, kb, ke);
+    else
+      march3d_x2<T, TY, true, MODE, false>(src, dst, V, a, xs, lane, y0, kb, ke);
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -213,7 +213,7 @@ template <class S> constexpr int factor_slots(int NS) {
   return last + 2;
 }
 
-template <typename T, class S, int K, int AX0, int AX1, bool UP, int MODE>
+template <typename T, class S, int K, int AX0, int AX1, bool UP, int MODE, bool EDGE>
 __device__ __forceinline__ void march2d(const T* __restrict__ src, T* __restrict__ dst,
                                         const double* __restrict__ V, const SweepArgs& a,
                                         int64_t xs, int lane, int64_t jb, int64_t je,
@@ -239,8 +239,18 @@ __device__ __forceinline__ void march2d(const T* __restrict__ src, T* __restrict
   auto out_row = [&](int it, int done) -> int64_t {
     return UP ? in_row(it) - done : in_row(it) + done;
   };
+  // Row out_row(it, d) lies in the box iff lo <= it - d < hi.  The bounds
+  // are wave-uniform and clamped to 32 bits (it - d spans -NS .. nit + L), so
+  // the wall tests of the loop are scalar compares.
+  auto clamp_it = [&](int64_t e) -> int {
+    return static_cast<int>(e < -64 ? -64 : (e > nit + 64 ? nit + 64 : e));
+  };
+  const int64_t lo64 = UP ? NS - jb : je + NS - ny;
+  const int lo = clamp_it(lo64), hi = clamp_it(lo64 + ny);
+  auto row_in = [&](int e) -> bool { return e >= lo && e < hi; };
   auto load_in = [&](int it, Site<T>& m, double& v, double* at) {
-    const int64_t r = read_row(in_row(it), ny, a.periodic);
+    int64_t r = in_row(it);
+    if (!row_in(it)) r = read_row(r, ny, a.periodic);
     load_site(src + (r * nx + c.col) * 8, m);
     v = read_v ? V[r * nx + c.col] : 0.0;
     if constexpr (FIELD) {
@@ -292,9 +302,8 @@ __device__ __forceinline__ void march2d(const T* __restrict__ src, T* __restrict
       }
       load_in(it + L, ring[(k + L) % RS], vr[(k + L) % RS], ar[(k + L) % RS]);
       if (zero_walls) {  // cells beyond a wall read as zero
-        const int64_t r = in_row(it);
-        if (r < 0 || r >= ny) zero(cur);
-        if (!c.full && c.out) zero(cur);
+        if (!row_in(it)) zero(cur);
+        if (EDGE && !c.full && c.out) zero(cur);
       }
       FT& fnew = f[k % P];
       if constexpr (FIELD)
@@ -328,9 +337,8 @@ __device__ __forceinline__ void march2d(const T* __restrict__ src, T* __restrict
           o = phi;
         }
         if (st < NS - 1 && zero_walls) {
-          const int64_t r = out_row(it, st + 1);
-          if (r < 0 || r >= ny) zero(o);
-          if (!c.full && !c.inside) zero(o);
+          if (!row_in(it - st - 1)) zero(o);
+          if (EDGE && !c.full && !c.inside) zero(o);
         }
         cur = o;
       }
@@ -395,16 +403,29 @@ __device__ __forceinline__ void one_row(const T* __restrict__ src, T* __restrict
 }
 
 // march a 2-D segment upwards (up = true) or downwards, writing lanes
-// wlane .. 63 - wlane (wlane >= the pass's x transports)
+// wlane .. 63 - wlane (wlane >= the pass's x transports).  With FP32 state,
+// waves with a lane beyond a zero wall run a variant that zeroes those lanes
+// at every stage and the others (nearly all) one without that work.  FP64
+// marches keep one variant per direction that tests at run time: their code
+// is twice as long and two more variants would crowd the instruction cache.
 template <typename T, class S, int K, int AX0, int AX1, int MODE>
 __device__ __forceinline__ void march_dir(const T* __restrict__ src, T* __restrict__ dst,
                                           const double* __restrict__ V, const SweepArgs& a,
                                           int64_t xs, int lane, int64_t jb, int64_t je, bool up,
                                           int wlane) {
-  if (up)
-    march2d<T, S, K, AX0, AX1, true, MODE>(src, dst, V, a, xs, lane, jb, je, wlane);
-  else
-    march2d<T, S, K, AX0, AX1, false, MODE>(src, dst, V, a, xs, lane, jb, je, wlane);
+  // wave-uniform
+  const bool edge = sizeof(T) == 8 || !lanes_of(a.nx, a.periodic, xs, 0).full;
+  if (edge) {
+    if (up)
+      march2d<T, S, K, AX0, AX1, true, MODE, true>(src, dst, V, a, xs, lane, jb, je, wlane);
+    else
+      march2d<T, S, K, AX0, AX1, false, MODE, true>(src, dst, V, a, xs, lane, jb, je, wlane);
+  } else {
+    if (up)
+      march2d<T, S, K, AX0, AX1, true, MODE, false>(src, dst, V, a, xs, lane, jb, je, wlane);
+    else
+      march2d<T, S, K, AX0, AX1, false, MODE, false>(src, dst, V, a, xs, lane, jb, je, wlane);
+  }
 }
 
 }  // namespace dirac
