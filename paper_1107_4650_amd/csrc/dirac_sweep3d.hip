@@ -416,10 +416,31 @@ __global__ __launch_bounds__(256) void k_strang3d_aba(const T* __restrict__ src,
   if (c.inside && lane >= 2 && lane <= 61) store_site(dst + ((k * ny + j) * nx + c.x) * 8, o);
 }
 
-// A B A A B A on row j of plane k: the last three transports of one step and
-// the first three of the next, in one pass.  Rows j - 4, j and j + 4 give the
-// first A B A at rows j - 2 and j + 2, from which the second gives row j; a
-// wave holds 64 columns and writes the middle 56.
+// waves a Strang march grid aims for: sixteen per SIMD, in about four rounds
+// of the waves one SIMD holds at once, so that the last round is short
+constexpr int64_t kMarchWaves = 16384;
+
+// Wall test of a march: position kb - 4 + it (rows or planes) lies in [0, n)
+// iff lo <= it < hi, with lo, hi clamped to 32 bits (it spans 0 .. nit).
+struct MarchBounds {
+  int lo, hi;
+  __device__ MarchBounds(int64_t kb, int64_t n, int nit) {
+    auto clamp_it = [&](int64_t e) -> int {
+      return static_cast<int>(e < -64 ? -64 : (e > nit + 64 ? nit + 64 : e));
+    };
+    lo = clamp_it(4 - kb);
+    hi = clamp_it(4 - kb + n);
+  }
+  __device__ bool in(int it) const { return it >= lo && it < hi; }
+};
+
+// A B A A B A of plane k: the last three transports of one step and the first
+// three of the next, in one pass.  A wave holds 64 columns (writing the middle
+// 56) and marches up a segment [jb, je) of rows.  Reading row n completes the
+// first A B A at row n - 2 (B takes the right movers of row n - 4 from a ring
+// and the left movers of row n) and the second at row n - 4 (right movers of
+// row n - 6 from a second ring, left movers of row n - 2), so every row is
+// read once per segment, plus four halo rows at each end.
 template <typename T>
 __global__ __launch_bounds__(256) void k_strang3d_abaaba(const T* __restrict__ src,
                                                          T* __restrict__ dst, SweepArgs a) {
@@ -429,48 +450,67 @@ __global__ __launch_bounds__(256) void k_strang3d_abaaba(const T* __restrict__ s
   const int64_t nx = a.nx, ny = a.ny;
   const int64_t strip = tile % a.nstrips;
   const int64_t rest = tile / a.nstrips;
-  const int64_t j = rest % ny, k = rest / ny;
+  const int64_t k = rest % a.nz, seg = rest / a.nz;
+  const int64_t jb = seg * a.H;
+  const int64_t je = (jb + a.H < ny) ? jb + a.H : ny;
+  const int nit = static_cast<int>(je - jb) + 8;
   const Lanes c = lanes_of(nx, a.periodic, strip * strip_width(4) - 4, lane);
+  const bool own = c.inside && lane >= 4 && lane <= 59;
   const bool walls = !a.periodic;
   const bool lanes_out = walls && !c.full && !c.inside;
+  const MarchBounds rows(jb, ny, nit);
+  const T* plane = src + k * ny * nx * 8;
   auto load = [&](int64_t r, Site<T>& s) {
-    load_site(src + ((k * ny + wrap_or_clamp(r, ny, a.periodic)) * nx + c.col) * 8, s);
-    if (walls && (r < 0 || r >= ny || (!c.full && c.out))) zero(s);
+    load_site(plane + (wrap_or_clamp(r, ny, a.periodic) * nx + c.col) * 8, s);
   };
   auto A = [&](const Site<T>& in, Site<T>& out) {
     x_transport_inner<T, 0>(in, out);
     if (lanes_out) zero(out);
   };
-  // B at a row from the transported rows below and above it
-  auto B = [&](const Site<T>& below, const Site<T>& above, Site<T>& out) {
-    Mov<T> r1, l1, r2, l2;
-    Axis<1, T>::movers(below, r1, l1);
-    Axis<1, T>::movers(above, r2, l2);
-    Axis<1, T>::combine(r1, l2, out);
-    if (lanes_out) zero(out);
-  };
-  Site<T> p0, p1, p2, a0, a1, a2, t, ylo, yhi, clo, chi, o;
-  load(j - 4, p0);
-  load(j, p1);
-  load(j + 4, p2);
-  A(p0, a0);
-  A(p1, a1);
-  A(p2, a2);
-  B(a0, a1, t);  // first A B A at row j - 2
-  A(t, ylo);
-  if (walls && (j - 2 < 0 || j - 2 >= ny)) zero(ylo);
-  B(a1, a2, t);  // first A B A at row j + 2
-  A(t, yhi);
-  if (walls && (j + 2 < 0 || j + 2 >= ny)) zero(yhi);
-  A(ylo, clo);
-  A(yhi, chi);
-  B(clo, chi, t);
-  x_transport_inner<T, 0>(t, o);
-  if (c.inside && lane >= 4 && lane <= 59) store_site(dst + ((k * ny + j) * nx + c.x) * 8, o);
+  Mov<T> ra[4], rc[4];  // right movers after the first / second A, slot: row % 4
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    zero(ra[q]);
+    zero(rc[q]);
+  }
+  Site<T> nxt;
+  load(jb - 4, nxt);
+  for (int base = 0;; base += 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int it = base + u;
+      if (it >= nit) return;
+      const int64_t n = jb - 4 + it;  // row read
+      Site<T> s = nxt;
+      load(n + 1, nxt);
+      if (walls && (!rows.in(it) || (!c.full && c.out))) zero(s);
+      Site<T> t, y, cc, o;
+      A(s, t);
+      Mov<T> r, l;
+      Axis<1, T>::movers(t, r, l);
+      Axis<1, T>::combine(ra[u], l, y);  // first B at row n - 2
+      ra[u] = r;
+      if (lanes_out) zero(y);
+      A(y, t);
+      if (walls && !rows.in(it - 2)) zero(t);  // row n - 2 beyond a wall
+      A(t, cc);                                // second A B A starts
+      Axis<1, T>::movers(cc, r, l);
+      Axis<1, T>::combine(rc[(u + 2) % 4], l, y);  // second B at row n - 4
+      rc[(u + 2) % 4] = r;
+      if (lanes_out) zero(y);
+      x_transport_inner<T, 0>(y, o);
+      if (it >= 8 && own) store_site(dst + ((k * ny + n - 4) * nx + c.x) * 8, o);
+    }
+  }
 }
 
-// C D C on row j of plane k: planes k - 4, k and k + 4 give C at k - 2 and
-// k + 2, where D applies, and C again gives plane k.  64 columns per wave.
+// C D C along z: a wave holds 64 columns of row j and marches up a segment
+// [kb, ke) of planes.  Reading plane n completes C at plane n - 2 (right
+// movers of plane n - 4 from a ring, left movers of plane n), applies D
+// there, and completes the second C at plane n - 4 (right movers of plane
+// n - 6 from a second ring, left movers of plane n - 2).  Every plane is read
+// once per segment, plus four halo planes at each end, and the phase factors
+// of a cell are formed once.
 template <typename T, int MODE>
 __global__ __launch_bounds__(256) void k_strang3d_cdc(const T* __restrict__ src,
                                                       T* __restrict__ dst,
@@ -483,40 +523,51 @@ __global__ __launch_bounds__(256) void k_strang3d_cdc(const T* __restrict__ src,
   const int64_t nx = a.nx, ny = a.ny, nz = a.nz;
   const int64_t strip = tile % a.nstrips;
   const int64_t rest = tile / a.nstrips;
-  const int64_t j = rest % ny, k = rest / ny;
+  const int64_t j = rest % ny, seg = rest / ny;
+  const int64_t kb = seg * a.H;
+  const int64_t ke = (kb + a.H < nz) ? kb + a.H : nz;
+  const int nit = static_cast<int>(ke - kb) + 8;
   const int64_t x = strip * 64 + lane;
   const int64_t col = x < nx ? x : nx - 1;
   const bool walls = !a.periodic;
-  auto outside = [&](int64_t p) { return walls && (p < 0 || p >= nz); };
+  const MarchBounds planes(kb, nz, nit);
   auto cell = [&](int64_t p) { return (wrap_or_clamp(p, nz, a.periodic) * ny + j) * nx + col; };
-  Site<T> s0, s1, s2;
-  load_site(src + cell(k - 4) * 8, s0);
-  load_site(src + cell(k) * 8, s1);
-  load_site(src + cell(k + 4) * 8, s2);
-  if (outside(k - 4)) zero(s0);
-  if (outside(k + 4)) zero(s2);
-  Mov<T> r0, l0, r1, l1, r2, l2;
-  Axis<2, T>::movers(s0, r0, l0);
-  Axis<2, T>::movers(s1, r1, l1);
-  Axis<2, T>::movers(s2, r2, l2);
-  Site<T> cm, cp;
-  Axis<2, T>::combine(r0, l1, cm);  // C at plane k - 2
-  Axis<2, T>::combine(r1, l2, cp);  // C at plane k + 2
-  const double vm = (MODE == 2) ? V[cell(k - 2)] : 0.0;
-  const double vp = (MODE == 2) ? V[cell(k + 2)] : 0.0;
-  Factors fm = factors_of<MODE, TWO>(vm, a.ph), fp = factors_of<MODE, TWO>(vp, a.ph);
-  factors_fix<MODE, TWO>(fm, vm, a.ph);
-  factors_fix<MODE, TWO>(fp, vp, a.ph);
-  apply_local<MODE>(cm, fm, a.ph);
-  apply_local<MODE>(cp, fp, a.ph);
-  if (outside(k - 2)) zero(cm);
-  if (outside(k + 2)) zero(cp);
-  Mov<T> rm, lm, rp, lp;
-  Axis<2, T>::movers(cm, rm, lm);
-  Axis<2, T>::movers(cp, rp, lp);
-  Site<T> o;
-  Axis<2, T>::combine(rm, lp, o);
-  if (x < nx) store_site(dst + ((k * ny + j) * nx + x) * 8, o);
+  Mov<T> rs[4], rd[4];  // right movers of the input / of C D, slot: plane % 4
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    zero(rs[q]);
+    zero(rd[q]);
+  }
+  Site<T> nxt;
+  load_site(src + cell(kb - 4) * 8, nxt);
+  double vnxt = (MODE == 2) ? V[cell(kb - 6)] : 0.0;
+  for (int base = 0;; base += 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int it = base + u;
+      if (it >= nit) return;
+      const int64_t n = kb - 4 + it;  // plane read
+      Site<T> s = nxt;
+      const double v = vnxt;  // potential at plane n - 2
+      load_site(src + cell(n + 1) * 8, nxt);
+      if (MODE == 2) vnxt = V[cell(n - 1)];
+      if (walls && !planes.in(it)) zero(s);
+      Mov<T> r, l;
+      Axis<2, T>::movers(s, r, l);
+      Site<T> cd;
+      Axis<2, T>::combine(rs[u], l, cd);  // C at plane n - 2
+      rs[u] = r;
+      Factors f = factors_of<MODE, TWO>(v, a.ph);
+      factors_fix<MODE, TWO>(f, v, a.ph);
+      apply_local<MODE>(cd, f, a.ph);
+      if (walls && !planes.in(it - 2)) zero(cd);
+      Axis<2, T>::movers(cd, r, l);
+      Site<T> o;
+      Axis<2, T>::combine(rd[(u + 2) % 4], l, o);  // second C at plane n - 4
+      rd[(u + 2) % 4] = r;
+      if (it >= 8 && x < nx) store_site(dst + (((n - 4) * ny + j) * nx + x) * 8, o);
+    }
+  }
 }
 
 template <typename T>
@@ -531,10 +582,25 @@ static hipError_t strang3d_t(const void* src, void* dst, void* mid, const double
     t.ntiles = t.nstrips * a.ny * a.nz;
     return (t.ntiles + 3) / 4;
   };
+  // marches along the axis of extent n, `lines` waves per segment: segments
+  // as long as possible while the grid still holds kMarchWaves waves
+  auto march_grid = [&](int width, int64_t lines, int64_t n, SweepArgs& t) {
+    t = a;
+    t.nstrips = (a.nx + width - 1) / width;
+    const int64_t per_seg = t.nstrips * lines;
+    int64_t nseg = (kMarchWaves + per_seg - 1) / per_seg;
+    nseg = nseg < 1 ? 1 : (nseg > n ? n : nseg);
+    const int64_t H = (n + nseg - 1) / nseg;
+    if (H > INT32_MAX - 64) return int64_t(INT32_MAX) + 1;  // refused below
+    t.H = static_cast<int>(H);
+    t.nseg = (n + H - 1) / H;
+    t.ntiles = per_seg * t.nseg;
+    return (t.ntiles + 3) / 4;
+  };
   SweepArgs ab, abab, cd;
   const int64_t bab = plane_grid(strip_width(2), ab);
-  const int64_t babab = plane_grid(strip_width(4), abab);
-  const int64_t bcd = plane_grid(64, cd);
+  const int64_t babab = march_grid(strip_width(4), a.nz, a.ny, abab);
+  const int64_t bcd = march_grid(64, a.ny, a.nz, cd);
   if (bab > INT32_MAX || babab > INT32_MAX || bcd > INT32_MAX) return hipErrorInvalidValue;
   auto cdc = [&](const T* in, T* out) {
     const dim3 g(static_cast<unsigned>(bcd));

@@ -111,6 +111,21 @@ def test_strang3d_vs_oracle(shape, bc):
     assert close(gpu_step(psi, None, m=1.0, nsteps=4, dtype="c128", **kw), refm, 1e-13)
 
 
+@pytest.mark.parametrize("bc", ["zero", "periodic"])
+def test_strang3d_long_march_segments_vs_oracle(bc):
+    """A grid large enough that the y and z marches of the 3-D passes run
+    segments of many rows and planes (every slot of their mover rings taken
+    several times, halo rows and planes at both segment ends) matches the
+    oracle: two full FP64 steps to relative L2 1e-12."""
+    announce(f"strang 3-D long segments {bc}")
+    shape = (64, 1024, 160)
+    psi = random_spinor(shape[::-1], seed=12)
+    V = np.random.default_rng(13).uniform(-2, 2, size=shape[::-1]) * C * C
+    kw = dict(dx=DX, dt=DT3, c=C, m=1.0, axes=(0, 1, 2), bc=bc, scheme="strang")
+    ref = O.step_strang(psi, V, dt=DT3, c=C, m=1.0, nsteps=2, axes=(0, 1, 2), bc=bc)
+    assert rel_l2(gpu_step(psi, V, nsteps=2, dtype="c128", **kw), ref) <= 1e-12
+
+
 @pytest.mark.parametrize("shape", [(37, 21, 13), (64, 9, 10), (3, 6, 5)])
 @pytest.mark.parametrize("bc", ["zero", "periodic"])
 def test_strang3d_grouped_steps_same_bits(shape, bc):
