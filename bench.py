@@ -390,7 +390,8 @@ def bench_3d(args):
                                                         BYTES_F32, 1),
             ("f64", torch.complex128, BYTES_F64, None),
             ("f32_second_order", torch.complex64, None, None),
-            ("f32_vector_potential", torch.complex64, None, None))
+            ("f32_vector_potential", torch.complex64, None, None),
+            ("f32_adjoint", torch.complex64, None, None))
     for dt_name, tdt, bps, depth in runs:
         f = (gz[:, None, None] * gy[None, :, None] * gx[None, None, :])
         psi = (f[..., None] * u).to(tdt).contiguous()
@@ -415,6 +416,32 @@ def bench_3d(args):
                             "hbm_frac": 96 * n ** 3 / (msf * 1e-3) / 1e9 / HBM_PEAK_GBS}
             log(f"3-D 512^3 {dt_name}: {msf:.3f} ms/step")
             del psi, At
+            torch.cuda.empty_cache()
+            continue
+        if dt_name.endswith("adjoint"):
+            # reverse steps (dl_grad_step) from lambda = [x > 0] psi: per step one pass
+            # with the dL/dV term, D^H and T_z^H, one with T_y^H and T_x^H
+            with L.Plan((n, n, n), dx, dx / c, c, m, dtype="complex64") as p:
+                lam = torch.empty_like(psi)
+                Q = torch.empty_like(V)
+                p.seed_adjoint(psi, 0.0, lam, Q)
+                p.grad_step(psi, lam, V, Q, 1)
+                torch.cuda.synchronize()
+                s_, e_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                nr = min(steps, 10)
+                s_.record()
+                p.grad_step(psi, lam, V, Q, nr)
+                e_.record()
+                torch.cuda.synchronize()
+                msr = s_.elapsed_time(e_) / nr
+            # first pass: psi, lambda, V, Q read, Q and both fields written (152 B);
+            # second pass: both fields read and written (128 B)
+            out[dt_name] = {"reverse_steps": nr, "ms_per_reverse_step": msr,
+                            "passes_per_reverse_step": 2,
+                            "site_updates_per_s": n ** 3 / (msr * 1e-3),
+                            "hbm_frac": 280 * n ** 3 / (msr * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            log(f"3-D 512^3 {dt_name}: {msr:.3f} ms per reverse step")
+            del psi, lam, Q
             torch.cuda.empty_cache()
             continue
         strang = dt_name.endswith("second_order")
