@@ -419,8 +419,8 @@ def bench_3d(args):
             torch.cuda.empty_cache()
             continue
         if dt_name.endswith("adjoint"):
-            # reverse steps (dl_grad_step) from lambda = [x > 0] psi: per step one pass
-            # with the dL/dV term, D^H and T_z^H, one with T_y^H and T_x^H
+            # reverse steps (dl_grad_step) from lambda = [x > 0] psi: one pass per step
+            # (the dL/dV term, D^H, T_z^H, T_y^H, T_x^H)
             with L.Plan((n, n, n), dx, dx / c, c, m, dtype="complex64") as p:
                 lam = torch.empty_like(psi)
                 Q = torch.empty_like(V)
@@ -434,12 +434,11 @@ def bench_3d(args):
                 e_.record()
                 torch.cuda.synchronize()
                 msr = s_.elapsed_time(e_) / nr
-            # first pass: psi, lambda, V, Q read, Q and both fields written (152 B);
-            # second pass: both fields read and written (128 B)
+            # psi, lambda, V and Q read, both fields and Q written: 152 B per cell
             out[dt_name] = {"reverse_steps": nr, "ms_per_reverse_step": msr,
-                            "passes_per_reverse_step": 2,
+                            "passes_per_reverse_step": 1,
                             "site_updates_per_s": n ** 3 / (msr * 1e-3),
-                            "hbm_frac": 280 * n ** 3 / (msr * 1e-3) / 1e9 / HBM_PEAK_GBS}
+                            "hbm_frac": 152 * n ** 3 / (msr * 1e-3) / 1e9 / HBM_PEAK_GBS}
             log(f"3-D 512^3 {dt_name}: {msr:.3f} ms per reverse step")
             del psi, lam, Q
             torch.cuda.empty_cache()

@@ -179,8 +179,9 @@ int dl_seed_adjoint(dl_plan p, const void *psi, double x_b, void *lam, double *Q
  * dL/dV and psi is the reconstructed psi_0.  Up to 3 reverse steps (2 with
  * complex128 state) are fused into one pass over psi, lam, V and Q, with the
  * bits of single reverse steps (the terms of Q added in the same order).
- * 3-D grids: two passes per reverse step (Q, D^H and T_z^H; then T_y^H and
- * T_x^H).  Lowest-order four-component plans only (DL_ERR_ARG else). */
+ * 3-D grids: one pass per reverse step (Q, D^H, T_z^H, T_y^H, T_x^H) through
+ * the plan's scratch states, the result copied back to psi and lam after an
+ * odd count.  Lowest-order four-component plans only (DL_ERR_ARG else). */
 int dl_grad_step(dl_plan p, void *psi, void *lam, const double *V, double *Q,
                  int64_t nsteps, void *stream);
 

@@ -24,6 +24,8 @@
 #include "dirac_plan.h"
 #include "dirac_sweep_impl.h"
 
+#include <utility>
+
 namespace dirac {
 
 struct RevArgs {
@@ -475,18 +477,28 @@ static int rev_occ(bool fp64, int depth, int axes_code) {
 }
 
 // ---------------------------------------------------------------------------
-// 3-D reverse step, two passes.  The first adds the step's term to dL/dV at
-// every cell, applies D^H at the planes k - 1 and k + 1 and completes T_z^H at
-// plane k (right movers from k + 1, left movers from k - 1); the second
-// applies T_y^H and then T_x^H within the plane (62 columns per wave).
+// 3-D reverse step in one pass.  A wave holds 64 columns (writing the middle
+// 62) and a block of TY rows, and marches up a segment [kb, ke) of planes.
+// Reading plane n it adds the step's term to dL/dV at its own cells of that
+// plane, applies D^H to the rows y0 - 1 .. y0 + TY of the plane and completes
+// T_z^H at plane n - 1 for those rows (right movers of plane n, left movers of
+// plane n - 2 kept in a two-slot ring); then T_y^H and T_x^H give the TY own
+// rows of plane n - 1.  The T_z^H results are rounded as the stored state of
+// a pass would be, so the bits are those of transports applied one by one.
 // ---------------------------------------------------------------------------
 struct Rev3Args {
   int64_t nx, ny, nz;
   int periodic;
-  int64_t nstrips, ntiles;
+  int64_t nstrips, nyblk, nseg, ntiles;
+  int H;  // planes per segment
   double qscale;
   PhaseK ph;
 };
+
+// rows per wave and resident blocks per CU of the 3-D reverse pass
+template <typename T> struct Rev3Shape;
+template <> struct Rev3Shape<float> { static constexpr int TY = 2, kMinBlocks = 2; };
+template <> struct Rev3Shape<double> { static constexpr int TY = 2, kMinBlocks = 1; };
 
 __device__ __forceinline__ int64_t rev_wrap(int64_t r, int64_t n, int periodic) {
   if (periodic) return ((r % n) + n) % n;
@@ -494,137 +506,175 @@ __device__ __forceinline__ int64_t rev_wrap(int64_t r, int64_t n, int periodic) 
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_reverse3d_z(T* __restrict__ psi_out,
-                                                     T* __restrict__ lam_out,
-                                                     const T* __restrict__ psi,
-                                                     const T* __restrict__ lam,
-                                                     const double* __restrict__ V,
-                                                     double* __restrict__ Q, Rev3Args a) {
+__global__ __launch_bounds__(256, Rev3Shape<T>::kMinBlocks) void k_reverse3d(
+    T* __restrict__ psi_out, T* __restrict__ lam_out, const T* __restrict__ psi,
+    const T* __restrict__ lam, const double* __restrict__ V, double* __restrict__ Q,
+    Rev3Args a) {
+  constexpr int TY = Rev3Shape<T>::TY;
+  constexpr int R = TY + 2;  // rows y0 - 1 .. y0 + TY
+  constexpr bool TWO = sizeof(T) == 8;
   const int lane = threadIdx.x & 63;
   const int64_t tile = int64_t(blockIdx.x) * 4 + wave_in_block();
   if (tile >= a.ntiles) return;
   const int64_t nx = a.nx, ny = a.ny, nz = a.nz;
   const int64_t strip = tile % a.nstrips;
   const int64_t rest = tile / a.nstrips;
-  const int64_t j = rest % ny, k = rest / ny;
-  const int64_t x = strip * 64 + lane;
-  const int64_t col = x < nx ? x : nx - 1;
+  const int64_t yblk = rest % a.nyblk, seg = rest / a.nyblk;
+  const int64_t y0 = yblk * TY;
+  const int64_t kb = seg * a.H;
+  const int64_t ke = (kb + a.H < nz) ? kb + a.H : nz;
+  const int nit = static_cast<int>(ke - kb) + 2;  // planes kb - 1 .. ke
+  const Lanes c = lanes_of(nx, a.periodic, strip * strip_width(1) - 1, lane);
+  const bool own = c.inside && lane >= 1 && lane <= 62;
   const bool walls = !a.periodic;
-  auto cell = [&](int64_t p) { return (rev_wrap(p, nz, a.periodic) * ny + j) * nx + col; };
-  // the step's term of dL/dV at the input time level
-  const int64_t q = (k * ny + j) * nx + col;
-  Site<T> p0, l0;
-  load_site(psi + q * 8, p0);
-  load_site(lam + q * 8, l0);
-  const double qn = fma(a.qscale, im_dot(l0, p0), Q[q]);
-  // D^H at the neighbouring planes, then T_z^H
-  Site<T> pm, lm, pp, lp;
-  const int64_t qm = cell(k - 1), qp = cell(k + 1);
-  load_site(psi + qm * 8, pm);
-  load_site(lam + qm * 8, lm);
-  load_site(psi + qp * 8, pp);
-  load_site(lam + qp * 8, lp);
   const bool read_v = (a.ph.mode == 2);
-  const Factors fm = adjoint_factors<sizeof(T) == 8>(read_v ? V[qm] : 0.0, a.ph);
-  const Factors fp = adjoint_factors<sizeof(T) == 8>(read_v ? V[qp] : 0.0, a.ph);
-  adjoint_local(pm, fm, a.ph);
-  adjoint_local(lm, fm, a.ph);
-  adjoint_local(pp, fp, a.ph);
-  adjoint_local(lp, fp, a.ph);
-  if (walls && k - 1 < 0) {
-    zero(pm);
-    zero(lm);
+  // plane kb - 1 + it lies in the box iff klo <= it < khi (wave-uniform)
+  auto clamp_it = [&](int64_t e) -> int {
+    return static_cast<int>(e < -64 ? -64 : (e > nit + 64 ? nit + 64 : e));
+  };
+  const int klo = clamp_it(1 - kb), khi = clamp_it(1 - kb + nz);
+  // the tile's rows: offset of the row read, and bit t set for rows in the box
+  int64_t rowoff[R];
+  uint32_t rin = 0;
+#pragma unroll
+  for (int t = 0; t < R; ++t) {
+    const int64_t y = y0 - 1 + t;
+    rowoff[t] = rev_wrap(y, ny, a.periodic) * nx;
+    if (y >= 0 && y < ny) rin |= 1u << t;
   }
-  if (walls && k + 1 >= nz) {
-    zero(pp);
-    zero(lp);
+  rin = __builtin_amdgcn_readfirstlane(rin);
+  Mov<T> lpr[2][R], llr[2][R];  // left movers of D^H psi, lambda; slot: plane % 2
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+      zero(lpr[q][t]);
+      zero(llr[q][t]);
+    }
   }
-  Mov<T> rpm, lpm, rpp, lpp, rlm, llm, rlp, llp;
-  Axis<2, T>::movers(pm, rpm, lpm);
-  Axis<2, T>::movers(pp, rpp, lpp);
-  Axis<2, T>::movers(lm, rlm, llm);
-  Axis<2, T>::movers(lp, rlp, llp);
-  Site<T> op, ol;
-  Axis<2, T>::combine(rpp, lpm, op);
-  Axis<2, T>::combine(rlp, llm, ol);
-  if (x < nx) {
-    Q[q] = qn;
-    store_site(psi_out + q * 8, op);
-    store_site(lam_out + q * 8, ol);
+  for (int base = 0;; base += 2) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int it = base + u;
+      if (it >= nit) return;
+      const int64_t n = kb - 1 + it;  // plane read
+      const bool n_in = it >= klo && it < khi;
+      const bool n_own = it >= 1 && it < nit - 1;  // kb <= n < ke
+      const int64_t pbase = rev_wrap(n, nz, a.periodic) * ny * nx + c.col;
+      Site<T> zp[R], zl[R];  // T_z^H of psi and lambda at plane n - 1
+#pragma unroll
+      for (int t = 0; t < R; ++t) {
+        const int64_t q = pbase + rowoff[t];
+        Site<T> ps, ls;
+        load_site(psi + q * 8, ps);
+        load_site(lam + q * 8, ls);
+        const double v = read_v ? V[q] : 0.0;
+        // the step's term of dL/dV, once per cell: own rows, lanes and planes
+        if (t >= 1 && t <= TY && n_own && ((rin >> t) & 1u) && own)
+          Q[q] = fma(a.qscale, im_dot(ls, ps), Q[q]);
+        const Factors f = adjoint_factors<TWO>(v, a.ph);
+        adjoint_local(ps, f, a.ph);
+        adjoint_local(ls, f, a.ph);
+        if (walls && !n_in) {
+          zero(ps);
+          zero(ls);
+        }
+        Mov<T> rp, lp, rl, ll;
+        Axis<2, T>::movers(ps, rp, lp);
+        Axis<2, T>::movers(ls, rl, ll);
+        Axis<2, T>::combine(rp, lpr[u][t], zp[t]);
+        Axis<2, T>::combine(rl, llr[u][t], zl[t]);
+        lpr[u][t] = lp;
+        llr[u][t] = ll;
+      }
+      if (it < 2) continue;  // plane n - 1 lies before the segment
+      // rows beyond a wall and lanes beyond a side wall read as zero
+#pragma unroll
+      for (int t = 0; t < R; ++t) {
+        if (walls && (!((rin >> t) & 1u) || (!c.full && c.out))) {
+          zero(zp[t]);
+          zero(zl[t]);
+        }
+      }
+      const int64_t obase = ((n - 1) * ny + y0) * nx + c.x;
+#pragma unroll
+      for (int w = 0; w < TY; ++w) {
+        // T_y^H at row y0 + w: right movers from the row above, left from below
+        Mov<T> r2, l2, r1, l1;
+        Site<T> yp, yl, op, ol;
+        Axis<1, T>::movers(zp[w + 2], r2, l2);
+        Axis<1, T>::movers(zp[w], r1, l1);
+        Axis<1, T>::combine(r2, l1, yp);
+        Axis<1, T>::movers(zl[w + 2], r2, l2);
+        Axis<1, T>::movers(zl[w], r1, l1);
+        Axis<1, T>::combine(r2, l1, yl);
+        if (walls && !c.full && !c.inside) {
+          zero(yp);
+          zero(yl);
+        }
+        x_transport_adj<T, 0>(yp, op);
+        x_transport_adj<T, 0>(yl, ol);
+        if (own && y0 + w < ny) {
+          store_site(psi_out + (obase + w * nx) * 8, op);
+          store_site(lam_out + (obase + w * nx) * 8, ol);
+        }
+      }
+    }
   }
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_reverse3d_xy(T* __restrict__ psi_out,
-                                                      T* __restrict__ lam_out,
-                                                      const T* __restrict__ psi,
-                                                      const T* __restrict__ lam, Rev3Args a) {
-  const int lane = threadIdx.x & 63;
-  const int64_t tile = int64_t(blockIdx.x) * 4 + wave_in_block();
-  if (tile >= a.ntiles) return;
-  const int64_t nx = a.nx, ny = a.ny;
-  const int64_t strip = tile % a.nstrips;
-  const int64_t rest = tile / a.nstrips;
-  const int64_t j = rest % ny, k = rest / ny;
-  const Lanes c = lanes_of(nx, a.periodic, strip * strip_width(1) - 1, lane);
-  const bool walls = !a.periodic;
-  auto load = [&](const T* f, int64_t r, Site<T>& s) {
-    load_site(f + ((k * ny + rev_wrap(r, ny, a.periodic)) * nx + c.col) * 8, s);
-    if (walls && (r < 0 || r >= ny || (!c.full && c.out))) zero(s);
-  };
-  Site<T> pd, pu, ld, lu;
-  load(psi, j - 1, pd);
-  load(psi, j + 1, pu);
-  load(lam, j - 1, ld);
-  load(lam, j + 1, lu);
-  // T_y^H: right movers from row j + 1, left movers from row j - 1
-  Mov<T> r1, l1, r2, l2;
-  Site<T> yp, yl, op, ol;
-  Axis<1, T>::movers(pd, r1, l1);
-  Axis<1, T>::movers(pu, r2, l2);
-  Axis<1, T>::combine(r2, l1, yp);
-  Axis<1, T>::movers(ld, r1, l1);
-  Axis<1, T>::movers(lu, r2, l2);
-  Axis<1, T>::combine(r2, l1, yl);
-  if (walls && !c.full && !c.inside) {
-    zero(yp);
-    zero(yl);
+static int rev3_occupancy() {
+  static int occ = -1;
+  if (occ < 0) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_reverse3d<T>, 256, 0) != hipSuccess) {
+      (void)hipGetLastError();
+      n = 0;
+    }
+    occ = n > 0 ? n : Rev3Shape<T>::kMinBlocks;
   }
-  x_transport_adj<T, 0>(yp, op);
-  x_transport_adj<T, 0>(yl, ol);
-  if (c.inside && lane >= 1 && lane <= 62) {
-    const int64_t off = ((k * ny + j) * nx + c.x) * 8;
-    store_site(psi_out + off, op);
-    store_site(lam_out + off, ol);
-  }
+  return occ;
 }
 
-// one reverse step on a 3-D grid: (pi, li) -> (pb, lb) -> (pi, li)
-static hipError_t launch_rev3d(bool fp64, void* pi, void* li, void* pb, void* lb,
-                               const double* V, double* Q, Rev3Args a, hipStream_t st) {
-  Rev3Args az = a, axy = a;
-  az.nstrips = (a.nx + 63) / 64;
-  az.ntiles = az.nstrips * a.ny * a.nz;
-  axy.nstrips = (a.nx + strip_width(1) - 1) / strip_width(1);
-  axy.ntiles = axy.nstrips * a.ny * a.nz;
-  const int64_t bz = (az.ntiles + 3) / 4, bxy = (axy.ntiles + 3) / 4;
-  if (bz > INT32_MAX || bxy > INT32_MAX) return hipErrorInvalidValue;
-  if (fp64) {
-    hipLaunchKernelGGL(k_reverse3d_z<double>, dim3(static_cast<unsigned>(bz)), dim3(256), 0, st,
-                       static_cast<double*>(pb), static_cast<double*>(lb),
-                       static_cast<const double*>(pi), static_cast<const double*>(li), V, Q, az);
-    hipLaunchKernelGGL(k_reverse3d_xy<double>, dim3(static_cast<unsigned>(bxy)), dim3(256), 0,
-                       st, static_cast<double*>(pi), static_cast<double*>(li),
-                       static_cast<const double*>(pb), static_cast<const double*>(lb), axy);
-  } else {
-    hipLaunchKernelGGL(k_reverse3d_z<float>, dim3(static_cast<unsigned>(bz)), dim3(256), 0, st,
-                       static_cast<float*>(pb), static_cast<float*>(lb),
-                       static_cast<const float*>(pi), static_cast<const float*>(li), V, Q, az);
-    hipLaunchKernelGGL(k_reverse3d_xy<float>, dim3(static_cast<unsigned>(bxy)), dim3(256), 0, st,
-                       static_cast<float*>(pi), static_cast<float*>(li),
-                       static_cast<const float*>(pb), static_cast<const float*>(lb), axy);
+// one reverse step on a 3-D grid, (pi, li) -> (po, lo).  Segments along z
+// from a cost model: (rounds of resident waves) x (H + 2 plane iterations).
+template <typename T>
+static hipError_t rev3d_t(const void* pi, const void* li, void* po, void* lo, const double* V,
+                          double* Q, Rev3Args a, int cu_count, hipStream_t st) {
+  constexpr int TY = Rev3Shape<T>::TY;
+  a.nstrips = (a.nx + strip_width(1) - 1) / strip_width(1);
+  a.nyblk = (a.ny + TY - 1) / TY;
+  const int64_t per_seg = a.nstrips * a.nyblk;
+  const int64_t resident = int64_t(rev3_occupancy<T>()) * 4 * (cu_count > 0 ? cu_count : 256);
+  int64_t best_H = a.nz, best_cost = -1;
+  for (int64_t nseg = 1; nseg <= 64 && nseg <= a.nz; ++nseg) {
+    const int64_t H = (a.nz + nseg - 1) / nseg;
+    const int64_t segs = (a.nz + H - 1) / H;
+    const int64_t rounds = (per_seg * segs + resident - 1) / resident;
+    const int64_t cost = rounds * (H + 2);
+    if (best_cost < 0 || cost < best_cost) {
+      best_cost = cost;
+      best_H = H;
+    }
   }
+  if (best_H > INT32_MAX - 64) return hipErrorInvalidValue;
+  a.H = static_cast<int>(best_H);
+  a.nseg = (a.nz + best_H - 1) / best_H;
+  a.ntiles = per_seg * a.nseg;
+  const int64_t blocks = (a.ntiles + 3) / 4;
+  if (blocks > INT32_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_reverse3d<T>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st,
+                     static_cast<T*>(po), static_cast<T*>(lo), static_cast<const T*>(pi),
+                     static_cast<const T*>(li), V, Q, a);
   return hipGetLastError();
+}
+
+static hipError_t launch_rev3d(bool fp64, const void* pi, const void* li, void* po, void* lo,
+                               const double* V, double* Q, const Rev3Args& a, int cu_count,
+                               hipStream_t st) {
+  return fp64 ? rev3d_t<double>(pi, li, po, lo, V, Q, a, cu_count, st)
+              : rev3d_t<float>(pi, li, po, lo, V, Q, a, cu_count, st);
 }
 
 }  // namespace dirac
@@ -729,7 +779,7 @@ extern "C" int dl_grad_step(dl_plan p, void* psi, void* lam, const double* V, do
     }
   }
   const PhaseK ph = make_phase(p->g.ndim, p->dt, p->c, p->m, phase_mode(p->m, V), p->fp64);
-  if (p->g.ndim == 3) {  // two passes per reverse step, ending in psi and lam
+  if (p->g.ndim == 3) {  // one pass per reverse step, alternating buffers, ending in psi and lam
     Rev3Args a{};
     a.nx = p->g.n[0];
     a.ny = p->g.n[1];
@@ -737,9 +787,21 @@ extern "C" int dl_grad_step(dl_plan p, void* psi, void* lam, const double* V, do
     a.periodic = (p->bc == DL_BC_PERIODIC);
     a.qscale = 2.0 * p->dt * p->dx * p->dx * p->dx;
     a.ph = ph;
+    void* pa = psi;
+    void* la = lam;
+    void* pb = p->tmp;
+    void* lb = p->tmp2;
     for (int64_t s = 0; s < nsteps; ++s) {
-      hipError_t e = launch_rev3d(p->fp64, psi, lam, p->tmp, p->tmp2, V, Q, a, st);
+      hipError_t e = launch_rev3d(p->fp64, pa, la, pb, lb, V, Q, a, p->cu_count, st);
       if (e != hipSuccess) return set_hip_error(e, "reverse sweep launch");
+      std::swap(pa, pb);
+      std::swap(la, lb);
+    }
+    if (pa != psi) {  // odd step count: the result sits in the plan's buffers
+      hipError_t e = hipMemcpyAsync(psi, pa, p->state_bytes, hipMemcpyDeviceToDevice, st);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(lam, la, p->state_bytes, hipMemcpyDeviceToDevice, st);
+      if (e != hipSuccess) return set_hip_error(e, "reverse sweep copy");
     }
     return DL_OK;
   }

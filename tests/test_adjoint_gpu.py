@@ -54,7 +54,10 @@ def test_seed_and_expand_and_project(dtype):
                                            ((130, 45), (0, 2), "periodic"),
                                            ((70, 66), (1, 2), "zero"),
                                            ((40, 24, 18), (0, 1, 2), "zero"),
-                                           ((70, 13, 11), (0, 1, 2), "periodic")])
+                                           ((70, 13, 11), (0, 1, 2), "periodic"),
+                                           # long z segments of the 3-D reverse pass
+                                           ((64, 64, 96), (0, 1, 2), "zero"),
+                                           ((100, 70, 200), (0, 1, 2), "periodic")])
 def test_reverse_step_is_the_adjoint(shape, axes, bc):
     """<S^H lam, psi> = <lam, S psi> with S from dl_step and S^H from dl_grad_step."""
     import torch
