@@ -77,8 +77,8 @@ typedef enum { DL_BC_ZERO = 0, DL_BC_PERIODIC = 1 } dl_bc;
                         one-cell shift, so the plan needs c*dt = 2*dx.  3-D
                         grids: A(dt/4) B(dt/2) A(dt/4) C(dt/2) D(dt) C(dt/2)
                         A(dt/4) B(dt/2) A(dt/4) with c*dt = 4*dx: A shifts one
-                        cell, B and C two (three passes over memory per step,
-                        one extra state buffer in the plan).  DL_ERR_CFL on any
+                        cell, B and C two (K + 1 passes over memory per group
+                        of K steps, one extra state buffer in the plan).  DL_ERR_CFL on any
                         other c*dt.  The adjoint entry points, and
                         dl_step_field on 3-D grids, refuse such a plan
                         (DL_ERR_ARG). */

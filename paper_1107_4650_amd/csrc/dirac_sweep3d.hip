@@ -364,12 +364,12 @@ __global__ __launch_bounds__(256, kMinBlocks3D2) void k_sweep3d_x2(const T* __re
 // ---------------------------------------------------------------------------
 // 3-D second-order step (Sec. 2.4): A(dt/4) B(dt/2) A(dt/4) C(dt/2) D(dt)
 // C(dt/2) A(dt/4) B(dt/2) A(dt/4), with c dt/4 = a: A is the one-cell x
-// shift, B and C the two-cell y and z shifts.  It runs as passes over
-// memory: A B A on every (x, y) plane, C D C along z, A B A again; within a
-// group of steps the trailing A B A of a step and the leading one of the
-// next share a pass.  The
-// factors 1/2 of the eight transports are deferred to the local step (scale
-// 2^-8), so the stored intermediate states carry exact powers of two.
+// shift, B and C the two-cell y and z shifts.  A group of steps runs as one
+// pass per step (the x-y transports that open the step, preceded from the
+// second step on by those that close the previous one, then C D C along z)
+// and a pass with the closing A B A.  The factors 1/2 of the eight transports
+// are deferred to the local step (scale 2^-8), so the intermediate states
+// carry exact powers of two.
 // ---------------------------------------------------------------------------
 
 // r wrapped into [0, n) around a periodic box, else clamped (cells beyond a
@@ -416,10 +416,6 @@ __global__ __launch_bounds__(256) void k_strang3d_aba(const T* __restrict__ src,
   if (c.inside && lane >= 2 && lane <= 61) store_site(dst + ((k * ny + j) * nx + c.x) * 8, o);
 }
 
-// waves a Strang march grid aims for: sixteen per SIMD, in about four rounds
-// of the waves one SIMD holds at once, so that the last round is short
-constexpr int64_t kMarchWaves = 16384;
-
 // Wall test of a march: position kb - 4 + it (rows or planes) lies in [0, n)
 // iff lo <= it < hi, with lo, hi clamped to 32 bits (it spans 0 .. nit).
 struct MarchBounds {
@@ -434,140 +430,192 @@ struct MarchBounds {
   __device__ bool in(int it) const { return it >= lo && it < hi; }
 };
 
-// A B A A B A of plane k: the last three transports of one step and the first
-// three of the next, in one pass.  A wave holds 64 columns (writing the middle
-// 56) and marches up a segment [jb, je) of rows.  Reading row n completes the
-// first A B A at row n - 2 (B takes the right movers of row n - 4 from a ring
-// and the left movers of row n) and the second at row n - 4 (right movers of
-// row n - 6 from a second ring, left movers of row n - 2), so every row is
-// read once per segment, plus four halo rows at each end.
-template <typename T>
-__global__ __launch_bounds__(256) void k_strang3d_abaaba(const T* __restrict__ src,
-                                                         T* __restrict__ dst, SweepArgs a) {
-  const int lane = threadIdx.x & 63;
-  const int64_t tile = int64_t(blockIdx.x) * 4 + wave_in_block();
-  if (tile >= a.ntiles) return;
-  const int64_t nx = a.nx, ny = a.ny;
-  const int64_t strip = tile % a.nstrips;
-  const int64_t rest = tile / a.nstrips;
-  const int64_t k = rest % a.nz, seg = rest / a.nz;
-  const int64_t jb = seg * a.H;
-  const int64_t je = (jb + a.H < ny) ? jb + a.H : ny;
-  const int nit = static_cast<int>(je - jb) + 8;
-  const Lanes c = lanes_of(nx, a.periodic, strip * strip_width(4) - 4, lane);
-  const bool own = c.inside && lane >= 4 && lane <= 59;
-  const bool walls = !a.periodic;
-  const bool lanes_out = walls && !c.full && !c.inside;
-  const MarchBounds rows(jb, ny, nit);
-  const T* plane = src + k * ny * nx * 8;
-  auto load = [&](int64_t r, Site<T>& s) {
-    load_site(plane + (wrap_or_clamp(r, ny, a.periodic) * nx + c.col) * 8, s);
-  };
-  auto A = [&](const Site<T>& in, Site<T>& out) {
-    x_transport_inner<T, 0>(in, out);
-    if (lanes_out) zero(out);
-  };
-  Mov<T> ra[4], rc[4];  // right movers after the first / second A, slot: row % 4
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    zero(ra[q]);
-    zero(rc[q]);
-  }
-  Site<T> nxt;
-  load(jb - 4, nxt);
-  for (int base = 0;; base += 4) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int it = base + u;
-      if (it >= nit) return;
-      const int64_t n = jb - 4 + it;  // row read
-      Site<T> s = nxt;
-      load(n + 1, nxt);
-      if (walls && (!rows.in(it) || (!c.full && c.out))) zero(s);
-      Site<T> t, y, cc, o;
-      A(s, t);
-      Mov<T> r, l;
-      Axis<1, T>::movers(t, r, l);
-      Axis<1, T>::combine(ra[u], l, y);  // first B at row n - 2
-      ra[u] = r;
-      if (lanes_out) zero(y);
-      A(y, t);
-      if (walls && !rows.in(it - 2)) zero(t);  // row n - 2 beyond a wall
-      A(t, cc);                                // second A B A starts
-      Axis<1, T>::movers(cc, r, l);
-      Axis<1, T>::combine(rc[(u + 2) % 4], l, y);  // second B at row n - 4
-      rc[(u + 2) % 4] = r;
-      if (lanes_out) zero(y);
-      x_transport_inner<T, 0>(y, o);
-      if (it >= 8 && own) store_site(dst + ((k * ny + n - 4) * nx + c.x) * 8, o);
-    }
-  }
-}
+// rows per wave and resident blocks per CU of the fused second-order pass
+template <typename T> struct StrangShape;
+template <> struct StrangShape<float> { static constexpr int TY = 2, kMinBlocks = 2; };
+template <> struct StrangShape<double> { static constexpr int TY = 2, kMinBlocks = 1; };
 
-// C D C along z: a wave holds 64 columns of row j and marches up a segment
-// [kb, ke) of planes.  Reading plane n completes C at plane n - 2 (right
-// movers of plane n - 4 from a ring, left movers of plane n), applies D
-// there, and completes the second C at plane n - 4 (right movers of plane
-// n - 6 from a second ring, left movers of plane n - 2).  Every plane is read
-// once per segment, plus four halo planes at each end, and the phase factors
-// of a cell are formed once.
-template <typename T, int MODE>
-__global__ __launch_bounds__(256) void k_strang3d_cdc(const T* __restrict__ src,
-                                                      T* __restrict__ dst,
-                                                      const double* __restrict__ V,
-                                                      SweepArgs a) {
+// One pass of the 3-D second-order step: the transports along x and y that
+// open it (A B A for the first step of a group, else the A B A that closes
+// the previous step followed by the one that opens this step), then C D C.
+// A wave holds 64 columns and TY rows and marches up a segment [kb, ke) of
+// planes.  Reading plane n it applies the x-y transports to its rows (a march
+// over the TY + 2 XL rows of the tile with two four-slot rings of right
+// movers, XL = 2 or 4 halo rows and lanes on each side) and feeds each output
+// row to C D C along z, which completes C at plane n - 2, applies D there and
+// completes the second C at plane n - 4 (rings of the right movers of the last
+// four planes per row).  The x-y results are rounded as a stored pass would
+// round them, so the bits are those of the separate passes.
+template <typename T, int MODE, bool FIRST>
+__global__ __launch_bounds__(256, StrangShape<T>::kMinBlocks) void k_strang3d_step(
+    const T* __restrict__ src, T* __restrict__ dst, const double* __restrict__ V,
+    SweepArgs a) {
   constexpr bool TWO = sizeof(T) == 8;
+  constexpr int TY = StrangShape<T>::TY;
+  constexpr int XL = FIRST ? 2 : 4;  // halo lanes and rows
+  constexpr int NR = TY + 2 * XL;    // rows read per plane
   const int lane = threadIdx.x & 63;
   const int64_t tile = int64_t(blockIdx.x) * 4 + wave_in_block();
   if (tile >= a.ntiles) return;
   const int64_t nx = a.nx, ny = a.ny, nz = a.nz;
-  const int64_t strip = tile % a.nstrips;
-  const int64_t rest = tile / a.nstrips;
-  const int64_t j = rest % ny, seg = rest / ny;
+  // tile order: row blocks fastest (neighbours share their halo rows), then
+  // x strips, then z segments
+  const int64_t yblk = tile % a.nyblk;
+  const int64_t rest = tile / a.nyblk;
+  const int64_t strip = rest % a.nstrips, seg = rest / a.nstrips;
+  const int64_t y0 = yblk * TY;
   const int64_t kb = seg * a.H;
   const int64_t ke = (kb + a.H < nz) ? kb + a.H : nz;
   const int nit = static_cast<int>(ke - kb) + 8;
-  const int64_t x = strip * 64 + lane;
-  const int64_t col = x < nx ? x : nx - 1;
+  const Lanes c = lanes_of(nx, a.periodic, strip * strip_width(XL) - XL, lane);
+  const bool own = c.inside && lane >= XL && lane <= 63 - XL;
   const bool walls = !a.periodic;
+  const bool lanes_out = walls && !c.full && !c.inside;
   const MarchBounds planes(kb, nz, nit);
-  auto cell = [&](int64_t p) { return (wrap_or_clamp(p, nz, a.periodic) * ny + j) * nx + col; };
-  Mov<T> rs[4], rd[4];  // right movers of the input / of C D, slot: plane % 4
+  // the rows read (wrapped or clamped) and, bit t, whether row y0 - XL + t
+  // lies in the box
+  int64_t rowoff[NR];
+  uint32_t rin = 0;
+#pragma unroll
+  for (int t = 0; t < NR; ++t) {
+    const int64_t y = y0 - XL + t;
+    rowoff[t] = wrap_or_clamp(y, ny, a.periodic) * nx + c.col;
+    if (y >= 0 && y < ny) rin |= 1u << t;
+  }
+  rin = __builtin_amdgcn_readfirstlane(rin);
+  auto row_in = [&](int t) -> bool { return (rin >> t) & 1u; };
+  auto A = [&](const Site<T>& in, Site<T>& out) {
+    x_transport_inner<T, 0>(in, out);
+    if (lanes_out) zero(out);
+  };
+  Mov<T> rs[4][TY], rd[4][TY];  // right movers of the input / of C D, slot: plane % 4
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    zero(rs[q]);
-    zero(rd[q]);
+#pragma unroll
+    for (int w = 0; w < TY; ++w) {
+      zero(rs[q][w]);
+      zero(rd[q][w]);
+    }
   }
-  Site<T> nxt;
-  load_site(src + cell(kb - 4) * 8, nxt);
-  double vnxt = (MODE == 2) ? V[cell(kb - 6)] : 0.0;
   for (int base = 0;; base += 4) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int it = base + u;
       if (it >= nit) return;
       const int64_t n = kb - 4 + it;  // plane read
-      Site<T> s = nxt;
-      const double v = vnxt;  // potential at plane n - 2
-      load_site(src + cell(n + 1) * 8, nxt);
-      if (MODE == 2) vnxt = V[cell(n - 1)];
-      if (walls && !planes.in(it)) zero(s);
-      Mov<T> r, l;
-      Axis<2, T>::movers(s, r, l);
-      Site<T> cd;
-      Axis<2, T>::combine(rs[u], l, cd);  // C at plane n - 2
-      rs[u] = r;
-      Factors f = factors_of<MODE, TWO>(v, a.ph);
-      factors_fix<MODE, TWO>(f, v, a.ph);
-      apply_local<MODE>(cd, f, a.ph);
-      if (walls && !planes.in(it - 2)) zero(cd);
-      Axis<2, T>::movers(cd, r, l);
-      Site<T> o;
-      Axis<2, T>::combine(rd[(u + 2) % 4], l, o);  // second C at plane n - 4
-      rd[(u + 2) % 4] = r;
-      if (it >= 8 && x < nx) store_site(dst + (((n - 4) * ny + j) * nx + x) * 8, o);
+      const bool n_in = planes.in(it);
+      const T* plane = src + wrap_or_clamp(n, nz, a.periodic) * ny * nx * 8;
+      const int64_t vplane = wrap_or_clamp(n - 2, nz, a.periodic) * ny;
+      Mov<T> ra[4], rc[4];  // right movers after the first / second A, slot: row % 4
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        zero(ra[q]);
+        zero(rc[q]);
+      }
+#pragma unroll
+      for (int t = 0; t < NR; ++t) {
+        Site<T> sv, tt, yb, o;
+        load_site(plane + rowoff[t] * 8, sv);
+        if (walls && (!row_in(t) || (!c.full && c.out))) zero(sv);
+        A(sv, tt);
+        Mov<T> r, l;
+        Axis<1, T>::movers(tt, r, l);
+        if (t < 4) {
+          ra[t % 4] = r;
+          continue;
+        }
+        Axis<1, T>::combine(ra[t % 4], l, yb);  // first B at tile row t - 2
+        ra[t % 4] = r;
+        if (lanes_out) zero(yb);
+        int w;  // output row y0 + w of the x-y transports
+        if constexpr (FIRST) {
+          x_transport_inner<T, 0>(yb, o);
+          w = t - 4;
+        } else {
+          Site<T> t2, cc;
+          A(yb, t2);
+          if (walls && !row_in(t - 2)) zero(t2);  // row beyond a wall
+          A(t2, cc);                              // the next step's A B A starts
+          Mov<T> r2, l2;
+          Axis<1, T>::movers(cc, r2, l2);
+          if (t < 8) {
+            rc[t % 4] = r2;
+            continue;
+          }
+          Axis<1, T>::combine(rc[t % 4], l2, yb);  // second B at tile row t - 4
+          rc[t % 4] = r2;
+          if (lanes_out) zero(yb);
+          x_transport_inner<T, 0>(yb, o);
+          w = t - 8;
+        }
+        // C D C along z for row y0 + w
+        if (walls && !n_in) zero(o);
+        Axis<2, T>::movers(o, r, l);
+        Site<T> cd, out;
+        Axis<2, T>::combine(rs[u][w], l, cd);  // C at plane n - 2
+        rs[u][w] = r;
+        const double v =
+            (MODE == 2) ? V[(vplane + wrap_or_clamp(y0 + w, ny, a.periodic)) * nx + c.col] : 0.0;
+        Factors f = factors_of<MODE, TWO>(v, a.ph);
+        factors_fix<MODE, TWO>(f, v, a.ph);
+        apply_local<MODE>(cd, f, a.ph);
+        if (walls && !planes.in(it - 2)) zero(cd);
+        Axis<2, T>::movers(cd, r, l);
+        Axis<2, T>::combine(rd[(u + 2) % 4][w], l, out);  // second C at plane n - 4
+        rd[(u + 2) % 4][w] = r;
+        if (it >= 8 && own && y0 + w < ny)
+          store_site(dst + (((n - 4) * ny + y0 + w) * nx + c.x) * 8, out);
+      }
     }
   }
+}
+
+template <typename T, bool FIRST>
+static const void* strang_step_kernel(int mode) {
+  switch (mode) {
+    case 0: return reinterpret_cast<const void*>(&k_strang3d_step<T, 0, FIRST>);
+    case 1: return reinterpret_cast<const void*>(&k_strang3d_step<T, 1, FIRST>);
+    default: return reinterpret_cast<const void*>(&k_strang3d_step<T, 2, FIRST>);
+  }
+}
+
+// grid of a fused second-order pass: z segments from a cost model, (rounds of
+// resident waves) x (H + 8 plane iterations)
+template <typename T, bool FIRST>
+static int64_t strang_step_grid(const SweepArgs& a, SweepArgs& t) {
+  constexpr int TY = StrangShape<T>::TY;
+  constexpr int XL = FIRST ? 2 : 4;
+  static int resident = 0;
+  if (resident == 0) {
+    int occ = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, strang_step_kernel<T, FIRST>(2), 256,
+                                                     0) != hipSuccess)
+      occ = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      cus = 0;
+    (void)hipGetLastError();
+    resident = (occ > 0 ? occ : StrangShape<T>::kMinBlocks) * 4 * (cus > 0 ? cus : 256);
+  }
+  t = a;
+  t.nstrips = (a.nx + strip_width(XL) - 1) / strip_width(XL);
+  t.nyblk = (a.ny + TY - 1) / TY;
+  const int64_t per_seg = t.nstrips * t.nyblk;
+  int64_t best_H = a.nz, best_cost = -1;
+  for (int64_t nseg = 1; nseg <= 64 && nseg <= a.nz; ++nseg) {
+    const int64_t H = (a.nz + nseg - 1) / nseg;
+    const int64_t segs = (a.nz + H - 1) / H;
+    const int64_t cost = ((per_seg * segs + resident - 1) / resident) * (H + 8);
+    if (best_cost < 0 || cost < best_cost) {
+      best_cost = cost;
+      best_H = H;
+    }
+  }
+  if (best_H > INT32_MAX - 64) return int64_t(INT32_MAX) + 1;  // refused by the caller
+  t.H = static_cast<int>(best_H);
+  t.nseg = (a.nz + best_H - 1) / best_H;
+  t.ntiles = per_seg * t.nseg;
+  return (t.ntiles + 3) / 4;
 }
 
 template <typename T>
@@ -582,45 +630,43 @@ static hipError_t strang3d_t(const void* src, void* dst, void* mid, const double
     t.ntiles = t.nstrips * a.ny * a.nz;
     return (t.ntiles + 3) / 4;
   };
-  // marches along the axis of extent n, `lines` waves per segment: segments
-  // as long as possible while the grid still holds kMarchWaves waves
-  auto march_grid = [&](int width, int64_t lines, int64_t n, SweepArgs& t) {
-    t = a;
-    t.nstrips = (a.nx + width - 1) / width;
-    const int64_t per_seg = t.nstrips * lines;
-    int64_t nseg = (kMarchWaves + per_seg - 1) / per_seg;
-    nseg = nseg < 1 ? 1 : (nseg > n ? n : nseg);
-    const int64_t H = (n + nseg - 1) / nseg;
-    if (H > INT32_MAX - 64) return int64_t(INT32_MAX) + 1;  // refused below
-    t.H = static_cast<int>(H);
-    t.nseg = (n + H - 1) / H;
-    t.ntiles = per_seg * t.nseg;
-    return (t.ntiles + 3) / 4;
-  };
-  SweepArgs ab, abab, cd;
+  SweepArgs ab, first, next;
   const int64_t bab = plane_grid(strip_width(2), ab);
-  const int64_t babab = march_grid(strip_width(4), a.nz, a.ny, abab);
-  const int64_t bcd = march_grid(64, a.ny, a.nz, cd);
-  if (bab > INT32_MAX || babab > INT32_MAX || bcd > INT32_MAX) return hipErrorInvalidValue;
-  auto cdc = [&](const T* in, T* out) {
-    const dim3 g(static_cast<unsigned>(bcd));
-    switch (a.ph.mode) {
-      case 0: hipLaunchKernelGGL((k_strang3d_cdc<T, 0>), g, dim3(256), 0, st, in, out, V, cd); break;
-      case 1: hipLaunchKernelGGL((k_strang3d_cdc<T, 1>), g, dim3(256), 0, st, in, out, V, cd); break;
-      default: hipLaunchKernelGGL((k_strang3d_cdc<T, 2>), g, dim3(256), 0, st, in, out, V, cd); break;
+  const int64_t bfirst = strang_step_grid<T, true>(a, first);
+  const int64_t bnext = strang_step_grid<T, false>(a, next);
+  if (bab > INT32_MAX || bfirst > INT32_MAX || bnext > INT32_MAX) return hipErrorInvalidValue;
+  const int mode = a.ph.mode;
+  // A B A + C D C, then per further step the closing A B A of one step and the
+  // opening one of the next + C D C, and a closing A B A: nsteps + 1 passes.
+  // The first pass writes the buffer that makes the last one land in `mid`.
+  auto step_pass = [&](bool first_pass, const T* in, T* out) {
+    const SweepArgs& t = first_pass ? first : next;
+    const dim3 g(static_cast<unsigned>(first_pass ? bfirst : bnext));
+    if (first_pass) {
+      switch (mode) {
+        case 0: hipLaunchKernelGGL((k_strang3d_step<T, 0, true>), g, dim3(256), 0, st, in, out, V, t); break;
+        case 1: hipLaunchKernelGGL((k_strang3d_step<T, 1, true>), g, dim3(256), 0, st, in, out, V, t); break;
+        default: hipLaunchKernelGGL((k_strang3d_step<T, 2, true>), g, dim3(256), 0, st, in, out, V, t); break;
+      }
+    } else {
+      switch (mode) {
+        case 0: hipLaunchKernelGGL((k_strang3d_step<T, 0, false>), g, dim3(256), 0, st, in, out, V, t); break;
+        case 1: hipLaunchKernelGGL((k_strang3d_step<T, 1, false>), g, dim3(256), 0, st, in, out, V, t); break;
+        default: hipLaunchKernelGGL((k_strang3d_step<T, 2, false>), g, dim3(256), 0, st, in, out, V, t); break;
+      }
     }
   };
-  // A B A, then C D C, and between two steps the trailing A B A of one and
-  // the leading A B A of the next in one pass: 2 nsteps + 1 passes
-  hipLaunchKernelGGL((k_strang3d_aba<T>), dim3(static_cast<unsigned>(bab)), dim3(256), 0, st, s,
-                     d, ab);
-  cdc(d, m);
+  T* cur = (nsteps % 2 == 1) ? m : d;
+  T* other = (cur == m) ? d : m;
+  step_pass(true, s, cur);
   for (int64_t n = 1; n < nsteps; ++n) {
-    hipLaunchKernelGGL((k_strang3d_abaaba<T>), dim3(static_cast<unsigned>(babab)), dim3(256), 0,
-                       st, m, d, abab);
-    cdc(d, m);
+    step_pass(false, cur, other);
+    T* t = cur;
+    cur = other;
+    other = t;
   }
-  hipLaunchKernelGGL((k_strang3d_aba<T>), dim3(static_cast<unsigned>(bab)), dim3(256), 0, st, m,
+  // cur == m here: the closing A B A into dst
+  hipLaunchKernelGGL((k_strang3d_aba<T>), dim3(static_cast<unsigned>(bab)), dim3(256), 0, st, cur,
                      d, ab);
   return hipGetLastError();
 }

@@ -78,7 +78,7 @@ def test_strang_klein_setup_small():
     assert rel_l2(got32, ref) <= 2e-5
 
 
-# ---- 3-D second-order steps: c dt = 4 dx, three passes per step ------------------
+# ---- 3-D second-order steps: c dt = 4 dx, K + 1 passes per group of K steps ------
 DT3 = 4 * DX / C
 SHAPES3 = [(37, 21, 13), (64, 8, 9), (70, 13, 11), (2, 3, 5)]
 
@@ -130,7 +130,7 @@ def test_strang3d_long_march_segments_vs_oracle(bc):
 @pytest.mark.parametrize("bc", ["zero", "periodic"])
 def test_strang3d_grouped_steps_same_bits(shape, bc):
     """Steps grouped so that consecutive A B A share a pass give the bits of
-    single steps (three passes each), for counts that are and are not
+    single steps (two passes each), for counts that are and are not
     multiples of the group."""
     announce(f"strang 3-D grouped {shape} {bc}")
     psi = random_spinor(shape[::-1], seed=8)
