@@ -94,5 +94,8 @@ void destroy_batch(dl_plan p);
 int reverse_depth(dl_plan p);
 // steps fused per pass of a batch
 int batch_depth(dl_plan b);
+// measures the occupancy of the 3-D second-order passes (called when such a
+// plan is created, outside any stream capture)
+void strang3d_prepare(bool fp64);
 
 }  // namespace dirac

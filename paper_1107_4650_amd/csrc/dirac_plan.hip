@@ -327,6 +327,7 @@ extern "C" int dl_plan_create(dl_plan* out, const dl_grid* g, double dx, double 
     p->cu_count = ncu;
   plan_tiling(p);
   const bool mid = strang && g->ndim == 3;  // the 3-D second-order step runs through a third buffer
+  if (mid) dirac::strang3d_prepare(p->fp64);
   if (hipMalloc(&p->tmp, p->state_bytes) != hipSuccess ||
       (mid && hipMalloc(&p->tmp2, p->state_bytes) != hipSuccess) ||
       hipMalloc(&p->partials, sizeof(double) * 2 * 8 * kObsBlocks) != hipSuccess ||

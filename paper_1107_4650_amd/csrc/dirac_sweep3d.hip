@@ -579,24 +579,49 @@ static const void* strang_step_kernel(int mode) {
   }
 }
 
+// waves of a step pass the device holds at once, measured when a plan that
+// uses the pass is created (never while a stream is being captured)
+template <typename T, bool FIRST>
+static int& strang_resident() {
+  static int waves = 0;
+  return waves;
+}
+
+template <typename T, bool FIRST>
+static void strang_measure() {
+  int occ = 0, dev = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, strang_step_kernel<T, FIRST>(2), 256,
+                                                   0) != hipSuccess) {
+    (void)hipGetLastError();
+    occ = 0;
+  }
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    cus = 0;
+  }
+  strang_resident<T, FIRST>() =
+      (occ > 0 ? occ : StrangShape<T>::kMinBlocks) * 4 * (cus > 0 ? cus : 256);
+}
+
+void strang3d_prepare(bool fp64) {
+  if (fp64) {
+    strang_measure<double, true>();
+    strang_measure<double, false>();
+  } else {
+    strang_measure<float, true>();
+    strang_measure<float, false>();
+  }
+}
+
 // grid of a fused second-order pass: z segments from a cost model, (rounds of
 // resident waves) x (H + 8 plane iterations)
 template <typename T, bool FIRST>
 static int64_t strang_step_grid(const SweepArgs& a, SweepArgs& t) {
   constexpr int TY = StrangShape<T>::TY;
   constexpr int XL = FIRST ? 2 : 4;
-  static int resident = 0;
-  if (resident == 0) {
-    int occ = 0, dev = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, strang_step_kernel<T, FIRST>(2), 256,
-                                                     0) != hipSuccess)
-      occ = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-      cus = 0;
-    (void)hipGetLastError();
-    resident = (occ > 0 ? occ : StrangShape<T>::kMinBlocks) * 4 * (cus > 0 ? cus : 256);
-  }
+  int resident = strang_resident<T, FIRST>();
+  if (resident <= 0) resident = StrangShape<T>::kMinBlocks * 4 * 256;
   t = a;
   t.nstrips = (a.nx + strip_width(XL) - 1) / strip_width(XL);
   t.nyblk = (a.ny + TY - 1) / TY;
