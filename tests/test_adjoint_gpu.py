@@ -242,3 +242,28 @@ def test_gradient_3d_vs_oracle(dtype):
     else:
         assert np.max(np.abs(Qh - dLdV)) <= 1e-3 * np.max(np.abs(dLdV))
         assert rel_l2(psi_rec, psi0) < 1e-5
+
+
+def test_reverse_3d_full_size_vs_oracle():
+    """512^3 reverse steps at the launch configuration of the benchmark's
+    3-D adjoint line: S^H applied twice to a packet state, every cell against
+    the oracle's adjoint step, in both precisions."""
+    import torch
+    from paper_1107_4650_amd.inputs import config_3d_sphere
+    w = config_3d_sphere(n=512, nsteps=2)
+    announce("3-D 512^3 x 2 reverse steps")
+    ref = O.adjoint_step(w.psi0, w.V, dt=w.dt, c=w.c, m=w.m, nsteps=2, axes=w.axes)
+    tV = dev(w.V)
+    for dtype, tol in (("c128", 1e-12), ("c64", 5e-6)):
+        tdt = torch.complex128 if dtype == "c128" else torch.complex64
+        with L.Plan(w.shape, w.dx, w.dt, w.c, w.m, dtype=dtype) as p:
+            lam = dev(w.psi0).to(tdt)
+            psi = torch.zeros_like(lam)
+            Q = torch.zeros(w.psi0.shape[:-1], dtype=torch.float64, device="cuda")
+            p.grad_step(psi, lam, tV, Q, 2)
+            torch.cuda.synchronize()
+            got = lam.cpu().numpy()
+        del lam, psi, Q
+        err = rel_l2(got, ref)
+        announce(f"{dtype}: rel-L2 {err:.3e}")
+        assert err <= tol, dtype
