@@ -50,36 +50,32 @@ def kernel_source_hash() -> str:
 
 
 def timed_sweep(plan, psi, V, steps, warmup, fused=1):
-    """Alternate psi <-> tmp with passes of `fused` steps each (dl_step_out for
-    one step, dl_step_fused_out otherwise: one launch per pass within the
-    plan's depth); HIP events around every launch on the launch stream.
-    `steps` counts time steps and is rounded down to whole passes.  Returns
-    (wall seconds, mean per-launch ms, final tensor, steps timed)."""
+    """Advance psi by `steps` time steps (rounded down to whole passes of
+    `fused` steps) and time it.  The steps run as one dl_step call, which
+    enqueues the passes back to back in the library (ping-ponging psi and the
+    plan's buffer, ending in psi for an even pass count); HIP events are
+    recorded on the launch stream before and after the call (the pass count
+    is rounded down to an even number).  Returns
+    (wall seconds, mean per-launch ms from the events, final tensor, steps
+    timed)."""
     import torch
-    if fused == 1:
-        def launch(a, b):
-            plan.step_out(a, b, V)
-    else:
-        def launch(a, b):
-            plan.step_fused_out(a, b, V, fused)
     nl, nw = max(1, steps // fused), max(0, warmup // fused)
-    a, b = psi, torch.empty_like(psi)
-    for _ in range(nw):
-        launch(a, b)
-        a, b = b, a
+    if nl > 1 and nl % 2:
+        nl -= 1  # an even pass count ends in psi: no copy back inside the timed region
+    if fused > 1 and plan.info()["depth"] != fused:
+        plan.set_depth(fused)
+    if nw:
+        plan.step(psi, V, nw * fused)
     torch.cuda.synchronize()
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(nl)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(nl)]
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
-    for i in range(nl):
-        starts[i].record()
-        launch(a, b)
-        ends[i].record()
-        a, b = b, a
+    start.record()
+    plan.step(psi, V, nl * fused)
+    end.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    per = float(np.mean([s.elapsed_time(e) for s, e in zip(starts, ends)]))
-    return wall, per, a, nl * fused
+    per = start.elapsed_time(end) / nl
+    return wall, per, psi, nl * fused
 
 
 def to_dev(x, dtype=None):
@@ -470,6 +466,44 @@ def bench_3d(args):
         log(f"3-D 512^3 {dt_name}: {per:.3f} ms/launch of {K} step(s)")
         del psi
         torch.cuda.empty_cache()
+    if args.accuracy3d_steps > 0:
+        out["f32_vs_f64"] = accuracy_3d(n, dx, c, m, gx, gy, gz, u, V, args.accuracy3d_steps)
+    return out
+
+
+def accuracy_3d(n, dx, c, m, gx, gy, gz, u, V, steps):
+    """The 3-D workload's stated check: FP32 bulk vs the FP64 GPU run after
+    `steps` steps (2000 by default, the workload's length), relative L2 over
+    every cell, with each run's time."""
+    import torch
+    from paper_1107_4650_amd import libdirac as L
+    res = {}
+    for name, tdt in (("c128", torch.complex128), ("c64", torch.complex64)):
+        f = (gz[:, None, None] * gy[None, :, None] * gx[None, None, :])
+        psi = (f[..., None] * u).to(tdt).contiguous()
+        del f
+        with L.Plan((n, n, n), dx, dx / c, c, m, dtype=name) as p:
+            torch.cuda.synchronize()
+            s_, e_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            s_.record()
+            p.step(psi, V, steps)
+            e_.record()
+            torch.cuda.synchronize()
+            res[name] = (psi, s_.elapsed_time(e_), p.observables(psi, 0.0))
+    num = den = 0.0
+    for k in range(0, n, 64):
+        a = res["c64"][0][k:k + 64].to(torch.complex128)
+        b = res["c128"][0][k:k + 64]
+        num += float(torch.sum(torch.abs(a - b) ** 2))
+        den += float(torch.sum(torch.abs(b) ** 2))
+    err = (num / den) ** 0.5
+    out = {"steps": steps, "rel_l2": err, "bar": 1e-4,
+           "f32_s": res["c64"][1] / 1e3, "f64_s": res["c128"][1] / 1e3,
+           "norm_f32": res["c64"][2][0], "norm_f64": res["c128"][2][0]}
+    del res
+    torch.cuda.empty_cache()
+    log(f"3-D 512^3 FP32 vs FP64 after {steps} steps: rel-L2 {err:.3e} "
+        f"({out['f32_s']:.2f} s / {out['f64_s']:.2f} s)")
     return out
 
 
@@ -528,8 +562,13 @@ def bench_adjoint(args):
         gn = float(torch.linalg.vector_norm(g))
         K = p.info()["reverse_depth"]
     sites = w.sites * w.nsteps
-    log(f"adjoint: fwd {fwd_ms:.2f} ms, bwd {bwd_ms:.2f} ms, reconstruction {rec:.2e}")
+    g32 = g.cpu().numpy()
+    check = adjoint_checks(w, G, theta, g32)
+    log(f"adjoint: fwd {fwd_ms:.2f} ms, bwd {bwd_ms:.2f} ms, reconstruction {rec:.2e}, "
+        f"FP32 vs FP64 gradient {check['fp32_vs_fp64_max_rel']:.2e}, "
+        f"FD {check['fd_max_rel']:.2e}")
     return {"steps": w.nsteps, "forward_ms": fwd_ms, "backward_ms": bwd_ms,
+            "checks": check,
             "forward_site_updates_per_s": sites / (fwd_ms * 1e-3),
             "backward_site_updates_per_s": sites / (bwd_ms * 1e-3),
             # a reverse pass reads psi, lambda, V, Q and writes psi, lambda, Q once
@@ -537,6 +576,50 @@ def bench_adjoint(args):
             "backward_steps_per_pass": K, "backward_bytes_per_cell_per_pass": 152,
             "backward_roofline_frac": 152 / K * sites / (bwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "loss_P_T": L_T, "grad_norm": gn, "psi0_reconstruction_rel_l2": rec}
+
+
+def adjoint_checks(w, G, theta, g32, h_au=1e-3, nfd=4):
+    """The adjoint workload's stated checks: the FP32 dL/dtheta against the
+    FP64 GPU gradient, and the FP64 gradient against central finite
+    differences of the FP64 forward run, on the `nfd` bumps of largest
+    gradient.  The amplitudes are energies drawn from [-1, 1] m c^2; the
+    difference step is h_au = 1e-3 atomic units of energy (1e-3 / (m c^2) in
+    the units of theta here, where V = m c^2 sum theta_j g_j)."""
+    h = h_au / (w.m * w.c * w.c)
+    import torch
+    from paper_1107_4650_amd import libdirac as L
+    x_b = w.extra["x_b"]
+    with L.Plan(w.shape, w.dx, w.dt, w.c, w.m, dtype="c128", bc="periodic", xmin=w.xmin) as p:
+        V = torch.empty(w.psi0.shape[:-1], dtype=torch.float64, device="cuda")
+
+        def forward(th):
+            psi = to_dev(w.psi0)
+            p.expand(G, th, V)
+            p.step(psi, V, w.nsteps)
+            return psi, p.observables(psi, x_b)[4]
+
+        psi, _ = forward(theta)
+        lam = torch.empty_like(psi)
+        Q = torch.empty_like(V)
+        p.seed_adjoint(psi, x_b, lam, Q)
+        p.grad_step(psi, lam, V, Q, w.nsteps)
+        g = torch.empty(G.shape[0], dtype=torch.float64, device="cuda")
+        p.project(Q, G, g)
+        g64 = g.cpu().numpy()
+        scale = float(np.max(np.abs(g64)))
+        fd = {}
+        for j in np.argsort(-np.abs(g64))[:nfd]:
+            e = torch.zeros_like(theta)
+            e[int(j)] = h
+            lp = forward(theta + e)[1]
+            lm = forward(theta - e)[1]
+            fd[int(j)] = ((lp - lm) / (2 * h), float(g64[j]))
+        del psi, lam, Q, V
+    return {"fp32_vs_fp64_max_rel": float(np.max(np.abs(g32 - g64))) / scale, "bar_fp32": 1e-3,
+            "grad_norm_fp64": float(np.linalg.norm(g64)),
+            "fd_h_atomic_units": h_au, "theta_unit": "m c^2",
+            "fd": {str(j): {"central_difference": a, "adjoint_fp64": b} for j, (a, b) in fd.items()},
+            "fd_max_rel": max(abs(a - b) for a, b in fd.values()) / scale, "bar_fd": 1e-5}
 
 
 def bench_batch(args):
@@ -633,7 +716,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--steps3d", type=int, default=50)
     ap.add_argument("--adjoint-steps", type=int, default=4000)
-    ap.add_argument("--batch-steps", type=int, default=500)
+    ap.add_argument("--batch-steps", type=int, default=5000)
+    ap.add_argument("--accuracy3d-steps", type=int, default=2000,
+                    help="steps of the 3-D FP32-vs-FP64 check (0 skips it)")
     ap.add_argument("--klein-steps", type=int, default=12000,
                     help="steps of the paper's 2-D Klein run (0 skips it)")
     ap.add_argument("--only", choices=["all", "sweep", "main", "klein", "3d"], default="all")

@@ -57,7 +57,11 @@ typedef enum {
     DL_ERR_ALIGN = -4,  /* a pointer is not aligned as required */
     DL_ERR_NOMEM = -5,  /* device allocation failed */
     DL_ERR_HIP = -6,    /* a HIP runtime call or kernel failed */
-    DL_ERR_STATE = -7   /* call not allowed on this plan (e.g. a dry plan) */
+    DL_ERR_STATE = -7,  /* call not allowed on this plan (e.g. a dry plan) */
+    DL_ERR_NONFINITE = -8, /* dl_observables: the state holds a NaN or an infinity
+                              (out[] is still written; its sums are then not finite) */
+    DL_WARN_NORM = 1    /* dl_observables: the norm left the band set with
+                           dl_plan_set_norm_check (out[] is written; a warning) */
 } dl_status;
 
 typedef enum { DL_C64 = 0, DL_C128 = 1 } dl_dtype;
@@ -161,8 +165,23 @@ int dl_step_fused_out(dl_plan p, const void *src, void *dst, const double *V, in
  *   out[0] = N    = dV sum |psi|^2            (dV = dx^ndim)
  *   out[1..3]     = sum x_d |psi|^2 / sum |psi|^2 along grid dims 0..2 (0 if absent)
  *   out[4] = P_T  = dV sum_{x_0 > x_b} |psi|^2 (cell centres, strict >)
- * Synchronises `stream`. */
+ * Synchronises `stream`.  Returns DL_ERR_NONFINITE when a cell holds a NaN or
+ * an infinity (the sums then are not finite: no finite state gives an
+ * infinite N), and DL_WARN_NORM when the plan's norm check is set and N left
+ * its band (below); out[] is written in both cases. */
 int dl_observables(dl_plan p, const void *psi, double x_b, double out[5], void *stream);
+
+/* Norm watchdog of dl_observables.  The transports of eq:sol_dis_1-3 are
+ * unitary on a periodic box and, with the zero wall of Sec. 5, only lose the
+ * probability that crosses the wall; the local step D of eq:sol_dis_4 (and the
+ * U of Sec. 2.3) is unitary.  So N = dV sum |psi|^2 never grows beyond its
+ * value at the start of a run except by rounding (about 1e-7 relative per
+ * 1e4 steps in FP32), and on a periodic box it does not shrink either.  With
+ * tol > 0, dl_observables returns DL_WARN_NORM when N > N_ref (1 + tol), or,
+ * on a periodic plan, when N < N_ref (1 - tol).  tol = 0 (the default) turns
+ * the check off.  N_ref > 0 and tol >= 0, both finite (DL_ERR_ARG otherwise).
+ * Works on DL_DRY plans (it only records the values). */
+int dl_plan_set_norm_check(dl_plan p, double N_ref, double tol);
 
 /* Seed the adjoint of L = P_T(psi_N): lam = M psi with M the indicator of
  * x_0 > x_b, and Q = 0.  lam has psi's layout, Q one double per cell. */

@@ -56,6 +56,8 @@ struct dl_plan_s {
   bool resident = false;
   int res_threads = 0;
   int64_t graph_pairs = 32;  // a captured graph holds 2 * graph_pairs steps
+  double norm_ref = 0.0;     // norm watchdog of dl_observables (off while norm_tol == 0)
+  double norm_tol = 0.0;
   // scratch
   void* tmp = nullptr;         // second state buffer
   void* tmp2 = nullptr;        // second state buffer for the adjoint field

@@ -618,6 +618,27 @@ extern "C" int dl_step_fused_out(dl_plan p, const void* src, void* dst, const do
   return DL_OK;
 }
 
+// status of an observables result: a non-finite sum means a non-finite cell
+// (|psi|^2 of finite FP32 / FP64 values cannot overflow a double sum of fewer
+// than 2^40 cells); then the norm watchdog
+static int observables_status(dl_plan p, const double* out) {
+  for (int i = 0; i < 5; ++i)
+    if (!std::isfinite(out[i]))
+      return fail(DL_ERR_NONFINITE, "the state holds a NaN or an infinity (observable %d = %g)",
+                  i, out[i]);
+  if (p->norm_tol > 0.0) {
+    const double N = out[0], hi = p->norm_ref * (1.0 + p->norm_tol),
+                 lo = p->norm_ref * (1.0 - p->norm_tol);
+    if (N > hi)
+      return fail(DL_WARN_NORM, "norm %.17g exceeds the reference %.17g by more than %g", N,
+                  p->norm_ref, p->norm_tol);
+    if (p->bc == DL_BC_PERIODIC && N < lo)
+      return fail(DL_WARN_NORM, "norm %.17g fell below the reference %.17g by more than %g "
+                  "on a periodic box", N, p->norm_ref, p->norm_tol);
+  }
+  return DL_OK;
+}
+
 extern "C" int dl_observables(dl_plan p, const void* psi, double x_b, double out[5],
                               void* stream) {
   int rc = check_live(p);
@@ -644,6 +665,16 @@ extern "C" int dl_observables(dl_plan p, const void* psi, double x_b, double out
   e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
   for (int i = 0; i < 5; ++i) out[i] = p->hres[i];
+  return observables_status(p, out);
+}
+
+extern "C" int dl_plan_set_norm_check(dl_plan p, double N_ref, double tol) {
+  if (!p) return fail(DL_ERR_ARG, "plan is NULL");
+  if (p->is_batch) return fail(DL_ERR_STATE, "a batch handle has no observables");
+  if (!finite_pos(N_ref) || !std::isfinite(tol) || tol < 0.0)
+    return fail(DL_ERR_ARG, "need N_ref > 0 and tol >= 0, both finite");
+  p->norm_ref = N_ref;
+  p->norm_tol = tol;
   return DL_OK;
 }
 

@@ -17,8 +17,10 @@ LIB_PATH = os.path.join(_HERE, "lib", "libdirac.so")
 
 DL_OK, DL_ERR_ARG, DL_ERR_CFL, DL_ERR_DTYPE, DL_ERR_ALIGN, DL_ERR_NOMEM, DL_ERR_HIP, DL_ERR_STATE = (
     0, -1, -2, -3, -4, -5, -6, -7)
+DL_ERR_NONFINITE, DL_WARN_NORM = -8, 1
 STATUS_NAMES = {0: "DL_OK", -1: "DL_ERR_ARG", -2: "DL_ERR_CFL", -3: "DL_ERR_DTYPE",
-                -4: "DL_ERR_ALIGN", -5: "DL_ERR_NOMEM", -6: "DL_ERR_HIP", -7: "DL_ERR_STATE"}
+                -4: "DL_ERR_ALIGN", -5: "DL_ERR_NOMEM", -6: "DL_ERR_HIP", -7: "DL_ERR_STATE",
+                -8: "DL_ERR_NONFINITE", 1: "DL_WARN_NORM"}
 DL_C64, DL_C128 = 0, 1
 DL_BC_ZERO, DL_BC_PERIODIC = 0, 1
 DL_DRY, DL_GRAPH, DL_STRANG, DL_BISPINOR = 1, 2, 4, 8
@@ -26,7 +28,7 @@ DL_DRY, DL_GRAPH, DL_STRANG, DL_BISPINOR = 1, 2, 4, 8
 # every entry point of include/libdirac.h
 EXPORTS = ("dl_plan_create", "dl_plan_destroy", "dl_step", "dl_step_field", "dl_step_out",
            "dl_step_fused_out",
-           "dl_observables", "dl_seed_adjoint",
+           "dl_observables", "dl_plan_set_norm_check", "dl_seed_adjoint",
            "dl_grad_step", "dl_project", "dl_expand", "dl_batch_create", "dl_batch_step",
            "dl_plan_set_tiling", "dl_plan_set_depth", "dl_plan_info", "dl_batch_set",
            "dl_batch_autotune", "dl_last_error", "dl_version")
@@ -36,6 +38,11 @@ class DiracError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
         self.code = code
+
+
+class NormWarning(UserWarning):
+    """dl_observables reported DL_WARN_NORM: the norm left the band of the
+    plan's norm check."""
 
 
 class Grid(ctypes.Structure):
@@ -69,6 +76,7 @@ def load() -> ctypes.CDLL:
         "dl_step_fused_out": [vp, vp, vp, vp, i64, vp],
         "dl_plan_set_depth": [vp, ci],
         "dl_observables": [vp, vp, dbl, P(dbl), vp],
+        "dl_plan_set_norm_check": [vp, dbl, dbl],
         "dl_seed_adjoint": [vp, vp, dbl, vp, vp, vp],
         "dl_grad_step": [vp, vp, vp, vp, vp, i64, vp],
         "dl_project": [vp, vp, vp, ci, vp, vp],
@@ -219,10 +227,23 @@ class Plan:
         check(self.lib.dl_plan_set_depth(self.handle, int(depth)))
 
     def observables(self, psi, x_b=0.0) -> np.ndarray:
+        """[N, <x>, <y>, <z>, P_T].  Raises DiracError (DL_ERR_NONFINITE) for a
+        state holding a NaN or an infinity; warns (NormWarning) when the norm
+        check set with set_norm_check trips."""
         out = (ctypes.c_double * 5)()
-        check(self.lib.dl_observables(self.handle, self._state(psi), float(x_b), out,
-                                      _stream_handle()))
+        rc = self.lib.dl_observables(self.handle, self._state(psi), float(x_b), out,
+                                     _stream_handle())
+        if rc == DL_WARN_NORM:
+            import warnings
+            warnings.warn(self.lib.dl_last_error().decode(), NormWarning, stacklevel=2)
+        else:
+            check(rc)
         return np.array(out[:])
+
+    def set_norm_check(self, N_ref, tol):
+        """Norm watchdog of observables(): warn when N > N_ref (1 + tol), or on a
+        periodic box N < N_ref (1 - tol); tol = 0 turns it off."""
+        check(self.lib.dl_plan_set_norm_check(self.handle, float(N_ref), float(tol)))
 
     def seed_adjoint(self, psi, x_b, lam, Q):
         check(self.lib.dl_seed_adjoint(self.handle, self._state(psi), float(x_b),

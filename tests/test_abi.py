@@ -202,3 +202,15 @@ def test_dry_batch_validation(lib):
     with pytest.raises(L.DiracError) as ei:
         L.Batch([(128,), (64, 32)], [0.01, 0.01], [0.01 / C, 0.02 / C], C, 1.0, dry=True)
     assert ei.value.code == L.DL_ERR_CFL
+
+
+def test_dry_norm_check_arguments(lib):
+    """dl_plan_set_norm_check records its band on any plan and rejects bad values."""
+    p = dry((64,))
+    p.set_norm_check(1.0, 1e-6)
+    p.set_norm_check(1.0, 0.0)  # off
+    for ref, tol in ((0.0, 1e-6), (-1.0, 1e-6), (1.0, -1e-6), (float("nan"), 1e-6),
+                     (1.0, float("inf"))):
+        assert code_of(lambda: p.set_norm_check(ref, tol)) == L.DL_ERR_ARG
+    p.close()
+    assert lib.dl_plan_set_norm_check(None, 1.0, 0.0) == L.DL_ERR_ARG

@@ -267,3 +267,101 @@ def test_reverse_3d_full_size_vs_oracle():
         err = rel_l2(got, ref)
         announce(f"{dtype}: rel-L2 {err:.3e}")
         assert err <= tol, dtype
+
+
+def _adjoint_run(w, dtype, theta):
+    """Forward (dl_expand, dl_step, dl_observables) and reverse sweep
+    (dl_seed_adjoint, dl_grad_step, dl_project) of the adjoint workload;
+    returns (L, dL/dtheta, rel-L2 of the rebuilt psi_0)."""
+    import torch
+    tdt = torch.complex128 if dtype == "c128" else torch.complex64
+    G = dev(w.extra["dVdtheta"])
+    x_b = w.extra["x_b"]
+    with L.Plan(w.shape, w.dx, w.dt, w.c, w.m, dtype=dtype, bc="periodic", xmin=w.xmin) as p:
+        psi0 = dev(w.psi0).to(tdt)
+        psi = psi0.clone()
+        V = torch.empty(w.psi0.shape[:-1], dtype=torch.float64, device="cuda")
+        p.expand(G, dev(theta), V)
+        p.step(psi, V, w.nsteps)
+        loss = p.observables(psi, x_b)[4]
+        lam = torch.empty_like(psi)
+        Q = torch.empty_like(V)
+        p.seed_adjoint(psi, x_b, lam, Q)
+        p.grad_step(psi, lam, V, Q, w.nsteps)
+        g = torch.empty(G.shape[0], dtype=torch.float64, device="cuda")
+        p.project(Q, G, g)
+        torch.cuda.synchronize()
+        a = psi.to(torch.complex128)
+        b = psi0.to(torch.complex128)
+        rec = float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+        return loss, g.cpu().numpy(), rec
+
+
+def _forward_loss(w, theta):
+    import torch
+    G = dev(w.extra["dVdtheta"])
+    with L.Plan(w.shape, w.dx, w.dt, w.c, w.m, dtype="c128", bc="periodic", xmin=w.xmin) as p:
+        psi = dev(w.psi0)
+        V = torch.empty(w.psi0.shape[:-1], dtype=torch.float64, device="cuda")
+        p.expand(G, dev(theta), V)
+        p.step(psi, V, w.nsteps)
+        return p.observables(psi, w.extra["x_b"])[4]
+
+
+def test_config_adjoint_full_size():
+    """The adjoint workload as stated: 1024^2 periodic box, V from 64 Gaussian
+    bumps, 4000 steps, L = probability past x_b = 5.  dL/dtheta from the FP32
+    state against the FP64 GPU gradient (the FP64 path is pinned to the
+    oracle's checkpointed gradient above), and the FP64 gradient against
+    central finite differences of the FP64 forward run on the four bumps of
+    largest gradient.  The amplitudes theta_j are energies (drawn from
+    [-1, 1] m c^2) and the difference step is h = 1e-3 atomic units of
+    energy: the phase it adds over the run, h t = 6e-4 rad, keeps the
+    difference in the linear regime (a step of 1e-3 m c^2 would add 11 rad)."""
+    from paper_1107_4650_amd.inputs import config_adjoint
+    w = config_adjoint(n=1024, nsteps=4000)
+    theta = w.extra["theta"]
+    announce("adjoint 1024^2 x 4000 steps: FP64 and FP32 gradients")
+    L64, g64, rec64 = _adjoint_run(w, "c128", theta)
+    L32, g32, rec32 = _adjoint_run(w, "c64", theta)
+    scale = float(np.max(np.abs(g64)))
+    err32 = float(np.max(np.abs(g32 - g64))) / scale
+    announce(f"L = {L64:.15f} (FP32 {L32:.9f}); |g| = {np.linalg.norm(g64):.6e}; "
+             f"FP32 vs FP64 max rel {err32:.3e}; psi0 rebuilt to {rec64:.2e} / {rec32:.2e}")
+    assert abs(L32 - L64) <= 1e-5
+    assert err32 <= 1e-3
+    assert rec64 <= 1e-11 and rec32 <= 1e-4
+    # theta here is in units of m c^2 (V = m c^2 sum theta_j g_j): the step of
+    # 1e-3 atomic units is 1e-3 / (m c^2) in these units
+    h = 1e-3 / (w.m * w.c * w.c)
+    fd_err = []
+    for j in np.argsort(-np.abs(g64))[:4]:
+        e = np.zeros_like(theta)
+        e[j] = h
+        fd = (_forward_loss(w, theta + e) - _forward_loss(w, theta - e)) / (2 * h)
+        fd_err.append(abs(fd - g64[j]) / scale)
+        announce(f"bump {j}: adjoint {g64[j]:.9e}, central FD {fd:.9e}")
+    assert max(fd_err) <= 1e-5, fd_err
+
+
+def test_autograd_warns_when_a_wall_breaks_the_reconstruction():
+    """Zero walls: once the packet has crossed a wall, S^H no longer inverts the
+    forward steps; backward says so (ReconstructionWarning).  The same run
+    stopped before the packet reaches the wall raises no warning."""
+    import torch
+    import warnings
+    from paper_1107_4650_amd.autograd import ReconstructionWarning, transmitted_probability
+    announce("autograd wall warning")
+    shape, dx = (400,), 0.01
+    xmin = [-2.0]
+    G = bump_basis(shape, dx, np.array([[0.3]]), 0.2) * (C * C)
+    psi0 = packet(shape, dx, delta=0.1, p0=[60.0], r0=[1.2])
+    with L.Plan(shape, dx, dx / C, C, 1.0, dtype="c128", xmin=xmin) as p:
+        for nsteps, expect in ((40, False), (600, True)):
+            theta = dev(np.array([0.2])).requires_grad_(True)
+            Lv = transmitted_probability(theta, p, dev(psi0), dev(G), nsteps, 0.0)
+            with warnings.catch_warnings(record=True) as rec:
+                warnings.simplefilter("always")
+                Lv.backward()
+            got = any(issubclass(r.category, ReconstructionWarning) for r in rec)
+            assert got == expect, (nsteps, [str(r.message) for r in rec])

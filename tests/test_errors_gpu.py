@@ -1,0 +1,128 @@
+"""Error paths of the C ABI on real (non-dry) plans: misaligned pointers,
+negative step counts, a NaN in V or an infinity in psi (DL_ERR_NONFINITE from
+dl_observables), and the norm watchdog (DL_WARN_NORM).  No kernel is made to
+fault: every rejected call is refused on the host, and the NaN / infinity
+cases run ordinary kernels on ordinary (if non-finite) values."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_1107_4650_amd import libdirac as L
+from paper_1107_4650_amd.inputs import C_LIGHT, packet, random_spinor
+from tests.gpu_util import announce
+
+pytestmark = pytest.mark.gpu
+
+DX = 0.01
+
+
+def _plan(shape, dtype="c64", bc="zero"):
+    return L.Plan(shape, DX, DX / C_LIGHT, C_LIGHT, 1.0, dtype=dtype, bc=bc)
+
+
+def test_misaligned_pointers_and_negative_counts():
+    import torch
+    announce("errors: alignment and counts")
+    lib = L.load()
+    with _plan((64, 32)) as p:
+        raw = torch.zeros(32 * 64 * 4 * 2 + 4, dtype=torch.float32, device="cuda")
+        base = raw.data_ptr()
+        assert base % 16 == 0
+        V = torch.zeros((32, 64), dtype=torch.float64, device="cuda")
+        st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        # psi 8 bytes off a 16-byte boundary
+        assert lib.dl_step(p.handle, ctypes.c_void_p(base + 8), None, 1, st) == L.DL_ERR_ALIGN
+        assert b"aligned" in lib.dl_last_error()
+        assert lib.dl_step_out(p.handle, ctypes.c_void_p(base), ctypes.c_void_p(base + 8 + 65536),
+                               None, st) == L.DL_ERR_ALIGN
+        # V 4 bytes off an 8-byte boundary
+        vraw = torch.zeros(32 * 64 + 1, dtype=torch.float64, device="cuda")
+        assert lib.dl_step(p.handle, ctypes.c_void_p(base), ctypes.c_void_p(vraw.data_ptr() + 4),
+                           1, st) == L.DL_ERR_ALIGN
+        # negative step counts
+        assert lib.dl_step(p.handle, ctypes.c_void_p(base), ctypes.c_void_p(V.data_ptr()), -1,
+                           st) == L.DL_ERR_ARG
+        assert b"< 0" in lib.dl_last_error()
+        lam = torch.zeros((32, 64, 4), dtype=torch.complex64, device="cuda")
+        Q = torch.zeros((32, 64), dtype=torch.float64, device="cuda")
+        assert lib.dl_grad_step(p.handle, ctypes.c_void_p(base), ctypes.c_void_p(lam.data_ptr()),
+                                None, ctypes.c_void_p(Q.data_ptr()), -3, st) == L.DL_ERR_ARG
+        assert lib.dl_step_fused_out(p.handle, ctypes.c_void_p(base),
+                                     ctypes.c_void_p(lam.data_ptr()), None, 0, st) == L.DL_ERR_ARG
+        # nothing was enqueued by the refused calls: the buffer is still zero
+        torch.cuda.synchronize()
+        assert float(raw.abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_nan_in_V_is_reported_by_observables(dtype):
+    import torch
+    announce(f"errors: NaN in V {dtype}")
+    shape = (96, 40)
+    psi0 = packet(shape, DX, delta=0.1, p0=[20.0, 0.0], r0=[0.0, 0.0])
+    V = np.zeros(shape[::-1])
+    V[20, 48] = np.nan
+    tdt = torch.complex64 if dtype == "c64" else torch.complex128
+    with _plan(shape, dtype) as p:
+        psi = torch.from_numpy(psi0).to("cuda").to(tdt)
+        obs = p.observables(psi)
+        assert np.all(np.isfinite(obs))
+        p.step(psi, torch.from_numpy(V).to("cuda"), 7)
+        with pytest.raises(L.DiracError) as ei:
+            p.observables(psi)
+        assert ei.value.code == L.DL_ERR_NONFINITE
+        # an infinity in an otherwise finite state is flagged the same way
+        psi = torch.from_numpy(psi0).to("cuda").to(tdt)
+        psi[3, 5, 2] = complex(float("inf"), 0.0)
+        with pytest.raises(L.DiracError) as ei:
+            p.observables(psi)
+        assert ei.value.code == L.DL_ERR_NONFINITE
+
+
+def test_norm_watchdog():
+    """Periodic box: 200 FP64 steps keep N within 1e-12 of its start (no
+    warning); a state scaled by 1 + 1e-6 trips a band of 1e-9 either way.
+    Zero walls: a packet leaving the box lowers N without a warning, a
+    growing norm still warns."""
+    import torch
+    import warnings
+    announce("errors: norm watchdog")
+    shape = (64, 48)
+    psi0 = random_spinor(shape[::-1], seed=5)
+    V = torch.from_numpy(np.random.default_rng(6).uniform(-1, 1, shape[::-1]) * C_LIGHT ** 2)
+    with _plan(shape, "c128", bc="periodic") as p:
+        psi = torch.from_numpy(psi0).to("cuda")
+        N0 = p.observables(psi)[0]
+        p.set_norm_check(N0, 1e-12)
+        p.step(psi, V.to("cuda"), 200)
+        with warnings.catch_warnings():
+            warnings.simplefilter("error")
+            N1 = p.observables(psi)[0]
+        assert abs(N1 - N0) <= 1e-12 * N0
+        p.set_norm_check(N0, 1e-9)
+        for f in (1.0 + 1e-6, 1.0 - 1e-6):
+            with pytest.warns(L.NormWarning):
+                p.observables(psi * f)
+        rc = p.lib.dl_observables(p.handle, ctypes.c_void_p((psi * 1.001).data_ptr()), 0.0,
+                                  (ctypes.c_double * 5)(), None)
+        assert rc == L.DL_WARN_NORM
+    # a massless packet of right movers only (spinor (g, 0, 0, g) is an
+    # eigenvector of alpha_x): it streams one cell per step and leaves through
+    # the right wall; N falls without a warning
+    shape = (200,)
+    x = np.arange(200)
+    g = np.exp(-((x - 150.0) / 6.0) ** 2)
+    psi0 = np.zeros((200, 4), dtype=np.complex128)
+    psi0[:, 0] = psi0[:, 3] = g
+    with L.Plan(shape, DX, DX / C_LIGHT, C_LIGHT, 0.0, dtype="c128") as p:
+        psi = torch.from_numpy(psi0).to("cuda")
+        N0 = p.observables(psi)[0]
+        p.set_norm_check(N0, 1e-9)
+        p.step(psi, None, 50)  # half of the packet has crossed the wall
+        with warnings.catch_warnings():
+            warnings.simplefilter("error")
+            N1 = p.observables(psi)[0]
+        assert 0.3 * N0 < N1 < 0.7 * N0
+        with pytest.warns(L.NormWarning):
+            p.observables(psi * float(np.sqrt(2.0 * N0 / N1)))

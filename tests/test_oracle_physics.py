@@ -130,9 +130,13 @@ def test_klein_1d_transmission_coarse(oracle, V0):
         assert abs(T - Tth) / Tth < 0.02
 
 
-@pytest.mark.slow
-@pytest.mark.parametrize("V0", [4.5e4, 6.0e4, 1.0e5])
+@pytest.mark.parametrize("V0", [
+    pytest.param(4.5e4, marks=pytest.mark.slow),
+    6.0e4,  # runs by default: the paper's own accuracy claim pins the oracle
+    pytest.param(1.0e5, marks=pytest.mark.slow),
+])
 def test_klein_1d_transmission_paper_cell(oracle, V0):
-    """The paper's cell size a = 6.10e-4 (dt = 4.45e-6): within 0.5 %."""
+    """The paper's cell size a = 6.10e-4 (dt = 4.45e-6): within 0.5 % of
+    eq:trans_co, the accuracy Sec. 5.2.1 reports for every barrier height."""
     T, Tth = _klein_run(oracle, V0, a=10.0 / 16384)
     assert abs(T - Tth) / Tth < 0.005
