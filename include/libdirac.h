@@ -147,6 +147,36 @@ int dl_step(dl_plan p, void *psi, const double *V, int64_t nsteps, void *stream)
 int dl_step_field(dl_plan p, void *psi, const double *V, const double *A, int64_t nsteps,
                   void *stream);
 
+/* A time-dependent vector potential A(t, x) = f(t) P(x): a laser pulse with a
+ * linear turn-on ramp, the kind of field whose integral Sec. 2.3 notes is
+ * known in closed form.  f(t) = w(t) sin(omega t + phase), with the
+ * trapezoid envelope w: 0 for t < 0, t / t_on on [0, t_on), 1 on
+ * [t_on, t_on + t_flat), falling linearly to 0 over t_off, 0 afterwards (a
+ * zero t_on or t_off is a step).  All in atomic units. */
+typedef struct {
+    double omega;   /* carrier angular frequency */
+    double phase;   /* carrier phase at t = 0 */
+    double t_on;    /* rise time of the envelope (>= 0) */
+    double t_flat;  /* duration of the plateau (>= 0) */
+    double t_off;   /* fall time (>= 0) */
+} dl_pulse;
+
+/* nsteps steps whose local step carries the pulse (eq:sol_dis_4 with the U of
+ * Sec. 2.3, as dl_step_field): step n = 0 .. nsteps - 1 covers
+ * [t0 + n dt, t0 + (n + 1) dt] and uses the field integral (eq:field_dis1)
+ *     At^n(x) = P(x) F_n,  F_n = int_{t0 + n dt}^{t0 + (n + 1) dt} f(t) dt,
+ * F_n evaluated on the device in closed form for every step (so passes still
+ * fuse up to 3 lowest-order steps, each with its own F_n; 1-D and 2-D grids,
+ * both splittings).  3-D grids: lowest-order steps, one per pass (DL_ERR_ARG
+ * for 3-D DL_STRANG plans).  P: device array of 3 * cells doubles, planar
+ * (x, y, z blocks in psi's cell order): e times the amplitude of A at the
+ * cell centres.  pulse: HOST struct; finite values, durations >= 0 (DL_ERR_ARG
+ * otherwise).  V as in dl_step.  The bits do not depend on how the steps are
+ * grouped into passes (a step's time is formed from its index).  Same buffers
+ * and copy rule as dl_step. */
+int dl_step_pulse(dl_plan p, void *psi, const double *V, const double *P,
+                  const dl_pulse *pulse, double t0, int64_t nsteps, void *stream);
+
 /* One step out of place: dst = S src (same step as dl_step with nsteps = 1).
  * src and dst must not overlap; src is left unchanged.  Lets a caller keep
  * both time levels, or alternate two buffers without the copy dl_step makes

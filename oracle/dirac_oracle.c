@@ -40,6 +40,13 @@
  *     A = sqrt((m c^2 dt)^2 + Atilde . Atilde), written as the printed 4x4
  *     matrix; Atilde (the field integral e int A dtau over the step,
  *     eq:field_dis1) is given per cell.
+ *   - A time-dependent vector potential A(t, x) = f(t) P(x) of the kind
+ *     Sec. 2.3 names (a laser pulse with a linear turn-on ramp):
+ *     f(t) = w(t) sin(omega t + phase) with a trapezoid envelope w.  The
+ *     field integral of each step, Atilde^n(x) = P(x) int_{t_n}^{t_{n+1}} f
+ *     (eq:field_dis1), is evaluated by Gauss-Legendre quadrature on the
+ *     pieces of the step between the envelope's corners; D is then the field
+ *     step above with that Atilde.
  *   - Observables: norm, mean coordinates and the probability beyond x_b
  *     (Sec. 5.2.1, R/T integrals), as sequential Neumaier sums in FP64.
  *   - The discrete adjoint of the step (derived from eq:sol_dis_1-4) by
@@ -499,6 +506,147 @@ int oracle_step_field(int ndim, const int64_t *n, const int *axis, int bc, int s
         }
     }
     free(tmp);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* A laser pulse with a linear turn-on ramp (Sec. 2.3)                  */
+/* ------------------------------------------------------------------ */
+
+/* params: omega, phase, t_on, t_flat, t_off.  The envelope w(t) is 0 for
+ * t < 0, rises linearly to 1 over [0, t_on), stays 1 for t_flat, falls
+ * linearly to 0 over t_off and is 0 afterwards (a zero t_on or t_off is a
+ * step). */
+static double pulse_envelope(const double *pp, double t)
+{
+    const double t_on = pp[2], t1 = pp[2] + pp[3], t2 = pp[2] + pp[3] + pp[4];
+    if (t < 0.0 || t >= t2) return 0.0;
+    if (t < t_on) return t / t_on;
+    if (t < t1) return 1.0;
+    return (t2 - t) / pp[4];
+}
+
+static double pulse_f(const double *pp, double t)
+{
+    return pulse_envelope(pp, t) * sin(pp[0] * t + pp[1]);
+}
+
+/* Gauss-Legendre rule of order n on [-1, 1]: the roots of the Legendre
+ * polynomial P_n found by Newton's method from cos(pi (k + 3/4) / (n + 1/2)),
+ * with P_n and P_n' from the three-term recurrence; weights
+ * 2 / ((1 - x^2) P_n'(x)^2). */
+#define GL_N 16
+static void gauss_legendre(int n, double *x, double *w)
+{
+    for (int k = 0; k < n; ++k) {
+        double z = cos(3.14159265358979323846 * (k + 0.75) / (n + 0.5)), dp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int j = 2; j <= n; ++j) {
+                const double p2 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p0) / j;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            const double dz = p1 / dp;
+            z -= dz;
+            if (fabs(dz) < 1e-17) break;
+        }
+        double p0 = 1.0, p1 = z;
+        for (int j = 2; j <= n; ++j) {
+            const double p2 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p0) / j;
+            p0 = p1;
+            p1 = p2;
+        }
+        dp = n * (z * p1 - p0) / (z * z - 1.0);
+        x[k] = z;
+        w[k] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+void oracle_gauss_legendre(double *x, double *w) { gauss_legendre(GL_N, x, w); }
+
+/* int_a^b f(t) dt for a piece on which w is linear: Gauss-Legendre on
+ * sub-intervals short enough that omega * length <= 1 */
+static double pulse_piece(const double *pp, double a, double b, const double *gx,
+                          const double *gw)
+{
+    int nsub = (int)ceil(fabs(pp[0]) * (b - a));
+    if (nsub < 1) nsub = 1;
+    double sum = 0.0;
+    for (int q = 0; q < nsub; ++q) {
+        const double lo = a + (b - a) * q / nsub, hi = a + (b - a) * (q + 1) / nsub;
+        const double h = 0.5 * (hi - lo), mid = 0.5 * (hi + lo);
+        double part = 0.0;
+        for (int k = 0; k < GL_N; ++k) part += gw[k] * pulse_f(pp, mid + h * gx[k]);
+        sum += h * part;
+    }
+    return sum;
+}
+
+/* The field-integral factor of one step, int_{ta}^{tb} f(t) dt: the interval
+ * is cut at the envelope's corners 0, t_on, t_on + t_flat, t_on + t_flat +
+ * t_off, where w has a kink, and each piece integrated as above. */
+double oracle_pulse_integral(const double *pp, double ta, double tb)
+{
+    double gx[GL_N], gw[GL_N];
+    gauss_legendre(GL_N, gx, gw);
+    const double corners[4] = {0.0, pp[2], pp[2] + pp[3], pp[2] + pp[3] + pp[4]};
+    double cuts[6];
+    int nc = 0;
+    cuts[nc++] = ta;
+    for (int k = 0; k < 4; ++k)
+        if (corners[k] > ta && corners[k] < tb) cuts[nc++] = corners[k];
+    cuts[nc++] = tb;
+    double sum = 0.0;
+    for (int k = 0; k + 1 < nc; ++k) sum += pulse_piece(pp, cuts[k], cuts[k + 1], gx, gw);
+    return sum;
+}
+
+/* nsteps steps with the pulse: step st covers [t0 + st dt, t0 + (st + 1) dt]
+ * and its local step carries Atilde = P * oracle_pulse_integral over that
+ * interval (P planar, 3 * sites); scheme as in oracle_step_field. */
+int oracle_step_pulse(int ndim, const int64_t *n, const int *axis, int bc, int scheme,
+                      double dt, double c, double m, const double *V, const double *P,
+                      const double *pp, double t0, double *psi, int64_t nsteps, int nthreads)
+{
+    grid_t g;
+    if ((scheme == 1 && ndim > 2) || scheme < 0 || scheme > 1 || !P || !pp ||
+        grid_from_args(&g, ndim, n, axis, bc) || nsteps < 0)
+        return -1;
+    build_matrices();
+    set_threads(nthreads);
+    const int64_t ns = nsites(&g);
+    zd *tmp = (zd *)malloc((size_t)ns * 4 * sizeof(zd));
+    double *At = (double *)malloc((size_t)ns * 3 * sizeof(double));
+    if (!tmp || !At) {
+        free(tmp);
+        free(At);
+        return -2;
+    }
+    int order[3];
+    const int k = transport_order(&g, order);
+    const int64_t bytes = ns * 4 * (int64_t)sizeof(zd);
+    zd *p = (zd *)psi;
+    for (int64_t st = 0; st < nsteps; ++st) {
+        const double F = oracle_pulse_integral(pp, t0 + (double)st * dt, t0 + (double)(st + 1) * dt);
+        for (int64_t q = 0; q < 3 * ns; ++q) At[q] = F * P[q];
+        for (int t = 0; t < k; ++t) {
+            const int a = g.axis[order[t]];
+            transport_d(&g, order[t], 1, PROJ[a][0], PROJ[a][1], p, tmp);
+            memcpy(p, tmp, (size_t)bytes);
+        }
+        local_step_field(&g, p, V, At, dt, c, m);
+        if (scheme == 1) {
+            for (int t = k - 1; t >= 0; --t) {
+                const int a = g.axis[order[t]];
+                transport_d(&g, order[t], 1, PROJ[a][0], PROJ[a][1], p, tmp);
+                memcpy(p, tmp, (size_t)bytes);
+            }
+        }
+    }
+    free(tmp);
+    free(At);
     return 0;
 }
 

@@ -53,6 +53,14 @@ def _load():
         lib.oracle_step_field.argtypes = [ctypes.c_int, i64p, ip, ctypes.c_int, ctypes.c_int,
                                           ctypes.c_double, ctypes.c_double, ctypes.c_double, dp,
                                           dp, dp, ctypes.c_int64, ctypes.c_int]
+        lib.oracle_step_pulse.argtypes = [ctypes.c_int, i64p, ip, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_double, ctypes.c_double, ctypes.c_double, dp,
+                                          dp, dp, ctypes.c_double, dp, ctypes.c_int64,
+                                          ctypes.c_int]
+        lib.oracle_pulse_integral.argtypes = [dp, ctypes.c_double, ctypes.c_double]
+        lib.oracle_pulse_integral.restype = ctypes.c_double
+        lib.oracle_gauss_legendre.argtypes = [dp, dp]
+        lib.oracle_gauss_legendre.restype = None
         lib.oracle_stream_f32.argtypes = [ctypes.c_int, i64p, ip, ctypes.c_int, dp,
                                           ctypes.c_int64, ctypes.c_int]
         lib.oracle_observables.argtypes = [ctypes.c_int, i64p, ctypes.c_double, dp, dp,
@@ -64,7 +72,7 @@ def _load():
         lib.oracle_dirac_matrices.argtypes = [dp]
         lib.oracle_max_threads.restype = ctypes.c_int
         for f in (lib.oracle_step, lib.oracle_adjoint_step, lib.oracle_step_strang,
-                  lib.oracle_step_field,
+                  lib.oracle_step_field, lib.oracle_step_pulse,
                   lib.oracle_stream_f32,
                   lib.oracle_observables, lib.oracle_grad):
             f.restype = ctypes.c_int
@@ -149,6 +157,46 @@ def step_field(psi, V=None, A=None, *, dt, c, m, nsteps, axes=None, bc="zero", s
                                    int(threads))
     if rc:
         raise RuntimeError(f"oracle_step_field failed ({rc})")
+    return psi
+
+
+def _pulse_params(pulse) -> np.ndarray:
+    return np.ascontiguousarray([float(pulse[k]) for k in
+                                 ("omega", "phase", "t_on", "t_flat", "t_off")], dtype=np.float64)
+
+
+def pulse_integral(pulse, ta, tb) -> float:
+    """int_ta^tb f(t) dt for the pulse f(t) = w(t) sin(omega t + phase) with
+    the trapezoid envelope w (dict with omega, phase, t_on, t_flat, t_off)."""
+    pp = _pulse_params(pulse)
+    return float(_load().oracle_pulse_integral(_ptr(pp), float(ta), float(tb)))
+
+
+def gauss_legendre16():
+    """The oracle's 16-point Gauss-Legendre nodes and weights on [-1, 1]."""
+    x = np.zeros(16)
+    w = np.zeros(16)
+    _load().oracle_gauss_legendre(_ptr(x), _ptr(w))
+    return x, w
+
+
+def step_pulse(psi, V=None, P=None, pulse=None, *, t0=0.0, dt, c, m, nsteps, axes=None,
+               bc="zero", scheme="lie", threads=0):
+    """Return psi after `nsteps` steps whose local step carries the field
+    integral Atilde^n = P * int_{t_n}^{t_{n+1}} f of the pulse f (t_n =
+    t0 + n dt); P: shape (3,) + grid."""
+    psi = np.array(psi, dtype=np.complex128, order="C", copy=True)
+    V = _check_V(V, psi)
+    P = np.ascontiguousarray(P, dtype=np.float64)
+    if P.shape != (3,) + psi.shape[:-1]:
+        raise ValueError("P must have shape (3,) + grid")
+    pp = _pulse_params(pulse)
+    ndim, n, ax = _grid_args(psi, axes)
+    rc = _load().oracle_step_pulse(ndim, n, ax, _bc(bc), {"lie": 0, "strang": 1}[scheme], dt, c,
+                                   m, None if V is None else _ptr(V), _ptr(P), _ptr(pp),
+                                   float(t0), _ptr(psi), int(nsteps), int(threads))
+    if rc:
+        raise RuntimeError(f"oracle_step_pulse failed ({rc})")
     return psi
 
 

@@ -15,8 +15,10 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "lib", "libdirac.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
-SOURCES = ["dirac_plan.hip", "dirac_sweep.hip", "dirac_sweep3d.hip", "dirac_reduce.hip", "dirac_adjoint.hip",
-           "dirac_batch.hip"]
+SOURCES = ["dirac_sweep2d_f32_hi.hip", "dirac_sweep2d_f64_hi.hip", "dirac_sweep2d_f32_lo.hip",
+           "dirac_sweep2d_f64_lo.hip", "dirac_sweep2d_strang.hip", "dirac_batch.hip",
+           "dirac_sweep3d.hip", "dirac_adjoint.hip", "dirac_plan.hip", "dirac_sweep.hip",
+           "dirac_reduce.hip"]
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

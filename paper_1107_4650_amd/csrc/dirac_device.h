@@ -500,23 +500,32 @@ __device__ __forceinline__ bool field_far(double V, double ax, double ay, double
   return far_arg(sqrt(mu * mu + ax * ax + ay * ay + az * az)) || far_arg(V * k.dt);
 }
 
+// ph = s e^{-i V dt}, the scalar part of the local step
 template <bool TWO, bool ANY>
-__device__ __forceinline__ FieldFactors field_factors(double V, double ax, double ay, double az,
-                                                      const PhaseK& k) {
+__device__ __forceinline__ void scalar_phase(double V, const PhaseK& k, double& pr, double& pi) {
+  constexpr int ACC = TWO ? 2 : 1;
+  double sv, cv;
+  if constexpr (ANY)
+    sincos_any<ACC>(V * k.dt, &sv, &cv);
+  else
+    sincos_fast<ACC>(V * k.dt, &sv, &cv);
+  pr = k.scale * cv;
+  pi = -k.scale * sv;
+}
+
+// U ph for the field integral At = (ax, ay, az) of the step, given ph
+template <bool TWO, bool ANY>
+__device__ __forceinline__ FieldFactors field_with(double pr, double pi, double ax, double ay,
+                                                   double az, const PhaseK& k) {
   constexpr int ACC = TWO ? 2 : 1;
   const double mu = k.mc2 * k.dt;
   const double A = sqrt(mu * mu + ax * ax + ay * ay + az * az);
-  double sA, cA, sv, cv;
-  if constexpr (ANY) {
+  double sA, cA;
+  if constexpr (ANY)
     sincos_any<ACC>(A, &sA, &cA);
-    sincos_any<ACC>(V * k.dt, &sv, &cv);
-  } else {
+  else
     sincos_fast<ACC>(A, &sA, &cA);
-    sincos_fast<ACC>(V * k.dt, &sv, &cv);
-  }
   const double sa = (A > 0.0) ? sA / A : 1.0;
-  // ph = s e^{-i V dt}
-  const double pr = k.scale * cv, pi = -k.scale * sv;
   const double ms = mu * sa;
   FieldFactors f;
   f.ur = fma(pr, cA, pi * ms);   // ph * (cA - i ms)
@@ -529,6 +538,14 @@ __device__ __forceinline__ FieldFactors field_factors(double V, double ax, doubl
   f.ay = ay;
   f.az = az;
   return f;
+}
+
+template <bool TWO, bool ANY>
+__device__ __forceinline__ FieldFactors field_factors(double V, double ax, double ay, double az,
+                                                      const PhaseK& k) {
+  double pr, pi;
+  scalar_phase<TWO, ANY>(V, k, pr, pi);
+  return field_with<TWO, ANY>(pr, pi, ax, ay, az, k);
 }
 
 // if any lane of the wave has an angle outside the fast reduction range,
@@ -567,9 +584,123 @@ __device__ __forceinline__ void apply_field(Site<T>& s, const FieldFactors& f) {
   mix(dr, di, f.dr, f.di, t4r, t4i, s.v[6], s.v[7]);
 }
 
-// Phase factors of a cell for phase mode MODE (3: with a vector potential)
+// ---------------------------------------------------------------------------
+// A time-dependent vector potential A(t, x) = f(t) P(x): a laser pulse with a
+// linear turn-on ramp, the kind of field whose integral Sec. 2.3 notes can be
+// found analytically.  f(t) = w(t) sin(omega t + phase) with the trapezoid
+// envelope w: 0 before t = 0, t / t_on on [0, t_on), 1 for t_flat, a linear
+// fall to 0 over t_off, 0 afterwards.  The local step of step n carries the
+// field integral At^n(x) = P(x) F_n, F_n = int f over [t0 + n dt,
+// t0 + (n + 1) dt] (eq:field_dis1), evaluated here in closed form per step.
+// ---------------------------------------------------------------------------
+struct PulseK {
+  double omega, phase;           // carrier
+  double t_on, t_flat, t_off;    // envelope
+  double t0, dt;                 // step n starts at t0 + n dt
+  int64_t n0;                    // first step of the pass
+};
+
+// sin(u) / u
+__device__ __forceinline__ double sinc_d(double u) {
+  const double u2 = u * u;
+  if (fabs(u) < 1e-3) return 1.0 - u2 * (1.0 / 6.0 - u2 * (1.0 / 120.0));
+  return sin(u) / u;
+}
+
+// (sin u - u cos u) / u^2: a series below |u| = 1/4 (terms to u^11, the next
+// below 2e-19 relative), the direct form above (cancellation costs at most
+// 3 eps / u^2 < 5e-15 relative there)
+__device__ __forceinline__ double j1_d(double u) {
+  if (fabs(u) < 0.25) {
+    const double u2 = u * u;
+    double p = -1.0 / 518918400.0;          // -12 / 13!
+    p = fma(p, u2, 1.0 / 3991680.0);        //  10 / 11!
+    p = fma(p, u2, -1.0 / 45360.0);         //  -8 / 9!
+    p = fma(p, u2, 1.0 / 840.0);            //   6 / 7!
+    p = fma(p, u2, -1.0 / 30.0);            //  -4 / 5!
+    p = fma(p, u2, 1.0 / 3.0);              //   2 / 3!
+    return u * p;
+  }
+  double s, c;
+  sincos(u, &s, &c);
+  return (s - u * c) / (u * u);
+}
+
+// int_a^b (w_m + beta (t - m)) sin(omega t + phase) dt with m = (a + b) / 2,
+// h = (b - a) / 2, psi = omega m + phase:
+//   int sin(omega t + phase)        = 2 h sin(psi) sinc(omega h)
+//   int (t - m) sin(omega t + phase) = 2 h^2 cos(psi) j1(omega h)
+// (the product forms avoid the cancellation of a difference of cosines)
+__device__ __forceinline__ double lin_sin_integral(double a, double b, double w_m, double beta,
+                                                   double omega, double phase) {
+  const double h = 0.5 * (b - a), m = 0.5 * (a + b);
+  const double u = omega * h;
+  double sp, cp;
+  sincos(fma(omega, m, phase), &sp, &cp);
+  const double i0 = 2.0 * h * sp * sinc_d(u);
+  const double i1 = 2.0 * h * h * cp * j1_d(u);
+  return fma(w_m, i0, beta * i1);
+}
+
+// F = int_ta^tb f(t) dt, over the pieces of [ta, tb] on which w is linear
+__device__ __forceinline__ double pulse_integral(const PulseK& p, double ta, double tb) {
+  const double t1 = p.t_on + p.t_flat, t2 = t1 + p.t_off;
+  double sum = 0.0;
+  if (p.t_on > 0.0) {  // rise: w = t / t_on
+    const double a = fmax(ta, 0.0), b = fmin(tb, p.t_on);
+    if (a < b) sum += lin_sin_integral(a, b, 0.5 * (a + b) / p.t_on, 1.0 / p.t_on, p.omega, p.phase);
+  }
+  {  // flat top: w = 1
+    const double a = fmax(ta, p.t_on), b = fmin(tb, t1);
+    if (a < b) sum += lin_sin_integral(a, b, 1.0, 0.0, p.omega, p.phase);
+  }
+  if (p.t_off > 0.0) {  // fall: w = (t2 - t) / t_off
+    const double a = fmax(ta, t1), b = fmin(tb, t2);
+    if (a < b)
+      sum += lin_sin_integral(a, b, (t2 - 0.5 * (a + b)) / p.t_off, -1.0 / p.t_off, p.omega,
+                              p.phase);
+  }
+  return sum;
+}
+
+// F of step n0 + s of the pass (the time of a step is formed from its global
+// index, so a pass of K steps and K passes of one step see the same values)
+__device__ __forceinline__ double pulse_step_integral(const PulseK& p, int s) {
+  const double n = static_cast<double>(p.n0 + s);
+  return pulse_integral(p, fma(n, p.dt, p.t0), fma(n + 1.0, p.dt, p.t0));
+}
+
+// what a row carries between its read and its local steps under a pulse:
+// ph = s e^{-i V dt} and the field profile P
+struct PulseRow {
+  double pr, pi;
+  double px, py, pz;
+};
+
+template <bool TWO>
+__device__ __forceinline__ PulseRow pulse_row(double V, double px, double py, double pz,
+                                              const PhaseK& k) {
+  PulseRow r;
+  scalar_phase<TWO, false>(V, k, r.pr, r.pi);
+  if (__any(far_arg(V * k.dt))) scalar_phase<TWO, true>(V, k, r.pr, r.pi);
+  r.px = px;
+  r.py = py;
+  r.pz = pz;
+  return r;
+}
+
+// U ph of the step whose field integral factor is F
+template <bool TWO>
+__device__ __forceinline__ FieldFactors pulse_factors(const PulseRow& r, double F,
+                                                      const PhaseK& k) {
+  return field_with<TWO, true>(r.pr, r.pi, F * r.px, F * r.py, F * r.pz, k);
+}
+
+// Phase factors of a cell for phase mode MODE (3: with a static vector
+// potential; 4: with a pulse, formed per step from the row's PulseRow)
 template <int MODE> struct FactorOf { using type = Factors; };
 template <> struct FactorOf<3> { using type = FieldFactors; };
+template <> struct FactorOf<4> { using type = PulseRow; };
 
 // Full local step on one site (V ignored unless mode == 2).
 template <typename T>

@@ -33,9 +33,12 @@ __host__ __device__ constexpr int max_depth(bool fp64, bool strang) {
 }
 // resident 256-thread blocks per CU the 1-D / 2-D kernel is compiled for, by
 // the steps and stages (steps x stages per step) of its pass and its phase
-// mode (mode 3, the vector potential, carries more per row)
+// mode (modes 3 and 4, the static and the pulsed vector potential, carry more
+// per row)
 __host__ __device__ constexpr int sweep2d_min_blocks(bool fp64, int depth, int stages, int mode) {
-  return ((fp64 && stages > 2) || (mode == 3 && (fp64 ? depth > 1 : stages > 3))) ? 1 : 2;
+  return ((fp64 && stages > 2) || ((mode == 3 || mode == 4) && (fp64 ? depth > 1 : stages > 3)))
+             ? 1
+             : 2;
 }
 // reverse (adjoint) passes fuse up to this many reverse steps
 constexpr int kMaxRevDepthF32 = 3;
@@ -62,8 +65,11 @@ struct SweepArgs {
   int xcd_remap;       // blocks dealt XCD-contiguously (grid a multiple of 8)
   int axes_code;       // 1-D: axis; 2-D: 10*axis0 + axis1 with axis1 > axis0 ... see plan
   PhaseK ph;
-  // phase mode 3: field integrals At, planar (x, y, z blocks of `cells`)
+  // phase mode 3: field integrals At, planar (x, y, z blocks of `cells`);
+  // phase mode 4: the pulse's field profile P in the same layout
   const double* At;
+  PulseK pulse;        // phase mode 4 (and 3-D passes with pulse_on)
+  int pulse_on;        // 3-D passes: the field integral is P times the pulse's F
   int64_t cells;
   int nc;              // components stored per cell: 4, or 2 (two-component 1-D line)
 };

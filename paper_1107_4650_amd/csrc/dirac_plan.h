@@ -48,9 +48,11 @@ struct dl_plan_s {
   int depth = 1;                        // fused steps per pass in use
   int waves_per_cu = 0;        // 0: size the grid from the kernels' occupancy
   int cu_count = 256;
-  dirac::PlanTiling tiling[4];  // per phase mode (3: with a vector potential)
+  dirac::PlanTiling tiling[5];  // per phase mode (3: a vector potential, 4: a pulse)
   int depth_field = 1;          // fused steps per pass with a vector potential
-  const double* field = nullptr;  // field integrals of the current call (mode 3)
+  const double* field = nullptr;  // field integrals (mode 3) or profile (mode 4) of the call
+  dirac::PulseK pulse{};          // mode 4: the pulse; pulse.n0 counts the call's steps
+  bool pulse_on = false;
   int seg_override = 0;
   bool allow_resident = true;
   bool resident = false;

@@ -196,7 +196,7 @@ int dirac::transports_per_step(dl_plan p) {
 
 // make the tilings of phase mode `mode` current
 static void select_tiling(dl_plan p, int mode) {
-  const PlanTiling& t = p->tiling[mode < 0 || mode > 3 ? 2 : mode];
+  const PlanTiling& t = p->tiling[mode < 0 || mode > 4 ? 2 : mode];
   for (int d = 0; d < kMaxDepth; ++d) {
     p->sw[d] = t.a[d];
     p->bl[d] = t.b[d];
@@ -234,10 +234,10 @@ static int plan_tiling(dl_plan p) {
   }
   p->depth = depth;
   p->depth_field = (p->g.ndim == 3) ? 1 : std::min(depth, field_max_depth(p->fp64, p->strang));
-  for (int mode = 0; mode < 4; ++mode) {
+  for (int mode = 0; mode < 5; ++mode) {
     PlanTiling& t = p->tiling[mode];
     if (p->g.ndim == 3) {
-      if (mode == 3) {  // with a vector potential: one step per pass
+      if (mode >= 3) {  // with a vector potential (static or pulsed): one step per pass
         make_tiling3d(p->g, p->fp64 ? kTY3D_F64 : kTY3D_F32, 64, 2, resident_waves(p, 3, 1),
                       p->seg_override, t.a[0], t.b[0]);
         for (int d = 0; d < kMaxDepth; ++d) t.a[d].periodic = (p->bc == DL_BC_PERIODIC);
@@ -250,7 +250,7 @@ static int plan_tiling(dl_plan p) {
                       resident_waves(p, mode, 2),
                       p->seg_override, t.a[1], t.b[1]);
     } else {
-      for (int d = 1; d <= (mode == 3 ? p->depth_field : depth); ++d)
+      for (int d = 1; d <= (mode >= 3 ? p->depth_field : depth); ++d)
         make_tiling(p->g, resident_waves(p, mode, d), p->seg_override, t.a[d - 1], t.b[d - 1],
                     strip_width(pass_xlanes(p->strang, d)));
     }
@@ -400,6 +400,8 @@ hipError_t launch_pass(dl_plan p, int depth, const void* src, void* dst, const d
     SweepArgs a = p->sw[p->strang ? 0 : depth - 1];  // second-order passes size their own grids
     a.ph = p->ph;
     a.At = p->field;
+    a.pulse = p->pulse;
+    a.pulse_on = p->pulse_on ? 1 : 0;
     a.cells = p->cells;
     if (p->strang) return launch_strang3d(p->fp64, src, dst, p->tmp2, V, a, depth, st);
     return launch_sweep3d(p->fp64, depth, src, dst, V, a, p->bl[depth - 1], st);
@@ -407,6 +409,8 @@ hipError_t launch_pass(dl_plan p, int depth, const void* src, void* dst, const d
   SweepArgs a = p->sw[depth - 1];
   a.ph = p->ph;
   a.At = p->field;
+  a.pulse = p->pulse;
+  a.pulse_on = p->pulse_on ? 1 : 0;
   a.cells = p->cells;
   a.nc = p->nc;
   return launch_sweep2d(p->fp64, p->strang, depth, src, dst, V, a, p->bl[depth - 1], st);
@@ -420,11 +424,12 @@ hipError_t enqueue_steps(dl_plan p, void* psi, const double* V, int64_t nsteps, 
   void* a = psi;
   void* b = p->tmp;
   int64_t left = nsteps;
-  const int dmax = (p->ph.mode == 3) ? p->depth_field : p->depth;
+  const int dmax = (p->ph.mode >= 3) ? p->depth_field : p->depth;
   for (int d = dmax; d >= 1; --d) {
     for (; left >= d; left -= d) {
       hipError_t e = launch_pass(p, d, a, b, V, st);
       if (e != hipSuccess) return e;
+      p->pulse.n0 += d;  // the pulse's step index of the next pass
       void* t = a;
       a = b;
       b = t;
@@ -552,6 +557,47 @@ extern "C" int dl_step_field(dl_plan p, void* psi, const double* V, const double
   void* res = nullptr;
   hipError_t e = enqueue_steps(p, psi, V, nsteps, st, &res);
   p->field = nullptr;
+  if (e != hipSuccess) return hip_fail(e, "sweep launch");
+  if (res != psi) {
+    e = hipMemcpyAsync(psi, res, p->state_bytes, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+  }
+  return DL_OK;
+}
+
+extern "C" int dl_step_pulse(dl_plan p, void* psi, const double* V, const double* P,
+                             const dl_pulse* pulse, double t0, int64_t nsteps, void* stream) {
+  int rc = check_live(p);
+  if (rc) return rc;
+  if ((rc = check_state_ptr(psi, "psi"))) return rc;
+  if ((rc = check_f64_ptr(V, "V", true))) return rc;
+  if ((rc = check_f64_ptr(P, "P", false))) return rc;
+  if (!pulse) return fail(DL_ERR_ARG, "pulse is NULL");
+  const double pv[5] = {pulse->omega, pulse->phase, pulse->t_on, pulse->t_flat, pulse->t_off};
+  for (double v : pv)
+    if (!std::isfinite(v)) return fail(DL_ERR_ARG, "pulse parameters must be finite");
+  if (pulse->t_on < 0.0 || pulse->t_flat < 0.0 || pulse->t_off < 0.0)
+    return fail(DL_ERR_ARG, "pulse durations must be >= 0");
+  if (!std::isfinite(t0)) return fail(DL_ERR_ARG, "t0 must be finite");
+  if (p->g.ndim == 3 && p->strang)
+    return fail(DL_ERR_ARG, "the 3-D second-order step carries no vector potential");
+  if (p->nc != 4) return fail(DL_ERR_ARG, "a vector potential couples all four components");
+  if (nsteps < 0) return fail(DL_ERR_ARG, "nsteps = %lld < 0", static_cast<long long>(nsteps));
+  if (nsteps == 0) return DL_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  // 1-D / 2-D: phase mode 4 forms each step's field integral in the pass; 3-D
+  // passes (one step each) run the static-field kernel with At = F P
+  const int mode = (p->g.ndim == 3) ? 3 : 4;
+  p->ph = make_phase(transports_per_step(p), p->dt, p->c, p->m, mode, p->fp64);
+  p->field = P;
+  p->pulse = PulseK{pulse->omega, pulse->phase, pulse->t_on, pulse->t_flat, pulse->t_off,
+                    t0, p->dt, 0};
+  p->pulse_on = true;
+  select_tiling(p, mode);
+  void* res = nullptr;
+  hipError_t e = enqueue_steps(p, psi, V, nsteps, st, &res);
+  p->field = nullptr;
+  p->pulse_on = false;
   if (e != hipSuccess) return hip_fail(e, "sweep launch");
   if (res != psi) {
     e = hipMemcpyAsync(psi, res, p->state_bytes, hipMemcpyDeviceToDevice, st);

@@ -2,11 +2,12 @@
 // observables (norm, mean coordinates, probability beyond x_b; the R/T
 // integrals of Sec. 5.2.1 on the cell grid).
 //
-// Each thread keeps Neumaier (sum, compensation) pairs over a fixed
-// grid-stride set of cells; pairs are merged with an exact two-sum in a fixed
-// shuffle tree, then across the four waves of the block, then in a final
-// one-block pass over the per-block partials in block order.  The grid size
-// is fixed, so results do not depend on scheduling.
+// Each thread keeps Neumaier (sum, compensation) pairs over a fixed set of
+// cells (a contiguous range per block, strided by the block size); pairs are
+// merged with an exact two-sum in a fixed shuffle tree, then across the four
+// waves of the block, then in a final one-block pass over the per-block
+// partials in block order.  The grid size is fixed, so results do not depend
+// on scheduling.
 #include "dirac_launch.h"
 
 namespace dirac {
@@ -65,6 +66,28 @@ __device__ void block_reduce(NSum (&acc)[NQ], NSum (*lds)[4]) {
   }
 }
 
+// |psi|^2 of one cell over its stored components, in FP64 (a two-component
+// line stores a pair whose partners are zero, so the sum is the same)
+template <typename T, int NC>
+__device__ __forceinline__ void load_obs(const T* __restrict__ psi, int64_t c, T (&s)[2 * NC]) {
+  if constexpr (NC == 4) {
+    Site<T> q;
+    load_site(psi + c * 8, q);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s[k] = q.v[k];
+  } else {
+    load_pair(psi + c * 4, s[0], s[1], s[2], s[3]);
+  }
+}
+
+// Block b sums the contiguous cells [b * per, min((b + 1) * per, ncell)),
+// per a multiple of 256, thread t the cells b * per + t + 256 j.  A thread
+// derives its cell's grid coordinates once and then advances them by 256
+// cells per iteration (a wrap of the x index moves the row on), so no cell
+// needs an integer division.  Cells are loaded kObsBatch at a time, their
+// addresses linear in j, so the loads of a batch are in flight together.
+constexpr int kObsBatch = 8;
+
 template <typename T, int NC>
 __global__ __launch_bounds__(256) void k_obs_partial(const T* __restrict__ psi, ObsArgs a,
                                                      double* __restrict__ partials) {
@@ -73,36 +96,50 @@ __global__ __launch_bounds__(256) void k_obs_partial(const T* __restrict__ psi, 
 #pragma unroll
   for (int q = 0; q < kQ; ++q) acc[q] = NSum{0.0, 0.0};
   const int64_t ncell = a.n0 * a.n1 * a.n2;
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  for (int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; c < ncell;
-       c += stride) {
-    // |psi|^2 over the stored components (a two-component line stores a pair
-    // whose partners are zero, so the sum is the same)
-    T s[2 * NC];
-    if constexpr (NC == 4) {
-      Site<T> q;
-      load_site(psi + c * 8, q);
+  const int64_t per = ((ncell + gridDim.x - 1) / gridDim.x + 255) / 256 * 256;
+  const int64_t cb = static_cast<int64_t>(blockIdx.x) * per;
+  const int64_t ce = cb + per < ncell ? cb + per : ncell;
+  int64_t c = cb + threadIdx.x;
+  // coordinates of this thread's first cell
+  int64_t i0 = c % a.n0, r = c / a.n0;
+  int64_t i1 = r % a.n1, i2 = r / a.n1;
+  for (; c < ce; c += 256 * kObsBatch) {
+    T s[kObsBatch][2 * NC];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) s[k] = q.v[k];
-    } else {
-      load_pair(psi + c * 4, s[0], s[1], s[2], s[3]);
-    }
-    double rho = 0.0;
+    for (int j = 0; j < kObsBatch; ++j) {
+      if (c + 256 * j < ce) {
+        load_obs<T, NC>(psi, c + 256 * j, s[j]);
+      } else {
 #pragma unroll
-    for (int k = 0; k < 2 * NC; ++k) {
-      const double v = static_cast<double>(s[k]);
-      rho = fma(v, v, rho);
+        for (int k = 0; k < 2 * NC; ++k) s[j][k] = T(0);
+      }
     }
-    const int64_t i0 = c % a.n0;
-    const int64_t r = c / a.n0;
-    const int64_t i1 = r % a.n1;
-    const int64_t i2 = r / a.n1;
-    const double x0 = a.xmin0 + (static_cast<double>(i0) + 0.5) * a.dx;
-    nadd(acc[0], rho);
-    nadd(acc[1], x0 * rho);
-    if (a.ndim > 1) nadd(acc[2], (a.xmin1 + (static_cast<double>(i1) + 0.5) * a.dx) * rho);
-    if (a.ndim > 2) nadd(acc[3], (a.xmin2 + (static_cast<double>(i2) + 0.5) * a.dx) * rho);
-    if (x0 > a.x_b) nadd(acc[4], rho);
+#pragma unroll
+    for (int j = 0; j < kObsBatch; ++j) {
+      if (c + 256 * j < ce) {
+        double rho = 0.0;
+#pragma unroll
+        for (int k = 0; k < 2 * NC; ++k) {
+          const double v = static_cast<double>(s[j][k]);
+          rho = fma(v, v, rho);
+        }
+        const double x0 = a.xmin0 + (static_cast<double>(i0) + 0.5) * a.dx;
+        nadd(acc[0], rho);
+        nadd(acc[1], x0 * rho);
+        if (a.ndim > 1) nadd(acc[2], (a.xmin1 + (static_cast<double>(i1) + 0.5) * a.dx) * rho);
+        if (a.ndim > 2) nadd(acc[3], (a.xmin2 + (static_cast<double>(i2) + 0.5) * a.dx) * rho);
+        if (x0 > a.x_b) nadd(acc[4], rho);
+      }
+      // advance the coordinates by 256 cells
+      i0 += 256;
+      while (i0 >= a.n0) {
+        i0 -= a.n0;
+        if (++i1 == a.n1) {
+          i1 = 0;
+          ++i2;
+        }
+      }
+    }
   }
   block_reduce<kQ>(acc, lds);
   if (threadIdx.x == 0) {

@@ -18,39 +18,15 @@
 //     segments (workgroups are dealt to the 8 XCDs round-robin).
 // Passes of K fused steps (temporal blocking) write the 64 - 2K middle cells
 // of a wave and advance them by K full steps per read and write of psi.
-// 3-D grids: dirac_sweep3d.hip.
+// The kernel template is in dirac_sweep2d_kernels.h and its instances in the
+// dirac_sweep2d_*.hip units; this file holds the 1-D resident kernel, the
+// dispatch and the launchers.  3-D grids: dirac_sweep3d.hip.
 #include "dirac_device.h"
 #include "dirac_launch.h"
 #include "dirac_sweep_impl.h"
+#include "dirac_sweep2d_kernels.h"
 
 namespace dirac {
-
-// K full steps of scheme S per launch on a 1-D line or a 2-D plane (64 - 2X
-// output columns per wave, X = x transports of the pass; march segments of
-// H rows in 2-D)
-template <typename T, class S, int K, int AX0, int AX1, int MODE, int NC = 4>
-__global__ __launch_bounds__(256, sweep2d_min_blocks(sizeof(T) == 8, K, K * S::kStages, MODE))
-void k_sweep2d(const T* __restrict__ src, T* __restrict__ dst, const double* __restrict__ V,
-               SweepArgs a) {
-  static_assert(NC == 4 || AX1 < 0, "two-component states are 1-D lines");
-  constexpr int X = halo_lanes<S>(K);
-  const int lane = threadIdx.x & 63;
-  int64_t blk = blockIdx.x;
-  if (a.xcd_remap) blk = (blk % 8) * (gridDim.x / 8) + blk / 8;
-  const int64_t tile = blk * 4 + wave_in_block();
-  if (tile >= a.ntiles) return;
-  const int64_t strip = tile % a.nstrips;
-  const int64_t seg = tile / a.nstrips;
-  const int64_t xs = strip * strip_width(X) - X;  // lanes X .. 63 - X are written
-  if constexpr (AX1 < 0) {
-    one_row<T, S, K, AX0, MODE, NC>(src, dst, V, a, xs, lane, X);  // 1-D: one row, no march
-  } else {
-    const int64_t jb = seg * a.H;
-    const int64_t je = (jb + a.H < a.ny) ? jb + a.H : a.ny;
-    // even segments march up, odd ones down
-    march_dir<T, S, K, AX0, AX1, MODE>(src, dst, V, a, xs, lane, jb, je, (seg & 1) == 0, X);
-  }
-}
 
 // ---------------------------------------------------------------------------
 // 1-D resident kernel: a whole 1-D instance lives in one workgroup's
@@ -126,83 +102,16 @@ __global__ __launch_bounds__(1024) void k_resident1d(T* __restrict__ psi,
   }
 }
 
-// ---------------------------------------------------------------------------
-// launchers: the 1-D / 2-D kernel for (type, depth, axes, phase mode)
-// ---------------------------------------------------------------------------
-template <typename T, class S, int K, int AX0, int AX1, int NC>
-static const void* kernel2d_mode(int mode) {
-  constexpr bool kField = NC == 4 &&
-      K <= field_max_depth(sizeof(T) == 8, std::is_same<S, StrangStep>::value);
-  switch (mode) {
-    case 0: return reinterpret_cast<const void*>(&k_sweep2d<T, S, K, AX0, AX1, 0, NC>);
-    case 1: return reinterpret_cast<const void*>(&k_sweep2d<T, S, K, AX0, AX1, 1, NC>);
-    case 2: return reinterpret_cast<const void*>(&k_sweep2d<T, S, K, AX0, AX1, 2, NC>);
-    case 3:
-      if constexpr (kField)
-        return reinterpret_cast<const void*>(&k_sweep2d<T, S, K, AX0, AX1, 3, NC>);
-      else
-        return nullptr;
-    default: return nullptr;
-  }
-}
-
-template <typename T, class S, int K>
-static const void* kernel2d_axes(int axes_code, int mode, int nc) {
-  if (nc == 2) {  // two-component 1-D lines
-    switch (axes_code) {
-      case 0: return kernel2d_mode<T, S, K, 0, -1, 2>(mode);
-      case 1: return kernel2d_mode<T, S, K, 1, -1, 2>(mode);
-      case 2: return kernel2d_mode<T, S, K, 2, -1, 2>(mode);
-      default: return nullptr;
-    }
-  }
-  switch (axes_code) {
-    case 0: return kernel2d_mode<T, S, K, 0, -1, 4>(mode);
-    case 1: return kernel2d_mode<T, S, K, 1, -1, 4>(mode);
-    case 2: return kernel2d_mode<T, S, K, 2, -1, 4>(mode);
-    case 10: return kernel2d_mode<T, S, K, 0, 1, 4>(mode);
-    case 20: return kernel2d_mode<T, S, K, 0, 2, 4>(mode);
-    case 21: return kernel2d_mode<T, S, K, 1, 2, 4>(mode);
-    default: return nullptr;
-  }
-}
-
 // nullptr for combinations that are not built (depths beyond max_depth)
 static const void* kernel2d(bool fp64, bool strang, int depth, int axes_code, int mode, int nc) {
-  if (strang) {
-    if (fp64) {
-      switch (depth) {
-        case 1: return kernel2d_axes<double, StrangStep, 1>(axes_code, mode, nc);
-        case 2: return kernel2d_axes<double, StrangStep, 2>(axes_code, mode, nc);
-        default: return nullptr;
-      }
-    }
-    switch (depth) {
-      case 1: return kernel2d_axes<float, StrangStep, 1>(axes_code, mode, nc);
-      case 2: return kernel2d_axes<float, StrangStep, 2>(axes_code, mode, nc);
-      default: return nullptr;
-    }
-  }
-  if (fp64) {
-    static_assert(kMaxDepthF64 <= 5, "FP64 kernels are built for depths 1 to 5");
-    if (depth > kMaxDepthF64) return nullptr;
-    switch (depth) {
-      case 1: return kernel2d_axes<double, LieStep, 1>(axes_code, mode, nc);
-      case 2: return kernel2d_axes<double, LieStep, 2>(axes_code, mode, nc);
-      case 3: return kernel2d_axes<double, LieStep, 3>(axes_code, mode, nc);
-      case 4: return kernel2d_axes<double, LieStep, 4>(axes_code, mode, nc);
-      case 5: return kernel2d_axes<double, LieStep, 5>(axes_code, mode, nc);
-      default: return nullptr;
-    }
-  }
-  switch (depth) {
-    case 1: return kernel2d_axes<float, LieStep, 1>(axes_code, mode, nc);
-    case 2: return kernel2d_axes<float, LieStep, 2>(axes_code, mode, nc);
-    case 3: return kernel2d_axes<float, LieStep, 3>(axes_code, mode, nc);
-    case 4: return kernel2d_axes<float, LieStep, 4>(axes_code, mode, nc);
-    case 5: return kernel2d_axes<float, LieStep, 5>(axes_code, mode, nc);
-    default: return nullptr;
-  }
+  if (strang) return kernel2d_strang(fp64, depth, axes_code, mode, nc);
+  static_assert(kMaxDepth <= 5 && kMaxDepthF64 <= 5, "kernels are built for depths 1 to 5");
+  if (depth < 1 || depth > (fp64 ? kMaxDepthF64 : kMaxDepth)) return nullptr;
+  if (fp64)
+    return depth <= 2 ? kernel2d_lie_f64_lo(depth, axes_code, mode, nc)
+                      : kernel2d_lie_f64_hi(depth, axes_code, mode, nc);
+  return depth <= 2 ? kernel2d_lie_f32_lo(depth, axes_code, mode, nc)
+                    : kernel2d_lie_f32_hi(depth, axes_code, mode, nc);
 }
 
 hipError_t launch_sweep2d(bool fp64, bool strang, int depth, const void* src, void* dst,

@@ -1,0 +1,15 @@
+// dirac_sweep2d_f32_lo.hip -- FP32-state lowest-order passes of 1 and 2 steps
+// (instances of the 1-D / 2-D fused-pass kernel; see dirac_sweep2d_kernels.h)
+#include "dirac_sweep2d_kernels.h"
+
+namespace dirac {
+
+const void* kernel2d_lie_f32_lo(int depth, int axes_code, int mode, int nc) {
+  switch (depth) {
+    case 1: return kernel2d_axes<float, LieStep, 1>(axes_code, mode, nc);
+    case 2: return kernel2d_axes<float, LieStep, 2>(axes_code, mode, nc);
+    default: return nullptr;
+  }
+}
+
+}  // namespace dirac

@@ -31,6 +31,11 @@ __device__ __forceinline__ void march3d(const T* __restrict__ src, T* __restrict
   const int64_t x = x0 + lane;
   const int64_t xv = x < nx ? x : nx - 1;
   const bool read_v = (MODE == 2) || (FIELD && V != nullptr);
+  // under a pulse the array holds the profile P and the step's field integral
+  // is F P (a pass is one step; the scale is exactly 1 for a static field)
+  double fscale = 1.0;
+  if constexpr (FIELD)
+    if (a.pulse_on) fscale = pulse_step_integral(a.pulse, 0);
   auto kout_of = [&](int it) -> int64_t { return UP ? kb - 2 + it : ke - it + 1; };
   // the potential (and field integrals) of the TY output rows of iteration it
   auto load_v = [&](int it, double* v, double (*at)[3]) {
@@ -42,9 +47,9 @@ __device__ __forceinline__ void march3d(const T* __restrict__ src, T* __restrict
       const int64_t q = (k * ny + y) * nx + xv;
       v[t] = read_v ? V[q] : 0.0;
       if constexpr (FIELD) {
-        at[t][0] = a.At[q];
-        at[t][1] = a.At[a.cells + q];
-        at[t][2] = a.At[2 * a.cells + q];
+        at[t][0] = fscale * a.At[q];
+        at[t][1] = fscale * a.At[a.cells + q];
+        at[t][2] = fscale * a.At[2 * a.cells + q];
       }
     }
   };

@@ -230,9 +230,14 @@ __device__ __forceinline__ void march2d(const T* __restrict__ src, T* __restrict
   const int nit = static_cast<int>(je - jb) + 2 * NS;  // iterations with work
   const Lanes c = lanes_of(nx, a.periodic, xs, lane);
   const bool own = c.inside && lane >= wlane && lane <= 63 - wlane;  // wlane >= X
-  constexpr bool FIELD = MODE == 3;             // local step with a vector potential
+  constexpr bool PULSE = MODE == 4;             // ... with a pulse (per-step field integral)
+  constexpr bool FIELD = MODE == 3 || PULSE;    // local step with a vector potential
   using FT = typename FactorOf<MODE>::type;
   const bool read_v = (MODE == 2) || (FIELD && V != nullptr) || (MODE < 0 && a.ph.mode == 2);
+  // pulse: the field integral factor of each step of the pass
+  double Fs[PULSE ? K : 1];
+#pragma unroll
+  for (int s = 0; s < (PULSE ? K : 1); ++s) Fs[s] = PULSE ? pulse_step_integral(a.pulse, s) : 0.0;
   const bool zero_walls = !a.periodic;
   // input row of iteration it; stage st completes row in_row(it) -+ (st + 1)
   auto in_row = [&](int it) -> int64_t { return UP ? jb - NS + it : je - 1 + NS - it; };
@@ -306,7 +311,9 @@ __device__ __forceinline__ void march2d(const T* __restrict__ src, T* __restrict
         if (EDGE && !c.full && c.out) zero(cur);
       }
       FT& fnew = f[k % P];
-      if constexpr (FIELD)
+      if constexpr (PULSE)
+        fnew = pulse_row<TWO>(vcur, acur[0], acur[1], acur[2], a.ph);
+      else if constexpr (FIELD)
         fnew = field_factors<TWO, false>(vcur, acur[0], acur[1], acur[2], a.ph);
       else
         fnew = factors_of<MODE, TWO>(vcur, a.ph);
@@ -326,7 +333,10 @@ __device__ __forceinline__ void march2d(const T* __restrict__ src, T* __restrict
           Axis<AX1, T>::combine(ry, mv[st][k % 2], o);
         mv[st][k % 2] = UP ? ry : ly;
         if (S::phase(st)) {
-          if constexpr (FIELD)
+          if constexpr (PULSE)
+            apply_field(o, pulse_factors<TWO>(f[((k - st - 1) % P + P) % P],
+                                              Fs[st / S::kStages], a.ph));
+          else if constexpr (FIELD)
             apply_field(o, f[((k - st - 1) % P + P) % P]);
           else
             apply_local<MODE>(o, f[((k - st - 1) % P + P) % P], a.ph);
@@ -343,7 +353,9 @@ __device__ __forceinline__ void march2d(const T* __restrict__ src, T* __restrict
         cur = o;
       }
       if (it >= 2 * NS && own) store_site(dst + (out_row(it, NS) * nx + c.x) * 8, cur);
-      if constexpr (FIELD)
+      if constexpr (PULSE)
+        ;  // pulse_row repaired far phase arguments itself
+      else if constexpr (FIELD)
         field_fix<TWO>(fnew, vcur, acur[0], acur[1], acur[2], a.ph);
       else
         factors_fix<MODE, TWO>(fnew, vcur, a.ph);
@@ -366,11 +378,14 @@ __device__ __forceinline__ void one_row(const T* __restrict__ src, T* __restrict
   Site<T> m;
   load_cell<NC, AX>(src, c.col, m);
   if (c.out) zero(m);
-  constexpr bool FIELD = MODE == 3;
+  constexpr bool PULSE = MODE == 4;
+  constexpr bool FIELD = MODE == 3 || PULSE;
   const bool read_v = (MODE == 2) || (FIELD && V != nullptr) || (MODE < 0 && a.ph.mode == 2);
   const double v = read_v ? V[c.col] : 0.0;
   typename FactorOf<MODE>::type f;
-  if constexpr (FIELD) {
+  if constexpr (PULSE) {
+    f = pulse_row<TWO>(v, a.At[c.col], a.At[a.cells + c.col], a.At[2 * a.cells + c.col], a.ph);
+  } else if constexpr (FIELD) {
     const double ax = a.At[c.col], ay = a.At[a.cells + c.col], az = a.At[2 * a.cells + c.col];
     f = field_factors<TWO, false>(v, ax, ay, az, a.ph);
     field_fix<TWO>(f, v, ax, ay, az, a.ph);
@@ -387,7 +402,9 @@ __device__ __forceinline__ void one_row(const T* __restrict__ src, T* __restrict
       if (walls) zero(m);
     }
     if (S::phase(s)) {
-      if constexpr (FIELD)
+      if constexpr (PULSE)
+        apply_field(m, pulse_factors<TWO>(f, pulse_step_integral(a.pulse, s / S::kStages), a.ph));
+      else if constexpr (FIELD)
         apply_field(m, f);
       else
         apply_local<MODE>(m, f, a.ph);

@@ -26,7 +26,8 @@ DL_BC_ZERO, DL_BC_PERIODIC = 0, 1
 DL_DRY, DL_GRAPH, DL_STRANG, DL_BISPINOR = 1, 2, 4, 8
 
 # every entry point of include/libdirac.h
-EXPORTS = ("dl_plan_create", "dl_plan_destroy", "dl_step", "dl_step_field", "dl_step_out",
+EXPORTS = ("dl_plan_create", "dl_plan_destroy", "dl_step", "dl_step_field", "dl_step_pulse",
+           "dl_step_out",
            "dl_step_fused_out",
            "dl_observables", "dl_plan_set_norm_check", "dl_seed_adjoint",
            "dl_grad_step", "dl_project", "dl_expand", "dl_batch_create", "dl_batch_step",
@@ -43,6 +44,14 @@ class DiracError(RuntimeError):
 class NormWarning(UserWarning):
     """dl_observables reported DL_WARN_NORM: the norm left the band of the
     plan's norm check."""
+
+
+class Pulse(ctypes.Structure):
+    """dl_pulse: f(t) = w(t) sin(omega t + phase), w the trapezoid envelope
+    (rise t_on, plateau t_flat, fall t_off)."""
+    _fields_ = [("omega", ctypes.c_double), ("phase", ctypes.c_double),
+                ("t_on", ctypes.c_double), ("t_flat", ctypes.c_double),
+                ("t_off", ctypes.c_double)]
 
 
 class Grid(ctypes.Structure):
@@ -73,6 +82,7 @@ def load() -> ctypes.CDLL:
         "dl_step": [vp, vp, vp, i64, vp],
         "dl_step_out": [vp, vp, vp, vp, vp],
         "dl_step_field": [vp, vp, vp, vp, i64, vp],
+        "dl_step_pulse": [vp, vp, vp, vp, P(Pulse), dbl, i64, vp],
         "dl_step_fused_out": [vp, vp, vp, vp, i64, vp],
         "dl_plan_set_depth": [vp, ci],
         "dl_observables": [vp, vp, dbl, P(dbl), vp],
@@ -199,6 +209,18 @@ class Plan:
         the local step."""
         check(self.lib.dl_step_field(self.handle, self._state(psi), self._cells(V, "V"),
                                      self._field(A), int(nsteps), _stream_handle()))
+        return psi
+
+    def step_pulse(self, psi, V=None, P=None, pulse=None, t0=0.0, nsteps=1):
+        """dl_step_pulse: steps whose field integral is P times the integral
+        of the pulse over each step; pulse: dict (omega, phase, t_on, t_flat,
+        t_off); P: float64, shape (3,) + grid."""
+        if P is None or pulse is None:
+            raise ValueError("P and pulse are required")
+        pk = Pulse(*[float(pulse[k]) for k in ("omega", "phase", "t_on", "t_flat", "t_off")])
+        check(self.lib.dl_step_pulse(self.handle, self._state(psi), self._cells(V, "V"),
+                                     self._field(P), ctypes.byref(pk), float(t0), int(nsteps),
+                                     _stream_handle()))
         return psi
 
     def _field(self, A):
