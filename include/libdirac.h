@@ -201,6 +201,23 @@ int dl_step_fused_out(dl_plan p, const void *src, void *dst, const double *V, in
  * its band (below); out[] is written in both cases. */
 int dl_observables(dl_plan p, const void *psi, double x_b, double out[5], void *stream);
 
+/* dl_observables for callers that cannot allocate (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): no plan, no
+ * allocation, no synchronisation.  The state psi (device, layout of the
+ * conventions above; flags = DL_BISPINOR for a two-component 1-D line, else 0)
+ * on grid g with cell size dx; out is a DEVICE array of 5 doubles, written
+ * with the values of dl_observables (same kernels, same bits), stream-ordered.
+ * The per-block partial sums live in a static device array of the library
+ * (80 KiB per GPU, held until the process ends) that every call on that GPU
+ * shares: calls that overlap on one GPU (two streams, or two threads) race,
+ * so serialise them.  Each call writes every partial it reads, so nothing
+ * needs clearing.  Grids of any valid size fit (the reduction always uses the
+ * same 1024 partials); grids beyond 2^40 cells, a NULL or misaligned pointer,
+ * or a bad dtype / flag are refused (DL_ERR_ARG, DL_ERR_ALIGN, DL_ERR_DTYPE).
+ * The first call on a device looks up the array's device address. */
+int dl_observables_noalloc(const dl_grid *g, double dx, dl_dtype dtype, unsigned flags,
+                           const void *psi, double x_b, double *out, void *stream);
+
 /* Norm watchdog of dl_observables.  The transports of eq:sol_dis_1-3 are
  * unitary on a periodic box and, with the zero wall of Sec. 5, only lose the
  * probability that crosses the wall; the local step D of eq:sol_dis_4 (and the

@@ -8,7 +8,14 @@
 // waves of the block, then in a final one-block pass over the per-block
 // partials in block order.  The grid size is fixed, so results do not depend
 // on scheduling.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <mutex>
+
+#include "../../include/libdirac.h"
 #include "dirac_launch.h"
+#include "dirac_plan.h"
 
 namespace dirac {
 
@@ -202,3 +209,86 @@ hipError_t launch_observables(bool fp64, const void* psi, const ObsArgs& a, doub
 }
 
 }  // namespace dirac
+
+// ===========================================================================
+// dl_observables_noalloc: the observables of a state without a plan and
+// without any allocation.  The per-block partial sums live in a file-scope
+// device array; the host reaches it through the address that
+// hipGetSymbolAddress returns for the current device (looked up on the first
+// call on each device and kept), never through the array's name.
+// ===========================================================================
+namespace {
+
+constexpr int kScratchDoubles = dirac::kObsBlocks * dirac::kQ * 2;  // 80 KiB
+static_assert(kScratchDoubles >= dirac::kObsBlocks * dirac::kQ * 2,
+              "scratch must hold the partials of every block");
+
+__device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[kMaxDevices] = {};
+
+// device address of this device's scratch array
+int scratch_of_current_device(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return dirac::set_hip_error(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices)
+    return dirac::set_error(DL_ERR_ARG, "device index beyond the scratch table (64 devices)");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return dirac::set_hip_error(e, "hipGetSymbolAddress(scratch)");
+    g_scratch[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch[dev];
+  return DL_OK;
+}
+
+}  // namespace
+
+extern "C" int dl_observables_noalloc(const dl_grid* g, double dx, dl_dtype dtype, unsigned flags,
+                                      const void* psi, double x_b, double* out, void* stream) {
+  using namespace dirac;
+  if (!g) return set_error(DL_ERR_ARG, "grid is NULL");
+  if (g->ndim < 1 || g->ndim > 3) return set_error(DL_ERR_ARG, "ndim must be 1..3");
+  int64_t cells = 1;
+  for (int d = 0; d < g->ndim; ++d) {
+    if (g->n[d] < 1 || g->n[d] > (int64_t(1) << 31))
+      return set_error(DL_ERR_ARG, "cell count of a grid dimension out of range");
+    if (!std::isfinite(g->xmin[d])) return set_error(DL_ERR_ARG, "xmin not finite");
+    if (cells > (int64_t(1) << 40) / g->n[d])
+      return set_error(DL_ERR_ARG, "grid beyond 2^40 cells");
+    cells *= g->n[d];
+  }
+  if (!std::isfinite(dx) || dx <= 0.0) return set_error(DL_ERR_ARG, "dx must be finite and > 0");
+  if (dtype != DL_C64 && dtype != DL_C128) return set_error(DL_ERR_DTYPE, "unknown dtype");
+  if (flags & ~DL_BISPINOR) return set_error(DL_ERR_ARG, "only DL_BISPINOR is a valid flag");
+  const bool pair = (flags & DL_BISPINOR) != 0;
+  if (pair && g->ndim != 1) return set_error(DL_ERR_ARG, "two-component states are 1-D lines");
+  int rc = check_state_ptr(psi, "psi");
+  if (rc) return rc;
+  if ((rc = check_f64_ptr(out, "out", false))) return rc;
+  if (std::isnan(x_b)) return set_error(DL_ERR_ARG, "x_b is NaN");
+  // the partials of kObsBlocks blocks, 2 * kQ doubles each, must fit the array
+  if (int64_t(kObsBlocks) * kQ * 2 > kScratchDoubles)
+    return set_error(DL_ERR_ARG, "reduction partials exceed the static scratch");
+  double* sp = nullptr;
+  if ((rc = scratch_of_current_device(&sp))) return rc;
+  ObsArgs a{};
+  a.n0 = g->n[0];
+  a.n1 = g->ndim > 1 ? g->n[1] : 1;
+  a.n2 = g->ndim > 2 ? g->n[2] : 1;
+  a.ndim = g->ndim;
+  a.dx = dx;
+  a.xmin0 = g->xmin[0];
+  a.xmin1 = g->ndim > 1 ? g->xmin[1] : 0.0;
+  a.xmin2 = g->ndim > 2 ? g->xmin[2] : 0.0;
+  a.x_b = x_b;
+  a.nc = pair ? 2 : 4;
+  hipError_t e = launch_observables(dtype == DL_C128, psi, a, sp, out,
+                                    static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? DL_OK : set_hip_error(e, "observables launch");
+}

@@ -29,7 +29,8 @@ DL_DRY, DL_GRAPH, DL_STRANG, DL_BISPINOR = 1, 2, 4, 8
 EXPORTS = ("dl_plan_create", "dl_plan_destroy", "dl_step", "dl_step_field", "dl_step_pulse",
            "dl_step_out",
            "dl_step_fused_out",
-           "dl_observables", "dl_plan_set_norm_check", "dl_seed_adjoint",
+           "dl_observables", "dl_observables_noalloc", "dl_plan_set_norm_check",
+           "dl_seed_adjoint",
            "dl_grad_step", "dl_project", "dl_expand", "dl_batch_create", "dl_batch_step",
            "dl_plan_set_tiling", "dl_plan_set_depth", "dl_plan_info", "dl_batch_set",
            "dl_batch_autotune", "dl_last_error", "dl_version")
@@ -87,6 +88,7 @@ def load() -> ctypes.CDLL:
         "dl_plan_set_depth": [vp, ci],
         "dl_observables": [vp, vp, dbl, P(dbl), vp],
         "dl_plan_set_norm_check": [vp, dbl, dbl],
+        "dl_observables_noalloc": [P(Grid), dbl, ci, ctypes.c_uint, vp, dbl, vp, vp],
         "dl_seed_adjoint": [vp, vp, dbl, vp, vp, vp],
         "dl_grad_step": [vp, vp, vp, vp, vp, i64, vp],
         "dl_project": [vp, vp, vp, ci, vp, vp],
