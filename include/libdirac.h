@@ -266,7 +266,10 @@ int dl_expand(dl_plan p, const double *G, const double *theta, int nb, double *V
 /* ---- batches: many independent plans advanced by shared launches ------- */
 
 /* Build a batch of `count` instances; grids[k], dx[k], dt[k], c[k], m[k] as in
- * dl_plan_create, one dtype and bc for all.  Instances must be 1-D or 2-D. */
+ * dl_plan_create, one dtype and bc for all.  Instances must be 1-D or 2-D.
+ * Flags: DL_GRAPH (each call of one shape is captured once and replayed as
+ * one graph), DL_DRY.  The batch owns a second state buffer per instance, a
+ * second stream and two events. */
 int dl_batch_create(dl_plan *out, const dl_grid *grids, const double *dx,
                     const double *dt, const double *c, const double *m, int count,
                     dl_dtype dtype, dl_bc bc, unsigned flags);
@@ -274,7 +277,14 @@ int dl_batch_create(dl_plan *out, const dl_grid *grids, const double *dx,
 /* Advance instance k in place by nsteps[k] steps: psi[k] (device), V[k]
  * (device or NULL).  The arrays psi, V and nsteps are HOST arrays of length
  * count.  Each instance's result is bit-identical to dl_step on a plan with
- * the same parameters. */
+ * the same parameters.  1-D instances of up to 4096 cells, or of up to four
+ * times an even share of the batch's cells per compute unit if that is more
+ * (at most 2^20 cells), run whole in a
+ * persistent kernel (a workgroup carries a bin of such lines through all of
+ * their steps); the others advance by one launch per pass of fused steps over
+ * a table of tiles; the two run concurrently (a second stream forked from and
+ * joined to `stream`).  Synchronises `stream` before it rewrites the
+ * descriptors of the previous call. */
 int dl_batch_step(dl_plan b, void *const *psi, const double *const *V,
                   const int64_t *nsteps, void *stream);
 
@@ -307,20 +317,31 @@ int dl_plan_set_depth(dl_plan p, int depth);
  * [9] graph_pairs, [10] fused steps per pass, [11] workgroups of a
  * single-step pass, [12] reverse steps per pass of dl_grad_step, [13] steps
  * per pass of dl_step_field.  Works on DL_DRY plans.  On a batch handle every
- * value is 0 but [10], the steps fused per pass of the batch. */
+ * value is 0 but [10], the steps fused per pass of the batch, [14] the
+ * instances run whole by the lines kernel, [15] its workgroups (0 on a dry
+ * batch) and [16] their threads. */
 int dl_plan_info(dl_plan p, int64_t *info, int n);
 
-/* Batch tiling: seg_len >= 1 rows per 2-D march segment of every instance,
- * graph_pairs >= 1 as in dl_plan_set_tiling.  Results stay bit-identical. */
-int dl_batch_set(dl_plan b, int seg_len, int graph_pairs);
+/* Batch tiling: seg_len >= 1 rows per 2-D march segment of every size class,
+ * depth in 1 .. the batch's largest (5, less on periodic boxes of few rows)
+ * fused steps per pass.  Results stay bit-identical. */
+int dl_batch_set(dl_plan b, int seg_len, int depth);
 
-/* Autotuner of the batch: times `trials` passes at each candidate segment
- * length (8, 16, 32, 64, 128 rows) on a device copy of the states psi[k]
- * (HOST array of count device pointers; V as in dl_batch_step), keeps the
- * fastest and writes it to *chosen (HOST, may be NULL).  The caller's states
- * are not modified.  Allocates a scratch copy of all states for the call;
- * synchronises `stream`.  When the environment variable LIBDIRAC_TUNE_CACHE
- * names a file, appends "f32|f64:count seg_len" to it. */
+/* Autotuner of the batch's tile shapes: a coordinate search, timed on a
+ * device copy of the states psi[k] (HOST array of count device pointers; V as
+ * in dl_batch_step; the caller's states are not modified), over the steps
+ * fused per pass (3 .. the largest; the strip width 64 - 2 depth follows),
+ * then the march segment length (16 .. 512 rows) of each 2-D size class
+ * present (class = floor(log2(rows))), then the workgroup size of the lines
+ * kernel (256 .. 1024 threads, 512 with complex128).  Each candidate runs
+ * `trials` passes after a warm-up and is scored by its time per step.
+ * chosen (HOST, may be NULL) receives 3 ints: the depth, the lines workgroup
+ * size and the segment length of the largest size class (0 if none).
+ * Allocates a scratch copy of all states for the call; synchronises
+ * `stream`.  When the environment variable LIBDIRAC_TUNE_CACHE names a file,
+ * appends one line per setting, "dirac-batch <c64|c128> <key> <value>" with
+ * key 2d-depth, 2d-rows<class>-seg or 1d-threads; dl_batch_create reads that
+ * file and applies the settings whose dtype (and size class) match. */
 int dl_batch_autotune(dl_plan b, void *const *psi, const double *const *V, int trials,
                       int *chosen, void *stream);
 

@@ -98,6 +98,8 @@ void destroy_batch(dl_plan p);
 int reverse_depth(dl_plan p);
 // steps fused per pass of a batch
 int batch_depth(dl_plan b);
+// dl_plan_info of a batch handle
+void batch_info(dl_plan b, int64_t* info, int n);
 // measures the occupancy of the 3-D second-order passes (called when such a
 // plan is created, outside any stream capture)
 void strang3d_prepare(bool fp64);

@@ -751,8 +751,8 @@ extern "C" int dl_plan_set_depth(dl_plan p, int depth) {
 
 extern "C" int dl_plan_info(dl_plan p, int64_t* info, int n) {
   if (!p || !info) return fail(DL_ERR_ARG, "NULL argument");
-  if (p->is_batch) {  // a batch reports its steps per pass only
-    for (int i = 0; i < n; ++i) info[i] = (i == 10) ? batch_depth(p) : 0;
+  if (p->is_batch) {
+    batch_info(p, info, n);
     return DL_OK;
   }
   const SweepArgs& t = p->sw[p->depth - 1];  // tiling of the deepest pass in use

@@ -390,21 +390,30 @@ class Batch:
         ns = (ctypes.c_int64 * self.count)(*[int(_at(nsteps, k)) for k in range(self.count)])
         check(self.lib.dl_batch_step(self.handle, P, Vp, ns, _stream_handle()))
 
-    def autotune(self, psis, Vs, trials=4) -> int:
+    def autotune(self, psis, Vs, trials=4) -> dict:
+        """Tune the tile shapes on a copy of the states; returns the choice
+        (depth, line_threads, seg_len of the largest 2-D size class)."""
         P, Vp = self._ptrs(psis, Vs)
-        out = ctypes.c_int(0)
-        check(self.lib.dl_batch_autotune(self.handle, P, Vp, int(trials), ctypes.byref(out),
+        out = (ctypes.c_int * 3)()
+        check(self.lib.dl_batch_autotune(self.handle, P, Vp, int(trials), out,
                                          _stream_handle()))
-        return out.value
+        return {"depth": out[0], "line_threads": out[1], "seg_len": out[2]}
 
-    def set(self, seg_len=32, graph_pairs=16):
-        check(self.lib.dl_batch_set(self.handle, int(seg_len), int(graph_pairs)))
+    def set(self, seg_len=64, depth=None):
+        """Segment length of every 2-D size class and steps per pass (None:
+        the current depth)."""
+        check(self.lib.dl_batch_set(self.handle, int(seg_len),
+                                    int(self.depth() if depth is None else depth)))
+
+    def info(self) -> dict:
+        buf = (ctypes.c_int64 * 17)()
+        check(self.lib.dl_plan_info(self.handle, buf, 17))
+        return {"depth": int(buf[10]), "lines": int(buf[14]), "line_bins": int(buf[15]),
+                "line_threads": int(buf[16])}
 
     def depth(self) -> int:
         """Steps fused per pass of the batch."""
-        buf = (ctypes.c_int64 * 11)()
-        check(self.lib.dl_plan_info(self.handle, buf, 11))
-        return int(buf[10])
+        return self.info()["depth"]
 
     def close(self):
         if getattr(self, "handle", None):

@@ -2,8 +2,9 @@
 oracle's run of that instance (relative L2 1e-12 for complex128 state, 5e-6 for
 complex64) and ends bit-identical to the same instance advanced alone with
 dl_step, for uneven step counts (odd, even, zero), both dtypes, with and
-without graph replay, and after autotuning (which must leave the caller's
-states untouched)."""
+without graphs, whether an instance runs whole in the lines kernel or pass by
+pass over tiles, at every pass depth, and after autotuning (which must leave
+the caller's states untouched and records its choice in the cache file)."""
 import numpy as np
 import pytest
 
@@ -70,7 +71,7 @@ def test_batch_matches_oracle_and_single_runs(dtype, graph):
     Vs = [torch.from_numpy(w.V).to("cuda") for w in ws]
     with L.Batch([w.shape for w in ws], [w.dx for w in ws], [w.dt for w in ws],
                  [w.c for w in ws], [w.m for w in ws], dtype=dtype, graph=graph) as b:
-        b.set(seg_len=24, graph_pairs=8)
+        b.set(seg_len=24)
         b.step(psis, Vs, nsteps)
         torch.cuda.synchronize()
     for w, n, t in zip(ws, nsteps, psis):
@@ -89,9 +90,11 @@ def test_autotune_leaves_inputs_and_keeps_bits():
     before = [t.cpu().numpy() for t in psis]
     with L.Batch([w.shape for w in ws], [w.dx for w in ws], [w.dt for w in ws],
                  [w.c for w in ws], [w.m for w in ws], dtype="c64") as b:
-        H = b.autotune(psis, Vs, trials=2)
+        ch = b.autotune(psis, Vs, trials=2)
         torch.cuda.synchronize()
-        assert H in (8, 16, 32, 64, 128)
+        assert ch["depth"] in (3, 4, 5) and ch["seg_len"] in (16, 32, 64, 128, 256, 512)
+        assert ch["line_threads"] in (256, 512, 1024)
+        assert b.depth() == ch["depth"]
         for t, ref in zip(psis, before):
             assert same_bits(t.cpu().numpy(), ref)
         b.step(psis, Vs, [40] * len(ws))
@@ -117,7 +120,7 @@ def test_batch_graph_replay_of_fused_passes(dtype):
     Vs = [None if k % 3 == 2 else torch.from_numpy(w.V).to("cuda") for k, w in enumerate(ws)]
     with L.Batch([w.shape for w in ws], [w.dx for w in ws], [w.dt for w in ws],
                  [w.c for w in ws], [w.m for w in ws], dtype=dtype, graph=True) as b:
-        b.set(seg_len=32, graph_pairs=4)
+        b.set(seg_len=32)
         b.step(psis, Vs, nsteps)
         torch.cuda.synchronize()
     for k, (w, n, t) in enumerate(zip(ws, nsteps, psis)):
@@ -153,3 +156,74 @@ def test_batch_periodic_thin_instances():
             p.step(psi, torch.from_numpy(v0).to("cuda"), n)
             torch.cuda.synchronize()
         assert same_bits(got, psi.cpu().numpy()), (s, n)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("graph", [False, True])
+def test_lines_kernel_and_depths(dtype, graph):
+    """Only 1-D instances (all run whole by the lines kernel, several per
+    workgroup) and a mix where a long line stays on the tiles; every pass depth
+    gives the bits of the single-plan run and matches the oracle."""
+    import torch
+    from paper_1107_4650_amd.inputs import packet, potential_tanh
+    announce(f"batch lines {dtype} graph={graph}")
+    tdt = torch.complex64 if dtype == "c64" else torch.complex128
+    lines = [(n,) for n in (300, 1000, 4000, 777, 2000, 64, 1500)]
+    mixed = lines[:3] + [(96, 80), (200000,)]
+    for shapes in (lines, mixed):
+        ws = []
+        for k, s_ in enumerate(shapes):
+            psi = packet(s_, 0.01, delta=0.2, p0=[30.0] + [0.0] * (len(s_) - 1),
+                         r0=[0.0] * len(s_))
+            ws.append((s_, psi, potential_tanh(s_, 0.01, (0.5 + 0.3 * k) * C_LIGHT ** 2, 0.1)))
+        nsteps = [23 + 5 * k for k in range(len(shapes))]
+        nsteps[1] = 0
+        for depth in (5, 3, 1):
+            psis = [torch.from_numpy(p_).to("cuda").to(tdt) for _, p_, _ in ws]
+            Vs = [torch.from_numpy(v).to("cuda") for _, _, v in ws]
+            with L.Batch(shapes, 0.01, 0.01 / C_LIGHT, C_LIGHT, 1.0, dtype=dtype,
+                         graph=graph) as b:
+                b.set(seg_len=32, depth=depth)
+                info = b.info()
+                b.step(psis, Vs, nsteps)
+                b.step(psis, Vs, nsteps)  # a second call of the same shape (graph reuse)
+                torch.cuda.synchronize()
+            # lines of up to 4096 cells always qualify; the 200000-cell one here
+            # exceeds four even shares of the batch per compute unit
+            n_short = sum(1 for s_ in shapes if len(s_) == 1 and s_[0] <= 4096)
+            assert info["lines"] == n_short and info["line_bins"] >= 1, info
+            for (s_, p_, v), n, t in zip(ws, nsteps, psis):
+                got = t.cpu().numpy()
+                start = p_.astype(np.complex64 if dtype == "c64" else np.complex128)
+                ax = tuple(range(len(s_)))
+                check_oracle(start, v, 2 * n, got, dt=0.01 / C_LIGHT, c=C_LIGHT, m=1.0,
+                             axes=ax, bc="zero", dtype=dtype, what=(s_, n, depth))
+                tp = torch.from_numpy(p_).to("cuda").to(tdt)
+                with L.Plan(s_, 0.01, 0.01 / C_LIGHT, C_LIGHT, 1.0, dtype=dtype) as p:
+                    p.step(tp, torch.from_numpy(v).to("cuda"), 2 * n)
+                    torch.cuda.synchronize()
+                assert same_bits(got, tp.cpu().numpy()), (s_, n, depth)
+
+
+def test_autotune_cache_file(tmp_path, monkeypatch):
+    """The tuner appends its choice keyed by dtype and size class; a new batch of
+    the same kind reads it back."""
+    import torch
+    announce("batch tune cache")
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("LIBDIRAC_TUNE_CACHE", str(cache))
+    ws = _instances(5, seed=21)
+    psis = [torch.from_numpy(w.psi0).to("cuda").to(torch.complex64) for w in ws]
+    Vs = [torch.from_numpy(w.V).to("cuda") for w in ws]
+    args = ([w.shape for w in ws], [w.dx for w in ws], [w.dt for w in ws],
+            [w.c for w in ws], [w.m for w in ws])
+    with L.Batch(*args, dtype="c64") as b:
+        ch = b.autotune(psis, Vs, trials=2)
+    text = cache.read_text().split("\n")
+    assert f"dirac-batch c64 2d-depth {ch['depth']}" in text
+    assert f"dirac-batch c64 1d-threads {ch['line_threads']}" in text
+    assert any(t.startswith("dirac-batch c64 2d-rows") for t in text)
+    with L.Batch(*args, dtype="c64") as b2:
+        assert b2.depth() == ch["depth"] and b2.info()["line_threads"] == ch["line_threads"]
+    with L.Batch(*args, dtype="c128") as b3:  # another dtype: defaults
+        assert b3.depth() == 5
