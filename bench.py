@@ -43,7 +43,8 @@ def log(msg):
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("dirac_device.h", "dirac_sweep_impl.h", "dirac_sweep.hip", "dirac_launch.h"):
+    for f in ("dirac_device.h", "dirac_sweep_impl.h", "dirac_sweep2d_kernels.h",
+              "dirac_sweep2d_f32_hi.hip", "dirac_launch.h"):
         with open(os.path.join(ROOT, "paper_1107_4650_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -426,6 +426,59 @@ __device__ __forceinline__ void apply_factors(Site<T>& s, const Factors& f) {
   cmul_round(s.v[6], s.v[7], f.dr, f.di);
 }
 
+// FP32 storage, the form kept in the 1-D / 2-D passes: every FP64 factor f is
+// held as an unevaluated pair of floats, f = hi + lo with hi = fl32(f) and
+// lo = fl32(f - hi) (split once per row, when the factors are formed), and
+// applied with FP32 fused multiply-adds, the small lo products first:
+//   re' = fma(-y, fi, fma(x, fr, fma(-y, fi_lo, x fr_lo)))   and likewise im'.
+// The pair carries the factor to about 2^-48 relative, so the modulus and
+// phase of the applied factor do not drift (what an FP32-rounded factor
+// would do, by about 1e-8 per step, coherently over the steps of a run); each
+// product is rounded at most twice in FP32.  No FP64 operation or conversion
+// remains in the stages.
+struct FactorsHL {
+  float ur, ui, dr, di;      // hi parts
+  float urL, uiL, drL, diL;  // lo parts
+};
+
+__device__ __forceinline__ void split_pair(double v, float& hi, float& lo) {
+  hi = static_cast<float>(v);
+  lo = static_cast<float>(v - static_cast<double>(hi));
+}
+
+__device__ __forceinline__ FactorsHL split_factors(const Factors& f) {
+  FactorsHL h;
+  split_pair(f.ur, h.ur, h.urL);
+  split_pair(f.ui, h.ui, h.uiL);
+  split_pair(f.dr, h.dr, h.drL);
+  split_pair(f.di, h.di, h.diL);
+  return h;
+}
+
+__device__ __forceinline__ void cmul_hl(float& re, float& im, float fr, float fi, float frL,
+                                        float fiL) {
+  const float x = re, y = im;
+  re = fmaf(-y, fi, fmaf(x, fr, fmaf(-y, fiL, x * frL)));
+  im = fmaf(y, fr, fmaf(x, fi, fmaf(y, frL, x * fiL)));
+}
+
+__device__ __forceinline__ void apply_factors(Site<float>& s, const FactorsHL& f) {
+  cmul_hl(s.v[0], s.v[1], f.ur, f.ui, f.urL, f.uiL);
+  cmul_hl(s.v[2], s.v[3], f.ur, f.ui, f.urL, f.uiL);
+  cmul_hl(s.v[4], s.v[5], f.dr, f.di, f.drL, f.diL);
+  cmul_hl(s.v[6], s.v[7], f.dr, f.di, f.drL, f.diL);
+}
+
+// the factors as a 1-D / 2-D pass keeps them for state type T
+template <typename T> struct Stored {
+  using type = Factors;
+  static __device__ __forceinline__ Factors of(const Factors& f) { return f; }
+};
+template <> struct Stored<float> {
+  using type = FactorsHL;
+  static __device__ __forceinline__ FactorsHL of(const Factors& f) { return split_factors(f); }
+};
+
 template <typename T> __device__ __forceinline__ T scale_of(const PhaseK& k);
 template <> __device__ __forceinline__ float scale_of<float>(const PhaseK& k) { return k.scale_f; }
 template <> __device__ __forceinline__ double scale_of<double>(const PhaseK& k) {
@@ -440,9 +493,10 @@ __device__ __forceinline__ void scale_site(Site<T>& s, const PhaseK& k) {
 }
 
 // Local step with the phase mode fixed at compile time (MODE < 0: read it
-// from k at run time); f holds the cell's factors for modes 1 and 2.
-template <int MODE, typename T>
-__device__ __forceinline__ void apply_local(Site<T>& s, const Factors& f, const PhaseK& k) {
+// from k at run time); f holds the cell's factors for modes 1 and 2 (as FP64
+// factors, or as FP32 hi + lo pairs).
+template <int MODE, typename T, typename F>
+__device__ __forceinline__ void apply_local(Site<T>& s, const F& f, const PhaseK& k) {
   if constexpr (MODE == 0) {
     scale_site(s, k);
   } else if constexpr (MODE > 0) {

@@ -44,16 +44,16 @@ __global__ __launch_bounds__(1024) void k_resident1d(T* __restrict__ psi,
   const int nthr = blockDim.x;
   const int64_t n = a.n;
   Site<T> s[SPT];
-  Factors f[SPT];
+  typename Stored<T>::type f[SPT];  // as the tiled passes keep them, for the same bits
 #pragma unroll
   for (int k = 0; k < SPT; ++k) {
     const int64_t x = static_cast<int64_t>(t) * SPT + k;
     if (x < n) {
       load_cell<NC, AX>(psi, x, s[k]);
-      f[k] = phase_factors((a.ph.mode == 2) ? V[x] : 0.0, a.ph);
+      f[k] = Stored<T>::of(phase_factors((a.ph.mode == 2) ? V[x] : 0.0, a.ph));
     } else {
       zero(s[k]);
-      f[k] = phase_factors(0.0, a.ph);
+      f[k] = Stored<T>::of(phase_factors(0.0, a.ph));
     }
   }
   for (int64_t step = 0; step < a.nsteps; ++step) {

@@ -11,6 +11,8 @@
 // rows in registers, so every row is loaded once per segment plus one halo
 // row at each end.
 #pragma once
+#include <type_traits>
+
 #include "dirac_device.h"
 #include "dirac_launch.h"
 
@@ -232,7 +234,9 @@ __device__ __forceinline__ void march2d(const T* __restrict__ src, T* __restrict
   const bool own = c.inside && lane >= wlane && lane <= 63 - wlane;  // wlane >= X
   constexpr bool PULSE = MODE == 4;             // ... with a pulse (per-step field integral)
   constexpr bool FIELD = MODE == 3 || PULSE;    // local step with a vector potential
-  using FT = typename FactorOf<MODE>::type;
+  // factor slots: the field's factors, else the phase factors as kept for T
+  using FT = typename std::conditional<FIELD, typename FactorOf<MODE>::type,
+                                       typename Stored<T>::type>::type;
   const bool read_v = (MODE == 2) || (FIELD && V != nullptr) || (MODE < 0 && a.ph.mode == 2);
   // pulse: the field integral factor of each step of the pass
   double Fs[PULSE ? K : 1];
@@ -281,7 +285,7 @@ __device__ __forceinline__ void march2d(const T* __restrict__ src, T* __restrict
     if constexpr (FIELD)
       f[q] = FT{};
     else
-      f[q] = const_factors(a.ph);
+      f[q] = Stored<T>::of(const_factors(a.ph));
   }
   // y movers of stage st, slot it % 2: the stage's input row two iterations
   // back (r movers when marching up, l movers when down)
@@ -310,15 +314,25 @@ __device__ __forceinline__ void march2d(const T* __restrict__ src, T* __restrict
         if (!row_in(it)) zero(cur);
         if (EDGE && !c.full && c.out) zero(cur);
       }
+      // this row's factors; stage st reads slot (it - st - 1) % P, never the
+      // current one, so the plain phase factors are stored at the end of the
+      // iteration, after their far-argument repair
       FT& fnew = f[k % P];
+      Factors fd{};
       if constexpr (PULSE)
         fnew = pulse_row<TWO>(vcur, acur[0], acur[1], acur[2], a.ph);
       else if constexpr (FIELD)
         fnew = field_factors<TWO, false>(vcur, acur[0], acur[1], acur[2], a.ph);
       else
-        fnew = factors_of<MODE, TWO>(vcur, a.ph);
+        fd = factors_of<MODE, TWO>(vcur, a.ph);
 #pragma unroll
       for (int st = 0; st < NS; ++st) {
+        // Filling the pipeline: stage st has a valid input from iteration
+        // 2 st on (stage st - 1's first valid row) and a valid output from
+        // 2 st + 2 on (it needs the y movers of the two rows before).  Earlier
+        // iterations would compute values no stored row depends on, so they
+        // stop here (wave-uniform scalar tests; the bits are unchanged).
+        if (it < 2 * st) break;
         if (S::pre_x(st)) {
           Site<T> phi;
           x_transport_inner<T, AX0>(cur, phi);
@@ -326,12 +340,16 @@ __device__ __forceinline__ void march2d(const T* __restrict__ src, T* __restrict
         }
         Mov<T> ry, ly;
         Axis<AX1, T>::movers(cur, ry, ly);
+        const bool live = it >= 2 * st + 2;
         Site<T> o;
-        if (UP)
-          Axis<AX1, T>::combine(mv[st][k % 2], ly, o);
-        else
-          Axis<AX1, T>::combine(ry, mv[st][k % 2], o);
+        if (live) {
+          if (UP)
+            Axis<AX1, T>::combine(mv[st][k % 2], ly, o);
+          else
+            Axis<AX1, T>::combine(ry, mv[st][k % 2], o);
+        }
         mv[st][k % 2] = UP ? ry : ly;
+        if (!live) break;
         if (S::phase(st)) {
           if constexpr (PULSE)
             apply_field(o, pulse_factors<TWO>(f[((k - st - 1) % P + P) % P],
@@ -353,12 +371,14 @@ __device__ __forceinline__ void march2d(const T* __restrict__ src, T* __restrict
         cur = o;
       }
       if (it >= 2 * NS && own) store_site(dst + (out_row(it, NS) * nx + c.x) * 8, cur);
-      if constexpr (PULSE)
-        ;  // pulse_row repaired far phase arguments itself
-      else if constexpr (FIELD)
+      if constexpr (PULSE) {
+        // pulse_row repaired far phase arguments itself
+      } else if constexpr (FIELD) {
         field_fix<TWO>(fnew, vcur, acur[0], acur[1], acur[2], a.ph);
-      else
-        factors_fix<MODE, TWO>(fnew, vcur, a.ph);
+      } else {
+        factors_fix<MODE, TWO>(fd, vcur, a.ph);
+        fnew = Stored<T>::of(fd);
+      }
     }
   }
 }
@@ -382,7 +402,8 @@ __device__ __forceinline__ void one_row(const T* __restrict__ src, T* __restrict
   constexpr bool FIELD = MODE == 3 || PULSE;
   const bool read_v = (MODE == 2) || (FIELD && V != nullptr) || (MODE < 0 && a.ph.mode == 2);
   const double v = read_v ? V[c.col] : 0.0;
-  typename FactorOf<MODE>::type f;
+  typename std::conditional<FIELD, typename FactorOf<MODE>::type,
+                            typename Stored<T>::type>::type f;
   if constexpr (PULSE) {
     f = pulse_row<TWO>(v, a.At[c.col], a.At[a.cells + c.col], a.At[2 * a.cells + c.col], a.ph);
   } else if constexpr (FIELD) {
@@ -390,8 +411,9 @@ __device__ __forceinline__ void one_row(const T* __restrict__ src, T* __restrict
     f = field_factors<TWO, false>(v, ax, ay, az, a.ph);
     field_fix<TWO>(f, v, ax, ay, az, a.ph);
   } else {
-    f = factors_of<MODE, TWO>(v, a.ph);
-    factors_fix<MODE, TWO>(f, v, a.ph);
+    Factors fd = factors_of<MODE, TWO>(v, a.ph);
+    factors_fix<MODE, TWO>(fd, v, a.ph);
+    f = Stored<T>::of(fd);
   }
 #pragma unroll
   for (int s = 0; s < K * S::kStages; ++s) {
