@@ -65,7 +65,8 @@ struct dl_plan_s {
   void* tmp2 = nullptr;        // second state buffer for the adjoint field
   double* partials = nullptr;  // reduction partials
   double* dres = nullptr;      // device results
-  double* hres = nullptr;      // pinned host results
+  double* hres = nullptr;      // pinned host results (mapped)
+  double* hres_dev = nullptr;  // their device address
   double* proj = nullptr;      // projection partials (grown on demand)
   size_t proj_bytes = 0;
   hipStream_t cap_stream = nullptr;

@@ -332,7 +332,9 @@ extern "C" int dl_plan_create(dl_plan* out, const dl_grid* g, double dx, double 
       (mid && hipMalloc(&p->tmp2, p->state_bytes) != hipSuccess) ||
       hipMalloc(&p->partials, sizeof(double) * 2 * 8 * kObsBlocks) != hipSuccess ||
       hipMalloc(&p->dres, sizeof(double) * 64) != hipSuccess ||
-      hipHostMalloc(&p->hres, sizeof(double) * 64, hipHostMallocDefault) != hipSuccess) {
+      hipHostMalloc(&p->hres, sizeof(double) * 64, hipHostMallocMapped) != hipSuccess ||
+      hipHostGetDevicePointer(reinterpret_cast<void**>(&p->hres_dev), p->hres, 0) !=
+          hipSuccess) {
     (void)hipGetLastError();
     dl_plan_destroy(p);
     return fail(DL_ERR_NOMEM, "device allocation of %zu bytes of scratch failed", p->state_bytes);
@@ -704,10 +706,10 @@ extern "C" int dl_observables(dl_plan p, const void* psi, double x_b, double out
   a.xmin2 = p->g.xmin[2];
   a.x_b = x_b;
   a.nc = p->nc;
-  hipError_t e = launch_observables(p->fp64, psi, a, p->partials, p->dres, st);
+  // the final reduction writes the five values straight into the plan's
+  // mapped pinned buffer (no copy back)
+  hipError_t e = launch_observables(p->fp64, psi, a, p->partials, p->hres_dev, st);
   if (e != hipSuccess) return hip_fail(e, "observables launch");
-  e = hipMemcpyAsync(p->hres, p->dres, 5 * sizeof(double), hipMemcpyDeviceToHost, st);
-  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
   e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
   for (int i = 0; i < 5; ++i) out[i] = p->hres[i];

@@ -93,7 +93,7 @@ __device__ __forceinline__ void load_obs(const T* __restrict__ psi, int64_t c, T
 // cells per iteration (a wrap of the x index moves the row on), so no cell
 // needs an integer division.  Cells are loaded kObsBatch at a time, their
 // addresses linear in j, so the loads of a batch are in flight together.
-constexpr int kObsBatch = 8;
+constexpr int kObsBatch = 4;
 
 template <typename T, int NC>
 __global__ __launch_bounds__(256) void k_obs_partial(const T* __restrict__ psi, ObsArgs a,
