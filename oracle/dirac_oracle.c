@@ -391,9 +391,10 @@ static void step_once_strang(const grid_t *g, zd *psi, zd *tmp, const double *V,
 /* One second-order step on a 3-D grid, the sequence printed in Sec. 2.4:
  *   A(dt/4) B(dt/2) A(dt/4) C(dt/2) D(dt) C(dt/2) A(dt/4) B(dt/2) A(dt/4).
  * With c dt/4 = a every A is the one-cell shift and every B and C the
- * two-cell shift of eq:sol_dis_1-3 (c dt/2 = 2a). */
+ * two-cell shift of eq:sol_dis_1-3 (c dt/2 = 2a).  D is local_step, or
+ * local_step_field with the field integral Atil when `field` is set. */
 static void step_once_strang3(const grid_t *g, zd *psi, zd *tmp, const double *V,
-                              double dt, double c, double m)
+                              const double *Atil, int field, double dt, double c, double m)
 {
     int order[3];
     transport_order(g, order);
@@ -404,12 +405,43 @@ static void step_once_strang3(const grid_t *g, zd *psi, zd *tmp, const double *V
     for (int t = 0; t < 9; ++t) {
         const int d = seq[t][0];
         if (d < 0) {
-            local_step(g, psi, V, dt, c, m, -1.0);
+            if (field)
+                local_step_field(g, psi, V, Atil, dt, c, m);
+            else
+                local_step(g, psi, V, dt, c, m, -1.0);
             continue;
         }
         const int a = g->axis[d];
         transport_d(g, d, seq[t][1], PROJ[a][0], PROJ[a][1], psi, tmp);
         memcpy(psi, tmp, (size_t)bytes);
+    }
+}
+
+/* One step whose D carries the field integral Atil: the lowest-order step
+ * (scheme 0) or the second-order step of Sec. 2.4 (scheme 1; on 3-D grids
+ * its nine-part sequence). */
+static void field_step_once(const grid_t *g, zd *psi, zd *tmp, const double *V,
+                            const double *Atil, int scheme, double dt, double c, double m)
+{
+    if (scheme == 1 && g->ndim == 3) {
+        step_once_strang3(g, psi, tmp, V, Atil, 1, dt, c, m);
+        return;
+    }
+    int order[3];
+    const int k = transport_order(g, order);
+    const int64_t bytes = nsites(g) * 4 * (int64_t)sizeof(zd);
+    for (int t = 0; t < k; ++t) {
+        const int a = g->axis[order[t]];
+        transport_d(g, order[t], 1, PROJ[a][0], PROJ[a][1], psi, tmp);
+        memcpy(psi, tmp, (size_t)bytes);
+    }
+    local_step_field(g, psi, V, Atil, dt, c, m);
+    if (scheme == 1) {
+        for (int t = k - 1; t >= 0; --t) {
+            const int a = g->axis[order[t]];
+            transport_d(g, order[t], 1, PROJ[a][0], PROJ[a][1], psi, tmp);
+            memcpy(psi, tmp, (size_t)bytes);
+        }
     }
 }
 
@@ -463,7 +495,7 @@ int oracle_step_strang(int ndim, const int64_t *n, const int *axis, int bc,
     if (!tmp) return -2;
     for (int64_t s = 0; s < nsteps; ++s) {
         if (ndim == 3)
-            step_once_strang3(&g, (zd *)psi, tmp, V, dt, c, m);
+            step_once_strang3(&g, (zd *)psi, tmp, V, NULL, 0, dt, c, m);
         else
             step_once_strang(&g, (zd *)psi, tmp, V, dt, c, m);
     }
@@ -472,39 +504,21 @@ int oracle_step_strang(int ndim, const int64_t *n, const int *axis, int bc,
 }
 
 /* nsteps steps with a vector potential: the lowest-order step (scheme 0) or
- * the second-order step of Sec. 2.4 (scheme 1, 1-D and 2-D), with D
- * replaced by local_step_field. */
+ * the second-order step of Sec. 2.4 (scheme 1), with D replaced by
+ * local_step_field. */
 int oracle_step_field(int ndim, const int64_t *n, const int *axis, int bc, int scheme,
                       double dt, double c, double m, const double *V, const double *Atil,
                       double *psi, int64_t nsteps, int nthreads)
 {
     grid_t g;
-    if ((scheme == 1 && ndim > 2) || scheme < 0 || scheme > 1 ||
-        grid_from_args(&g, ndim, n, axis, bc) || nsteps < 0)
+    if (scheme < 0 || scheme > 1 || grid_from_args(&g, ndim, n, axis, bc) || nsteps < 0)
         return -1;
     build_matrices();
     set_threads(nthreads);
     zd *tmp = (zd *)malloc((size_t)nsites(&g) * 4 * sizeof(zd));
     if (!tmp) return -2;
-    int order[3];
-    const int k = transport_order(&g, order);
-    const int64_t bytes = nsites(&g) * 4 * (int64_t)sizeof(zd);
-    zd *p = (zd *)psi;
-    for (int64_t st = 0; st < nsteps; ++st) {
-        for (int t = 0; t < k; ++t) {
-            const int a = g.axis[order[t]];
-            transport_d(&g, order[t], 1, PROJ[a][0], PROJ[a][1], p, tmp);
-            memcpy(p, tmp, (size_t)bytes);
-        }
-        local_step_field(&g, p, V, Atil, dt, c, m);
-        if (scheme == 1) {
-            for (int t = k - 1; t >= 0; --t) {
-                const int a = g.axis[order[t]];
-                transport_d(&g, order[t], 1, PROJ[a][0], PROJ[a][1], p, tmp);
-                memcpy(p, tmp, (size_t)bytes);
-            }
-        }
-    }
+    for (int64_t st = 0; st < nsteps; ++st)
+        field_step_once(&g, (zd *)psi, tmp, V, Atil, scheme, dt, c, m);
     free(tmp);
     return 0;
 }
@@ -611,8 +625,8 @@ int oracle_step_pulse(int ndim, const int64_t *n, const int *axis, int bc, int s
                       const double *pp, double t0, double *psi, int64_t nsteps, int nthreads)
 {
     grid_t g;
-    if ((scheme == 1 && ndim > 2) || scheme < 0 || scheme > 1 || !P || !pp ||
-        grid_from_args(&g, ndim, n, axis, bc) || nsteps < 0)
+    if (scheme < 0 || scheme > 1 || !P || !pp || grid_from_args(&g, ndim, n, axis, bc) ||
+        nsteps < 0)
         return -1;
     build_matrices();
     set_threads(nthreads);
@@ -624,26 +638,10 @@ int oracle_step_pulse(int ndim, const int64_t *n, const int *axis, int bc, int s
         free(At);
         return -2;
     }
-    int order[3];
-    const int k = transport_order(&g, order);
-    const int64_t bytes = ns * 4 * (int64_t)sizeof(zd);
-    zd *p = (zd *)psi;
     for (int64_t st = 0; st < nsteps; ++st) {
         const double F = oracle_pulse_integral(pp, t0 + (double)st * dt, t0 + (double)(st + 1) * dt);
         for (int64_t q = 0; q < 3 * ns; ++q) At[q] = F * P[q];
-        for (int t = 0; t < k; ++t) {
-            const int a = g.axis[order[t]];
-            transport_d(&g, order[t], 1, PROJ[a][0], PROJ[a][1], p, tmp);
-            memcpy(p, tmp, (size_t)bytes);
-        }
-        local_step_field(&g, p, V, At, dt, c, m);
-        if (scheme == 1) {
-            for (int t = k - 1; t >= 0; --t) {
-                const int a = g.axis[order[t]];
-                transport_d(&g, order[t], 1, PROJ[a][0], PROJ[a][1], p, tmp);
-                memcpy(p, tmp, (size_t)bytes);
-            }
-        }
+        field_step_once(&g, (zd *)psi, tmp, V, At, scheme, dt, c, m);
     }
     free(tmp);
     free(At);

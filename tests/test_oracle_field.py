@@ -84,3 +84,55 @@ def test_field_zero_reduces_to_plain_step_and_is_unitary(oracle, scheme):
     out = oracle.step_field(psi, V, A, dt=dt, c=C, m=1.0, nsteps=40, axes=(0, 2), bc="periodic",
                             scheme=scheme)
     assert abs(np.sum(np.abs(out) ** 2) / np.sum(np.abs(psi) ** 2) - 1) < 1e-12
+
+
+def test_field_symbol_3d_second_order(oracle):
+    """3-D second-order step with a uniform field on a periodic box: the symbol
+    of a Fourier mode is EA EB EA EC D EC EA EB EA with EA the one-cell shift
+    along x, EB and EC the two-cell shifts along y and z (c dt = 4 a) and D
+    the local step; modes with distinct wave numbers on every axis, so a
+    swapped, dropped or doubled sub-step fails."""
+    n = (6, 5, 4)
+    m = 1.0
+    dt = 4 * DX / C
+    a = np.array([-0.9, 0.6, 1.1])
+    A = np.broadcast_to(a[:, None, None, None], (3,) + n[::-1]).copy()
+    D = local_expm(m * C * C * dt, 0.0, a)
+    k, j, i = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
+    for jx, jy, jz in [(1, 2, 1), (2, 1, 3), (5, 3, 2), (0, 4, 1)]:
+        th = 2 * np.pi * np.array([jx / n[0], jy / n[1], jz / n[2]])
+        phase = np.exp(1j * (th[0] * i + th[1] * j + th[2] * k))
+        EA = scipy.linalg.expm(-1j * R.dirac_alpha(0) * th[0])
+        EB = scipy.linalg.expm(-1j * R.dirac_alpha(1) * 2 * th[1])
+        EC = scipy.linalg.expm(-1j * R.dirac_alpha(2) * 2 * th[2])
+        expect = EA @ EB @ EA @ EC @ D @ EC @ EA @ EB @ EA
+        M = np.zeros((4, 4), complex)
+        for col in range(4):
+            psi = np.zeros(n[::-1] + (4,), complex)
+            psi[..., col] = phase
+            out = oracle.step_field(psi, None, A, dt=dt, c=C, m=m, nsteps=1, axes=(0, 1, 2),
+                                    bc="periodic", scheme="strang")
+            ratio = out / phase[..., None]
+            assert np.max(np.abs(ratio - ratio[1, 2, 3])) < 1e-13  # one symbol for all cells
+            M[:, col] = ratio[1, 2, 3]
+        assert np.max(np.abs(M - expect)) < 1e-13, (jx, jy, jz)
+
+
+def test_field_zero_3d_second_order_is_the_plain_step(oracle):
+    """Atilde = 0 in the 3-D second-order step gives the plain 3-D
+    second-order step; with a varying field the step stays unitary on a
+    periodic box and differs from the field-free step."""
+    shape = (10, 8, 6)
+    dt = 4 * DX / C
+    psi = random_spinor(shape[::-1], seed=11)
+    V = np.random.default_rng(12).uniform(-3, 3, shape[::-1]) * C * C
+    plain = oracle.step_strang(psi, V, dt=dt, c=C, m=1.0, nsteps=6)
+    zero = oracle.step_field(psi, V, np.zeros((3,) + shape[::-1]), dt=dt, c=C, m=1.0, nsteps=6,
+                             scheme="strang")
+    assert np.linalg.norm(zero - plain) / np.linalg.norm(plain) < 1e-13
+    A = np.random.default_rng(13).uniform(-2, 2, (3,) + shape[::-1])
+    out = oracle.step_field(psi, V, A, dt=dt, c=C, m=1.0, nsteps=10, bc="periodic",
+                            scheme="strang")
+    assert abs(np.sum(np.abs(out) ** 2) / np.sum(np.abs(psi) ** 2) - 1) < 1e-12
+    free = oracle.step_strang(psi, V, dt=dt, c=C, m=1.0, nsteps=10, bc="periodic")
+    assert np.linalg.norm(out - free) > 1e-2 * np.linalg.norm(free)

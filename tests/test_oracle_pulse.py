@@ -94,6 +94,23 @@ def test_constant_pulse_equals_static_field(oracle):
     assert np.max(np.abs(got - ref)) < 1e-13
 
 
+def test_constant_pulse_equals_static_field_3d_second_order(oracle):
+    """The same identity through the 3-D second-order step (c dt = 4 a)."""
+    shape, dx, c = (12, 10, 8), 0.02, C_LIGHT
+    dt = 4 * dx / c
+    rng = np.random.default_rng(6)
+    psi = random_spinor(shape[::-1], seed=7)
+    V = rng.uniform(-1, 1, shape[::-1]) * c * c
+    P = rng.uniform(-1, 1, (3,) + shape[::-1]) * 500.0
+    box = dict(omega=0.0, phase=math.pi / 2, t_on=0.0, t_flat=1e6, t_off=0.0)
+    got = oracle.step_pulse(psi, V, P, box, t0=0.1, dt=dt, c=c, m=1.0, nsteps=5,
+                            scheme="strang")
+    ref = oracle.step_field(psi, V, dt * P, dt=dt, c=c, m=1.0, nsteps=5, scheme="strang")
+    assert np.max(np.abs(got - ref)) < 1e-13
+    free = oracle.step_strang(psi, V, dt=dt, c=c, m=1.0, nsteps=5)
+    assert np.linalg.norm(got - free) > 1e-2 * np.linalg.norm(free)
+
+
 @pytest.mark.parametrize("scheme", ["lie", "strang"])
 def test_pulse_steps_are_unitary(oracle, scheme):
     """Periodic box: transports and U are unitary, so the norm stays within
