@@ -83,9 +83,8 @@ typedef enum { DL_BC_ZERO = 0, DL_BC_PERIODIC = 1 } dl_bc;
                         A(dt/4) B(dt/2) A(dt/4) with c*dt = 4*dx: A shifts one
                         cell, B and C two (K + 1 passes over memory per group
                         of K steps, one extra state buffer in the plan).  DL_ERR_CFL on any
-                        other c*dt.  The adjoint entry points, and
-                        dl_step_field on 3-D grids, refuse such a plan
-                        (DL_ERR_ARG). */
+                        other c*dt.  The adjoint entry points refuse such a
+                        plan (DL_ERR_ARG). */
 #define DL_BISPINOR 8u /* two-component state, 1-D grids only (Sec. 2.4): with
                         one transport axis the pair of components that contains
                         psi_1 -- (psi_1, psi_4) for alpha_x and alpha_y,
@@ -142,8 +141,9 @@ int dl_step(dl_plan p, void *psi, const double *V, int64_t nsteps, void *stream)
  * steps of the call (a time-dependent field is applied by calls over shorter
  * spans).  A = NULL is dl_step.  1-D and 2-D grids, both splittings, passes
  * of at most 3 steps (1 with DL_STRANG) with the bits of single steps; 3-D
- * grids, lowest-order steps one per pass (DL_ERR_ARG for 3-D DL_STRANG
- * plans).  Same buffers and copy rule as dl_step. */
+ * grids: lowest-order steps one per pass, second-order steps with U in the
+ * middle D of each step and the same grouping of steps as dl_step.  Same
+ * buffers and copy rule as dl_step. */
 int dl_step_field(dl_plan p, void *psi, const double *V, const double *A, int64_t nsteps,
                   void *stream);
 
@@ -167,8 +167,8 @@ typedef struct {
  *     At^n(x) = P(x) F_n,  F_n = int_{t0 + n dt}^{t0 + (n + 1) dt} f(t) dt,
  * F_n evaluated on the device in closed form for every step (so passes still
  * fuse up to 3 lowest-order steps, each with its own F_n; 1-D and 2-D grids,
- * both splittings).  3-D grids: lowest-order steps, one per pass (DL_ERR_ARG
- * for 3-D DL_STRANG plans).  P: device array of 3 * cells doubles, planar
+ * both splittings).  3-D grids: lowest-order steps one per pass, second-order
+ * steps grouped as in dl_step, each D with its own F_n.  P: device array of 3 * cells doubles, planar
  * (x, y, z blocks in psi's cell order): e times the amplitude of A at the
  * cell centres.  pulse: HOST struct; finite values, durations >= 0 (DL_ERR_ARG
  * otherwise).  V as in dl_step.  The bits do not depend on how the steps are

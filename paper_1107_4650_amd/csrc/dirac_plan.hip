@@ -233,7 +233,10 @@ static int plan_tiling(dl_plan p) {
       while (depth > 1 && p->g.n[1] < 2 * stages_per_step * depth) --depth;
   }
   p->depth = depth;
-  p->depth_field = (p->g.ndim == 3) ? 1 : std::min(depth, field_max_depth(p->fp64, p->strang));
+  // with a vector potential: 3-D lowest-order passes carry one step; the 3-D
+  // second-order passes carry one D each and group steps as without a field
+  p->depth_field = (p->g.ndim == 3) ? (p->strang ? depth : 1)
+                                    : std::min(depth, field_max_depth(p->fp64, p->strang));
   for (int mode = 0; mode < 5; ++mode) {
     PlanTiling& t = p->tiling[mode];
     if (p->g.ndim == 3) {
@@ -547,8 +550,6 @@ extern "C" int dl_step_field(dl_plan p, void* psi, const double* V, const double
   if ((rc = check_state_ptr(psi, "psi"))) return rc;
   if ((rc = check_f64_ptr(V, "V", true))) return rc;
   if ((rc = check_f64_ptr(A, "A", false))) return rc;
-  if (p->g.ndim == 3 && p->strang)
-    return fail(DL_ERR_ARG, "the 3-D second-order step carries no vector potential");
   if (p->nc != 4) return fail(DL_ERR_ARG, "a vector potential couples all four components");
   if (nsteps < 0) return fail(DL_ERR_ARG, "nsteps = %lld < 0", static_cast<long long>(nsteps));
   if (nsteps == 0) return DL_OK;
@@ -581,14 +582,12 @@ extern "C" int dl_step_pulse(dl_plan p, void* psi, const double* V, const double
   if (pulse->t_on < 0.0 || pulse->t_flat < 0.0 || pulse->t_off < 0.0)
     return fail(DL_ERR_ARG, "pulse durations must be >= 0");
   if (!std::isfinite(t0)) return fail(DL_ERR_ARG, "t0 must be finite");
-  if (p->g.ndim == 3 && p->strang)
-    return fail(DL_ERR_ARG, "the 3-D second-order step carries no vector potential");
   if (p->nc != 4) return fail(DL_ERR_ARG, "a vector potential couples all four components");
   if (nsteps < 0) return fail(DL_ERR_ARG, "nsteps = %lld < 0", static_cast<long long>(nsteps));
   if (nsteps == 0) return DL_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);
   // 1-D / 2-D: phase mode 4 forms each step's field integral in the pass; 3-D
-  // passes (one step each) run the static-field kernel with At = F P
+  // passes (one D each) run the static-field kernels with At = F P
   const int mode = (p->g.ndim == 3) ? 3 : 4;
   p->ph = make_phase(transports_per_step(p), p->dt, p->c, p->m, mode, p->fp64);
   p->field = P;

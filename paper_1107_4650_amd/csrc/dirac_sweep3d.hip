@@ -447,7 +447,8 @@ template <> struct StrangShape<double> { static constexpr int TY = 2, kMinBlocks
 // planes.  Reading plane n it applies the x-y transports to its rows (a march
 // over the TY + 2 XL rows of the tile with two four-slot rings of right
 // movers, XL = 2 or 4 halo rows and lanes on each side) and feeds each output
-// row to C D C along z, which completes C at plane n - 2, applies D there and
+// row to C D C along z, which completes C at plane n - 2, applies D there
+// (phase mode 3: with the field integral of the vector potential) and
 // completes the second C at plane n - 4 (rings of the right movers of the last
 // four planes per row).  The x-y results are rounded as a stored pass would
 // round them, so the bits are those of the separate passes.
@@ -477,6 +478,11 @@ __global__ __launch_bounds__(256, StrangShape<T>::kMinBlocks) void k_strang3d_st
   const bool walls = !a.periodic;
   const bool lanes_out = walls && !c.full && !c.inside;
   const MarchBounds planes(kb, nz, nit);
+  // phase mode 3: under a pulse the field array holds the profile P and the
+  // step's integral is F P (a pass carries one step's D)
+  double fscale = 1.0;
+  if constexpr (MODE == 3)
+    if (a.pulse_on) fscale = pulse_step_integral(a.pulse, 0);
   // the rows read (wrapped or clamped) and, bit t, whether row y0 - XL + t
   // lies in the box
   int64_t rowoff[NR];
@@ -559,11 +565,20 @@ __global__ __launch_bounds__(256, StrangShape<T>::kMinBlocks) void k_strang3d_st
         Site<T> cd, out;
         Axis<2, T>::combine(rs[u][w], l, cd);  // C at plane n - 2
         rs[u][w] = r;
-        const double v =
-            (MODE == 2) ? V[(vplane + wrap_or_clamp(y0 + w, ny, a.periodic)) * nx + c.col] : 0.0;
-        Factors f = factors_of<MODE, TWO>(v, a.ph);
-        factors_fix<MODE, TWO>(f, v, a.ph);
-        apply_local<MODE>(cd, f, a.ph);
+        const int64_t q = (vplane + wrap_or_clamp(y0 + w, ny, a.periodic)) * nx + c.col;
+        if constexpr (MODE == 3) {  // D with the step's field integral
+          const double v = V ? V[q] : 0.0;
+          const double ax = fscale * a.At[q], ay = fscale * a.At[a.cells + q],
+                       az = fscale * a.At[2 * a.cells + q];
+          FieldFactors f = field_factors<TWO, false>(v, ax, ay, az, a.ph);
+          field_fix<TWO>(f, v, ax, ay, az, a.ph);
+          apply_field(cd, f);
+        } else {
+          const double v = (MODE == 2) ? V[q] : 0.0;
+          Factors f = factors_of<MODE, TWO>(v, a.ph);
+          factors_fix<MODE, TWO>(f, v, a.ph);
+          apply_local<MODE>(cd, f, a.ph);
+        }
         if (walls && !planes.in(it - 2)) zero(cd);
         Axis<2, T>::movers(cd, r, l);
         Axis<2, T>::combine(rd[(u + 2) % 4][w], l, out);  // second C at plane n - 4
@@ -580,6 +595,7 @@ static const void* strang_step_kernel(int mode) {
   switch (mode) {
     case 0: return reinterpret_cast<const void*>(&k_strang3d_step<T, 0, FIRST>);
     case 1: return reinterpret_cast<const void*>(&k_strang3d_step<T, 1, FIRST>);
+    case 3: return reinterpret_cast<const void*>(&k_strang3d_step<T, 3, FIRST>);
     default: return reinterpret_cast<const void*>(&k_strang3d_step<T, 2, FIRST>);
   }
 }
@@ -669,28 +685,31 @@ static hipError_t strang3d_t(const void* src, void* dst, void* mid, const double
   // A B A + C D C, then per further step the closing A B A of one step and the
   // opening one of the next + C D C, and a closing A B A: nsteps + 1 passes.
   // The first pass writes the buffer that makes the last one land in `mid`.
-  auto step_pass = [&](bool first_pass, const T* in, T* out) {
-    const SweepArgs& t = first_pass ? first : next;
+  auto step_pass = [&](bool first_pass, int64_t step, const T* in, T* out) {
+    SweepArgs t = first_pass ? first : next;
+    t.pulse.n0 += step;  // the pulse's step index of this pass's D
     const dim3 g(static_cast<unsigned>(first_pass ? bfirst : bnext));
     if (first_pass) {
       switch (mode) {
         case 0: hipLaunchKernelGGL((k_strang3d_step<T, 0, true>), g, dim3(256), 0, st, in, out, V, t); break;
         case 1: hipLaunchKernelGGL((k_strang3d_step<T, 1, true>), g, dim3(256), 0, st, in, out, V, t); break;
+        case 3: hipLaunchKernelGGL((k_strang3d_step<T, 3, true>), g, dim3(256), 0, st, in, out, V, t); break;
         default: hipLaunchKernelGGL((k_strang3d_step<T, 2, true>), g, dim3(256), 0, st, in, out, V, t); break;
       }
     } else {
       switch (mode) {
         case 0: hipLaunchKernelGGL((k_strang3d_step<T, 0, false>), g, dim3(256), 0, st, in, out, V, t); break;
         case 1: hipLaunchKernelGGL((k_strang3d_step<T, 1, false>), g, dim3(256), 0, st, in, out, V, t); break;
+        case 3: hipLaunchKernelGGL((k_strang3d_step<T, 3, false>), g, dim3(256), 0, st, in, out, V, t); break;
         default: hipLaunchKernelGGL((k_strang3d_step<T, 2, false>), g, dim3(256), 0, st, in, out, V, t); break;
       }
     }
   };
   T* cur = (nsteps % 2 == 1) ? m : d;
   T* other = (cur == m) ? d : m;
-  step_pass(true, s, cur);
+  step_pass(true, 0, s, cur);
   for (int64_t n = 1; n < nsteps; ++n) {
-    step_pass(false, cur, other);
+    step_pass(false, n, cur, other);
     T* t = cur;
     cur = other;
     other = t;

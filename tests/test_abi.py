@@ -124,6 +124,9 @@ def test_dry_3d_pass_depth(lib):
     assert dry((64, 30)).info()["field_depth"] == 3
     assert dry((64, 30), dtype="c128").info()["field_depth"] == 3
     assert dry((64, 30), dt=2 * 0.01 / C, scheme="strang").info()["field_depth"] == 1
+    p3 = dry((16, 8, 8), dt=4 * 0.01 / C, scheme="strang")
+    assert p3.info()["field_depth"] == p3.info()["depth"] >= 2  # one D per pass, steps grouped
+    p3.close()
     assert dry((64, 4), bc="periodic").info()["field_depth"] == 2
     p = dry((1 << 28, 2, 2))
     assert p.info()["depth"] == 1

@@ -93,12 +93,28 @@ def test_field_step_3d_vs_oracle(shape, bc):
     assert rel_l2(gpu_step(psi, None, dtype="c128", **{**kw, "nsteps": 4}), refA) <= 1e-12
 
 
-def test_field_refused_on_3d_second_order():
-    import torch
-    from paper_1107_4650_amd import libdirac as L
-    with L.Plan((16, 8, 8), DX, 4 * DX / C, C, 1.0, dtype="c64", scheme="strang") as p:
-        psi = torch.zeros(p.tshape, dtype=torch.complex64, device="cuda")
-        A = torch.zeros((3,) + p.tshape[:-1], dtype=torch.float64, device="cuda")
-        with pytest.raises(L.DiracError) as ei:
-            p.step_field(psi, None, A, 1)
-        assert ei.value.code == L.DL_ERR_ARG
+@pytest.mark.parametrize("shape", [(37, 21, 13), (70, 9, 11), (3, 4, 5)])
+@pytest.mark.parametrize("bc", ["zero", "periodic"])
+def test_field_step_3d_second_order_vs_oracle(shape, bc):
+    """3-D second-order steps (Sec. 2.4, c dt = 4 a) whose middle D carries the
+    field: against the oracle's nine-part sequence, over calls that group 7
+    steps in passes of 3 + 3 + 1 and of 7 single-step groups, which give the
+    same bits; far field angles with zero walls; V = NULL."""
+    announce(f"field 3-D second order {shape} {bc}")
+    dt = 4 * DX / C
+    psi = random_spinor(shape[::-1], seed=31 + sum(shape))
+    V, A = _fields(shape, 37, far=(bc == "zero"))
+    ref = O.step_field(psi, V, A, dt=dt, c=C, m=1.0, nsteps=7, axes=(0, 1, 2), bc=bc,
+                       scheme="strang")
+    kw = dict(dx=DX, dt=dt, c=C, m=1.0, nsteps=7, axes=(0, 1, 2), bc=bc, A=A, scheme="strang")
+    g3 = gpu_step(psi, V, dtype="c128", depth=3, **kw)
+    assert rel_l2(g3, ref) <= 1e-12
+    assert same_bits(gpu_step(psi, V, dtype="c128", depth=1, **kw), g3)
+    f32 = gpu_step(psi.astype(np.complex64), V, dtype="c64", **kw)
+    assert rel_l2(f32, ref) <= 5e-6
+    refA = O.step_field(psi, None, A, dt=dt, c=C, m=1.0, nsteps=4, axes=(0, 1, 2), bc=bc,
+                        scheme="strang")
+    assert rel_l2(gpu_step(psi, None, dtype="c128", **{**kw, "nsteps": 4}), refA) <= 1e-12
+    # the field acted
+    free = O.step_strang(psi, V, dt=dt, c=C, m=1.0, nsteps=7, axes=(0, 1, 2), bc=bc)
+    assert rel_l2(free, ref) > 1e-2

@@ -3,7 +3,8 @@ A(t, x) = f(t) P(x)) through dl_step_pulse, against the oracle's pulse step
 (whose per-step field integrals come from Gauss-Legendre quadrature, the
 library's from a closed form): relative L2 1e-12 with FP64 state, 5e-6 with
 FP32 state, over runs that cross the envelope's corners; passes of 1, 2 and 3
-fused steps give the same bits; refused arguments."""
+fused steps give the same bits (and 3-D second-order groups of 1, 2 and 5
+steps); refused arguments."""
 import ctypes
 
 import numpy as np
@@ -62,7 +63,8 @@ def _gpu(psi, V, P, pulse, *, t0, dt, nsteps, axes, bc="zero", dtype="c128", sch
 
 CASES = [((300,), (0,), "zero", "lie"), ((96, 70), (0, 1), "zero", "lie"),
          ((90, 64), (0, 2), "periodic", "lie"), ((80, 66), (1, 2), "zero", "lie"),
-         ((96, 70), (0, 1), "zero", "strang"), ((40, 24, 18), (0, 1, 2), "zero", "lie")]
+         ((96, 70), (0, 1), "zero", "strang"), ((40, 24, 18), (0, 1, 2), "zero", "lie"),
+         ((40, 24, 18), (0, 1, 2), "zero", "strang"), ((33, 20, 12), (0, 1, 2), "periodic", "strang")]
 
 
 @pytest.mark.parametrize("shape,axes,bc,scheme", CASES,
@@ -70,7 +72,7 @@ CASES = [((300,), (0,), "zero", "lie"), ((96, 70), (0, 1), "zero", "lie"),
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_pulse_vs_oracle(shape, axes, bc, scheme, dtype):
     announce(f"pulse {shape} {axes} {bc} {scheme} {dtype}")
-    dt = (2 if scheme == "strang" else 1) * DX / C
+    dt = (1 if scheme == "lie" else (2 if len(shape) < 3 else 4)) * DX / C
     nsteps = 60
     psi = packet(shape, DX, delta=0.15, p0=[25.0] + [5.0] * (len(shape) - 1),
                  r0=[0.0] * len(shape))
@@ -138,8 +140,22 @@ def test_pulse_refusals():
                                  None) == L.DL_ERR_ARG
         assert lib.dl_step_pulse(h, vp(psi), None, vp(P), ctypes.byref(ok), 0.0, -1,
                                  None) == L.DL_ERR_ARG
-    with L.Plan((8, 8, 8), DX, 4 * DX / C, C, 1.0, dtype="c64", scheme="strang") as p:
-        t = torch.zeros((8, 8, 8, 4), dtype=torch.complex64, device="cuda")
-        P3 = torch.zeros((3, 8, 8, 8), dtype=torch.float64, device="cuda")
-        assert lib.dl_step_pulse(p.handle, vp(t), None, vp(P3), ctypes.byref(ok), 0.0, 1,
-                                 None) == L.DL_ERR_ARG
+
+
+def test_pulse_3d_second_order_groups_keep_the_bits():
+    """3-D second-order plans: groups of 1, 2 and 5 steps per call of the
+    fused passes give the same bits; a run split over two calls agrees."""
+    announce("pulse 3-D second-order grouping")
+    shape, axes = (36, 20, 14), (0, 1, 2)
+    dt = 4 * DX / C
+    nsteps = 11
+    psi = random_spinor(shape[::-1], seed=4).astype(np.complex64)
+    V = np.random.default_rng(2).uniform(-1, 1, shape[::-1]) * C * C
+    P = _profile(shape)
+    pulse = _pulse(dt, nsteps)
+    kw = dict(t0=-dt, dt=dt, nsteps=nsteps, axes=axes, dtype="c64", scheme="strang")
+    runs = [_gpu(psi, V, P, pulse, depth=d, **kw) for d in (1, 2, 5)]
+    assert same_bits(runs[0], runs[1]) and same_bits(runs[0], runs[2])
+    # the second call starts from t0 + 4 dt, whose rounding can move F_n by an ulp
+    split = _gpu(psi, V, P, pulse, chunks=[4, 7], **kw)
+    assert rel_l2(split, runs[0]) <= 1e-6
