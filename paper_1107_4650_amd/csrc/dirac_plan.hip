@@ -142,11 +142,12 @@ void make_tiling(const dl_grid& g, int64_t target, int seg_override, SweepArgs& 
 }
 
 // 3-D tiling: strips of `strip_width` x cells by blocks of `ty` y rows, march
-// segments along z.  A wave of a segment of H planes runs H + halo plane
-// iterations; with `target` waves resident at once, the segment count is the
-// one that minimises (rounds of resident waves) x (H + halo).
+// segments along z.  A tile (a wave, or with per_block = 1 a workgroup) of a
+// segment of H planes runs H + halo plane iterations; with `target` tiles
+// resident at once, the segment count is the one that minimises (rounds of
+// resident tiles) x (H + halo).  per_block: tiles per workgroup (4 or 1).
 void make_tiling3d(const dl_grid& g, int ty, int strip_width, int halo, int64_t target,
-                   int seg_override, SweepArgs& a, int& blocks) {
+                   int seg_override, SweepArgs& a, int& blocks, int per_block) {
   a.nx = g.n[0];
   a.ny = g.n[1];
   a.nz = g.n[2];
@@ -176,8 +177,13 @@ void make_tiling3d(const dl_grid& g, int ty, int strip_width, int halo, int64_t 
   a.H = static_cast<int>(H);
   a.nseg = (a.nz + H - 1) / H;
   a.ntiles = per_seg * a.nseg;
-  blocks = static_cast<int>((a.ntiles + 3) / 4);
-  a.xcd_remap = (blocks % 8 == 0) ? 1 : 0;
+  if (per_block == 1) {  // one workgroup per tile, XCD-contiguous runs of tiles
+    blocks = static_cast<int>((a.ntiles + 7) / 8 * 8);
+    a.xcd_remap = 1;
+  } else {
+    blocks = static_cast<int>((a.ntiles + 3) / 4);
+    a.xcd_remap = (blocks % 8 == 0) ? 1 : 0;
+  }
   a.axes_code = 210;
 }
 
@@ -242,16 +248,15 @@ static int plan_tiling(dl_plan p) {
     if (p->g.ndim == 3) {
       if (mode >= 3) {  // with a vector potential (static or pulsed): one step per pass
         make_tiling3d(p->g, p->fp64 ? kTY3D_F64 : kTY3D_F32, 64, 2, resident_waves(p, 3, 1),
-                      p->seg_override, t.a[0], t.b[0]);
+                      p->seg_override, t.a[0], t.b[0], 4);
         for (int d = 0; d < kMaxDepth; ++d) t.a[d].periodic = (p->bc == DL_BC_PERIODIC);
         continue;
       }
       make_tiling3d(p->g, p->fp64 ? kTY3D_F64 : kTY3D_F32, 64, 2, resident_waves(p, mode, 1),
-                    p->seg_override, t.a[0], t.b[0]);
-      if (depth >= 2)
+                    p->seg_override, t.a[0], t.b[0], 4);
+      if (depth >= 2)  // workgroup tiles: resident workgroups are the target
         make_tiling3d(p->g, p->fp64 ? kTY3D2_F64 : kTY3D2_F32, strip_width(2), 4,
-                      resident_waves(p, mode, 2),
-                      p->seg_override, t.a[1], t.b[1]);
+                      resident_waves(p, mode, 2) / 4, p->seg_override, t.a[1], t.b[1], 1);
     } else {
       for (int d = 1; d <= (mode >= 3 ? p->depth_field : depth); ++d)
         make_tiling(p->g, resident_waves(p, mode, d), p->seg_override, t.a[d - 1], t.b[d - 1],

@@ -161,29 +161,53 @@ __global__ __launch_bounds__(256) void k_sweep3d(const T* __restrict__ src, T* _
 }
 
 // ---------------------------------------------------------------------------
-// 3-D pass of two fused steps (temporal blocking).  A wave holds 64 x
-// columns (writing the middle 60) and a block of TY y rows, and marches along
-// z.  Each plane iteration reads TY + 4 rows of the input plane (two halo rows
-// on each side); the rows of the next plane and their potential are loaded
-// while the current plane computes.  The first step completes, in streaming
-// order, the TY + 2 rows y0 - 1 .. y0 + TY of the plane one behind (its own y
-// halo for the second step); each of those rows feeds the second step at
-// once, which completes the TY output rows of the plane two behind.  The z
-// movers of two previous planes are kept per step and row.  The phase
-// factors of a row are formed once, by the first step, and kept for the
+// 3-D pass of two fused steps (temporal blocking).  A workgroup of four waves
+// holds 64 x columns (writing the middle 60) and WY = 4 TW y rows (TW output
+// rows per wave) and marches along z.  Each plane iteration shares the work
+// of the tile's rows among the waves through LDS, so no row is transported
+// twice:
+//  1. each wave reads TW + 1 of the WY + 4 input rows of the plane (two halo
+//     rows on each side), applies the x transport and leaves the y movers in
+//     LDS;
+//  2. after a barrier, each wave completes the first step (y and z transports
+//     and D) on its own TW rows of the plane one behind -- waves 0 and 3 also
+//     on the halo row y0 - 1 or y0 + WY that the second step needs -- applies
+//     the second step's x transport and leaves those y movers in LDS;
+//  3. after a second barrier, each wave completes the second step on its own
+//     rows of the plane two behind.
+// The z movers of two previous planes are kept per step and row.  The phase
+// factors of an own row are formed once, by the first step, and kept for the
 // second step, which reaches the same row and plane one iteration later.
 // Intermediate states are rounded as stored steps and zeroed outside the box
 // with zero walls, so the pass gives the bits of two single steps.
 // ---------------------------------------------------------------------------
-template <typename T, int TY, bool UP, int MODE, bool EDGE>
+template <typename T> struct X2Tile {
+  static constexpr int WY = sizeof(T) == 8 ? kTY3D2_F64 : kTY3D2_F32;  // output rows
+  static constexpr int TW = WY / 4;                                  // per wave
+  static constexpr int NI = WY + 4;  // input rows per plane
+  static constexpr int N1 = NI / 4;  // input rows per wave
+  static constexpr int NS = WY + 2;  // first-step rows per plane
+  static_assert(NI <= 32, "row mask");
+};
+
+// y movers of the input rows (index t: row y0 - 2 + t): right movers of rows
+// t < NI - 2 at [t], left movers of rows t >= 2 at [t - 2]; of the
+// first-step rows (index u: row y0 - 1 + u): right movers of u < NS - 2 at
+// [u], left movers of u >= 2 at [u - 2]
+template <typename T> struct X2Lds {
+  using S = X2Tile<T>;
+  Mov<T> r1[S::NI - 2][64], l1[S::NI - 2][64];
+  Mov<T> r2[S::NS - 2][64], l2[S::NS - 2][64];
+};
+
+template <typename T, bool UP, int MODE, bool EDGE>
 __device__ __forceinline__ void march3d_x2(const T* __restrict__ src, T* __restrict__ dst,
                                            const double* __restrict__ V, const SweepArgs& a,
-                                           int64_t xs, int lane, int64_t y0, int64_t kb,
-                                           int64_t ke) {
+                                           X2Lds<T>& sh, int lane, int wv, int64_t xs,
+                                           int64_t y0, int64_t kb, int64_t ke) {
+  using S = X2Tile<T>;
   constexpr bool TWO = sizeof(T) == 8;
-  constexpr int K = 2;
-  constexpr int R0 = TY + 4;  // rows read per plane
-  constexpr int R1 = TY + 2;  // rows completed by the first step
+  constexpr int K = 2, TW = S::TW, NI = S::NI, N1 = S::N1, NS = S::NS;
   const int64_t nx = a.nx, ny = a.ny, nz = a.nz;
   const int64_t plane_cells = nx * ny;
   const int nit = static_cast<int>(ke - kb) + 2 * K;
@@ -201,7 +225,7 @@ __device__ __forceinline__ void march3d_x2(const T* __restrict__ src, T* __restr
   };
   // wall tests as wave-uniform 32-bit compares: plane plane_of(it, st) lies
   // in the box iff klo <= it - st < khi (it - st spans -K .. nit), and bit t
-  // of ymask says whether row y0 - 2 + t does
+  // of ymask says whether input row y0 - 2 + t does
   auto clamp_it = [&](int64_t e) -> int {
     return static_cast<int>(e < -64 ? -64 : (e > nit + 64 ? nit + 64 : e));
   };
@@ -210,159 +234,154 @@ __device__ __forceinline__ void march3d_x2(const T* __restrict__ src, T* __restr
   auto plane_in = [&](int e) -> bool { return e >= klo && e < khi; };
   uint32_t ymask = 0;
 #pragma unroll
-  for (int t = 0; t < R0; ++t)
+  for (int t = 0; t < NI; ++t)
     if (y0 - 2 + t >= 0 && y0 - 2 + t < ny) ymask |= 1u << t;
   ymask = __builtin_amdgcn_readfirstlane(ymask);
-  // input rows of iteration it (slot it % 2) and the V of its first-step rows;
-  // the plane of iteration it + 1 is loaded while iteration it computes
-  Site<T> buf[2][R0];
-  double vb[2][R1];
-  auto load_plane = [&](int it, Site<T>* rows, double* v) {
-    const int64_t kr = read_row(in_plane(it), nz, a.periodic);
-    const T* plane = src + kr * plane_cells * 8;
+  // first-step rows of this wave: slots j < TW are its own rows u = 1 + wv TW
+  // + j (output rows y0 + wv TW + j); slot TW is the halo row u = 0 (wave 0)
+  // or u = NS - 1 (wave 3)
+  const bool halo = (wv == 0) || (wv == 3);
+  const int u_halo = (wv == 0) ? 0 : NS - 1;
+  auto srow = [&](int j) -> int { return j < TW ? 1 + wv * TW + j : u_halo; };
+  int64_t inrow[N1], srow_off[TW + 1];
 #pragma unroll
-    for (int t = 0; t < R0; ++t)
-      load_site(plane + read_row(y0 - 2 + t, ny, a.periodic) * nx * 8 + cell_off, rows[t]);
-    const int64_t k1r = read_row(plane_of(it, 1), nz, a.periodic);
+  for (int j = 0; j < N1; ++j) inrow[j] = read_row(y0 - 2 + wv * N1 + j, ny, a.periodic) * nx * 8;
 #pragma unroll
-    for (int u = 0; u < R1; ++u)
-      v[u] = read_v ? (V + (k1r * ny + read_row(y0 - 1 + u, ny, a.periodic)) * nx)[v_off] : 0.0;
-  };
-  // z movers of two previous planes, per step and row (slot it % 2)
-  Mov<T> zm1[2][R1], zm2[2][TY];
-  // factors of the output rows, formed by the first step on plane k1 and used
-  // by the second step on the same plane one iteration later
-  Factors fc[TY];
+  for (int j = 0; j <= TW; ++j) srow_off[j] = read_row(y0 - 1 + srow(j), ny, a.periodic) * nx;
+  Mov<T> zm1[2][TW + 1], zm2[2][TW];  // z movers of two previous planes, slot it % 2
+  Factors fc[TW];  // factors of the own rows, formed by the first step one iteration earlier
 #pragma unroll
-  for (int w = 0; w < TY; ++w) fc[w] = Factors{};
+  for (int j = 0; j < TW; ++j) fc[j] = Factors{};
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
 #pragma unroll
-    for (int u = 0; u < R1; ++u) {
-      zero(zm1[q][u]);
-      vb[q][u] = 0.0;
-    }
+    for (int j = 0; j <= TW; ++j) zero(zm1[q][j]);
 #pragma unroll
-    for (int w = 0; w < TY; ++w) zero(zm2[q][w]);
+    for (int j = 0; j < TW; ++j) zero(zm2[q][j]);
   }
-  load_plane(0, buf[0], vb[0]);
   for (int pair = 0;; ++pair) {
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       const int it = 2 * pair + k;
-      if (it >= nit) return;
+      if (it >= nit) return;  // uniform over the workgroup
       const int64_t k2 = plane_of(it, 2);
-      load_plane(it + 1, buf[k ^ 1], vb[k ^ 1]);
-      Factors pend{};  // factors of the previous first-step row
-      // streaming over rows: first step (y movers of two rows back), then second
-      Mov<T> ya1, yb1, ya2, yb2;  // r movers of rows t - 1 and t - 2 (first, second step)
-      zero(ya1);
-      zero(yb1);
-      zero(ya2);
-      zero(yb2);
+      // this wave's input rows of the plane read and the V of its first-step
+      // rows on the plane one behind
+      Site<T> in[N1];
+      double vb[TW + 1];
+      {
+        const T* plane = src + read_row(in_plane(it), nz, a.periodic) * plane_cells * 8;
 #pragma unroll
-      for (int t = 0; t < R0; ++t) {
-        Site<T> in = buf[k][t];
+        for (int j = 0; j < N1; ++j) load_site(plane + inrow[j] + cell_off, in[j]);
+        const double* vp = V + read_row(plane_of(it, 1), nz, a.periodic) * plane_cells;
+#pragma unroll
+        for (int j = 0; j <= TW; ++j)
+          vb[j] = (read_v && (j < TW || halo)) ? (vp + srow_off[j])[v_off] : 0.0;
+      }
+      // 1. x transport of the input rows, y movers to LDS
+#pragma unroll
+      for (int j = 0; j < N1; ++j) {
+        const int t = wv * N1 + j;
+        Site<T> s0 = in[j], phi;
         if (zero_walls) {
-          if (!plane_in(it) || !((ymask >> t) & 1u)) zero(in);
-          if (EDGE && c.out) zero(in);
+          if (!plane_in(it) || !((ymask >> t) & 1u)) zero(s0);
+          if (EDGE && c.out) zero(s0);
         }
-        Site<T> phi;
-        x_transport_inner<T, 0>(in, phi);
+        x_transport_inner<T, 0>(s0, phi);
         Mov<T> ry, ly;
         Axis<1, T>::movers(phi, ry, ly);
-        if (t >= 2) {
-          const int u = t - 2;  // first-step row y0 - 1 + u of plane k1
-          Site<T> py;
-          Axis<1, T>::combine(yb1, ly, py);
-          Mov<T> rz, lz;
-          Axis<2, T>::movers(py, rz, lz);
-          Site<T> o1;
-          if (UP)
-            Axis<2, T>::combine(zm1[k][u], lz, o1);
-          else
-            Axis<2, T>::combine(rz, zm1[k][u], o1);
-          zm1[k][u] = UP ? rz : lz;
-          Factors f1 = factors_of<MODE, TWO>(vb[k][u], a.ph);
-          factors_fix<MODE, TWO>(f1, vb[k][u], a.ph);
-          apply_local<MODE>(o1, f1, a.ph);
-          if (zero_walls) {
-            if (!plane_in(it - 1) || !((ymask >> (u + 1)) & 1u)) zero(o1);
-            if (EDGE && !c.inside) zero(o1);
-          }
-          // second step on first-step row u
-          Site<T> phi2;
-          x_transport_inner<T, 0>(o1, phi2);
-          Mov<T> ry2, ly2;
-          Axis<1, T>::movers(phi2, ry2, ly2);
-          if (u >= 2) {
-            const int w = u - 2;  // output row y0 + w of plane k2
-            Site<T> py2;
-            Axis<1, T>::combine(yb2, ly2, py2);
-            Mov<T> rz2, lz2;
-            Axis<2, T>::movers(py2, rz2, lz2);
-            Site<T> o2;
-            if (UP)
-              Axis<2, T>::combine(zm2[k][w], lz2, o2);
-            else
-              Axis<2, T>::combine(rz2, zm2[k][w], o2);
-            zm2[k][w] = UP ? rz2 : lz2;
-            apply_local<MODE>(o2, fc[w], a.ph);
-            const int64_t y = y0 + w;
-            if (it >= 2 * K && own && y < ny)
-              store_site(dst + (k2 * ny + y) * nx * 8 + cell_off, o2);
-            // row y0 + w of plane k1 takes these factors in the next iteration
-            fc[w] = pend;
-          }
-          pend = f1;
-          yb2 = ya2;
-          ya2 = ry2;
+        if (t < NI - 2) sh.r1[t][lane] = ry;
+        if (t >= 2) sh.l1[t - 2][lane] = ly;
+      }
+      __syncthreads();
+      // 2. first step on the first-step rows of the plane one behind, then the
+      //    second step's x transport, y movers to LDS
+      Factors fnew[TW];
+#pragma unroll
+      for (int j = 0; j <= TW; ++j) {
+        if (j == TW && !halo) break;
+        const int u = srow(j);
+        Site<T> py, o1;
+        Axis<1, T>::combine(sh.r1[u][lane], sh.l1[u][lane], py);
+        Mov<T> rz, lz;
+        Axis<2, T>::movers(py, rz, lz);
+        if (UP)
+          Axis<2, T>::combine(zm1[k][j], lz, o1);
+        else
+          Axis<2, T>::combine(rz, zm1[k][j], o1);
+        zm1[k][j] = UP ? rz : lz;
+        Factors f1 = factors_of<MODE, TWO>(vb[j], a.ph);
+        factors_fix<MODE, TWO>(f1, vb[j], a.ph);
+        apply_local<MODE>(o1, f1, a.ph);
+        if (zero_walls) {
+          if (!plane_in(it - 1) || !((ymask >> (u + 1)) & 1u)) zero(o1);
+          if (EDGE && !c.inside) zero(o1);
         }
-        yb1 = ya1;
-        ya1 = ry;
+        Site<T> phi2;
+        x_transport_inner<T, 0>(o1, phi2);
+        Mov<T> ry2, ly2;
+        Axis<1, T>::movers(phi2, ry2, ly2);
+        if (u < NS - 2) sh.r2[u][lane] = ry2;
+        if (u >= 2) sh.l2[u - 2][lane] = ly2;
+        if (j < TW) fnew[j] = f1;
+      }
+      __syncthreads();
+      // 3. second step on the own rows of the plane two behind
+#pragma unroll
+      for (int j = 0; j < TW; ++j) {
+        const int w = wv * TW + j;  // output row y0 + w: first-step rows w and w + 2
+        Site<T> py2, o2;
+        Axis<1, T>::combine(sh.r2[w][lane], sh.l2[w][lane], py2);
+        Mov<T> rz2, lz2;
+        Axis<2, T>::movers(py2, rz2, lz2);
+        if (UP)
+          Axis<2, T>::combine(zm2[k][j], lz2, o2);
+        else
+          Axis<2, T>::combine(rz2, zm2[k][j], o2);
+        zm2[k][j] = UP ? rz2 : lz2;
+        apply_local<MODE>(o2, fc[j], a.ph);
+        const int64_t y = y0 + w;
+        if (it >= 2 * K && own && y < ny)
+          store_site(dst + (k2 * ny + y) * nx * 8 + cell_off, o2);
+        fc[j] = fnew[j];
       }
     }
   }
 }
 
-template <typename T, int TY, int MODE>
-__global__ __launch_bounds__(256, kMinBlocks3D2) void k_sweep3d_x2(const T* __restrict__ src,
+template <typename T, int MODE>
+__global__ __launch_bounds__(256, 2) void k_sweep3d_x2(const T* __restrict__ src,
                                                        T* __restrict__ dst,
                                                        const double* __restrict__ V,
                                                        SweepArgs a) {
+  __shared__ X2Lds<T> sh;
   const int lane = threadIdx.x & 63;
+  const int wv = wave_in_block();
   int64_t blk = blockIdx.x;
   if (a.xcd_remap) blk = (blk % 8) * (gridDim.x / 8) + blk / 8;
-  const int64_t tile = blk * 4 + wave_in_block();
-  if (tile >= a.ntiles) return;
-  // tile order: x strips fastest, then y row blocks, then z segments; with
-  // blocks of two rows (FP64), whose halo rows outnumber their own, y row
-  // blocks fastest, so that the waves of a workgroup share their halo rows
-  constexpr bool kYFast = TY <= 2;
-  const int64_t n0 = kYFast ? a.nyblk : a.nstrips;
-  const int64_t n1 = kYFast ? a.nstrips : a.nyblk;
-  const int64_t i0 = tile % n0;
-  const int64_t rest = tile / n0;
-  const int64_t i1 = rest % n1;
-  const int64_t seg = rest / n1;
-  const int64_t strip = kYFast ? i1 : i0;
-  const int64_t yblk = kYFast ? i0 : i1;
-  const int64_t xs = strip * strip_width(2) - 2, y0 = yblk * TY;
+  if (blk >= a.ntiles) return;  // the whole workgroup
+  // tile order: y row blocks fastest (neighbouring tiles share their halo
+  // rows), then x strips, then z segments
+  const int64_t yblk = blk % a.nyblk;
+  const int64_t rest = blk / a.nyblk;
+  const int64_t strip = rest % a.nstrips;
+  const int64_t seg = rest / a.nstrips;
+  const int64_t xs = strip * strip_width(2) - 2, y0 = yblk * X2Tile<T>::WY;
   const int64_t kb = seg * a.H;
   const int64_t ke = (kb + a.H < a.nz) ? kb + a.H : a.nz;
-  // waves with a lane beyond a zero wall zero those lanes at every step;
+  // tiles with a lane beyond a zero wall zero those lanes at every step;
   // the others skip that work
   const bool edge = !lanes_of(a.nx, a.periodic, xs, 0).full;
   if (edge) {
     if (seg & 1)
-      march3d_x2<T, TY, false, MODE, true>(src, dst, V, a, xs, lane, y0, kb, ke);
+      march3d_x2<T, false, MODE, true>(src, dst, V, a, sh, lane, wv, xs, y0, kb, ke);
     else
-      march3d_x2<T, TY, true, MODE, true>(src, dst, V, a, xs, lane, y0, kb, ke);
+      march3d_x2<T, true, MODE, true>(src, dst, V, a, sh, lane, wv, xs, y0, kb, ke);
   } else {
     if (seg & 1)
-      march3d_x2<T, TY, false, MODE, false>(src, dst, V, a, xs, lane, y0, kb, ke);
+      march3d_x2<T, false, MODE, false>(src, dst, V, a, sh, lane, wv, xs, y0, kb, ke);
     else
-      march3d_x2<T, TY, true, MODE, false>(src, dst, V, a, xs, lane, y0, kb, ke);
+      march3d_x2<T, true, MODE, false>(src, dst, V, a, sh, lane, wv, xs, y0, kb, ke);
   }
 }
 
@@ -380,7 +399,14 @@ __global__ __launch_bounds__(256, kMinBlocks3D2) void k_sweep3d_x2(const T* __re
 // r wrapped into [0, n) around a periodic box, else clamped (cells beyond a
 // wall are zeroed where they are used)
 __device__ __forceinline__ int64_t wrap_or_clamp(int64_t r, int64_t n, int periodic) {
-  if (periodic) return ((r % n) + n) % n;
+  if (periodic) {
+    // one wrap covers the halos of any box of a few cells or more; the
+    // division only runs for smaller boxes
+    if (r < 0 && r >= -n) return r + n;
+    if (r >= n && r < 2 * n) return r - n;
+    if (r >= 0 && r < n) return r;
+    return ((r % n) + n) % n;
+  }
   return r < 0 ? 0 : (r >= n ? n - 1 : r);
 }
 
@@ -435,41 +461,62 @@ struct MarchBounds {
   __device__ bool in(int it) const { return it >= lo && it < hi; }
 };
 
-// rows per wave and resident blocks per CU of the fused second-order pass
+// rows per wave of the fused second-order pass; a workgroup of four waves
+// holds 4 TW rows
 template <typename T> struct StrangShape;
-template <> struct StrangShape<float> { static constexpr int TY = 2, kMinBlocks = 2; };
-template <> struct StrangShape<double> { static constexpr int TY = 2, kMinBlocks = 1; };
+template <> struct StrangShape<float> { static constexpr int TW = 2; };
+template <> struct StrangShape<double> { static constexpr int TW = 1; };
+constexpr int kStrangWaves = 4;
 
 // One pass of the 3-D second-order step: the transports along x and y that
 // open it (A B A for the first step of a group, else the A B A that closes
 // the previous step followed by the one that opens this step), then C D C.
-// A wave holds 64 columns and TY rows and marches up a segment [kb, ke) of
-// planes.  Reading plane n it applies the x-y transports to its rows (a march
-// over the TY + 2 XL rows of the tile with two four-slot rings of right
-// movers, XL = 2 or 4 halo rows and lanes on each side) and feeds each output
-// row to C D C along z, which completes C at plane n - 2, applies D there
-// (phase mode 3: with the field integral of the vector potential) and
-// completes the second C at plane n - 4 (rings of the right movers of the last
-// four planes per row).  The x-y results are rounded as a stored pass would
-// round them, so the bits are those of the separate passes.
+// A workgroup holds 64 columns and WY = 4 TW rows (TW per wave) and marches
+// up a segment [kb, ke) of planes.  For plane n the four waves share the x-y
+// transports of the tile's WY + 2 XL rows (XL = 2 or 4 halo rows and lanes on
+// each side) through LDS: each wave applies A to its share of the rows read
+// and leaves their y movers in LDS; after a barrier, B is formed for the
+// rows that are still needed (with the second A B A, shares of those rows go
+// through LDS once more), so every x-y transport of the tile is computed
+// once.  Each wave then feeds its TW output rows to C D C along z, which
+// completes C at plane n - 2, applies D there (phase mode 3: with the field
+// integral of the vector potential) and completes the second C at plane
+// n - 4 (rings of the right movers of the last four planes per row).  The
+// x-y results are rounded as a stored pass would round them, so the bits are
+// those of the separate passes.
 template <typename T, int MODE, bool FIRST>
-__global__ __launch_bounds__(256, StrangShape<T>::kMinBlocks) void k_strang3d_step(
-    const T* __restrict__ src, T* __restrict__ dst, const double* __restrict__ V,
-    SweepArgs a) {
+__global__ __launch_bounds__(256, 2) void k_strang3d_step(const T* __restrict__ src,
+                                                          T* __restrict__ dst,
+                                                          const double* __restrict__ V,
+                                                          SweepArgs a) {
   constexpr bool TWO = sizeof(T) == 8;
-  constexpr int TY = StrangShape<T>::TY;
-  constexpr int XL = FIRST ? 2 : 4;  // halo lanes and rows
-  constexpr int NR = TY + 2 * XL;    // rows read per plane
+  constexpr int TW = StrangShape<T>::TW;
+  constexpr int WY = kStrangWaves * TW;  // output rows of the workgroup
+  constexpr int XL = FIRST ? 2 : 4;      // halo lanes and rows
+  constexpr int NR = WY + 2 * XL;        // rows read per plane
+  constexpr int N1 = NR / kStrangWaves;  // rows read per wave
+  constexpr int NL = NR - 4;             // rows whose first-B movers are kept
+  constexpr int NB = NL / kStrangWaves;  // second A B A: first-B rows per wave
+  constexpr int NBUF = FIRST ? 2 : 1;    // one barrier per plane: two buffers
+  static_assert(NR <= 32 && NR % kStrangWaves == 0, "row mask and shares");
+  // y movers of the rows read: right movers of tile rows t < NR - 4 at [t],
+  // left movers of rows t >= 4 at [t - 4]; after the first B (second A B A
+  // only) right movers of rows s in [2, WY + 2) at [s - 2], left movers of
+  // rows s in [6, WY + 6) at [s - 6]
+  __shared__ Mov<T> r1s[NBUF][NL][64], l1s[NBUF][NL][64];
+  __shared__ Mov<T> r2s[FIRST ? 1 : WY][64], l2s[FIRST ? 1 : WY][64];
   const int lane = threadIdx.x & 63;
-  const int64_t tile = int64_t(blockIdx.x) * 4 + wave_in_block();
-  if (tile >= a.ntiles) return;
+  const int wv = wave_in_block();
+  int64_t blk = blockIdx.x;
+  if (a.xcd_remap) blk = (blk % 8) * (gridDim.x / 8) + blk / 8;
+  if (blk >= a.ntiles) return;  // the whole workgroup
   const int64_t nx = a.nx, ny = a.ny, nz = a.nz;
   // tile order: row blocks fastest (neighbours share their halo rows), then
   // x strips, then z segments
-  const int64_t yblk = tile % a.nyblk;
-  const int64_t rest = tile / a.nyblk;
+  const int64_t yblk = blk % a.nyblk;
+  const int64_t rest = blk / a.nyblk;
   const int64_t strip = rest % a.nstrips, seg = rest / a.nstrips;
-  const int64_t y0 = yblk * TY;
+  const int64_t y0 = yblk * WY;
   const int64_t kb = seg * a.H;
   const int64_t ke = (kb + a.H < nz) ? kb + a.H : nz;
   const int nit = static_cast<int>(ke - kb) + 8;
@@ -483,27 +530,40 @@ __global__ __launch_bounds__(256, StrangShape<T>::kMinBlocks) void k_strang3d_st
   double fscale = 1.0;
   if constexpr (MODE == 3)
     if (a.pulse_on) fscale = pulse_step_integral(a.pulse, 0);
-  // the rows read (wrapped or clamped) and, bit t, whether row y0 - XL + t
-  // lies in the box
-  int64_t rowoff[NR];
+  // bit t: row y0 - XL + t lies in the box
   uint32_t rin = 0;
 #pragma unroll
   for (int t = 0; t < NR; ++t) {
     const int64_t y = y0 - XL + t;
-    rowoff[t] = wrap_or_clamp(y, ny, a.periodic) * nx + c.col;
     if (y >= 0 && y < ny) rin |= 1u << t;
   }
   rin = __builtin_amdgcn_readfirstlane(rin);
   auto row_in = [&](int t) -> bool { return (rin >> t) & 1u; };
+  // the rows this wave reads (wrapped or clamped): tile rows wv N1 + j
+  int64_t rowoff[N1];
+#pragma unroll
+  for (int j = 0; j < N1; ++j)
+    rowoff[j] = wrap_or_clamp(y0 - XL + wv * N1 + j, ny, a.periodic) * nx + c.col;
+  // the output rows of this wave: y0 + wv TW + j
+  int64_t voff[TW];
+#pragma unroll
+  for (int j = 0; j < TW; ++j)
+    voff[j] = wrap_or_clamp(y0 + wv * TW + j, ny, a.periodic) * nx + c.col;
   auto A = [&](const Site<T>& in, Site<T>& out) {
     x_transport_inner<T, 0>(in, out);
     if (lanes_out) zero(out);
   };
-  Mov<T> rs[4][TY], rd[4][TY];  // right movers of the input / of C D, slot: plane % 4
+  Site<T> ld[N1];  // this wave's rows of the plane read
+  auto load_rows = [&](int it) {
+    const T* plane = src + wrap_or_clamp(kb - 4 + it, nz, a.periodic) * ny * nx * 8;
+#pragma unroll
+    for (int j = 0; j < N1; ++j) load_site(plane + rowoff[j] * 8, ld[j]);
+  };
+  Mov<T> rs[4][TW], rd[4][TW];  // right movers of the input / of C D, slot: plane % 4
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
 #pragma unroll
-    for (int w = 0; w < TY; ++w) {
+    for (int w = 0; w < TW; ++w) {
       zero(rs[q][w]);
       zero(rd[q][w]);
     }
@@ -512,79 +572,102 @@ __global__ __launch_bounds__(256, StrangShape<T>::kMinBlocks) void k_strang3d_st
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int it = base + u;
-      if (it >= nit) return;
+      if (it >= nit) return;  // uniform over the workgroup
       const int64_t n = kb - 4 + it;  // plane read
       const bool n_in = planes.in(it);
-      const T* plane = src + wrap_or_clamp(n, nz, a.periodic) * ny * nx * 8;
-      const int64_t vplane = wrap_or_clamp(n - 2, nz, a.periodic) * ny;
-      Mov<T> ra[4], rc[4];  // right movers after the first / second A, slot: row % 4
+      const int bf = FIRST ? (u & 1) : 0;
+      load_rows(it);
+      // A on this wave's rows of plane n, their y movers to LDS
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        zero(ra[q]);
-        zero(rc[q]);
-      }
-#pragma unroll
-      for (int t = 0; t < NR; ++t) {
-        Site<T> sv, tt, yb, o;
-        load_site(plane + rowoff[t] * 8, sv);
+      for (int j = 0; j < N1; ++j) {
+        const int t = wv * N1 + j;
+        Site<T> sv = ld[j], tt;
         if (walls && (!row_in(t) || (!c.full && c.out))) zero(sv);
         A(sv, tt);
         Mov<T> r, l;
         Axis<1, T>::movers(tt, r, l);
-        if (t < 4) {
-          ra[t % 4] = r;
-          continue;
+        if (t < NR - 4) r1s[bf][t][lane] = r;
+        if (t >= 4) l1s[bf][t - 4][lane] = l;
+      }
+      // potential (and field integrals) of the output rows at plane n - 2
+      const int64_t vplane = wrap_or_clamp(n - 2, nz, a.periodic) * ny * nx;
+      double vv[TW], ax[TW], ay[TW], az[TW];
+#pragma unroll
+      for (int j = 0; j < TW; ++j) {
+        const int64_t q = vplane + voff[j];
+        vv[j] = (MODE == 2 || (MODE == 3 && V != nullptr)) ? V[q] : 0.0;
+        if constexpr (MODE == 3) {
+          ax[j] = fscale * a.At[q];
+          ay[j] = fscale * a.At[a.cells + q];
+          az[j] = fscale * a.At[2 * a.cells + q];
         }
-        Axis<1, T>::combine(ra[t % 4], l, yb);  // first B at tile row t - 2
-        ra[t % 4] = r;
-        if (lanes_out) zero(yb);
-        int w;  // output row y0 + w of the x-y transports
-        if constexpr (FIRST) {
-          x_transport_inner<T, 0>(yb, o);
-          w = t - 4;
-        } else {
-          Site<T> t2, cc;
+      }
+      __syncthreads();
+      Site<T> o[TW];  // output rows of the x-y transports
+      if constexpr (FIRST) {
+        // B at tile row w + 2 from rows w and w + 4, then A
+#pragma unroll
+        for (int j = 0; j < TW; ++j) {
+          const int w = wv * TW + j;
+          Site<T> yb;
+          Axis<1, T>::combine(r1s[bf][w][lane], l1s[bf][w][lane], yb);
+          if (lanes_out) zero(yb);
+          x_transport_inner<T, 0>(yb, o[j]);
+        }
+      } else {
+        // first B at tile rows s in [2, NR - 2), then A A (closing one step,
+        // opening the next), their y movers to LDS
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          const int s = 2 + wv * NB + j;
+          Site<T> yb, t2, cc;
+          Axis<1, T>::combine(r1s[0][s - 2][lane], l1s[0][s - 2][lane], yb);
+          if (lanes_out) zero(yb);
           A(yb, t2);
-          if (walls && !row_in(t - 2)) zero(t2);  // row beyond a wall
-          A(t2, cc);                              // the next step's A B A starts
+          if (walls && !row_in(s)) zero(t2);  // row beyond a wall
+          A(t2, cc);
           Mov<T> r2, l2;
           Axis<1, T>::movers(cc, r2, l2);
-          if (t < 8) {
-            rc[t % 4] = r2;
-            continue;
-          }
-          Axis<1, T>::combine(rc[t % 4], l2, yb);  // second B at tile row t - 4
-          rc[t % 4] = r2;
-          if (lanes_out) zero(yb);
-          x_transport_inner<T, 0>(yb, o);
-          w = t - 8;
+          if (s < WY + 2) r2s[s - 2][lane] = r2;
+          if (s >= 6) l2s[s - 6][lane] = l2;
         }
-        // C D C along z for row y0 + w
-        if (walls && !n_in) zero(o);
-        Axis<2, T>::movers(o, r, l);
+        __syncthreads();
+        // second B at tile row w + 4 from first-B rows w + 2 and w + 6, then A
+#pragma unroll
+        for (int j = 0; j < TW; ++j) {
+          const int w = wv * TW + j;
+          Site<T> yb;
+          Axis<1, T>::combine(r2s[w][lane], l2s[w][lane], yb);
+          if (lanes_out) zero(yb);
+          x_transport_inner<T, 0>(yb, o[j]);
+        }
+      }
+      // C D C along z for the output rows y0 + wv TW + j
+#pragma unroll
+      for (int j = 0; j < TW; ++j) {
+        Site<T> oz = o[j];
+        if (walls && !n_in) zero(oz);
+        Mov<T> r, l;
+        Axis<2, T>::movers(oz, r, l);
         Site<T> cd, out;
-        Axis<2, T>::combine(rs[u][w], l, cd);  // C at plane n - 2
-        rs[u][w] = r;
-        const int64_t q = (vplane + wrap_or_clamp(y0 + w, ny, a.periodic)) * nx + c.col;
+        Axis<2, T>::combine(rs[u][j], l, cd);  // C at plane n - 2
+        rs[u][j] = r;
         if constexpr (MODE == 3) {  // D with the step's field integral
-          const double v = V ? V[q] : 0.0;
-          const double ax = fscale * a.At[q], ay = fscale * a.At[a.cells + q],
-                       az = fscale * a.At[2 * a.cells + q];
-          FieldFactors f = field_factors<TWO, false>(v, ax, ay, az, a.ph);
-          field_fix<TWO>(f, v, ax, ay, az, a.ph);
+          FieldFactors f = field_factors<TWO, false>(vv[j], ax[j], ay[j], az[j], a.ph);
+          field_fix<TWO>(f, vv[j], ax[j], ay[j], az[j], a.ph);
           apply_field(cd, f);
         } else {
-          const double v = (MODE == 2) ? V[q] : 0.0;
-          Factors f = factors_of<MODE, TWO>(v, a.ph);
-          factors_fix<MODE, TWO>(f, v, a.ph);
+          Factors f = factors_of<MODE, TWO>(vv[j], a.ph);
+          factors_fix<MODE, TWO>(f, vv[j], a.ph);
           apply_local<MODE>(cd, f, a.ph);
         }
         if (walls && !planes.in(it - 2)) zero(cd);
         Axis<2, T>::movers(cd, r, l);
-        Axis<2, T>::combine(rd[(u + 2) % 4][w], l, out);  // second C at plane n - 4
-        rd[(u + 2) % 4][w] = r;
-        if (it >= 8 && own && y0 + w < ny)
-          store_site(dst + (((n - 4) * ny + y0 + w) * nx + c.x) * 8, out);
+        Axis<2, T>::combine(rd[(u + 2) % 4][j], l, out);  // second C at plane n - 4
+        rd[(u + 2) % 4][j] = r;
+        const int64_t y = y0 + wv * TW + j;
+        if (it >= 8 && own && y < ny)
+          store_site(dst + (((n - 4) * ny + y) * nx + c.x) * 8, out);
       }
     }
   }
@@ -600,12 +683,12 @@ static const void* strang_step_kernel(int mode) {
   }
 }
 
-// waves of a step pass the device holds at once, measured when a plan that
-// uses the pass is created (never while a stream is being captured)
+// workgroups of a step pass the device holds at once, measured when a plan
+// that uses the pass is created (never while a stream is being captured)
 template <typename T, bool FIRST>
 static int& strang_resident() {
-  static int waves = 0;
-  return waves;
+  static int groups = 0;
+  return groups;
 }
 
 template <typename T, bool FIRST>
@@ -621,8 +704,7 @@ static void strang_measure() {
     (void)hipGetLastError();
     cus = 0;
   }
-  strang_resident<T, FIRST>() =
-      (occ > 0 ? occ : StrangShape<T>::kMinBlocks) * 4 * (cus > 0 ? cus : 256);
+  strang_resident<T, FIRST>() = (occ > 0 ? occ : 2) * (cus > 0 ? cus : 256);
 }
 
 void strang3d_prepare(bool fp64) {
@@ -635,17 +717,19 @@ void strang3d_prepare(bool fp64) {
   }
 }
 
-// grid of a fused second-order pass: z segments from a cost model, (rounds of
-// resident waves) x (H + 8 plane iterations)
+// grid of a fused second-order pass, one workgroup per tile: z segments from
+// a cost model, (rounds of resident workgroups) x (H + 8 plane iterations);
+// the grid is a multiple of 8 so that each XCD takes a contiguous run of
+// tiles (neighbouring row blocks share their halo rows in its L2)
 template <typename T, bool FIRST>
 static int64_t strang_step_grid(const SweepArgs& a, SweepArgs& t) {
-  constexpr int TY = StrangShape<T>::TY;
+  constexpr int WY = kStrangWaves * StrangShape<T>::TW;
   constexpr int XL = FIRST ? 2 : 4;
   int resident = strang_resident<T, FIRST>();
-  if (resident <= 0) resident = StrangShape<T>::kMinBlocks * 4 * 256;
+  if (resident <= 0) resident = 2 * 256;
   t = a;
   t.nstrips = (a.nx + strip_width(XL) - 1) / strip_width(XL);
-  t.nyblk = (a.ny + TY - 1) / TY;
+  t.nyblk = (a.ny + WY - 1) / WY;
   const int64_t per_seg = t.nstrips * t.nyblk;
   int64_t best_H = a.nz, best_cost = -1;
   for (int64_t nseg = 1; nseg <= 64 && nseg <= a.nz; ++nseg) {
@@ -661,7 +745,8 @@ static int64_t strang_step_grid(const SweepArgs& a, SweepArgs& t) {
   t.H = static_cast<int>(best_H);
   t.nseg = (a.nz + best_H - 1) / best_H;
   t.ntiles = per_seg * t.nseg;
-  return (t.ntiles + 3) / 4;
+  t.xcd_remap = 1;
+  return (t.ntiles + 7) / 8 * 8;
 }
 
 template <typename T>
@@ -733,11 +818,10 @@ static const void* kernel3d(int depth, int mode) {
   constexpr bool F64 = sizeof(T) == 8;
   constexpr int TY1 = F64 ? kTY3D_F64 : kTY3D_F32;
   if (depth == 2) {  // phase modes 0 to 2
-    constexpr int TY2 = F64 ? kTY3D2_F64 : kTY3D2_F32;
     switch (mode) {
-      case 0: return reinterpret_cast<const void*>(&k_sweep3d_x2<T, TY2, 0>);
-      case 1: return reinterpret_cast<const void*>(&k_sweep3d_x2<T, TY2, 1>);
-      case 2: return reinterpret_cast<const void*>(&k_sweep3d_x2<T, TY2, 2>);
+      case 0: return reinterpret_cast<const void*>(&k_sweep3d_x2<T, 0>);
+      case 1: return reinterpret_cast<const void*>(&k_sweep3d_x2<T, 1>);
+      case 2: return reinterpret_cast<const void*>(&k_sweep3d_x2<T, 2>);
       default: return nullptr;
     }
   }

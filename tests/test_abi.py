@@ -102,20 +102,20 @@ def test_dry_strang_plans(lib):
 
 
 def test_dry_3d_pass_depth(lib):
-    """3-D plans fuse two steps per pass (waves write 60 columns, row blocks
-    of 4 with FP32 state, 2 with FP64); rows of 2^28 cells or more and a
+    """3-D plans fuse two steps per pass (workgroup tiles write 60 columns of
+    8 rows with FP32 state, 4 with FP64); rows of 2^28 cells or more and a
     depth cap of one keep single steps."""
     p = dry((64, 30, 16))
     info = p.info()
     assert info["depth"] == 2 and info["nstrips"] == 2
-    assert info["ntiles"] == 2 * 8 * info["nseg"]
+    assert info["ntiles"] == 2 * 4 * info["nseg"]  # workgroup tiles of 8 rows
     p.set_depth(1)
     assert p.info()["depth"] == 1 and p.info()["nstrips"] == 1
     p.close()
     p = dry((64, 30, 16), dtype="c128")
     info = p.info()
     assert info["depth"] == 2 and info["nstrips"] == 2
-    assert info["ntiles"] == 2 * 15 * info["nseg"]  # row blocks of 2 with FP64 state
+    assert info["ntiles"] == 2 * 8 * info["nseg"]  # tiles of 4 rows with FP64 state
     p.close()
     assert dry((64, 30)).info()["reverse_depth"] == 3
     assert dry((64, 30), dtype="c128").info()["reverse_depth"] == 2
