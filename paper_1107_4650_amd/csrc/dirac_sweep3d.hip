@@ -259,25 +259,29 @@ __device__ __forceinline__ void march3d_x2(const T* __restrict__ src, T* __restr
 #pragma unroll
     for (int j = 0; j < TW; ++j) zero(zm2[q][j]);
   }
+  // this wave's input rows of the plane read at iteration it and the V of its
+  // first-step rows on the plane one behind, loaded one iteration ahead
+  Site<T> in[N1];
+  double vn[TW + 1];
+  auto load_inputs = [&](int it) {
+    const T* plane = src + read_row(in_plane(it), nz, a.periodic) * plane_cells * 8;
+#pragma unroll
+    for (int j = 0; j < N1; ++j) load_site(plane + inrow[j] + cell_off, in[j]);
+    const double* vp = V + read_row(plane_of(it, 1), nz, a.periodic) * plane_cells;
+#pragma unroll
+    for (int j = 0; j <= TW; ++j)
+      vn[j] = (read_v && (j < TW || halo)) ? (vp + srow_off[j])[v_off] : 0.0;
+  };
+  load_inputs(0);
   for (int pair = 0;; ++pair) {
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       const int it = 2 * pair + k;
       if (it >= nit) return;  // uniform over the workgroup
       const int64_t k2 = plane_of(it, 2);
-      // this wave's input rows of the plane read and the V of its first-step
-      // rows on the plane one behind
-      Site<T> in[N1];
       double vb[TW + 1];
-      {
-        const T* plane = src + read_row(in_plane(it), nz, a.periodic) * plane_cells * 8;
 #pragma unroll
-        for (int j = 0; j < N1; ++j) load_site(plane + inrow[j] + cell_off, in[j]);
-        const double* vp = V + read_row(plane_of(it, 1), nz, a.periodic) * plane_cells;
-#pragma unroll
-        for (int j = 0; j <= TW; ++j)
-          vb[j] = (read_v && (j < TW || halo)) ? (vp + srow_off[j])[v_off] : 0.0;
-      }
+      for (int j = 0; j <= TW; ++j) vb[j] = vn[j];
       // 1. x transport of the input rows, y movers to LDS
 #pragma unroll
       for (int j = 0; j < N1; ++j) {
@@ -293,6 +297,7 @@ __device__ __forceinline__ void march3d_x2(const T* __restrict__ src, T* __restr
         if (t < NI - 2) sh.r1[t][lane] = ry;
         if (t >= 2) sh.l1[t - 2][lane] = ly;
       }
+      if (it + 1 < nit) load_inputs(it + 1);
       __syncthreads();
       // 2. first step on the first-step rows of the plane one behind, then the
       //    second step's x transport, y movers to LDS
