@@ -208,11 +208,11 @@ int dl_observables(dl_plan p, const void *psi, double x_b, double out[5], void *
  * on grid g with cell size dx; out is a DEVICE array of 5 doubles, written
  * with the values of dl_observables (same kernels, same bits), stream-ordered.
  * The per-block partial sums live in a static device array of the library
- * (80 KiB per GPU, held until the process ends) that every call on that GPU
+ * (40 KiB per GPU, held until the process ends) that every call on that GPU
  * shares: calls that overlap on one GPU (two streams, or two threads) race,
  * so serialise them.  Each call writes every partial it reads, so nothing
  * needs clearing.  Grids of any valid size fit (the reduction always uses the
- * same 1024 partials); grids beyond 2^40 cells, a NULL or misaligned pointer,
+ * same 512 partials); grids beyond 2^40 cells, a NULL or misaligned pointer,
  * or a bad dtype / flag are refused (DL_ERR_ARG, DL_ERR_ALIGN, DL_ERR_DTYPE).
  * The first call on a device looks up the array's device address. */
 int dl_observables_noalloc(const dl_grid *g, double dx, dl_dtype dtype, unsigned flags,

@@ -113,7 +113,7 @@ hipError_t launch_resident1d(bool fp64, int axis, void* psi, const double* V,
                              const ResidentArgs& a, int spt, int threads, hipStream_t st);
 
 // observables: per-block partials (10 doubles per block) then final pass
-constexpr int kObsBlocks = 1024;
+constexpr int kObsBlocks = 512;
 hipError_t launch_observables(bool fp64, const void* psi, const ObsArgs& a, double* partials,
                               double* out5, hipStream_t st);
 

@@ -110,26 +110,37 @@ __global__ __launch_bounds__(256) void k_obs_partial(const T* __restrict__ psi, 
   // coordinates of this thread's first cell
   int64_t i0 = c % a.n0, r = c / a.n0;
   int64_t i1 = r % a.n1, i2 = r / a.n1;
-  for (; c < ce; c += 256 * kObsBatch) {
-    T s[kObsBatch][2 * NC];
+  T s[kObsBatch][2 * NC];
+  auto load_batch = [&](int64_t cc) {
 #pragma unroll
     for (int j = 0; j < kObsBatch; ++j) {
-      if (c + 256 * j < ce) {
-        load_obs<T, NC>(psi, c + 256 * j, s[j]);
+      if (cc + 256 * j < ce) {
+        load_obs<T, NC>(psi, cc + 256 * j, s[j]);
       } else {
 #pragma unroll
         for (int k = 0; k < 2 * NC; ++k) s[j][k] = T(0);
       }
     }
+  };
+  if (c < ce) load_batch(c);
+  for (; c < ce; c += 256 * kObsBatch) {
+    double rho_b[kObsBatch];
+#pragma unroll
+    for (int j = 0; j < kObsBatch; ++j) {
+      double rho = 0.0;
+#pragma unroll
+      for (int k = 0; k < 2 * NC; ++k) {
+        const double v = static_cast<double>(s[j][k]);
+        rho = fma(v, v, rho);
+      }
+      rho_b[j] = rho;
+    }
+    // the next batch is in flight while this one is summed
+    if (c + 256 * kObsBatch < ce) load_batch(c + 256 * kObsBatch);
 #pragma unroll
     for (int j = 0; j < kObsBatch; ++j) {
       if (c + 256 * j < ce) {
-        double rho = 0.0;
-#pragma unroll
-        for (int k = 0; k < 2 * NC; ++k) {
-          const double v = static_cast<double>(s[j][k]);
-          rho = fma(v, v, rho);
-        }
+        const double rho = rho_b[j];
         const double x0 = a.xmin0 + (static_cast<double>(i0) + 0.5) * a.dx;
         nadd(acc[0], rho);
         nadd(acc[1], x0 * rho);
@@ -219,7 +230,7 @@ hipError_t launch_observables(bool fp64, const void* psi, const ObsArgs& a, doub
 // ===========================================================================
 namespace {
 
-constexpr int kScratchDoubles = dirac::kObsBlocks * dirac::kQ * 2;  // 80 KiB
+constexpr int kScratchDoubles = dirac::kObsBlocks * dirac::kQ * 2;  // 40 KiB
 static_assert(kScratchDoubles >= dirac::kObsBlocks * dirac::kQ * 2,
               "scratch must hold the partials of every block");
 
