@@ -194,7 +194,8 @@ template <typename T> struct X2Tile {
 // t < NI - 2 at [t], left movers of rows t >= 2 at [t - 2]; of the
 // first-step rows (index u: row y0 - 1 + u): right movers of u < NS - 2 at
 // [u], left movers of u >= 2 at [u - 2]
-template <typename T> struct X2Lds {
+// (16-byte aligned, so that a lane's mover moves as one 128-bit LDS access)
+template <typename T> struct alignas(16) X2Lds {
   using S = X2Tile<T>;
   Mov<T> r1[S::NI - 2][64], l1[S::NI - 2][64];
   Mov<T> r2[S::NS - 2][64], l2[S::NS - 2][64];
