@@ -34,6 +34,9 @@
  *    allocated in dl_plan_create.  One plan must not be used from two
  *    streams or threads at once.
  *  - psi and lam must be 16-byte aligned, V, Q and G 8-byte aligned.
+ *  - The plan, step, observables, adjoint and batch calls each open a named
+ *    roctx range (the call's name) for rocprofv3 --marker-trace, so a trace
+ *    shows every call on the host timeline beside the kernels it enqueued.
  */
 #ifndef LIBDIRAC_H
 #define LIBDIRAC_H

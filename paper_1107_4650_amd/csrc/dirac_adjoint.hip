@@ -23,6 +23,7 @@
 #include "dirac_device.h"
 #include "dirac_plan.h"
 #include "dirac_sweep_impl.h"
+#include "dirac_trace.h"
 
 #include <utility>
 
@@ -739,6 +740,7 @@ static int check_adjoint_plan(dl_plan p) {
 
 extern "C" int dl_seed_adjoint(dl_plan p, const void* psi, double x_b, void* lam, double* Q,
                                void* stream) {
+  dirac::TraceRange trace_range("dl_seed_adjoint");
   int rc = check_adjoint_plan(p);
   if (rc) return rc;
   if ((rc = check_state_ptr(psi, "psi")) || (rc = check_state_ptr(lam, "lam")) ||
@@ -761,6 +763,7 @@ extern "C" int dl_seed_adjoint(dl_plan p, const void* psi, double x_b, void* lam
 
 extern "C" int dl_grad_step(dl_plan p, void* psi, void* lam, const double* V, double* Q,
                             int64_t nsteps, void* stream) {
+  dirac::TraceRange trace_range("dl_grad_step");
   int rc = check_adjoint_plan(p);
   if (rc) return rc;
   if ((rc = check_state_ptr(psi, "psi")) || (rc = check_state_ptr(lam, "lam")) ||
@@ -834,6 +837,7 @@ extern "C" int dl_grad_step(dl_plan p, void* psi, void* lam, const double* V, do
 
 extern "C" int dl_project(dl_plan p, const double* Q, const double* G, int nb, double* out,
                           void* stream) {
+  dirac::TraceRange trace_range("dl_project");
   int rc = check_live(p);
   if (rc) return rc;
   if ((rc = check_f64_ptr(Q, "Q", false)) || (rc = check_f64_ptr(G, "G", false)) ||
@@ -863,6 +867,7 @@ extern "C" int dl_project(dl_plan p, const double* Q, const double* G, int nb, d
 
 extern "C" int dl_expand(dl_plan p, const double* G, const double* theta, int nb, double* V,
                          void* stream) {
+  dirac::TraceRange trace_range("dl_expand");
   int rc = check_live(p);
   if (rc) return rc;
   if ((rc = check_f64_ptr(G, "G", false)) || (rc = check_f64_ptr(theta, "theta", false)) ||

@@ -38,6 +38,7 @@
 
 #include "dirac_plan.h"
 #include "dirac_sweep_impl.h"
+#include "dirac_trace.h"
 
 namespace dirac {
 
@@ -592,6 +593,7 @@ void batch_info(dl_plan b, int64_t* info, int n) {
 extern "C" int dl_batch_create(dl_plan* out, const dl_grid* grids, const double* dx,
                                const double* dt, const double* c, const double* m, int count,
                                dl_dtype dtype, dl_bc bc, unsigned flags) {
+  dirac::TraceRange trace_range("dl_batch_create");
   if (!out) return set_error(DL_ERR_ARG, "out is NULL");
   *out = nullptr;
   if (!grids || !dx || !dt || !c || !m) return set_error(DL_ERR_ARG, "NULL parameter array");
@@ -683,6 +685,7 @@ extern "C" int dl_batch_create(dl_plan* out, const dl_grid* grids, const double*
 
 extern "C" int dl_batch_step(dl_plan b, void* const* psi, const double* const* V,
                              const int64_t* nsteps, void* stream) {
+  dirac::TraceRange trace_range("dl_batch_step");
   if (!b) return set_error(DL_ERR_ARG, "batch is NULL");
   if (!b->is_batch) return set_error(DL_ERR_STATE, "not a batch (use dl_step)");
   if (b->dry) return set_error(DL_ERR_STATE, "dry batch: no device work allowed");
@@ -710,6 +713,7 @@ extern "C" int dl_batch_step(dl_plan b, void* const* psi, const double* const* V
 // warm-up run, without graphs, and is scored by its time per step.
 extern "C" int dl_batch_autotune(dl_plan b, void* const* psi, const double* const* V, int trials,
                                  int* chosen, void* stream) {
+  dirac::TraceRange trace_range("dl_batch_autotune");
   if (!b || !b->is_batch) return set_error(DL_ERR_ARG, "not a batch");
   if (b->dry) return set_error(DL_ERR_STATE, "dry batch");
   if (!psi || trials < 1) return set_error(DL_ERR_ARG, "bad arguments");

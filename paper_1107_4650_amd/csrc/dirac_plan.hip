@@ -13,6 +13,7 @@
 
 #include "../../include/libdirac.h"
 #include "dirac_launch.h"
+#include "dirac_trace.h"
 #include "dirac_plan.h"
 
 using namespace dirac;
@@ -283,6 +284,7 @@ static int plan_tiling(dl_plan p) {
 
 extern "C" int dl_plan_create(dl_plan* out, const dl_grid* g, double dx, double dt, double c,
                               double m, dl_dtype dtype, dl_bc bc, unsigned flags) {
+  dirac::TraceRange trace_range("dl_plan_create");
   if (!out) return fail(DL_ERR_ARG, "out is NULL");
   *out = nullptr;
   const bool strang = (flags & DL_STRANG) != 0;
@@ -504,6 +506,7 @@ static hipError_t graph_for(dl_plan p, void* psi, const double* V, int64_t pairs
 }
 
 extern "C" int dl_step(dl_plan p, void* psi, const double* V, int64_t nsteps, void* stream) {
+  dirac::TraceRange trace_range("dl_step");
   int rc = check_live(p);
   if (rc) return rc;
   if ((rc = check_state_ptr(psi, "psi"))) return rc;
@@ -549,6 +552,7 @@ extern "C" int dl_step(dl_plan p, void* psi, const double* V, int64_t nsteps, vo
 
 extern "C" int dl_step_field(dl_plan p, void* psi, const double* V, const double* A,
                              int64_t nsteps, void* stream) {
+  dirac::TraceRange trace_range("dl_step_field");
   int rc = check_live(p);
   if (rc) return rc;
   if (!A) return dl_step(p, psi, V, nsteps, stream);
@@ -575,6 +579,7 @@ extern "C" int dl_step_field(dl_plan p, void* psi, const double* V, const double
 
 extern "C" int dl_step_pulse(dl_plan p, void* psi, const double* V, const double* P,
                              const dl_pulse* pulse, double t0, int64_t nsteps, void* stream) {
+  dirac::TraceRange trace_range("dl_step_pulse");
   int rc = check_live(p);
   if (rc) return rc;
   if ((rc = check_state_ptr(psi, "psi"))) return rc;
@@ -614,6 +619,7 @@ extern "C" int dl_step_pulse(dl_plan p, void* psi, const double* V, const double
 
 extern "C" int dl_step_out(dl_plan p, const void* src, void* dst, const double* V,
                            void* stream) {
+  dirac::TraceRange trace_range("dl_step_out");
   int rc = check_live(p);
   if (rc) return rc;
   if ((rc = check_state_ptr(src, "src"))) return rc;
@@ -633,6 +639,7 @@ extern "C" int dl_step_out(dl_plan p, const void* src, void* dst, const double* 
 
 extern "C" int dl_step_fused_out(dl_plan p, const void* src, void* dst, const double* V,
                                  int64_t nsteps, void* stream) {
+  dirac::TraceRange trace_range("dl_step_fused_out");
   int rc = check_live(p);
   if (rc) return rc;
   if ((rc = check_state_ptr(src, "src"))) return rc;
@@ -693,6 +700,7 @@ static int observables_status(dl_plan p, const double* out) {
 
 extern "C" int dl_observables(dl_plan p, const void* psi, double x_b, double out[5],
                               void* stream) {
+  dirac::TraceRange trace_range("dl_observables");
   int rc = check_live(p);
   if (rc) return rc;
   if ((rc = check_state_ptr(psi, "psi"))) return rc;

@@ -56,6 +56,17 @@ def code_of(fn):
     return ei.value.code
 
 
+def test_library_links_the_trace_ranges(lib):
+    """The entry points open named roctx ranges (rocprofv3 --marker-trace), so
+    the library depends on the roctx library, found at run time."""
+    import shutil
+    import subprocess
+    if not shutil.which("readelf"):
+        pytest.skip("readelf not available")
+    dyn = subprocess.run(["readelf", "-d", L.LIB_PATH], capture_output=True, text=True).stdout
+    assert "librocprofiler-sdk-roctx" in dyn
+
+
 def test_dry_plan_accepts_valid_grids(lib):
     for shape, axes in (((64,), (0,)), ((64,), (2,)), ((32, 16), (0, 1)), ((32, 16), (0, 2)),
                         ((32, 16), (1, 2)), ((8, 8, 8), (0, 1, 2))):
