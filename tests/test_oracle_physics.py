@@ -140,3 +140,29 @@ def test_klein_1d_transmission_paper_cell(oracle, V0):
     eq:trans_co, the accuracy Sec. 5.2.1 reports for every barrier height."""
     T, Tth = _klein_run(oracle, V0, a=10.0 / 16384)
     assert abs(T - Tth) / Tth < 0.005
+
+
+def test_golden_config2_state_is_consistent():
+    """The stored oracle state of the 2-D workload after 10^4 steps (written by
+    tests/golden/make_config2_golden.py): 512 distinct cells inside the grid,
+    finite values, a norm that a zero wall can only have lowered (the packet,
+    p0 = 40 from x0 ~ -4, reaches the wall at x = 10.24 well before t = 10^4
+    dt and leaves through it), P_T within the norm, a mean position that moved
+    with the packet, and components 2 and 3 exactly zero (alpha_x, alpha_y and
+    beta keep the pair (psi_1, psi_4) of the initial spinor to itself)."""
+    import os
+    from paper_1107_4650_amd.inputs import config_2d_tanh
+    from tests.golden_util import GOLDEN_CONFIG2 as GOLDEN, load_golden
+    if not os.path.exists(GOLDEN):
+        pytest.skip("golden state not written")
+    obs, idx, vals = load_golden()
+    assert len(idx) == 512 and len(set(idx.tolist())) == 512
+    assert idx.min() >= 0 and idx.max() < 2048 * 2048
+    assert np.all(np.isfinite(vals.real)) and np.all(np.isfinite(vals.imag))
+    w = config_2d_tanh(n=2048, nsteps=10000)
+    n0 = np.sum(np.abs(w.psi0) ** 2) * w.dx ** 2
+    assert 0.0 < obs[0] <= n0 * (1 + 1e-12)
+    assert 0.0 <= obs[4] <= obs[0]
+    assert obs[1] > w.extra["x0"]
+    assert np.all(vals[:, 1] == 0) and np.all(vals[:, 2] == 0)
+    assert np.all(np.abs(vals[:, 0]) + np.abs(vals[:, 3]) > 0)
