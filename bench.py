@@ -107,6 +107,42 @@ def load_profile(kernel_name):
     return ent
 
 
+GOLDEN_CONFIG2 = os.path.join(ROOT, "tests", "golden", "config2_2048_1e4.txt")
+
+
+def golden_check(L, V):
+    """The 2-D workload run for its stated 10^4 steps (untimed) against the
+    oracle's final state stored in tests/golden/ (512 cells and the grid's
+    observables, written by a script that calls only the oracle): relative L2
+    over the cells for FP32 and FP64 state."""
+    import torch
+    from paper_1107_4650_amd.inputs import config_2d_tanh
+    if not os.path.exists(GOLDEN_CONFIG2):
+        return None
+    idx, vals = [], []
+    with open(GOLDEN_CONFIG2) as f:
+        for line in f:
+            if line.startswith("cell "):
+                parts = line.split()
+                idx.append(int(parts[1]))
+                ri = np.array([float(v) for v in parts[2:]])
+                vals.append(ri[0::2] + 1j * ri[1::2])
+    ref = torch.from_numpy(np.array(vals)).to("cuda")
+    tidx = torch.tensor(idx, device="cuda")
+    w = config_2d_tanh(n=2048, nsteps=10000)
+    out = {"steps": w.nsteps, "cells": len(idx), "reference": "tests/golden/config2_2048_1e4.txt"}
+    for dt in ("c64", "c128"):
+        tdt = torch.complex64 if dt == "c64" else torch.complex128
+        with L.Plan(w.shape, w.dx, w.dt, w.c, w.m, dtype=dt, xmin=w.xmin) as p:
+            psi = to_dev(w.psi0, tdt)
+            p.step(psi, V, w.nsteps)
+            torch.cuda.synchronize()
+            got = psi.reshape(-1, 4)[tidx]
+        out[("fp32" if dt == "c64" else "fp64") + "_rel_l2"] = rel_l2(got, ref)
+        del psi
+    return out
+
+
 def bench_main(args):
     import torch
     from paper_1107_4650_amd import libdirac as L
@@ -144,6 +180,10 @@ def bench_main(args):
     log(f"fp64: {wall64 * 1e3 / n64:.4f} ms/step wall; fp32 vs fp64 rel-L2 {err:.3e}")
     del psi32, psi64, out32, out64
     torch.cuda.empty_cache()
+    gold = golden_check(L, V)
+    if gold:
+        log(f"vs stored oracle state after {gold['steps']} steps: fp32 rel-L2 "
+            f"{gold['fp32_rel_l2']:.3e}, fp64 {gold['fp64_rel_l2']:.3e}")
 
     # one launch advances every cell d32 steps, reading psi and V once and
     # writing psi once: 72 B per cell per launch, 72 / d32 B per site-update
@@ -193,6 +233,7 @@ def bench_main(args):
                  "roofline_frac": BYTES_F64 * sites / (per64 * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "fp32_vs_fp64_rel_l2": err,
         "fp32_vs_fp64_steps": n32 + args.warmup - args.warmup % d32,
+        "vs_oracle_after_1e4_steps": gold,
         "norm_fp32": obs32[0], "norm_fp64": obs64[0],
     }
     return line
