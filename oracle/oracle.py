@@ -40,8 +40,10 @@ _lib = None
 def _load():
     global _lib
     if _lib is None:
-        build()
-        lib = ctypes.CDLL(_LIB)
+        # DIRAC_ORACLE_LIB: a build of the oracle from a modified copy of its
+        # source, used by the test that plants mistakes to show the pins fail
+        path = os.environ.get("DIRAC_ORACLE_LIB") or build()
+        lib = ctypes.CDLL(path)
         i64p = ctypes.POINTER(ctypes.c_int64)
         ip = ctypes.POINTER(ctypes.c_int)
         dp = ctypes.c_void_p
