@@ -202,7 +202,7 @@ template <class S, int K> struct MarchShape;  // L: rows in flight; U: unroll
 template <> struct MarchShape<LieStep, 1> { static constexpr int L = 3, U = 4; };
 template <> struct MarchShape<LieStep, 2> { static constexpr int L = 2, U = 6; };
 template <> struct MarchShape<LieStep, 3> { static constexpr int L = 3, U = 4; };
-template <> struct MarchShape<LieStep, 4> { static constexpr int L = 4, U = 10; };
+template <> struct MarchShape<LieStep, 4> { static constexpr int L = 1, U = 10; };
 template <> struct MarchShape<LieStep, 5> { static constexpr int L = 2, U = 6; };
 template <> struct MarchShape<StrangStep, 1> { static constexpr int L = 3, U = 4; };
 template <> struct MarchShape<StrangStep, 2> { static constexpr int L = 3, U = 4; };
