@@ -201,7 +201,7 @@ template <class S> __host__ __device__ constexpr int halo_lanes(int K) { return 
 template <class S, int K> struct MarchShape;  // L: rows in flight; U: unroll
 template <> struct MarchShape<LieStep, 1> { static constexpr int L = 3, U = 4; };
 template <> struct MarchShape<LieStep, 2> { static constexpr int L = 2, U = 6; };
-template <> struct MarchShape<LieStep, 3> { static constexpr int L = 3, U = 4; };
+template <> struct MarchShape<LieStep, 3> { static constexpr int L = 1, U = 4; };
 template <> struct MarchShape<LieStep, 4> { static constexpr int L = 1, U = 10; };
 template <> struct MarchShape<LieStep, 5> { static constexpr int L = 2, U = 6; };
 template <> struct MarchShape<StrangStep, 1> { static constexpr int L = 3, U = 4; };
