@@ -556,14 +556,27 @@ def bench_observables():
     w = config_2d_tanh(n=2048, nsteps=1)
     with L.Plan(w.shape, w.dx, w.dt, w.c, w.m, dtype="c64", xmin=w.xmin) as p:
         psi = to_dev(w.psi0, torch.complex64)
+        V = to_dev(w.V, torch.float64)
         p.observables(psi, 0.0)
         reps = 20
         t0 = time.perf_counter()
         for _ in range(reps):
             p.observables(psi, 0.0)
         ms = (time.perf_counter() - t0) * 1e3 / reps
+        # one pass of five steps, then the observables: two calls, or one
+        # call whose pass sums the observables as it stores the state
+        def per_call(fn):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            return (time.perf_counter() - t0) * 1e3 / reps
+        ms_two = per_call(lambda: (p.step(psi, V, 5), p.observables(psi, 0.0)))
+        ms_fused = per_call(lambda: p.step_observables(psi, V, 5, 0.0))
     return {"ms_per_call_incl_sync": ms, "bytes_per_site": 32,
-            "GBps": 32 * w.sites / (ms * 1e-3) / 1e9}
+            "GBps": 32 * w.sites / (ms * 1e-3) / 1e9,
+            "step5_then_observables_ms": ms_two, "step5_observables_fused_ms": ms_fused}
 
 
 def bench_adjoint(args):

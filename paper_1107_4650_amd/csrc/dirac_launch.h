@@ -93,6 +93,14 @@ struct ObsArgs {
 // `blocks` 256-thread workgroups
 hipError_t launch_sweep2d(bool fp64, bool strang, int depth, const void* src, void* dst,
                           const double* V, const SweepArgs& a, int blocks, hipStream_t st);
+// the same lowest-order pass on a 2-D grid (phase modes 0-2, four components),
+// which also sums the observables of the cells it stores: 10 doubles per wave
+// with work (a.ntiles of them) at `partials`, reduced by launch_obs_final
+hipError_t launch_sweep2d_obs(bool fp64, int depth, const void* src, void* dst, const double* V,
+                              const SweepArgs& a, const ObsArgs& o, double* partials, int blocks,
+                              hipStream_t st);
+// true if launch_sweep2d_obs has a kernel for this depth and phase mode
+bool sweep2d_obs_available(bool fp64, int depth, int mode);
 // `depth` (1 or 2) full steps src -> dst in one pass over a 3-D grid (tiling
 // made by the 3-D tiler for that depth)
 hipError_t launch_sweep3d(bool fp64, int depth, const void* src, void* dst, const double* V,
@@ -112,9 +120,13 @@ hipError_t launch_strang3d(bool fp64, const void* src, void* dst, void* mid, con
 hipError_t launch_resident1d(bool fp64, int axis, void* psi, const double* V,
                              const ResidentArgs& a, int spt, int threads, hipStream_t st);
 
-// observables: per-block partials (10 doubles per block) then final pass
+// observables: per-block partials (kObsDoubles per block) then final pass
 constexpr int kObsBlocks = 512;
+constexpr int kObsDoubles = 10;  // Neumaier pairs of the five sums
 hipError_t launch_observables(bool fp64, const void* psi, const ObsArgs& a, double* partials,
                               double* out5, hipStream_t st);
+// the final pass alone: n partials (10 doubles each) in index order -> out5
+hipError_t launch_obs_final(const double* partials, int64_t n, const ObsArgs& a, double* out5,
+                            hipStream_t st);
 
 }  // namespace dirac

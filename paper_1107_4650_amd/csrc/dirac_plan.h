@@ -69,6 +69,8 @@ struct dl_plan_s {
   double* hres_dev = nullptr;  // their device address
   double* proj = nullptr;      // projection partials (grown on demand)
   size_t proj_bytes = 0;
+  double* tile_partials = nullptr;  // per-wave observables sums of a fused last pass
+  int64_t tile_partials_n = 0;      // (grown on demand: waves of the deepest tiling)
   hipStream_t cap_stream = nullptr;
   std::vector<dirac::GraphEntry> graphs;
   // batches

@@ -378,6 +378,7 @@ extern "C" int dl_plan_destroy(dl_plan p) {
     if (p->partials) (void)hipFree(p->partials);
     if (p->dres) (void)hipFree(p->dres);
     if (p->hres) (void)hipHostFree(p->hres);
+    if (p->tile_partials) (void)hipFree(p->tile_partials);
     (void)hipGetLastError();
   }
   delete p;
@@ -428,18 +429,39 @@ hipError_t launch_pass(dl_plan p, int depth, const void* src, void* dst, const d
   return launch_sweep2d(p->fp64, p->strang, depth, src, dst, V, a, p->bl[depth - 1], st);
 }
 
+// the last pass of a dl_step_observables call: a 2-D lowest-order pass that
+// also leaves the observables sums of every wave in p->tile_partials
+static hipError_t launch_pass_obs(dl_plan p, int depth, const void* src, void* dst,
+                                  const double* V, const ObsArgs& o, hipStream_t st,
+                                  int64_t* waves) {
+  SweepArgs a = p->sw[depth - 1];
+  a.ph = p->ph;
+  a.At = nullptr;
+  a.pulse = p->pulse;
+  a.pulse_on = 0;
+  a.cells = p->cells;
+  a.nc = p->nc;
+  *waves = a.ntiles;
+  return launch_sweep2d_obs(p->fp64, depth, src, dst, V, a, o, p->tile_partials,
+                            p->bl[depth - 1], st);
+}
+
 // enqueue `nsteps` steps ping-ponging between psi and the plan's tmp buffer,
 // starting from psi, in passes of the plan's depth (the remainder in
-// shallower passes); returns the buffer that holds the result
+// shallower passes); returns the buffer that holds the result.  With `obs`,
+// the last pass also sums the observables (launch_pass_obs; `obs_waves`
+// receives the number of partials it writes).
 hipError_t enqueue_steps(dl_plan p, void* psi, const double* V, int64_t nsteps, hipStream_t st,
-                         void** result) {
+                         void** result, const ObsArgs* obs = nullptr,
+                         int64_t* obs_waves = nullptr) {
   void* a = psi;
   void* b = p->tmp;
   int64_t left = nsteps;
   const int dmax = (p->ph.mode >= 3) ? p->depth_field : p->depth;
   for (int d = dmax; d >= 1; --d) {
     for (; left >= d; left -= d) {
-      hipError_t e = launch_pass(p, d, a, b, V, st);
+      hipError_t e = (obs && left == d) ? launch_pass_obs(p, d, a, b, V, *obs, st, obs_waves)
+                                        : launch_pass(p, d, a, b, V, st);
       if (e != hipSuccess) return e;
       p->pulse.n0 += d;  // the pulse's step index of the next pass
       void* t = a;
@@ -698,15 +720,7 @@ static int observables_status(dl_plan p, const double* out) {
   return DL_OK;
 }
 
-extern "C" int dl_observables(dl_plan p, const void* psi, double x_b, double out[5],
-                              void* stream) {
-  dirac::TraceRange trace_range("dl_observables");
-  int rc = check_live(p);
-  if (rc) return rc;
-  if ((rc = check_state_ptr(psi, "psi"))) return rc;
-  if (!out) return fail(DL_ERR_ARG, "out is NULL");
-  if (!std::isfinite(x_b) && !std::isinf(x_b)) return fail(DL_ERR_ARG, "x_b is NaN");
-  hipStream_t st = static_cast<hipStream_t>(stream);
+static ObsArgs obs_args(dl_plan p, double x_b) {
   ObsArgs a{};
   a.n0 = p->g.n[0];
   a.n1 = p->g.n[1];
@@ -718,14 +732,97 @@ extern "C" int dl_observables(dl_plan p, const void* psi, double x_b, double out
   a.xmin2 = p->g.xmin[2];
   a.x_b = x_b;
   a.nc = p->nc;
-  // the final reduction writes the five values straight into the plan's
-  // mapped pinned buffer (no copy back)
-  hipError_t e = launch_observables(p->fp64, psi, a, p->partials, p->hres_dev, st);
-  if (e != hipSuccess) return hip_fail(e, "observables launch");
-  e = hipStreamSynchronize(st);
+  return a;
+}
+
+// wait for the final reduction, which wrote the five values straight into
+// the plan's mapped pinned buffer (no copy back), and check them
+static int finish_observables(dl_plan p, hipStream_t st, double out[5]) {
+  hipError_t e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
   for (int i = 0; i < 5; ++i) out[i] = p->hres[i];
   return observables_status(p, out);
+}
+
+extern "C" int dl_observables(dl_plan p, const void* psi, double x_b, double out[5],
+                              void* stream) {
+  dirac::TraceRange trace_range("dl_observables");
+  int rc = check_live(p);
+  if (rc) return rc;
+  if ((rc = check_state_ptr(psi, "psi"))) return rc;
+  if (!out) return fail(DL_ERR_ARG, "out is NULL");
+  if (!std::isfinite(x_b) && !std::isinf(x_b)) return fail(DL_ERR_ARG, "x_b is NaN");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_observables(p->fp64, psi, obs_args(p, x_b), p->partials, p->hres_dev, st);
+  if (e != hipSuccess) return hip_fail(e, "observables launch");
+  return finish_observables(p, st, out);
+}
+
+extern "C" int dl_step_observables(dl_plan p, void* psi, const double* V, int64_t nsteps,
+                                   double x_b, double out[5], void* stream) {
+  dirac::TraceRange trace_range("dl_step_observables");
+  int rc = check_live(p);
+  if (rc) return rc;
+  if ((rc = check_state_ptr(psi, "psi"))) return rc;
+  if ((rc = check_f64_ptr(V, "V", true))) return rc;
+  if (nsteps < 0) return fail(DL_ERR_ARG, "nsteps = %lld < 0", static_cast<long long>(nsteps));
+  if (!out) return fail(DL_ERR_ARG, "out is NULL");
+  if (std::isnan(x_b)) return fail(DL_ERR_ARG, "x_b is NaN");
+  const int mode = phase_mode(p->m, V);
+  // the fused last pass exists for 2-D lowest-order plans of four-component
+  // states on grid axes (x, y); every other plan steps, then reduces
+  const bool fused = nsteps > 0 && p->g.ndim == 2 && !p->strang && p->nc == 4 &&
+                     axes_code(p->g) == 10 && mode <= 2;
+  if (!fused) {
+    rc = dl_step(p, psi, V, nsteps, stream);
+    if (rc) return rc;
+    return dl_observables(p, psi, x_b, out, stream);
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  p->ph = make_phase(transports_per_step(p), p->dt, p->c, p->m, mode, p->fp64);
+  p->field = nullptr;
+  select_tiling(p, mode);
+  for (int d = 1; d <= p->depth; ++d)
+    if (!sweep2d_obs_available(p->fp64, d, mode))
+      return fail(DL_ERR_STATE, "no fused observables pass of depth %d", d);
+  int64_t need = 0;
+  for (int d = 1; d <= p->depth; ++d) need = std::max<int64_t>(need, p->sw[d - 1].ntiles);
+  if (need > p->tile_partials_n) {
+    if (p->tile_partials) (void)hipFree(p->tile_partials);
+    p->tile_partials = nullptr;
+    p->tile_partials_n = 0;
+    hipError_t e = hipMalloc(&p->tile_partials, sizeof(double) * kObsDoubles * need);
+    if (e != hipSuccess) {
+      p->tile_partials = nullptr;
+      return hip_fail(e, "hipMalloc (observables partials)");
+    }
+    p->tile_partials_n = need;
+  }
+  // whole graphs for all but at least one step, which the fused pass takes
+  int64_t done = 0;
+  if (p->use_graph && nsteps - 1 >= 2 * p->graph_pairs) {
+    hipGraphExec_t ex = nullptr;
+    hipError_t e = graph_for(p, psi, V, p->graph_pairs, &ex);
+    if (e != hipSuccess) return hip_fail(e, "graph capture");
+    const int64_t reps = (nsteps - 1) / (2 * p->graph_pairs);
+    for (int64_t r = 0; r < reps; ++r) {
+      e = hipGraphLaunch(ex, st);
+      if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    }
+    done = reps * 2 * p->graph_pairs;
+  }
+  const ObsArgs o = obs_args(p, x_b);
+  void* res = nullptr;
+  int64_t waves = 0;
+  hipError_t e = enqueue_steps(p, psi, V, nsteps - done, st, &res, &o, &waves);
+  if (e != hipSuccess) return hip_fail(e, "sweep launch");
+  if (res != psi) {
+    e = hipMemcpyAsync(psi, res, p->state_bytes, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+  }
+  e = launch_obs_final(p->tile_partials, waves, o, p->hres_dev, st);
+  if (e != hipSuccess) return hip_fail(e, "observables launch");
+  return finish_observables(p, st, out);
 }
 
 extern "C" int dl_plan_set_norm_check(dl_plan p, double N_ref, double tol) {

@@ -15,48 +15,14 @@
 
 #include "../../include/libdirac.h"
 #include "dirac_launch.h"
+#include "dirac_obs.h"
 #include "dirac_plan.h"
 
 namespace dirac {
 
-struct NSum {
-  double s, c;
-};
-
-__device__ __forceinline__ void nadd(NSum& a, double x) {
-  const double t = a.s + x;
-  if (fabs(a.s) >= fabs(x))
-    a.c += (a.s - t) + x;
-  else
-    a.c += (x - t) + a.s;
-  a.s = t;
-}
-
-// merge b into a: two-sum of the sums, compensations added
-__device__ __forceinline__ void nmerge(NSum& a, const NSum& b) {
-  const double t = a.s + b.s;
-  const double bb = t - a.s;
-  const double err = (a.s - (t - bb)) + (b.s - bb);
-  a.c = a.c + b.c + err;
-  a.s = t;
-}
-
-__device__ __forceinline__ NSum shfl_xor(const NSum& v, int m) {
-  NSum r;
-  r.s = __shfl_xor(v.s, m, 64);
-  r.c = __shfl_xor(v.c, m, 64);
-  return r;
-}
-
-constexpr int kQ = 5;  // |psi|^2, x0|psi|^2, x1|psi|^2, x2|psi|^2, [x0 > x_b]|psi|^2
-
 template <int NQ>
 __device__ void block_reduce(NSum (&acc)[NQ], NSum (*lds)[4]) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) {
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) nmerge(acc[q], shfl_xor(acc[q], m));
-  }
+  wave_merge(acc);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if (lane == 0) {
 #pragma unroll
@@ -169,13 +135,14 @@ __global__ __launch_bounds__(256) void k_obs_partial(const T* __restrict__ psi, 
   }
 }
 
-__global__ __launch_bounds__(256) void k_obs_final(const double* __restrict__ partials, int nblk,
-                                                   ObsArgs a, double* __restrict__ out5) {
+__global__ __launch_bounds__(256) void k_obs_final(const double* __restrict__ partials,
+                                                   int64_t nblk, ObsArgs a,
+                                                   double* __restrict__ out5) {
   __shared__ NSum lds[kQ][4];
   NSum acc[kQ];
 #pragma unroll
   for (int q = 0; q < kQ; ++q) acc[q] = NSum{0.0, 0.0};
-  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+  for (int64_t b = threadIdx.x; b < nblk; b += blockDim.x) {
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
       const NSum p{partials[(static_cast<int64_t>(b) * kQ + q) * 2],
@@ -215,7 +182,12 @@ hipError_t launch_observables(bool fp64, const void* psi, const ObsArgs& a, doub
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_obs_final, dim3(1), dim3(256), 0, st, partials, kObsBlocks, a, out5);
+  return launch_obs_final(partials, kObsBlocks, a, out5, st);
+}
+
+hipError_t launch_obs_final(const double* partials, int64_t n, const ObsArgs& a, double* out5,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_obs_final, dim3(1), dim3(256), 0, st, partials, n, a, out5);
   return hipGetLastError();
 }
 

@@ -123,6 +123,22 @@ hipError_t launch_sweep2d(bool fp64, bool strang, int depth, const void* src, vo
   return hipLaunchKernel(fn, dim3(blocks), dim3(256), kargs, 0, st);
 }
 
+hipError_t launch_sweep2d_obs(bool fp64, int depth, const void* src, void* dst, const double* V,
+                              const SweepArgs& a, const ObsArgs& o, double* partials, int blocks,
+                              hipStream_t st) {
+  const void* fn = kernel2d_obs(fp64, depth, a.ph.mode);
+  if (!fn || blocks <= 0 || a.axes_code != 10 || a.nc != 4) return hipErrorInvalidValue;
+  SweepArgs args = a;
+  ObsArgs oargs = o;
+  void* kargs[] = {const_cast<void**>(&src), &dst, const_cast<double**>(&V), &args, &oargs,
+                   &partials};
+  return hipLaunchKernel(fn, dim3(blocks), dim3(256), kargs, 0, st);
+}
+
+bool sweep2d_obs_available(bool fp64, int depth, int mode) {
+  return kernel2d_obs(fp64, depth, mode) != nullptr;
+}
+
 // ---- occupancy queries (resident 256-thread blocks per CU) -------------------
 static int occ_of(const void* kernel) {
   if (!kernel) return 0;

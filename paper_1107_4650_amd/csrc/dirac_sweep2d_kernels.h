@@ -39,6 +39,42 @@ void k_sweep2d(const T* __restrict__ src, T* __restrict__ dst, const double* __r
   }
 }
 
+// K lowest-order steps of a 2-D plane (grid axes 0 and 1, four components),
+// as k_sweep2d, summing the observables of the cells the wave stores (each
+// lane those of its column); the wave's totals (a fixed butterfly over its
+// lanes) go to partials[tile], the Neumaier pairs of the kQ sums, for the
+// final reduction in tile order
+template <typename T, int K, int MODE>
+__global__ __launch_bounds__(256, sweep2d_min_blocks(sizeof(T) == 8, K, K, MODE))
+void k_sweep2d_obs(const T* __restrict__ src, T* __restrict__ dst, const double* __restrict__ V,
+                   SweepArgs a, ObsArgs o, double* __restrict__ partials) {
+  constexpr int X = halo_lanes<LieStep>(K);
+  const int lane = threadIdx.x & 63;
+  int64_t blk = blockIdx.x;
+  if (a.xcd_remap) blk = (blk % 8) * (gridDim.x / 8) + blk / 8;
+  const int64_t tile = blk * 4 + wave_in_block();
+  if (tile >= a.ntiles) return;
+  const int64_t strip = tile % a.nstrips;
+  const int64_t seg = tile / a.nstrips;
+  const int64_t xs = strip * strip_width(X) - X;
+  const int64_t jb = seg * a.H;
+  const int64_t je = (jb + a.H < a.ny) ? jb + a.H : a.ny;
+  NSum acc[kQ];
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) acc[q] = NSum{0.0, 0.0};
+  march_dir<T, LieStep, K, 0, 1, MODE, true>(src, dst, V, a, xs, lane, jb, je, (seg & 1) == 0,
+                                             X, acc, &o);
+  obs_column_close(acc, xs + lane, o);  // lanes that stored nothing hold zeros
+  wave_merge(acc);
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      partials[(tile * kQ + q) * 2 + 0] = acc[q].s;
+      partials[(tile * kQ + q) * 2 + 1] = acc[q].c;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // launchers: the 1-D / 2-D kernel for (type, depth, axes, phase mode)
 // ---------------------------------------------------------------------------
@@ -91,5 +127,7 @@ const void* kernel2d_lie_f32_hi(int depth, int axes_code, int mode, int nc);  //
 const void* kernel2d_lie_f64_lo(int depth, int axes_code, int mode, int nc);
 const void* kernel2d_lie_f64_hi(int depth, int axes_code, int mode, int nc);
 const void* kernel2d_strang(bool fp64, int depth, int axes_code, int mode, int nc);
+// k_sweep2d_obs for (type, depth 1..5, phase mode 0..2), else nullptr
+const void* kernel2d_obs(bool fp64, int depth, int mode);
 
 }  // namespace dirac

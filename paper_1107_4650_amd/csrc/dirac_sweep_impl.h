@@ -15,6 +15,7 @@
 
 #include "dirac_device.h"
 #include "dirac_launch.h"
+#include "dirac_obs.h"
 
 namespace dirac {
 
@@ -215,11 +216,14 @@ template <class S> constexpr int factor_slots(int NS) {
   return last + 2;
 }
 
-template <typename T, class S, int K, int AX0, int AX1, bool UP, int MODE, bool EDGE>
+// OBS: also add the observables of every stored cell to the lane's sums acc
+template <typename T, class S, int K, int AX0, int AX1, bool UP, int MODE, bool EDGE,
+          bool OBS = false>
 __device__ __forceinline__ void march2d(const T* __restrict__ src, T* __restrict__ dst,
                                         const double* __restrict__ V, const SweepArgs& a,
                                         int64_t xs, int lane, int64_t jb, int64_t je,
-                                        int wlane) {
+                                        int wlane, NSum* acc = nullptr,
+                                        const ObsArgs* ob = nullptr) {
   constexpr bool TWO = sizeof(T) == 8;
   constexpr int NS = K * S::kStages;          // stages of the pass
   constexpr int X = halo_lanes<S>(K);         // x transports of the pass
@@ -370,7 +374,10 @@ __device__ __forceinline__ void march2d(const T* __restrict__ src, T* __restrict
         }
         cur = o;
       }
-      if (it >= 2 * NS && own) store_site(dst + (out_row(it, NS) * nx + c.x) * 8, cur);
+      if (it >= 2 * NS && own) {
+        store_site(dst + (out_row(it, NS) * nx + c.x) * 8, cur);
+        if constexpr (OBS) obs_add_cell(acc, cur, out_row(it, NS), *ob);
+      }
       if constexpr (PULSE) {
         // pulse_row repaired far phase arguments itself
       } else if constexpr (FIELD) {
@@ -447,23 +454,28 @@ __device__ __forceinline__ void one_row(const T* __restrict__ src, T* __restrict
 // at every stage and the others (nearly all) one without that work.  FP64
 // marches keep one variant per direction that tests at run time: their code
 // is twice as long and two more variants would crowd the instruction cache.
-template <typename T, class S, int K, int AX0, int AX1, int MODE>
+template <typename T, class S, int K, int AX0, int AX1, int MODE, bool OBS = false>
 __device__ __forceinline__ void march_dir(const T* __restrict__ src, T* __restrict__ dst,
                                           const double* __restrict__ V, const SweepArgs& a,
                                           int64_t xs, int lane, int64_t jb, int64_t je, bool up,
-                                          int wlane) {
+                                          int wlane, NSum* acc = nullptr,
+                                          const ObsArgs* ob = nullptr) {
   // wave-uniform
   const bool edge = sizeof(T) == 8 || !lanes_of(a.nx, a.periodic, xs, 0).full;
   if (edge) {
     if (up)
-      march2d<T, S, K, AX0, AX1, true, MODE, true>(src, dst, V, a, xs, lane, jb, je, wlane);
+      march2d<T, S, K, AX0, AX1, true, MODE, true, OBS>(src, dst, V, a, xs, lane, jb, je,
+                                                        wlane, acc, ob);
     else
-      march2d<T, S, K, AX0, AX1, false, MODE, true>(src, dst, V, a, xs, lane, jb, je, wlane);
+      march2d<T, S, K, AX0, AX1, false, MODE, true, OBS>(src, dst, V, a, xs, lane, jb, je,
+                                                         wlane, acc, ob);
   } else {
     if (up)
-      march2d<T, S, K, AX0, AX1, true, MODE, false>(src, dst, V, a, xs, lane, jb, je, wlane);
+      march2d<T, S, K, AX0, AX1, true, MODE, false, OBS>(src, dst, V, a, xs, lane, jb, je,
+                                                         wlane, acc, ob);
     else
-      march2d<T, S, K, AX0, AX1, false, MODE, false>(src, dst, V, a, xs, lane, jb, je, wlane);
+      march2d<T, S, K, AX0, AX1, false, MODE, false, OBS>(src, dst, V, a, xs, lane, jb, je,
+                                                          wlane, acc, ob);
   }
 }
 

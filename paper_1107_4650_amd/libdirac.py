@@ -29,7 +29,8 @@ DL_DRY, DL_GRAPH, DL_STRANG, DL_BISPINOR = 1, 2, 4, 8
 EXPORTS = ("dl_plan_create", "dl_plan_destroy", "dl_step", "dl_step_field", "dl_step_pulse",
            "dl_step_out",
            "dl_step_fused_out",
-           "dl_observables", "dl_observables_noalloc", "dl_plan_set_norm_check",
+           "dl_observables", "dl_step_observables", "dl_observables_noalloc",
+           "dl_plan_set_norm_check",
            "dl_seed_adjoint",
            "dl_grad_step", "dl_project", "dl_expand", "dl_batch_create", "dl_batch_step",
            "dl_plan_set_tiling", "dl_plan_set_depth", "dl_plan_info", "dl_batch_set",
@@ -87,6 +88,7 @@ def load() -> ctypes.CDLL:
         "dl_step_fused_out": [vp, vp, vp, vp, i64, vp],
         "dl_plan_set_depth": [vp, ci],
         "dl_observables": [vp, vp, dbl, P(dbl), vp],
+        "dl_step_observables": [vp, vp, vp, i64, dbl, P(dbl), vp],
         "dl_plan_set_norm_check": [vp, dbl, dbl],
         "dl_observables_noalloc": [P(Grid), dbl, ci, ctypes.c_uint, vp, dbl, vp, vp],
         "dl_seed_adjoint": [vp, vp, dbl, vp, vp, vp],
@@ -257,9 +259,21 @@ class Plan:
         out = (ctypes.c_double * 5)()
         rc = self.lib.dl_observables(self.handle, self._state(psi), float(x_b), out,
                                      _stream_handle())
+        return self._observables_result(rc, out)
+
+    def step_observables(self, psi, V=None, nsteps=1, x_b=0.0) -> np.ndarray:
+        """step(psi, V, nsteps), then observables(psi, x_b), in one call: on 2-D
+        lowest-order plans the last pass sums the observables as it stores
+        the state (dl_step_observables)."""
+        out = (ctypes.c_double * 5)()
+        rc = self.lib.dl_step_observables(self.handle, self._state(psi), self._cells(V, "V"),
+                                          int(nsteps), float(x_b), out, _stream_handle())
+        return self._observables_result(rc, out)
+
+    def _observables_result(self, rc, out) -> np.ndarray:
         if rc == DL_WARN_NORM:
             import warnings
-            warnings.warn(self.lib.dl_last_error().decode(), NormWarning, stacklevel=2)
+            warnings.warn(self.lib.dl_last_error().decode(), NormWarning, stacklevel=3)
         else:
             check(rc)
         return np.array(out[:])

@@ -1,0 +1,176 @@
+"""dl_step_observables: the steps of dl_step and the observables of the
+stepped state in one call.  On 2-D lowest-order plans the last pass sums the
+observables as it stores the state; the state must keep dl_step's bits and the
+sums must agree with dl_observables (another summation order: 1e-14
+relative) and with the oracle (1e-12 after FP64 steps).  Other plans step and
+then reduce, so their results equal the two calls exactly."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1107_4650_amd import libdirac as L
+from paper_1107_4650_amd.inputs import random_spinor, config_2d_tanh, C_LIGHT
+from tests.gpu_util import announce, rel_l2, same_bits
+
+pytestmark = pytest.mark.gpu
+
+C = C_LIGHT
+DX = 0.01
+DT = DX / C
+
+
+def _close(got, ref, tol):
+    """observables [N, <x>, <y>, <z>, P_T] within tol (relative to N for the
+    sums, absolute in units of the box for the means)"""
+    assert abs(got[0] - ref[0]) <= tol * abs(ref[0])
+    for d in range(3):
+        assert abs(got[1 + d] - ref[1 + d]) <= tol * max(1.0, abs(ref[1 + d])) + 1e-15
+    assert abs(got[4] - ref[4]) <= tol * abs(ref[0])
+
+
+def _both(shape, psi, V, m, nsteps, x_b, *, dtype, bc="zero", depth=None, graph=False,
+          graph_pairs=None, scheme="lie", xmin=None, dt=DT, dx=DX, c=C):
+    """(state, observables) from dl_step_observables, and from dl_step then
+    dl_observables, on the same plan settings"""
+    import torch
+    tdt = torch.complex128 if dtype == "c128" else torch.complex64
+    tV = None if V is None else torch.from_numpy(np.ascontiguousarray(V)).to("cuda")
+    out = []
+    for fused in (True, False):
+        t = torch.from_numpy(np.ascontiguousarray(psi)).to("cuda").to(tdt).contiguous()
+        with L.Plan(shape, dx, dt, c, m, dtype=dtype, bc=bc, graph=graph, scheme=scheme,
+                    xmin=xmin) as p:
+            if graph_pairs is not None:
+                p.set_tiling(graph_pairs=graph_pairs)
+            if depth is not None:
+                p.set_depth(depth)
+            if fused:
+                obs = p.step_observables(t, tV, nsteps, x_b)
+            else:
+                p.step(t, tV, nsteps)
+                obs = p.observables(t, x_b)
+            torch.cuda.synchronize()
+        out.append((t.cpu().numpy(), obs))
+    return out
+
+
+@pytest.mark.parametrize("shape", [(150, 97), (300, 131), (64, 16)])
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("bc", ["zero", "periodic"])
+@pytest.mark.parametrize("nsteps", [1, 7, 12])
+def test_fused_matches_step_then_observables(shape, dtype, bc, nsteps):
+    announce(f"step_observables {shape} {dtype} {bc} n={nsteps}")
+    psi = random_spinor(shape[::-1], seed=sum(shape) + nsteps)
+    rng = np.random.default_rng(nsteps)
+    V = rng.uniform(-3, 3, size=shape[::-1]) * C * C
+    (s_f, o_f), (s_s, o_s) = _both(shape, psi, V, 1.0, nsteps, 0.137, dtype=dtype, bc=bc)
+    assert same_bits(s_f, s_s)
+    _close(o_f, o_s, 1e-14)
+
+
+@pytest.mark.parametrize("mode", ["streaming", "mass", "potential"])
+@pytest.mark.parametrize("depth", [1, 3, 5])
+def test_fused_phase_modes_and_depths(mode, depth):
+    announce(f"step_observables mode={mode} depth={depth}")
+    shape = (200, 77)
+    psi = random_spinor(shape[::-1], seed=depth)
+    V = np.random.default_rng(5).uniform(-2, 2, size=shape[::-1]) * C * C
+    m = 0.0 if mode == "streaming" else 1.0
+    Vm = V if mode == "potential" else None
+    for dtype in ("c64", "c128"):
+        (s_f, o_f), (s_s, o_s) = _both(shape, psi, Vm, m, 2 * depth + 1, -0.2, dtype=dtype,
+                                       depth=depth)
+        assert same_bits(s_f, s_s)
+        _close(o_f, o_s, 1e-14)
+
+
+def test_fused_vs_oracle():
+    """FP64 state and its observables against the oracle's steps and
+    sequential Neumaier sums."""
+    announce("step_observables vs oracle")
+    shape = (180, 75)
+    psi = random_spinor(shape[::-1], seed=11)
+    V = np.random.default_rng(2).uniform(-3, 3, size=shape[::-1]) * C * C
+    xmin = [-0.5 * n * DX for n in shape]
+    nsteps, x_b = 23, 0.05
+    ref_state = O.step(psi, V, dt=DT, c=C, m=1.0, nsteps=nsteps, axes=(0, 1))
+    ref = O.observables(ref_state, dx=DX, xmin=xmin, x_b=x_b)
+    (s_f, o_f), _ = _both(shape, psi, V, 1.0, nsteps, x_b, dtype="c128", xmin=xmin)
+    assert rel_l2(s_f, ref_state) <= 1e-12
+    _close(o_f, ref, 1e-12)
+    (s32, o32), _ = _both(shape, psi.astype(np.complex64), V, 1.0, nsteps, x_b, dtype="c64",
+                          xmin=xmin)
+    assert rel_l2(s32, ref_state) <= 5e-6
+    _close(o32, ref, 1e-5)
+
+
+def test_fused_after_graph_replays():
+    """Steps replayed from captured graphs, the last one in the fused pass."""
+    announce("step_observables graph")
+    shape = (128, 90)
+    psi = random_spinor(shape[::-1], seed=3)
+    V = np.random.default_rng(4).uniform(-1, 1, size=shape[::-1]) * C * C
+    for nsteps in (9, 8, 25):
+        (s_f, o_f), (s_s, o_s) = _both(shape, psi, V, 1.0, nsteps, 0.0, dtype="c64",
+                                       graph=True, graph_pairs=2)
+        assert same_bits(s_f, s_s)
+        _close(o_f, o_s, 1e-14)
+
+
+@pytest.mark.parametrize("case", ["1d", "3d", "strang", "zero_steps", "axes_xz"])
+def test_unfused_plans_equal_the_two_calls(case):
+    """Plans without a fused pass step and then reduce: the same bits and the
+    same observables as the two calls."""
+    announce(f"step_observables fallback {case}")
+    shape, nsteps, dt, scheme = {
+        "1d": ((777,), 9, DT, "lie"),
+        "3d": ((40, 21, 19), 3, DT, "lie"),
+        "strang": ((90, 70), 4, 2 * DT, "strang"),
+        "zero_steps": ((150, 97), 0, DT, "lie"),
+        "axes_xz": ((90, 70), 5, DT, "lie"),
+    }[case]
+    psi = random_spinor(shape[::-1], seed=len(shape))
+    V = np.random.default_rng(1).uniform(-1, 1, size=shape[::-1]) * C * C
+    if case == "axes_xz":
+        import torch
+        outs = []
+        for fused in (True, False):
+            t = torch.from_numpy(psi).to("cuda")
+            tV = torch.from_numpy(V).to("cuda")
+            with L.Plan(shape, DX, dt, C, 1.0, dtype="c128", axes=(0, 2)) as p:
+                if fused:
+                    o = p.step_observables(t, tV, nsteps, 0.1)
+                else:
+                    p.step(t, tV, nsteps)
+                    o = p.observables(t, 0.1)
+            outs.append((t.cpu().numpy(), o))
+        (s_f, o_f), (s_s, o_s) = outs
+    else:
+        (s_f, o_f), (s_s, o_s) = _both(shape, psi, V, 1.0, nsteps, 0.1, dtype="c128", dt=dt,
+                                       scheme=scheme)
+    assert same_bits(s_f, s_s)
+    assert np.array_equal(o_f, o_s)
+
+
+def test_fused_reports_a_nonfinite_state():
+    import torch
+    announce("step_observables NaN")
+    shape = (100, 70)
+    psi = random_spinor(shape[::-1], seed=9)
+    psi[33, 41, 2] = np.nan
+    t = torch.from_numpy(psi).to("cuda")
+    with L.Plan(shape, DX, DT, C, 1.0, dtype="c128") as p:
+        with pytest.raises(L.DiracError) as e:
+            p.step_observables(t, None, 5, 0.0)
+        assert e.value.code == L.DL_ERR_NONFINITE
+
+
+def test_fused_at_full_size():
+    """The 2048 x 2048 FP32 workload at its launch configuration (passes of
+    five steps): fused vs separate, state bits and sums."""
+    w = config_2d_tanh(n=2048, nsteps=10)
+    announce("step_observables 2048^2")
+    (s_f, o_f), (s_s, o_s) = _both(w.shape, w.psi0.astype(np.complex64), w.V, w.m, 10, 0.0,
+                                   dtype="c64", xmin=w.xmin, dt=w.dt, dx=w.dx, c=w.c)
+    assert same_bits(s_f, s_s)
+    _close(o_f, o_s, 1e-14)
