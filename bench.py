@@ -15,6 +15,7 @@ adjoint).
   python bench.py --calibrate-copy            # a plain copy of known size
   python bench.py --only klein                # the paper's 2-D Klein run alone
   python bench.py --only 3d                   # the 3-D 512^3 runs alone
+  python bench.py --only observables          # the observables calls alone (2048^2 FP32)
 """
 from __future__ import annotations
 
@@ -788,7 +789,8 @@ def main():
                     help="steps of the 3-D FP32-vs-FP64 check (0 skips it)")
     ap.add_argument("--klein-steps", type=int, default=12000,
                     help="steps of the paper's 2-D Klein run (0 skips it)")
-    ap.add_argument("--only", choices=["all", "sweep", "main", "klein", "3d"], default="all")
+    ap.add_argument("--only", choices=["all", "sweep", "main", "klein", "3d", "observables"],
+                    default="all")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
     args = ap.parse_args()
@@ -806,6 +808,9 @@ def main():
         return
     if args.only == "3d":
         print(json.dumps(bench_3d(args)), flush=True)
+        return
+    if args.only == "observables":
+        print(json.dumps(bench_observables()), flush=True)
         return
     line = bench_main(args)
     if line is None:
