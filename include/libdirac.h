@@ -31,7 +31,12 @@
  *    on it and the call returns without waiting, except where noted.
  *    Kernel faults surface at the next synchronising call as DL_ERR_HIP.
  *  - A plan owns its scratch (a second state buffer, reduction partials),
- *    allocated in dl_plan_create.  One plan must not be used from two
+ *    allocated in dl_plan_create.  Steps run in passes over memory that
+ *    alternate between psi and that buffer; a call that takes an odd number
+ *    of passes ends in the buffer and copies the result back into psi, except
+ *    that for three or more passes the plan allocates (once, on the first
+ *    such call outside stream capture) a third state buffer through which
+ *    the last pass writes psi directly.  One plan must not be used from two
  *    streams or threads at once.
  *  - psi and lam must be 16-byte aligned, V, Q and G 8-byte aligned.
  *  - The plan, step, observables, adjoint and batch calls each open a named
@@ -124,8 +129,9 @@ int dl_plan_destroy(dl_plan p);
  * then D).  V: potential energy per cell (FP64) or NULL for V = 0.  With m = 0
  * and V = NULL the step is pure streaming and D is skipped.
  * In the complex64 plan the state is stored in FP32 while the phase
- * exp(-i theta) is formed from the FP64 V and applied in FP64, then rounded
- * once to FP32.  nsteps = 0 is a no-op. */
+ * exp(-i theta) is formed in FP64 from the FP64 V and applied as an FP32
+ * hi + lo pair (1-D, 2-D) or in FP64 (3-D), the product rounded to FP32.
+ * nsteps = 0 is a no-op. */
 int dl_step(dl_plan p, void *psi, const double *V, int64_t nsteps, void *stream);
 /* (Several steps are fused into one pass over memory: up to 5 on 1-D and
  * 2-D grids, fewer on periodic 2-D boxes of fewer than twice that many rows,

@@ -63,6 +63,8 @@ struct dl_plan_s {
   // scratch
   void* tmp = nullptr;         // second state buffer
   void* tmp2 = nullptr;        // second state buffer for the adjoint field
+  void* alt = nullptr;         // third state buffer (odd pass counts end in psi)
+  bool alt_failed = false;     // its allocation failed once: keep copying back
   double* partials = nullptr;  // reduction partials
   double* dres = nullptr;      // device results
   double* hres = nullptr;      // pinned host results (mapped)

@@ -379,6 +379,7 @@ extern "C" int dl_plan_destroy(dl_plan p) {
     if (p->dres) (void)hipFree(p->dres);
     if (p->hres) (void)hipHostFree(p->hres);
     if (p->tile_partials) (void)hipFree(p->tile_partials);
+    if (p->alt) (void)hipFree(p->alt);
     (void)hipGetLastError();
   }
   delete p;
@@ -446,30 +447,65 @@ static hipError_t launch_pass_obs(dl_plan p, int depth, const void* src, void* d
                             p->bl[depth - 1], st);
 }
 
-// enqueue `nsteps` steps ping-ponging between psi and the plan's tmp buffer,
-// starting from psi, in passes of the plan's depth (the remainder in
-// shallower passes); returns the buffer that holds the result.  With `obs`,
-// the last pass also sums the observables (launch_pass_obs; `obs_waves`
-// receives the number of partials it writes).
+// passes of `nsteps` steps at the plan's current depth (deepest first)
+static int64_t pass_count(dl_plan p, int64_t nsteps) {
+  const int dmax = (p->ph.mode >= 3) ? p->depth_field : p->depth;
+  int64_t n = 0, left = nsteps;
+  for (int d = dmax; d >= 1; --d) {
+    n += left / d;
+    left %= d;
+  }
+  return n;
+}
+
+// The plan's third state buffer: with it, an odd number (>= 3) of passes
+// ends in psi (psi -> tmp -> alt -> tmp ... -> psi) instead of in tmp with a
+// copy back.  Allocated once, by the first call that needs it, and never
+// while the stream is being captured; without it the copy stays.
+static void want_alt(dl_plan p, int64_t nsteps, hipStream_t st) {
+  if (p->alt || p->alt_failed) return;
+  const int64_t n = pass_count(p, nsteps);
+  if (n < 3 || n % 2 == 0) return;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+    (void)hipGetLastError();
+    return;
+  }
+  if (hipMalloc(&p->alt, p->state_bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    p->alt = nullptr;
+    p->alt_failed = true;
+  }
+}
+
+// enqueue `nsteps` steps starting from psi, in passes of the plan's depth
+// (the remainder in shallower passes), alternating between psi and the plan's
+// tmp buffer, or, for an odd number (>= 3) of passes when the plan holds its
+// third buffer, through tmp and that buffer so that the last pass writes psi;
+// returns the buffer that holds the result.  With `obs`, the last pass also
+// sums the observables (launch_pass_obs; `obs_waves` receives the number of
+// partials it writes).
 hipError_t enqueue_steps(dl_plan p, void* psi, const double* V, int64_t nsteps, hipStream_t st,
                          void** result, const ObsArgs* obs = nullptr,
                          int64_t* obs_waves = nullptr) {
-  void* a = psi;
-  void* b = p->tmp;
-  int64_t left = nsteps;
+  want_alt(p, nsteps, st);
+  const int64_t passes = pass_count(p, nsteps);
+  void* third = (passes >= 3 && passes % 2 == 1) ? p->alt : nullptr;
+  void* in = psi;
+  int64_t i = 0, left = nsteps;
   const int dmax = (p->ph.mode >= 3) ? p->depth_field : p->depth;
   for (int d = dmax; d >= 1; --d) {
-    for (; left >= d; left -= d) {
-      hipError_t e = (obs && left == d) ? launch_pass_obs(p, d, a, b, V, *obs, st, obs_waves)
-                                        : launch_pass(p, d, a, b, V, st);
+    for (; left >= d; left -= d, ++i) {
+      void* out = third ? ((i == passes - 1) ? psi : (i % 2 == 0 ? p->tmp : third))
+                        : (in == psi ? p->tmp : psi);
+      hipError_t e = (obs && left == d) ? launch_pass_obs(p, d, in, out, V, *obs, st, obs_waves)
+                                        : launch_pass(p, d, in, out, V, st);
       if (e != hipSuccess) return e;
       p->pulse.n0 += d;  // the pulse's step index of the next pass
-      void* t = a;
-      a = b;
-      b = t;
+      in = out;
     }
   }
-  *result = a;
+  *result = in;
   return hipSuccess;
 }
 
@@ -496,6 +532,7 @@ static hipError_t graph_for(dl_plan p, void* psi, const double* V, int64_t pairs
     hipError_t e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) return e;
   }
+  want_alt(p, 2 * pairs, p->cap_stream);  // before the capture begins
   hipGraph_t graph = nullptr;
   hipError_t e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return e;
