@@ -484,12 +484,13 @@ def bench_3d(args):
             continue
         strang = dt_name.endswith("second_order")
         if strang:
-            # c dt = 4 dx: one pass per step plus one per group, four times the time per step
+            # c dt = 4 dx: one pass per step plus a closing one per call, four times
+            # the time per step
             with L.Plan((n, n, n), dx, 4 * dx / c, c, m, dtype="complex64", scheme="strang") as p:
-                K = p.info()["depth"]  # steps per launch sequence: K + 1 passes
+                K = p.info()["depth"]
                 wall, per, _, done = timed_sweep(p, psi, V, max(K, min(steps, 20)), K, fused=K)
             out[dt_name] = {"steps": done, "ms_per_step": wall * 1e3 / done,
-                            "steps_per_group": K, "passes_per_group": K + 1,
+                            "steps_per_call": done, "passes_per_call": done + 1,
                             "dt_over_lowest_order_dt": 4,
                             "site_updates_per_s": n ** 3 * done / wall}
             log(f"3-D 512^3 {dt_name}: {wall * 1e3 / done:.3f} ms/step (c dt = 4 dx)")

@@ -89,9 +89,11 @@ typedef enum { DL_BC_ZERO = 0, DL_BC_PERIODIC = 1 } dl_bc;
                         one-cell shift, so the plan needs c*dt = 2*dx.  3-D
                         grids: A(dt/4) B(dt/2) A(dt/4) C(dt/2) D(dt) C(dt/2)
                         A(dt/4) B(dt/2) A(dt/4) with c*dt = 4*dx: A shifts one
-                        cell, B and C two (K + 1 passes over memory per group
-                        of K steps, one extra state buffer in the plan).  DL_ERR_CFL on any
-                        other c*dt.  The adjoint entry points refuse such a
+                        cell, B and C two (a call of N steps takes N + 1
+                        passes over memory, in place through two scratch
+                        states of the plan, one of them an extra buffer; with
+                        dl_plan_set_depth(K < 5) groups of K steps take K + 1
+                        passes each).  DL_ERR_CFL on any other c*dt.  The adjoint entry points refuse such a
                         plan (DL_ERR_ARG). */
 #define DL_BISPINOR 8u /* two-component state, 1-D grids only (Sec. 2.4): with
                         one transport axis the pair of components that contains
@@ -136,8 +138,9 @@ int dl_step(dl_plan p, void *psi, const double *V, int64_t nsteps, void *stream)
 /* (Several steps are fused into one pass over memory: up to 5 on 1-D and
  * 2-D grids, fewer on periodic 2-D boxes of fewer than twice that many rows,
  * and 2 on 3-D grids with rows of fewer than 2^28 cells; the remainder of
- * nsteps runs in shallower passes.  The bits do not depend on this grouping;
- * dl_plan_set_depth caps it.) */
+ * nsteps runs in shallower passes.  Second-order steps on 3-D grids take one
+ * pass each plus one closing pass per call (see DL_STRANG).  The bits do not
+ * depend on this grouping; dl_plan_set_depth caps it.) */
 
 /* dl_step with a vector potential in the local step (eq:sol_dis_4 and the
  * closed-form exponential of Dirac matrices of Sec. 2.3):
@@ -329,8 +332,10 @@ int dl_plan_set_tiling(dl_plan p, int waves_per_cu, int seg_len, int allow_resid
  * passes (dl_step and friends) and reverse passes (dl_grad_step) use at most
  * this many steps, and never more than the kernels are built for (2-D and
  * 1-D: 5; 3-D: 2; second-order steps: 2; vector potential: 3,
- * second-order 1; reverse steps: 3, complex128 2).  The bits are independent of
- * the grouping.  DL_ERR_ARG outside 1..5. */
+ * second-order 1; reverse steps: 3, complex128 2).  On 3-D second-order
+ * plans a cap below 5 groups the steps of a call by that many, each group
+ * with its own closing pass.  The bits are independent of the grouping.
+ * DL_ERR_ARG outside 1..5. */
 int dl_plan_set_depth(dl_plan p, int depth);
 
 /* Up to n values describing the deepest forward pass in use, written to the

@@ -112,10 +112,11 @@ int sweep_occupancy(bool fp64, bool strang, int ndim, int axes_code, int mode, i
 // the same for the 3-D kernels
 int occupancy3d(bool fp64, int mode, int depth);
 // nsteps >= 1 second-order steps src -> dst on a 3-D grid (Sec. 2.4) in
-// 2 nsteps + 1 passes, through `mid` (a state buffer distinct from src and
-// dst); a needs nx, ny, nz, periodic and ph
-hipError_t launch_strang3d(bool fp64, const void* src, void* dst, void* mid, const double* V,
-                           const SweepArgs& a, int64_t nsteps, hipStream_t st);
+// nsteps + 1 passes through `mid` and `mid2` (state buffers distinct from src,
+// dst and each other; src == dst is allowed), or, with mid2 = NULL, through
+// mid and dst (src != dst); a needs nx, ny, nz, periodic and ph
+hipError_t launch_strang3d(bool fp64, const void* src, void* dst, void* mid, void* mid2,
+                           const double* V, const SweepArgs& a, int64_t nsteps, hipStream_t st);
 // nsteps in place in one workgroup of `threads` threads, `spt` cells each
 hipError_t launch_resident1d(bool fp64, int axis, void* psi, const double* V,
                              const ResidentArgs& a, int spt, int threads, hipStream_t st);

@@ -417,7 +417,7 @@ hipError_t launch_pass(dl_plan p, int depth, const void* src, void* dst, const d
     a.pulse = p->pulse;
     a.pulse_on = p->pulse_on ? 1 : 0;
     a.cells = p->cells;
-    if (p->strang) return launch_strang3d(p->fp64, src, dst, p->tmp2, V, a, depth, st);
+    if (p->strang) return launch_strang3d(p->fp64, src, dst, p->tmp2, nullptr, V, a, depth, st);
     return launch_sweep3d(p->fp64, depth, src, dst, V, a, p->bl[depth - 1], st);
   }
   SweepArgs a = p->sw[depth - 1];
@@ -464,6 +464,7 @@ static int64_t pass_count(dl_plan p, int64_t nsteps) {
 // while the stream is being captured; without it the copy stays.
 static void want_alt(dl_plan p, int64_t nsteps, hipStream_t st) {
   if (p->alt || p->alt_failed) return;
+  if (p->g.ndim == 3 && p->strang) return;  // second-order 3-D groups end in psi by themselves
   const int64_t n = pass_count(p, nsteps);
   if (n < 3 || n % 2 == 0) return;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -488,6 +489,22 @@ static void want_alt(dl_plan p, int64_t nsteps, hipStream_t st) {
 hipError_t enqueue_steps(dl_plan p, void* psi, const double* V, int64_t nsteps, hipStream_t st,
                          void** result, const ObsArgs* obs = nullptr,
                          int64_t* obs_waves = nullptr) {
+  if (p->g.ndim == 3 && p->strang && p->depth_limit >= kMaxDepth && nsteps > 0 && !obs) {
+    // second-order 3-D steps: the whole call is one group, nsteps + 1 passes
+    // in place through the plan's two scratch states (a cap on the depth
+    // keeps groups of that many steps instead)
+    SweepArgs a = p->sw[0];
+    a.ph = p->ph;
+    a.At = p->field;
+    a.pulse = p->pulse;
+    a.pulse_on = p->pulse_on ? 1 : 0;
+    a.cells = p->cells;
+    hipError_t e = launch_strang3d(p->fp64, psi, psi, p->tmp2, p->tmp, V, a, nsteps, st);
+    if (e != hipSuccess) return e;
+    p->pulse.n0 += nsteps;
+    *result = psi;
+    return hipSuccess;
+  }
   want_alt(p, nsteps, st);
   const int64_t passes = pass_count(p, nsteps);
   void* third = (passes >= 3 && passes % 2 == 1) ? p->alt : nullptr;

@@ -756,11 +756,12 @@ static int64_t strang_step_grid(const SweepArgs& a, SweepArgs& t) {
 }
 
 template <typename T>
-static hipError_t strang3d_t(const void* src, void* dst, void* mid, const double* V,
+static hipError_t strang3d_t(const void* src, void* dst, void* mid, void* mid2, const double* V,
                              const SweepArgs& a, int64_t nsteps, hipStream_t st) {
   const T* s = static_cast<const T*>(src);
   T* d = static_cast<T*>(dst);
   T* m = static_cast<T*>(mid);
+  T* m2 = mid2 ? static_cast<T*>(mid2) : d;  // the step passes alternate between m and m2
   auto plane_grid = [&](int width, SweepArgs& t) {
     t = a;
     t.nstrips = (a.nx + width - 1) / width;
@@ -775,7 +776,9 @@ static hipError_t strang3d_t(const void* src, void* dst, void* mid, const double
   const int mode = a.ph.mode;
   // A B A + C D C, then per further step the closing A B A of one step and the
   // opening one of the next + C D C, and a closing A B A: nsteps + 1 passes.
-  // The first pass writes the buffer that makes the last one land in `mid`.
+  // The first pass writes the buffer that makes the last one land in `mid`;
+  // src is only read by the first pass and dst only written by the last, so
+  // with a second scratch state (mid2) src and dst may be the same buffer.
   auto step_pass = [&](bool first_pass, int64_t step, const T* in, T* out) {
     SweepArgs t = first_pass ? first : next;
     t.pulse.n0 += step;  // the pulse's step index of this pass's D
@@ -796,8 +799,8 @@ static hipError_t strang3d_t(const void* src, void* dst, void* mid, const double
       }
     }
   };
-  T* cur = (nsteps % 2 == 1) ? m : d;
-  T* other = (cur == m) ? d : m;
+  T* cur = (nsteps % 2 == 1) ? m : m2;
+  T* other = (cur == m) ? m2 : m;
   step_pass(true, 0, s, cur);
   for (int64_t n = 1; n < nsteps; ++n) {
     step_pass(false, n, cur, other);
@@ -811,11 +814,12 @@ static hipError_t strang3d_t(const void* src, void* dst, void* mid, const double
   return hipGetLastError();
 }
 
-hipError_t launch_strang3d(bool fp64, const void* src, void* dst, void* mid, const double* V,
-                           const SweepArgs& a, int64_t nsteps, hipStream_t st) {
+hipError_t launch_strang3d(bool fp64, const void* src, void* dst, void* mid, void* mid2,
+                           const double* V, const SweepArgs& a, int64_t nsteps, hipStream_t st) {
   if (nsteps < 1) return hipErrorInvalidValue;
-  return fp64 ? strang3d_t<double>(src, dst, mid, V, a, nsteps, st)
-              : strang3d_t<float>(src, dst, mid, V, a, nsteps, st);
+  if (!mid2 && src == dst) return hipErrorInvalidValue;
+  return fp64 ? strang3d_t<double>(src, dst, mid, mid2, V, a, nsteps, st)
+              : strang3d_t<float>(src, dst, mid, mid2, V, a, nsteps, st);
 }
 
 // ---- 3-D kernels: one step, or a pass of two fused steps ---------------------

@@ -131,14 +131,15 @@ def test_strang3d_long_march_segments_vs_oracle(bc):
 def test_strang3d_grouped_steps_same_bits(shape, bc):
     """Steps grouped so that consecutive A B A share a pass give the bits of
     single steps (two passes each), for counts that are and are not
-    multiples of the group."""
+    multiples of the group; at the full depth a call is one group, run in
+    place through the plan's two scratch states."""
     announce(f"strang 3-D grouped {shape} {bc}")
     psi = random_spinor(shape[::-1], seed=8)
     V = np.random.default_rng(9).uniform(-2, 2, size=shape[::-1]) * C * C
     kw = dict(dx=DX, dt=DT3, c=C, m=1.0, axes=(0, 1, 2), bc=bc, scheme="strang")
     for dtype in ("c64", "c128"):
         p0 = psi.astype(np.complex64) if dtype == "c64" else psi
-        for n in (2, 3, 7):
+        for n in (2, 3, 7, 12):
             single = gpu_step(p0, V, nsteps=n, depth=1, dtype=dtype, **kw)
             for depth in (2, 5):
                 assert same_bits(single, gpu_step(p0, V, nsteps=n, depth=depth, dtype=dtype,
