@@ -207,6 +207,7 @@ template <> struct MarchShape<LieStep, 4> { static constexpr int L = 1, U = 10; 
 template <> struct MarchShape<LieStep, 5> { static constexpr int L = 2, U = 6; };
 template <> struct MarchShape<StrangStep, 1> { static constexpr int L = 3, U = 4; };
 template <> struct MarchShape<StrangStep, 2> { static constexpr int L = 3, U = 4; };
+template <> struct MarchShape<StrangStep, 3> { static constexpr int L = 1, U = 6; };
 
 // factor slots: rows from the newest read to the oldest still to be phased
 template <class S> constexpr int factor_slots(int NS) {
