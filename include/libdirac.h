@@ -331,7 +331,7 @@ int dl_plan_set_tiling(dl_plan p, int waves_per_cu, int seg_len, int allow_resid
 /* Cap on the steps fused into one pass over memory, depth in 1..5: forward
  * passes (dl_step and friends) and reverse passes (dl_grad_step) use at most
  * this many steps, and never more than the kernels are built for (2-D and
- * 1-D: 5; 3-D: 2; second-order steps: 3, complex128 2; vector potential: 3,
+ * 1-D: 5; 3-D: 2; second-order steps: 3; vector potential: 3,
  * second-order 1; reverse steps: 3, complex128 2).  On 3-D second-order
  * plans a cap below 5 groups the steps of a call by that many, each group
  * with its own closing pass.  The bits are independent of the grouping.

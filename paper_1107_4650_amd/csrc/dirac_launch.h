@@ -18,7 +18,7 @@ constexpr int kTY3D2_F64 = 4;
 __host__ __device__ constexpr int max_depth3d(bool) { return 2; }
 constexpr int64_t kMaxRow3DFused = int64_t(1) << 28;
 // 1-D / 2-D passes fuse up to kMaxDepth full lowest-order steps, or up to 3
-// second-order steps (2 with FP64 state).  A wave of 64 lanes writes 64 - 2X columns, X
+// second-order steps.  A wave of 64 lanes writes 64 - 2X columns, X
 // being the x transports of the pass (one per lowest-order step, two per
 // second-order step).  FP64 passes of more than two stages need more
 // registers than two waves per SIMD have: they run one wave per SIMD, the
@@ -26,7 +26,7 @@ constexpr int64_t kMaxRow3DFused = int64_t(1) << 28;
 constexpr int kMaxDepth = 5;
 constexpr int kMaxDepthF64 = 5;
 __host__ __device__ constexpr int max_depth(bool fp64, bool strang) {
-  return strang ? (fp64 ? 2 : 3) : (fp64 ? kMaxDepthF64 : kMaxDepth);
+  return strang ? 3 : (fp64 ? kMaxDepthF64 : kMaxDepth);
 }
 // resident 256-thread blocks per CU the 1-D / 2-D kernel is compiled for, by
 // the steps and stages (steps x stages per step) of its pass and its phase

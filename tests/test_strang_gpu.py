@@ -59,7 +59,7 @@ def test_strang_fused_passes_same_bits(shape, axes, bc, dtype):
               tiling={"allow_resident": False})
     for n in (1, 2, 3, 7, 8):
         single = gpu_step(psi, V, nsteps=n, depth=1, **kw)
-        for depth in (2, 3):  # three-step passes with FP32 state (capped at 2 with FP64)
+        for depth in (2, 3):
             assert same_bits(single, gpu_step(psi, V, nsteps=n, depth=depth, **kw)), (n, depth)
 
 
