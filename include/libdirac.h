@@ -136,7 +136,10 @@ int dl_plan_destroy(dl_plan p);
  * nsteps = 0 is a no-op. */
 int dl_step(dl_plan p, void *psi, const double *V, int64_t nsteps, void *stream);
 /* (Several steps are fused into one pass over memory: up to 5 on 1-D and
- * 2-D grids, fewer on periodic 2-D boxes of fewer than twice that many rows,
+ * 2-D grids (1-D lines of at most 65536 cells without a vector potential
+ * first run passes of 24 steps, each wave writing 16 cells, unless the depth
+ * is capped), fewer on
+ * periodic 2-D boxes of fewer than twice that many rows,
  * and 2 on 3-D grids with rows of fewer than 2^28 cells; the remainder of
  * nsteps runs in shallower passes.  Second-order steps on 3-D grids take one
  * pass each plus one closing pass per call (see DL_STRANG).  The bits do not
@@ -344,7 +347,9 @@ int dl_plan_set_depth(dl_plan p, int depth);
  * [7] waves_per_cu setting, [8] XCD-contiguous block order (0/1),
  * [9] graph_pairs, [10] fused steps per pass, [11] workgroups of a
  * single-step pass, [12] reverse steps per pass of dl_grad_step, [13] steps
- * per pass of dl_step_field.  Works on DL_DRY plans.  On a batch handle every
+ * per pass of dl_step_field, [14] steps per pass of the deep passes that 1-D
+ * lines run first (0 if the plan has none).  Works on DL_DRY plans.  On a
+ * batch handle every
  * value is 0 but [10], the steps fused per pass of the batch, [14] the
  * instances run whole by the lines kernel, [15] its workgroups (0 on a dry
  * batch) and [16] their threads. */

@@ -18,7 +18,7 @@ BUILD_DIR = os.path.join(ROOT, "_build")
 SOURCES = ["dirac_sweep2d_f32_hi.hip", "dirac_sweep2d_f64_hi.hip", "dirac_sweep2d_f32_lo.hip",
            "dirac_sweep2d_f64_lo.hip", "dirac_sweep2d_strang.hip", "dirac_batch.hip",
            "dirac_sweep3d.hip", "dirac_adjoint.hip", "dirac_plan.hip", "dirac_sweep.hip",
-           "dirac_reduce.hip", "dirac_sweep2d_obs.hip"]
+           "dirac_reduce.hip", "dirac_sweep2d_obs.hip", "dirac_sweep1d_deep.hip"]
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 ROCM_LIB = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -25,6 +25,13 @@ constexpr int64_t kMaxRow3DFused = int64_t(1) << 28;
 // compiler parking part of the working set in the accumulation registers.
 constexpr int kMaxDepth = 5;
 constexpr int kMaxDepthF64 = 5;
+// 1-D lines of at most kDeep1DMaxCells cells without a vector potential also
+// run passes of kDeep1D lowest-order steps (each wave writes 64 - 2 kDeep1D =
+// 16 cells): such a line's pass is short next to a kernel launch, so fewer,
+// deeper passes win, while on longer lines the fourfold arithmetic of the
+// deep pass costs more than the launches it saves
+constexpr int kDeep1D = 24;
+constexpr int64_t kDeep1DMaxCells = 65536;
 __host__ __device__ constexpr int max_depth(bool fp64, bool strang) {
   return strang ? 3 : (fp64 ? kMaxDepthF64 : kMaxDepth);
 }
@@ -101,6 +108,10 @@ hipError_t launch_sweep2d_obs(bool fp64, int depth, const void* src, void* dst, 
                               hipStream_t st);
 // true if launch_sweep2d_obs has a kernel for this depth and phase mode
 bool sweep2d_obs_available(bool fp64, int depth, int mode);
+// kDeep1D lowest-order steps src -> dst in one pass over a 1-D line (phase
+// modes 0-2; tiling made for strip_width(kDeep1D))
+hipError_t launch_sweep1d_deep(bool fp64, const void* src, void* dst, const double* V,
+                               const SweepArgs& a, int blocks, hipStream_t st);
 // `depth` (1 or 2) full steps src -> dst in one pass over a 3-D grid (tiling
 // made by the 3-D tiler for that depth)
 hipError_t launch_sweep3d(bool fp64, int depth, const void* src, void* dst, const double* V,

@@ -13,6 +13,8 @@ namespace dirac {
 struct PlanTiling {
   SweepArgs a[kMaxDepth]{};  // index depth - 1 (3-D grids: depth 1 only)
   int b[kMaxDepth] = {};     // blocks
+  SweepArgs deep{};          // 1-D lines: passes of kDeep1D steps
+  int deep_b = 0;
 };
 
 struct GraphEntry {
@@ -44,6 +46,8 @@ struct dl_plan_s {
   // for the phase mode of the current call
   dirac::SweepArgs sw[dirac::kMaxDepth]{};
   int bl[dirac::kMaxDepth] = {};
+  dirac::SweepArgs sw_deep{};  // 1-D lines: passes of kDeep1D steps
+  int bl_deep = 0;
   int depth_limit = dirac::kMaxDepth;  // caller's cap on fused steps per pass
   int depth = 1;                        // fused steps per pass in use
   int waves_per_cu = 0;        // 0: size the grid from the kernels' occupancy

@@ -208,6 +208,8 @@ static void select_tiling(dl_plan p, int mode) {
     p->sw[d] = t.a[d];
     p->bl[d] = t.b[d];
   }
+  p->sw_deep = t.deep;
+  p->bl_deep = t.deep_b;
 }
 
 // waves that can be resident at once for the sweep kernel of this plan
@@ -262,6 +264,11 @@ static int plan_tiling(dl_plan p) {
       for (int d = 1; d <= (mode >= 3 ? p->depth_field : depth); ++d)
         make_tiling(p->g, resident_waves(p, mode, d), p->seg_override, t.a[d - 1], t.b[d - 1],
                     strip_width(pass_xlanes(p->strang, d)));
+      if (p->g.ndim == 1 && !p->strang && mode <= 2 && p->g.n[0] <= kDeep1DMaxCells) {
+        make_tiling(p->g, resident_waves(p, mode, 1), p->seg_override, t.deep, t.deep_b,
+                    strip_width(kDeep1D));
+        t.deep.periodic = (p->bc == DL_BC_PERIODIC);
+      }
     }
     for (int d = 0; d < kMaxDepth; ++d) t.a[d].periodic = (p->bc == DL_BC_PERIODIC);
   }
@@ -447,10 +454,34 @@ static hipError_t launch_pass_obs(dl_plan p, int depth, const void* src, void* d
                             p->bl[depth - 1], st);
 }
 
+// 1-D lines of lowest-order steps without a vector potential (and no cap on
+// the depth) run passes of kDeep1D steps first
+static bool deep1d(dl_plan p) {
+  return p->g.ndim == 1 && !p->strang && p->ph.mode <= 2 && p->depth_limit >= kMaxDepth &&
+         p->bl_deep > 0;
+}
+
+// one pass of kDeep1D steps src -> dst on a 1-D line
+static hipError_t launch_pass_deep(dl_plan p, const void* src, void* dst, const double* V,
+                                   hipStream_t st) {
+  SweepArgs a = p->sw_deep;
+  a.ph = p->ph;
+  a.At = nullptr;
+  a.pulse = p->pulse;
+  a.pulse_on = 0;
+  a.cells = p->cells;
+  a.nc = p->nc;
+  return launch_sweep1d_deep(p->fp64, src, dst, V, a, p->bl_deep, st);
+}
+
 // passes of `nsteps` steps at the plan's current depth (deepest first)
 static int64_t pass_count(dl_plan p, int64_t nsteps) {
   const int dmax = (p->ph.mode >= 3) ? p->depth_field : p->depth;
   int64_t n = 0, left = nsteps;
+  if (deep1d(p)) {
+    n += left / kDeep1D;
+    left %= kDeep1D;
+  }
   for (int d = dmax; d >= 1; --d) {
     n += left / d;
     left %= d;
@@ -510,6 +541,16 @@ hipError_t enqueue_steps(dl_plan p, void* psi, const double* V, int64_t nsteps, 
   void* third = (passes >= 3 && passes % 2 == 1) ? p->alt : nullptr;
   void* in = psi;
   int64_t i = 0, left = nsteps;
+  if (deep1d(p)) {
+    for (; left >= kDeep1D; left -= kDeep1D, ++i) {
+      void* out = third ? ((i == passes - 1) ? psi : (i % 2 == 0 ? p->tmp : third))
+                        : (in == psi ? p->tmp : psi);
+      hipError_t e = launch_pass_deep(p, in, out, V, st);
+      if (e != hipSuccess) return e;
+      p->pulse.n0 += kDeep1D;
+      in = out;
+    }
+  }
   const int dmax = (p->ph.mode >= 3) ? p->depth_field : p->depth;
   for (int d = dmax; d >= 1; --d) {
     for (; left >= d; left -= d, ++i) {
@@ -924,7 +965,9 @@ extern "C" int dl_plan_info(dl_plan p, int64_t* info, int n) {
   const int64_t vals[] = {p->bl[p->depth - 1], t.H,          t.nseg,         t.nstrips,
                           t.ntiles,            p->resident,  p->res_threads, p->waves_per_cu,
                           t.xcd_remap,         p->graph_pairs, p->depth,     p->bl[0],
-                          reverse_depth(p),    p->depth_field};
+                          reverse_depth(p),    p->depth_field,
+                          (p->g.ndim == 1 && !p->strang && p->depth_limit >= kMaxDepth &&
+                           p->bl_deep > 0) ? kDeep1D : 0};
   const int nv = static_cast<int>(sizeof vals / sizeof vals[0]);
   for (int i = 0; i < n && i < nv; ++i) info[i] = vals[i];
   return DL_OK;

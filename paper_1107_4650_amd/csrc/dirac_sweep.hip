@@ -135,6 +135,15 @@ hipError_t launch_sweep2d_obs(bool fp64, int depth, const void* src, void* dst, 
   return hipLaunchKernel(fn, dim3(blocks), dim3(256), kargs, 0, st);
 }
 
+hipError_t launch_sweep1d_deep(bool fp64, const void* src, void* dst, const double* V,
+                               const SweepArgs& a, int blocks, hipStream_t st) {
+  const void* fn = kernel1d_deep(fp64, a.axes_code, a.ph.mode, a.nc);
+  if (!fn || blocks <= 0) return hipErrorInvalidValue;
+  SweepArgs args = a;
+  void* kargs[] = {const_cast<void**>(&src), &dst, const_cast<double**>(&V), &args};
+  return hipLaunchKernel(fn, dim3(blocks), dim3(256), kargs, 0, st);
+}
+
 bool sweep2d_obs_available(bool fp64, int depth, int mode) {
   return kernel2d_obs(fp64, depth, mode) != nullptr;
 }

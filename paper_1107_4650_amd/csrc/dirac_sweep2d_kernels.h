@@ -129,5 +129,8 @@ const void* kernel2d_lie_f64_hi(int depth, int axes_code, int mode, int nc);
 const void* kernel2d_strang(bool fp64, int depth, int axes_code, int mode, int nc);
 // k_sweep2d_obs for (type, depth 1..5, phase mode 0..2), else nullptr
 const void* kernel2d_obs(bool fp64, int depth, int mode);
+// the 1-D pass of kDeep1D lowest-order steps for (type, axis, phase mode
+// 0..2, stored components), else nullptr
+const void* kernel1d_deep(bool fp64, int axis, int mode, int nc);
 
 }  // namespace dirac

@@ -327,11 +327,11 @@ class Plan:
                                           int(bool(allow_resident)), int(graph_pairs)))
 
     def info(self) -> dict:
-        buf = (ctypes.c_int64 * 14)()
-        check(self.lib.dl_plan_info(self.handle, buf, 14))
+        buf = (ctypes.c_int64 * 15)()
+        check(self.lib.dl_plan_info(self.handle, buf, 15))
         keys = ("blocks", "seg_len", "nseg", "nstrips", "ntiles", "resident", "res_threads",
                 "waves_per_cu", "xcd_remap", "graph_pairs", "depth", "blocks_1", "reverse_depth",
-                "field_depth")
+                "field_depth", "deep_1d_depth")
         return dict(zip(keys, buf[:]))
 
     def close(self):

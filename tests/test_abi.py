@@ -147,6 +147,21 @@ def test_dry_3d_pass_depth(lib):
     p.close()
 
 
+def test_dry_deep_1d_passes(lib):
+    """1-D lowest-order plans run passes of 24 steps first; second-order
+    plans, plans on more axes and a depth cap have none."""
+    assert dry((777,)).info()["deep_1d_depth"] == 24
+    assert dry((777,), dtype="c128", bc="periodic").info()["deep_1d_depth"] == 24
+    assert dry((777,), dt=2 * 0.01 / C, scheme="strang").info()["deep_1d_depth"] == 0
+    assert dry((64, 30)).info()["deep_1d_depth"] == 0
+    assert dry((65536,)).info()["deep_1d_depth"] == 24
+    assert dry((65537,)).info()["deep_1d_depth"] == 0  # long lines: passes of up to 5
+    p = dry((777,))
+    p.set_depth(3)
+    assert p.info()["deep_1d_depth"] == 0
+    p.close()
+
+
 def test_dry_resident_choice(lib):
     """1-D lines of up to 4096 cells run on the one-workgroup kernel only when
     the plan fuses at most two steps per pass."""
