@@ -232,7 +232,7 @@ static int plan_tiling(dl_plan p) {
   int depth = 1;
   if (p->g.ndim == 3) {
     if (p->strang)
-      depth = p->depth_limit;  // steps grouped per call of the second-order passes
+      depth = p->depth_limit;  // second-order groups: a capped depth, else the whole call
     else if (p->g.n[0] < kMaxRow3DFused)
       depth = std::min(p->depth_limit, max_depth3d(p->fp64));
   } else {

@@ -79,7 +79,7 @@ def test_strang_klein_setup_small():
     assert rel_l2(got32, ref) <= 2e-5
 
 
-# ---- 3-D second-order steps: c dt = 4 dx, K + 1 passes per group of K steps ------
+# ---- 3-D second-order steps: c dt = 4 dx, N + 1 passes for a call of N steps -----
 DT3 = 4 * DX / C
 SHAPES3 = [(37, 21, 13), (64, 8, 9), (70, 13, 11), (2, 3, 5)]
 
