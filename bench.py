@@ -511,6 +511,26 @@ def bench_3d(args):
         log(f"3-D 512^3 {dt_name}: {per:.3f} ms/launch of {K} step(s)")
         del psi
         torch.cuda.empty_cache()
+    # two steps and the observables: two calls, or one whose two-step pass sums
+    # the observables as it stores the state
+    f = (gz[:, None, None] * gy[None, :, None] * gx[None, None, :])
+    psi = (f[..., None] * u).to(torch.complex64).contiguous()
+    del f
+    with L.Plan((n, n, n), dx, dx / c, c, m, dtype="complex64") as p:
+        def per_call(fn, reps=5):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            return (time.perf_counter() - t0) * 1e3 / reps
+        out["f32_step2_observables"] = {
+            "two_calls_ms": per_call(lambda: (p.step(psi, V, 2), p.observables(psi, 0.0))),
+            "fused_ms": per_call(lambda: p.step_observables(psi, V, 2, 0.0)),
+            "observables_alone_ms": per_call(lambda: p.observables(psi, 0.0))}
+    log(f"3-D 512^3 two steps + observables: {out['f32_step2_observables']}")
+    del psi
+    torch.cuda.empty_cache()
     if args.accuracy3d_steps > 0:
         out["f32_vs_f64"] = accuracy_3d(n, dx, c, m, gx, gy, gz, u, V, args.accuracy3d_steps)
     return out

@@ -221,12 +221,14 @@ int dl_observables(dl_plan p, const void *psi, double x_b, double out[5], void *
  * definitions and status codes of dl_observables; the sums are taken in
  * another order, so they agree with dl_observables' to rounding, ~1e-15
  * relative).  On 2-D lowest-order plans of four-component states on grid
- * axes (x, y) (phase modes without a vector potential) the last pass sums the
- * observables of the cells as it stores them (Sec. 5.2.1 R/T integrals taken
- * in the epilogue of the last step), so the state is not read again; other
- * plans, and nsteps = 0, step and then reduce.  The first fused call (and one
- * after a retiling that adds waves) allocates the plan's per-wave partials
- * (80 B per wave of the pass).  Synchronises `stream`. */
+ * axes (x, y), and on 3-D lowest-order plans whose passes fuse two steps
+ * (then nsteps >= 2; an odd count runs its single step first), without a
+ * vector potential, the last pass sums the observables of the cells as it
+ * stores them (Sec. 5.2.1 R/T integrals taken in the epilogue of the last
+ * step), so the state is not read again; other plans, and nsteps = 0, step
+ * and then reduce.  The first fused call (and one after a retiling that adds
+ * waves) allocates the plan's per-wave partials (80 B per wave of the pass).
+ * Synchronises `stream`. */
 int dl_step_observables(dl_plan p, void *psi, const double *V, int64_t nsteps, double x_b,
                         double out[5], void *stream);
 

@@ -112,6 +112,12 @@ bool sweep2d_obs_available(bool fp64, int depth, int mode);
 // modes 0-2; tiling made for strip_width(kDeep1D))
 hipError_t launch_sweep1d_deep(bool fp64, const void* src, void* dst, const double* V,
                                const SweepArgs& a, int blocks, hipStream_t st);
+// the two-step 3-D pass (phase modes 0-2) that also sums the observables of
+// the cells it stores: 10 doubles per wave (4 per workgroup tile, a.ntiles
+// tiles) at `partials`, reduced by launch_obs_final
+hipError_t launch_sweep3d_obs(bool fp64, const void* src, void* dst, const double* V,
+                              const SweepArgs& a, const ObsArgs& o, double* partials, int blocks,
+                              hipStream_t st);
 // `depth` (1 or 2) full steps src -> dst in one pass over a 3-D grid (tiling
 // made by the 3-D tiler for that depth)
 hipError_t launch_sweep3d(bool fp64, int depth, const void* src, void* dst, const double* V,

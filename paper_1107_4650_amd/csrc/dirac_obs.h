@@ -78,6 +78,16 @@ __device__ __forceinline__ void obs_add_cell(NSum* acc, const Site<T>& s, int64_
   nadd(acc[2], (o.xmin1 + (static_cast<double>(row) + 0.5) * o.dx) * rho);
 }
 
+// the same for a stored cell of a 3-D grid: |psi|^2, y |psi|^2, z |psi|^2
+template <typename T>
+__device__ __forceinline__ void obs_add_cell3(NSum* acc, const Site<T>& s, int64_t row,
+                                              int64_t plane, const ObsArgs& o) {
+  const double rho = cell_density(s);
+  nadd(acc[0], rho);
+  nadd(acc[2], (o.xmin1 + (static_cast<double>(row) + 0.5) * o.dx) * rho);
+  nadd(acc[3], (o.xmin2 + (static_cast<double>(plane) + 0.5) * o.dx) * rho);
+}
+
 // x (s + c) as a pair: the product's rounding error (exact, by fma) joins the
 // compensation
 __device__ __forceinline__ NSum nscale(const NSum& a, double x) {

@@ -437,11 +437,23 @@ hipError_t launch_pass(dl_plan p, int depth, const void* src, void* dst, const d
   return launch_sweep2d(p->fp64, p->strang, depth, src, dst, V, a, p->bl[depth - 1], st);
 }
 
-// the last pass of a dl_step_observables call: a 2-D lowest-order pass that
-// also leaves the observables sums of every wave in p->tile_partials
+// the last pass of a dl_step_observables call: a lowest-order pass (2-D, or
+// the two-step 3-D pass) that also leaves the observables sums of every wave
+// in p->tile_partials
 static hipError_t launch_pass_obs(dl_plan p, int depth, const void* src, void* dst,
                                   const double* V, const ObsArgs& o, hipStream_t st,
                                   int64_t* waves) {
+  if (p->g.ndim == 3) {
+    if (depth != 2) return hipErrorInvalidValue;
+    SweepArgs a = p->sw[1];
+    a.ph = p->ph;
+    a.At = nullptr;
+    a.pulse = p->pulse;
+    a.pulse_on = 0;
+    a.cells = p->cells;
+    *waves = a.ntiles * 4;  // four waves per workgroup tile
+    return launch_sweep3d_obs(p->fp64, src, dst, V, a, o, p->tile_partials, p->bl[1], st);
+  }
   SweepArgs a = p->sw[depth - 1];
   a.ph = p->ph;
   a.At = nullptr;
@@ -541,6 +553,18 @@ hipError_t enqueue_steps(dl_plan p, void* psi, const double* V, int64_t nsteps, 
   void* third = (passes >= 3 && passes % 2 == 1) ? p->alt : nullptr;
   void* in = psi;
   int64_t i = 0, left = nsteps;
+  if (obs && p->g.ndim == 3 && p->depth == 2 && left % 2 == 1 && left > 1) {
+    // the single step first, so that the last pass is a two-step one, the
+    // pass that sums the observables
+    void* out = third ? ((i == passes - 1) ? psi : (i % 2 == 0 ? p->tmp : third))
+                      : (in == psi ? p->tmp : psi);
+    hipError_t e = launch_pass(p, 1, in, out, V, st);
+    if (e != hipSuccess) return e;
+    p->pulse.n0 += 1;
+    in = out;
+    ++i;
+    --left;
+  }
   if (deep1d(p)) {
     for (; left >= kDeep1D; left -= kDeep1D, ++i) {
       void* out = third ? ((i == passes - 1) ? psi : (i % 2 == 0 ? p->tmp : third))
@@ -865,9 +889,12 @@ extern "C" int dl_step_observables(dl_plan p, void* psi, const double* V, int64_
   if (std::isnan(x_b)) return fail(DL_ERR_ARG, "x_b is NaN");
   const int mode = phase_mode(p->m, V);
   // the fused last pass exists for 2-D lowest-order plans of four-component
-  // states on grid axes (x, y); every other plan steps, then reduces
-  const bool fused = nsteps > 0 && p->g.ndim == 2 && !p->strang && p->nc == 4 &&
-                     axes_code(p->g) == 10 && mode <= 2;
+  // states on grid axes (x, y) and for 3-D lowest-order plans of two-step
+  // passes (then at least two steps); every other plan steps, then reduces
+  const bool fused2 = nsteps > 0 && p->g.ndim == 2 && !p->strang && p->nc == 4 &&
+                      axes_code(p->g) == 10 && mode <= 2;
+  const bool fused3 = nsteps > 1 && p->g.ndim == 3 && !p->strang && p->depth == 2 && mode <= 2;
+  const bool fused = fused2 || fused3;
   if (!fused) {
     rc = dl_step(p, psi, V, nsteps, stream);
     if (rc) return rc;
@@ -877,11 +904,15 @@ extern "C" int dl_step_observables(dl_plan p, void* psi, const double* V, int64_
   p->ph = make_phase(transports_per_step(p), p->dt, p->c, p->m, mode, p->fp64);
   p->field = nullptr;
   select_tiling(p, mode);
-  for (int d = 1; d <= p->depth; ++d)
-    if (!sweep2d_obs_available(p->fp64, d, mode))
-      return fail(DL_ERR_STATE, "no fused observables pass of depth %d", d);
+  if (fused2)
+    for (int d = 1; d <= p->depth; ++d)
+      if (!sweep2d_obs_available(p->fp64, d, mode))
+        return fail(DL_ERR_STATE, "no fused observables pass of depth %d", d);
   int64_t need = 0;
-  for (int d = 1; d <= p->depth; ++d) need = std::max<int64_t>(need, p->sw[d - 1].ntiles);
+  if (fused3)
+    need = p->sw[1].ntiles * 4;
+  else
+    for (int d = 1; d <= p->depth; ++d) need = std::max<int64_t>(need, p->sw[d - 1].ntiles);
   if (need > p->tile_partials_n) {
     if (p->tile_partials) (void)hipFree(p->tile_partials);
     p->tile_partials = nullptr;
@@ -893,13 +924,15 @@ extern "C" int dl_step_observables(dl_plan p, void* psi, const double* V, int64_
     }
     p->tile_partials_n = need;
   }
-  // whole graphs for all but at least one step, which the fused pass takes
+  // whole graphs for all but the steps of the fused pass (at least one step,
+  // two on 3-D grids)
   int64_t done = 0;
-  if (p->use_graph && nsteps - 1 >= 2 * p->graph_pairs) {
+  const int64_t keep = fused3 ? 2 : 1;
+  if (p->use_graph && nsteps - keep >= 2 * p->graph_pairs) {
     hipGraphExec_t ex = nullptr;
     hipError_t e = graph_for(p, psi, V, p->graph_pairs, &ex);
     if (e != hipSuccess) return hip_fail(e, "graph capture");
-    const int64_t reps = (nsteps - 1) / (2 * p->graph_pairs);
+    const int64_t reps = (nsteps - keep) / (2 * p->graph_pairs);
     for (int64_t r = 0; r < reps; ++r) {
       e = hipGraphLaunch(ex, st);
       if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");

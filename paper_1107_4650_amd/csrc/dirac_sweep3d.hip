@@ -7,6 +7,7 @@
 // (60 output columns, two halo rows in y and two halo planes in z).
 #include "dirac_device.h"
 #include "dirac_launch.h"
+#include "dirac_obs.h"
 #include "dirac_sweep_impl.h"
 
 namespace dirac {
@@ -201,11 +202,13 @@ template <typename T> struct alignas(16) X2Lds {
   Mov<T> r2[S::NS - 2][64], l2[S::NS - 2][64];
 };
 
-template <typename T, bool UP, int MODE, bool EDGE>
+// OBS: also add the observables of every stored cell to the lane's sums acc
+template <typename T, bool UP, int MODE, bool EDGE, bool OBS = false>
 __device__ __forceinline__ void march3d_x2(const T* __restrict__ src, T* __restrict__ dst,
                                            const double* __restrict__ V, const SweepArgs& a,
                                            X2Lds<T>& sh, int lane, int wv, int64_t xs,
-                                           int64_t y0, int64_t kb, int64_t ke) {
+                                           int64_t y0, int64_t kb, int64_t ke,
+                                           NSum* acc = nullptr, const ObsArgs* ob = nullptr) {
   using S = X2Tile<T>;
   constexpr bool TWO = sizeof(T) == 8;
   constexpr int K = 2, TW = S::TW, NI = S::NI, N1 = S::N1, NS = S::NS;
@@ -347,8 +350,10 @@ __device__ __forceinline__ void march3d_x2(const T* __restrict__ src, T* __restr
         zm2[k][j] = UP ? rz2 : lz2;
         apply_local<MODE>(o2, fc[j], a.ph);
         const int64_t y = y0 + w;
-        if (it >= 2 * K && own && y < ny)
+        if (it >= 2 * K && own && y < ny) {
           store_site(dst + (k2 * ny + y) * nx * 8 + cell_off, o2);
+          if constexpr (OBS) obs_add_cell3(acc, o2, y, k2, *ob);
+        }
         fc[j] = fnew[j];
       }
     }
@@ -388,6 +393,59 @@ __global__ __launch_bounds__(256, 2) void k_sweep3d_x2(const T* __restrict__ src
       march3d_x2<T, false, MODE, false>(src, dst, V, a, sh, lane, wv, xs, y0, kb, ke);
     else
       march3d_x2<T, true, MODE, false>(src, dst, V, a, sh, lane, wv, xs, y0, kb, ke);
+  }
+}
+
+// The two-step pass that also sums the observables of the cells it stores:
+// each wave's totals (every lane's column sums, merged in a fixed butterfly)
+// go to partials[blk * 4 + wave], for the final reduction in that order
+template <typename T, int MODE>
+__global__ __launch_bounds__(256, 2) void k_sweep3d_x2_obs(const T* __restrict__ src,
+                                                           T* __restrict__ dst,
+                                                           const double* __restrict__ V,
+                                                           SweepArgs a, ObsArgs o,
+                                                           double* __restrict__ partials) {
+  __shared__ X2Lds<T> sh;
+  const int lane = threadIdx.x & 63;
+  const int wv = wave_in_block();
+  int64_t blk = blockIdx.x;
+  if (a.xcd_remap) blk = (blk % 8) * (gridDim.x / 8) + blk / 8;
+  if (blk >= a.ntiles) return;  // the whole workgroup
+  const int64_t yblk = blk % a.nyblk;
+  const int64_t rest = blk / a.nyblk;
+  const int64_t strip = rest % a.nstrips;
+  const int64_t seg = rest / a.nstrips;
+  const int64_t xs = strip * strip_width(2) - 2, y0 = yblk * X2Tile<T>::WY;
+  const int64_t kb = seg * a.H;
+  const int64_t ke = (kb + a.H < a.nz) ? kb + a.H : a.nz;
+  NSum acc[kQ];
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) acc[q] = NSum{0.0, 0.0};
+  const bool edge = !lanes_of(a.nx, a.periodic, xs, 0).full;
+  if (edge) {
+    if (seg & 1)
+      march3d_x2<T, false, MODE, true, true>(src, dst, V, a, sh, lane, wv, xs, y0, kb, ke, acc,
+                                             &o);
+    else
+      march3d_x2<T, true, MODE, true, true>(src, dst, V, a, sh, lane, wv, xs, y0, kb, ke, acc,
+                                            &o);
+  } else {
+    if (seg & 1)
+      march3d_x2<T, false, MODE, false, true>(src, dst, V, a, sh, lane, wv, xs, y0, kb, ke, acc,
+                                              &o);
+    else
+      march3d_x2<T, true, MODE, false, true>(src, dst, V, a, sh, lane, wv, xs, y0, kb, ke, acc,
+                                             &o);
+  }
+  obs_column_close(acc, xs + lane, o);  // lanes that stored nothing hold zeros
+  wave_merge(acc);
+  if (lane == 0) {
+    const int64_t w = blk * 4 + wv;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      partials[(w * kQ + q) * 2 + 0] = acc[q].s;
+      partials[(w * kQ + q) * 2 + 1] = acc[q].c;
+    }
   }
 }
 
@@ -858,6 +916,28 @@ static int occ_of(const void* kernel) {
 int occupancy3d(bool fp64, int mode, int depth) {
   const int m = mode < 0 || mode > 3 ? 2 : mode;
   return occ_of(fp64 ? kernel3d<double>(depth, m) : kernel3d<float>(depth, m));
+}
+
+template <typename T>
+static const void* kernel3d_obs(int mode) {
+  switch (mode) {
+    case 0: return reinterpret_cast<const void*>(&k_sweep3d_x2_obs<T, 0>);
+    case 1: return reinterpret_cast<const void*>(&k_sweep3d_x2_obs<T, 1>);
+    case 2: return reinterpret_cast<const void*>(&k_sweep3d_x2_obs<T, 2>);
+    default: return nullptr;
+  }
+}
+
+hipError_t launch_sweep3d_obs(bool fp64, const void* src, void* dst, const double* V,
+                              const SweepArgs& a, const ObsArgs& o, double* partials, int blocks,
+                              hipStream_t st) {
+  const void* fn = fp64 ? kernel3d_obs<double>(a.ph.mode) : kernel3d_obs<float>(a.ph.mode);
+  if (!fn || blocks <= 0) return hipErrorInvalidValue;
+  SweepArgs args = a;
+  ObsArgs oargs = o;
+  void* kargs[] = {const_cast<void**>(&src), &dst, const_cast<double**>(&V), &args, &oargs,
+                   &partials};
+  return hipLaunchKernel(fn, dim3(blocks), dim3(256), kargs, 0, st);
 }
 
 hipError_t launch_sweep3d(bool fp64, int depth, const void* src, void* dst, const double* V,

@@ -1,9 +1,10 @@
 """dl_step_observables: the steps of dl_step and the observables of the
-stepped state in one call.  On 2-D lowest-order plans the last pass sums the
-observables as it stores the state; the state must keep dl_step's bits and the
-sums must agree with dl_observables (another summation order: 1e-14
-relative) and with the oracle (1e-12 after FP64 steps).  Other plans step and
-then reduce, so their results equal the two calls exactly."""
+stepped state in one call.  On 2-D lowest-order plans, and on 3-D ones with
+two-step passes, the last pass sums the observables as it stores the state;
+the state must keep dl_step's bits and the sums must agree with
+dl_observables (another summation order: 1e-14 relative) and with the oracle
+(1e-12 after FP64 steps).  Other plans step and then reduce, so their results
+equal the two calls exactly."""
 import numpy as np
 import pytest
 
@@ -117,14 +118,16 @@ def test_fused_after_graph_replays():
         _close(o_f, o_s, 1e-14)
 
 
-@pytest.mark.parametrize("case", ["1d", "3d", "strang", "zero_steps", "axes_xz"])
+@pytest.mark.parametrize("case", ["1d", "3d_one_step", "strang", "strang3d", "zero_steps",
+                                  "axes_xz"])
 def test_unfused_plans_equal_the_two_calls(case):
     """Plans without a fused pass step and then reduce: the same bits and the
     same observables as the two calls."""
     announce(f"step_observables fallback {case}")
     shape, nsteps, dt, scheme = {
         "1d": ((777,), 9, DT, "lie"),
-        "3d": ((40, 21, 19), 3, DT, "lie"),
+        "3d_one_step": ((40, 21, 19), 1, DT, "lie"),
+        "strang3d": ((24, 14, 12), 3, 4 * DT, "strang"),
         "strang": ((90, 70), 4, 2 * DT, "strang"),
         "zero_steps": ((150, 97), 0, DT, "lie"),
         "axes_xz": ((90, 70), 5, DT, "lie"),
@@ -150,6 +153,40 @@ def test_unfused_plans_equal_the_two_calls(case):
                                        scheme=scheme)
     assert same_bits(s_f, s_s)
     assert np.array_equal(o_f, o_s)
+
+
+@pytest.mark.parametrize("shape,bc", [((40, 21, 19), "zero"), ((64, 9, 10), "periodic"),
+                                      ((130, 17, 11), "zero")])
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("nsteps", [2, 3, 6])
+def test_fused_3d_matches_step_then_observables(shape, bc, dtype, nsteps):
+    """3-D plans: the two-step pass sums the observables (an odd count runs
+    its single step first)."""
+    announce(f"step_observables 3-D {shape} {bc} {dtype} n={nsteps}")
+    psi = random_spinor(shape[::-1], seed=nsteps + len(shape))
+    V = np.random.default_rng(nsteps).uniform(-2, 2, size=shape[::-1]) * C * C
+    (s_f, o_f), (s_s, o_s) = _both(shape, psi, V, 1.0, nsteps, -0.03, dtype=dtype, bc=bc)
+    assert same_bits(s_f, s_s)
+    _close(o_f, o_s, 1e-14)
+
+
+def test_fused_3d_vs_oracle_and_graphs():
+    announce("step_observables 3-D vs oracle, graphs")
+    shape = (30, 17, 13)
+    psi = random_spinor(shape[::-1], seed=21)
+    V = np.random.default_rng(22).uniform(-2, 2, size=shape[::-1]) * C * C
+    xmin = [-0.5 * n * DX for n in shape]
+    ref_state = O.step(psi, V, dt=DT, c=C, m=1.0, nsteps=5, axes=(0, 1, 2))
+    ref = O.observables(ref_state, dx=DX, xmin=xmin, x_b=0.02)
+    (s_f, o_f), _ = _both(shape, psi, V, 1.0, 5, 0.02, dtype="c128", xmin=xmin)
+    assert rel_l2(s_f, ref_state) <= 1e-12
+    _close(o_f, ref, 1e-12)
+    # graph replays of two steps, then the eager passes (single, then fused)
+    for nsteps in (7, 8):
+        (s_f, o_f), (s_s, o_s) = _both(shape, psi, V, 1.0, nsteps, 0.0, dtype="c64",
+                                       graph=True, graph_pairs=1)
+        assert same_bits(s_f, s_s)
+        _close(o_f, o_s, 1e-14)
 
 
 def test_fused_reports_a_nonfinite_state():
