@@ -126,3 +126,37 @@ def test_norm_watchdog():
         assert 0.3 * N0 < N1 < 0.7 * N0
         with pytest.warns(L.NormWarning):
             p.observables(psi * float(np.sqrt(2.0 * N0 / N1)))
+
+
+def test_step_observables_refusals_and_watchdog():
+    """dl_step_observables refuses what dl_step and dl_observables refuse
+    (before enqueueing anything) and reports the norm watchdog from its fused
+    pass as dl_observables does."""
+    import torch
+    import warnings
+    announce("errors: step_observables")
+    lib = L.load()
+    shape = (64, 48)
+    with _plan(shape, "c128", bc="periodic") as p:
+        psi = torch.from_numpy(random_spinor(shape[::-1], seed=7)).to("cuda")
+        keep = psi.clone()
+        st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        out = (ctypes.c_double * 5)()
+        ptr = ctypes.c_void_p(psi.data_ptr())
+        assert lib.dl_step_observables(p.handle, ptr, None, -1, 0.0, out, st) == L.DL_ERR_ARG
+        assert lib.dl_step_observables(p.handle, ptr, None, 3, 0.0, None, st) == L.DL_ERR_ARG
+        assert lib.dl_step_observables(p.handle, ptr, None, 3, float("nan"), out,
+                                       st) == L.DL_ERR_ARG
+        assert lib.dl_step_observables(p.handle, ctypes.c_void_p(psi.data_ptr() + 8), None, 3,
+                                       0.0, out, st) == L.DL_ERR_ALIGN
+        torch.cuda.synchronize()
+        assert torch.equal(psi, keep)  # nothing ran
+        N0 = p.observables(psi)[0]
+        p.set_norm_check(N0, 1e-12)
+        with warnings.catch_warnings():
+            warnings.simplefilter("error")
+            N1 = p.step_observables(psi, None, 9, 0.0)[0]
+        assert abs(N1 - N0) <= 1e-12 * N0
+        p.set_norm_check(N0 * (1.0 + 1e-6), 1e-9)  # the periodic norm now reads as fallen
+        with pytest.warns(L.NormWarning):
+            p.step_observables(psi, None, 5, 0.0)
