@@ -12,7 +12,7 @@ constexpr int kTY3D_F32 = 4;  // y rows per wave in the 3-D plane tile
 constexpr int kTY3D_F64 = 2;
 // two-step 3-D pass: y rows of a workgroup tile (four waves; FP32, FP64 state)
 constexpr int kTY3D2_F32 = 8;
-constexpr int kTY3D2_F64 = 4;
+constexpr int kTY3D2_F64 = 8;
 // 3-D passes fuse at most two lowest-order steps, on rows of fewer than 2^28
 // cells (per-lane offsets are 32-bit)
 __host__ __device__ constexpr int max_depth3d(bool) { return 2; }

@@ -163,8 +163,8 @@ __global__ __launch_bounds__(256) void k_sweep3d(const T* __restrict__ src, T* _
 
 // ---------------------------------------------------------------------------
 // 3-D pass of two fused steps (temporal blocking).  A workgroup of four waves
-// holds 64 x columns (writing the middle 60) and WY = 4 TW y rows (TW output
-// rows per wave) and marches along z.  Each plane iteration shares the work
+// holds 64 x columns (writing the middle 60) and WY = 4 TW y rows (TW = 2
+// output rows per wave, WY = 8) and marches along z.  Each plane iteration shares the work
 // of the tile's rows among the waves through LDS, so no row is transported
 // twice:
 //  1. each wave reads TW + 1 of the WY + 4 input rows of the plane (two halo
@@ -360,11 +360,11 @@ __device__ __forceinline__ void march3d_x2(const T* __restrict__ src, T* __restr
   }
 }
 
+// FP32 state: two waves per SIMD; FP64 state (8-row tiles, two rows per
+// wave): one, with the accumulation registers holding the rest
 template <typename T, int MODE>
-__global__ __launch_bounds__(256, 2) void k_sweep3d_x2(const T* __restrict__ src,
-                                                       T* __restrict__ dst,
-                                                       const double* __restrict__ V,
-                                                       SweepArgs a) {
+__global__ __launch_bounds__(256, sizeof(T) == 8 ? 1 : 2) void k_sweep3d_x2(
+    const T* __restrict__ src, T* __restrict__ dst, const double* __restrict__ V, SweepArgs a) {
   __shared__ X2Lds<T> sh;
   const int lane = threadIdx.x & 63;
   const int wv = wave_in_block();
@@ -400,11 +400,9 @@ __global__ __launch_bounds__(256, 2) void k_sweep3d_x2(const T* __restrict__ src
 // each wave's totals (every lane's column sums, merged in a fixed butterfly)
 // go to partials[blk * 4 + wave], for the final reduction in that order
 template <typename T, int MODE>
-__global__ __launch_bounds__(256, 2) void k_sweep3d_x2_obs(const T* __restrict__ src,
-                                                           T* __restrict__ dst,
-                                                           const double* __restrict__ V,
-                                                           SweepArgs a, ObsArgs o,
-                                                           double* __restrict__ partials) {
+__global__ __launch_bounds__(256, sizeof(T) == 8 ? 1 : 2) void k_sweep3d_x2_obs(
+    const T* __restrict__ src, T* __restrict__ dst, const double* __restrict__ V, SweepArgs a,
+    ObsArgs o, double* __restrict__ partials) {
   __shared__ X2Lds<T> sh;
   const int lane = threadIdx.x & 63;
   const int wv = wave_in_block();

@@ -114,8 +114,8 @@ def test_dry_strang_plans(lib):
 
 def test_dry_3d_pass_depth(lib):
     """3-D plans fuse two steps per pass (workgroup tiles write 60 columns of
-    8 rows with FP32 state, 4 with FP64); rows of 2^28 cells or more and a
-    depth cap of one keep single steps."""
+    8 rows); rows of 2^28 cells or more and a depth cap of one keep single
+    steps."""
     p = dry((64, 30, 16))
     info = p.info()
     assert info["depth"] == 2 and info["nstrips"] == 2
@@ -126,7 +126,7 @@ def test_dry_3d_pass_depth(lib):
     p = dry((64, 30, 16), dtype="c128")
     info = p.info()
     assert info["depth"] == 2 and info["nstrips"] == 2
-    assert info["ntiles"] == 2 * 8 * info["nseg"]  # tiles of 4 rows with FP64 state
+    assert info["ntiles"] == 2 * 4 * info["nseg"]  # tiles of 8 rows with FP64 state too
     p.close()
     assert dry((64, 30)).info()["reverse_depth"] == 3
     assert dry((64, 30), dtype="c128").info()["reverse_depth"] == 2
