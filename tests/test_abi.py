@@ -147,6 +147,21 @@ def test_dry_3d_pass_depth(lib):
     p.close()
 
 
+def test_dry_second_order_depths(lib):
+    """Second-order 1-D / 2-D passes fuse up to three steps (both state types),
+    fewer on periodic boxes of few rows; 3-D second-order plans group a call's
+    steps."""
+    for dtype in ("c64", "c128"):
+        assert dry((64, 30), dt=2 * 0.01 / C, scheme="strang", dtype=dtype).info()["depth"] == 3
+        assert dry((300,), dt=2 * 0.01 / C, scheme="strang", dtype=dtype).info()["depth"] == 3
+    # a periodic box needs 2 stages x 2 rows per fused step
+    assert dry((64, 8), dt=2 * 0.01 / C, scheme="strang", bc="periodic").info()["depth"] == 2
+    p = dry((64, 30), dt=2 * 0.01 / C, scheme="strang")
+    p.set_depth(2)
+    assert p.info()["depth"] == 2
+    p.close()
+
+
 def test_dry_deep_1d_passes(lib):
     """1-D lowest-order plans run passes of 24 steps first; second-order
     plans, plans on more axes and a depth cap have none."""
