@@ -478,14 +478,15 @@ static int rev_occ(bool fp64, int depth, int axes_code) {
 }
 
 // ---------------------------------------------------------------------------
-// 3-D reverse step in one pass.  A wave holds 64 columns (writing the middle
-// 62) and a block of TY rows, and marches up a segment [kb, ke) of planes.
-// Reading plane n it adds the step's term to dL/dV at its own cells of that
-// plane, applies D^H to the rows y0 - 1 .. y0 + TY of the plane and completes
-// T_z^H at plane n - 1 for those rows (right movers of plane n, left movers of
-// plane n - 2 kept in a two-slot ring); then T_y^H and T_x^H give the TY own
-// rows of plane n - 1.  The T_z^H results are rounded as the stored state of
-// a pass would be, so the bits are those of transports applied one by one.
+// 3-D reverse step in one pass.  A workgroup holds 64 columns (writing the
+// middle 62) and a block of WY rows, and marches up a segment [kb, ke) of
+// planes.  Reading plane n it adds the step's term to dL/dV at its own cells
+// of that plane, applies D^H to the rows y0 - 1 .. y0 + WY of the plane and
+// completes T_z^H at plane n - 1 for those rows (right movers of plane n, left
+// movers of plane n - 2 kept in a two-slot ring); then T_y^H and T_x^H give
+// the WY own rows of plane n - 1.  The T_z^H results are rounded as the stored
+// state of a pass would be, so the bits are those of transports applied one by
+// one.
 // ---------------------------------------------------------------------------
 struct Rev3Args {
   int64_t nx, ny, nz;
@@ -496,32 +497,56 @@ struct Rev3Args {
   PhaseK ph;
 };
 
-// rows per wave and resident blocks per CU of the 3-D reverse pass
+// resident blocks per CU the 3-D reverse pass is compiled for
 template <typename T> struct Rev3Shape;
-template <> struct Rev3Shape<float> { static constexpr int TY = 2, kMinBlocks = 2; };
-template <> struct Rev3Shape<double> { static constexpr int TY = 2, kMinBlocks = 1; };
+template <> struct Rev3Shape<float> { static constexpr int kMinBlocks = 2; };
+template <> struct Rev3Shape<double> { static constexpr int kMinBlocks = 1; };
 
 __device__ __forceinline__ int64_t rev_wrap(int64_t r, int64_t n, int periodic) {
   if (periodic) return ((r % n) + n) % n;
   return r < 0 ? 0 : (r >= n ? n - 1 : r);
 }
 
+// The tile of a workgroup: four waves own TW rows each (WY = 4 TW rows), and
+// the WY + 2 rows of a plane are read once, D^H and T_z^H applied by the wave
+// that reads them (wave w takes rows w, w + 4, ...), their y movers left in
+// LDS; after a barrier each wave completes T_y^H and T_x^H on its own rows (a
+// second barrier frees the LDS for the next plane).  Per cell the arithmetic
+// and its order are those of a wave that reads its own halo rows, so the bits
+// do not depend on the tile.
+template <typename T> struct Rev3Tile {
+  static constexpr int TW = 2;
+  static constexpr int WY = 4 * TW;       // rows written per workgroup
+  static constexpr int R = WY + 2;        // rows read: y0 - 1 .. y0 + WY
+  static constexpr int NL = (R + 3) / 4;  // rows read per wave (the last waves fewer)
+  static_assert(R <= 32, "row mask");
+};
+
+template <typename T> struct alignas(16) Rev3Lds {
+  // y movers of T_z^H psi (p) and lambda (l) of every row read: right (r) and
+  // left (l) movers
+  Mov<T> rp[Rev3Tile<T>::R][64], lp[Rev3Tile<T>::R][64];
+  Mov<T> rl[Rev3Tile<T>::R][64], ll[Rev3Tile<T>::R][64];
+};
+
 template <typename T>
-__global__ __launch_bounds__(256, Rev3Shape<T>::kMinBlocks) void k_reverse3d(
+__global__ __launch_bounds__(256, Rev3Shape<T>::kMinBlocks) void k_reverse3d_wg(
     T* __restrict__ psi_out, T* __restrict__ lam_out, const T* __restrict__ psi,
     const T* __restrict__ lam, const double* __restrict__ V, double* __restrict__ Q,
     Rev3Args a) {
-  constexpr int TY = Rev3Shape<T>::TY;
-  constexpr int R = TY + 2;  // rows y0 - 1 .. y0 + TY
+  using S = Rev3Tile<T>;
+  constexpr int TW = S::TW, WY = S::WY, R = S::R, NL = S::NL;
   constexpr bool TWO = sizeof(T) == 8;
+  __shared__ Rev3Lds<T> sh;
   const int lane = threadIdx.x & 63;
-  const int64_t tile = int64_t(blockIdx.x) * 4 + wave_in_block();
-  if (tile >= a.ntiles) return;
+  const int wv = wave_in_block();
+  const int64_t tile = blockIdx.x;
+  if (tile >= a.ntiles) return;  // the whole workgroup
   const int64_t nx = a.nx, ny = a.ny, nz = a.nz;
   const int64_t strip = tile % a.nstrips;
   const int64_t rest = tile / a.nstrips;
   const int64_t yblk = rest % a.nyblk, seg = rest / a.nyblk;
-  const int64_t y0 = yblk * TY;
+  const int64_t y0 = yblk * WY;
   const int64_t kb = seg * a.H;
   const int64_t ke = (kb + a.H < nz) ? kb + a.H : nz;
   const int nit = static_cast<int>(ke - kb) + 2;  // planes kb - 1 .. ke
@@ -529,49 +554,49 @@ __global__ __launch_bounds__(256, Rev3Shape<T>::kMinBlocks) void k_reverse3d(
   const bool own = c.inside && lane >= 1 && lane <= 62;
   const bool walls = !a.periodic;
   const bool read_v = (a.ph.mode == 2);
-  // plane kb - 1 + it lies in the box iff klo <= it < khi (wave-uniform)
   auto clamp_it = [&](int64_t e) -> int {
     return static_cast<int>(e < -64 ? -64 : (e > nit + 64 ? nit + 64 : e));
   };
   const int klo = clamp_it(1 - kb), khi = clamp_it(1 - kb + nz);
-  // the tile's rows: offset of the row read, and bit t set for rows in the box
-  int64_t rowoff[R];
-  uint32_t rin = 0;
+  uint32_t rin = 0;  // bit t: row y0 - 1 + t lies in the box
 #pragma unroll
   for (int t = 0; t < R; ++t) {
     const int64_t y = y0 - 1 + t;
-    rowoff[t] = rev_wrap(y, ny, a.periodic) * nx;
     if (y >= 0 && y < ny) rin |= 1u << t;
   }
   rin = __builtin_amdgcn_readfirstlane(rin);
-  Mov<T> lpr[2][R], llr[2][R];  // left movers of D^H psi, lambda; slot: plane % 2
+  int64_t rowoff[NL];  // this wave's rows t = wv + 4 j
+#pragma unroll
+  for (int j = 0; j < NL; ++j) rowoff[j] = rev_wrap(y0 - 1 + wv + 4 * j, ny, a.periodic) * nx;
+  Mov<T> lpr[2][NL], llr[2][NL];  // left z movers of D^H psi, lambda; slot: plane % 2
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
 #pragma unroll
-    for (int t = 0; t < R; ++t) {
-      zero(lpr[q][t]);
-      zero(llr[q][t]);
+    for (int j = 0; j < NL; ++j) {
+      zero(lpr[q][j]);
+      zero(llr[q][j]);
     }
   }
   for (int base = 0;; base += 2) {
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int it = base + u;
-      if (it >= nit) return;
+      if (it >= nit) return;  // uniform over the workgroup
       const int64_t n = kb - 1 + it;  // plane read
       const bool n_in = it >= klo && it < khi;
       const bool n_own = it >= 1 && it < nit - 1;  // kb <= n < ke
       const int64_t pbase = rev_wrap(n, nz, a.periodic) * ny * nx + c.col;
-      Site<T> zp[R], zl[R];  // T_z^H of psi and lambda at plane n - 1
 #pragma unroll
-      for (int t = 0; t < R; ++t) {
-        const int64_t q = pbase + rowoff[t];
+      for (int j = 0; j < NL; ++j) {
+        const int t = wv + 4 * j;
+        if (t >= R) break;  // wave-uniform
+        const int64_t q = pbase + rowoff[j];
         Site<T> ps, ls;
         load_site(psi + q * 8, ps);
         load_site(lam + q * 8, ls);
         const double v = read_v ? V[q] : 0.0;
         // the step's term of dL/dV, once per cell: own rows, lanes and planes
-        if (t >= 1 && t <= TY && n_own && ((rin >> t) & 1u) && own)
+        if (t >= 1 && t <= WY && n_own && ((rin >> t) & 1u) && own)
           Q[q] = fma(a.qscale, im_dot(ls, ps), Q[q]);
         const Factors f = adjoint_factors<TWO>(v, a.ph);
         adjoint_local(ps, f, a.ph);
@@ -581,34 +606,32 @@ __global__ __launch_bounds__(256, Rev3Shape<T>::kMinBlocks) void k_reverse3d(
           zero(ls);
         }
         Mov<T> rp, lp, rl, ll;
+        Site<T> zp, zl;  // T_z^H of psi and lambda at plane n - 1, row t
         Axis<2, T>::movers(ps, rp, lp);
         Axis<2, T>::movers(ls, rl, ll);
-        Axis<2, T>::combine(rp, lpr[u][t], zp[t]);
-        Axis<2, T>::combine(rl, llr[u][t], zl[t]);
-        lpr[u][t] = lp;
-        llr[u][t] = ll;
-      }
-      if (it < 2) continue;  // plane n - 1 lies before the segment
-      // rows beyond a wall and lanes beyond a side wall read as zero
-#pragma unroll
-      for (int t = 0; t < R; ++t) {
+        Axis<2, T>::combine(rp, lpr[u][j], zp);
+        Axis<2, T>::combine(rl, llr[u][j], zl);
+        lpr[u][j] = lp;
+        llr[u][j] = ll;
+        if (it < 2) continue;  // plane n - 1 lies before the segment
+        // rows beyond a wall and lanes beyond a side wall read as zero
         if (walls && (!((rin >> t) & 1u) || (!c.full && c.out))) {
-          zero(zp[t]);
-          zero(zl[t]);
+          zero(zp);
+          zero(zl);
         }
+        Axis<1, T>::movers(zp, sh.rp[t][lane], sh.lp[t][lane]);
+        Axis<1, T>::movers(zl, sh.rl[t][lane], sh.ll[t][lane]);
       }
+      if (it < 2) continue;  // uniform
+      __syncthreads();
       const int64_t obase = ((n - 1) * ny + y0) * nx + c.x;
 #pragma unroll
-      for (int w = 0; w < TY; ++w) {
+      for (int k = 0; k < TW; ++k) {
         // T_y^H at row y0 + w: right movers from the row above, left from below
-        Mov<T> r2, l2, r1, l1;
+        const int w = wv * TW + k;
         Site<T> yp, yl, op, ol;
-        Axis<1, T>::movers(zp[w + 2], r2, l2);
-        Axis<1, T>::movers(zp[w], r1, l1);
-        Axis<1, T>::combine(r2, l1, yp);
-        Axis<1, T>::movers(zl[w + 2], r2, l2);
-        Axis<1, T>::movers(zl[w], r1, l1);
-        Axis<1, T>::combine(r2, l1, yl);
+        Axis<1, T>::combine(sh.rp[w + 2][lane], sh.lp[w][lane], yp);
+        Axis<1, T>::combine(sh.rl[w + 2][lane], sh.ll[w][lane], yl);
         if (walls && !c.full && !c.inside) {
           zero(yp);
           zero(yl);
@@ -620,6 +643,7 @@ __global__ __launch_bounds__(256, Rev3Shape<T>::kMinBlocks) void k_reverse3d(
           store_site(lam_out + (obase + w * nx) * 8, ol);
         }
       }
+      __syncthreads();  // the next plane's movers overwrite these
     }
   }
 }
@@ -629,7 +653,8 @@ static int rev3_occupancy() {
   static int occ = -1;
   if (occ < 0) {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_reverse3d<T>, 256, 0) != hipSuccess) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_reverse3d_wg<T>, 256, 0) !=
+        hipSuccess) {
       (void)hipGetLastError();
       n = 0;
     }
@@ -643,11 +668,12 @@ static int rev3_occupancy() {
 template <typename T>
 static hipError_t rev3d_t(const void* pi, const void* li, void* po, void* lo, const double* V,
                           double* Q, Rev3Args a, int cu_count, hipStream_t st) {
-  constexpr int TY = Rev3Shape<T>::TY;
+  constexpr int WY = Rev3Tile<T>::WY;
   a.nstrips = (a.nx + strip_width(1) - 1) / strip_width(1);
-  a.nyblk = (a.ny + TY - 1) / TY;
+  a.nyblk = (a.ny + WY - 1) / WY;
   const int64_t per_seg = a.nstrips * a.nyblk;
-  const int64_t resident = int64_t(rev3_occupancy<T>()) * 4 * (cu_count > 0 ? cu_count : 256);
+  // workgroup tiles: resident workgroups are the target
+  const int64_t resident = int64_t(rev3_occupancy<T>()) * (cu_count > 0 ? cu_count : 256);
   int64_t best_H = a.nz, best_cost = -1;
   for (int64_t nseg = 1; nseg <= 64 && nseg <= a.nz; ++nseg) {
     const int64_t H = (a.nz + nseg - 1) / nseg;
@@ -663,9 +689,9 @@ static hipError_t rev3d_t(const void* pi, const void* li, void* po, void* lo, co
   a.H = static_cast<int>(best_H);
   a.nseg = (a.nz + best_H - 1) / best_H;
   a.ntiles = per_seg * a.nseg;
-  const int64_t blocks = (a.ntiles + 3) / 4;
+  const int64_t blocks = a.ntiles;
   if (blocks > INT32_MAX) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_reverse3d<T>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st,
+  hipLaunchKernelGGL(k_reverse3d_wg<T>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st,
                      static_cast<T*>(po), static_cast<T*>(lo), static_cast<const T*>(pi),
                      static_cast<const T*>(li), V, Q, a);
   return hipGetLastError();
