@@ -59,3 +59,16 @@ def test_deep_passes_two_component_line(dtype):
             torch.cuda.synchronize()
         out.append(t.cpu().numpy())
     assert same_bits(out[1], out[0])
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_deep_passes_in_graph_replays(dtype):
+    """Graph replays of 2 x 32 steps (two deep passes and the shallow rest) give
+    the bits of single steps."""
+    announce(f"deep 1-D graph {dtype}")
+    n = 4096
+    psi = random_spinor((n,), seed=11)
+    V = np.random.default_rng(12).uniform(-3, 3, size=(n,)) * C * C
+    kw = dict(dx=DX, dt=DT, c=C, m=1.0, axes=(0,), dtype=dtype)
+    single = gpu_step(psi, V, nsteps=200, depth=1, tiling={"allow_resident": False}, **kw)
+    assert same_bits(gpu_step(psi, V, nsteps=200, graph=True, **kw), single)
